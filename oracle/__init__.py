@@ -1,0 +1,360 @@
+"""CPU float64 oracle for light-field Richardson-Lucy deconvolution with the
+DCT-entropy stopping metric.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark use it.  The product (the HIP library and its binding)
+never imports it, and it never imports the product.
+
+Plain and slow on purpose.  The projections are direct spatial loops in C
+(``lfrl_oracle.c``); the Richardson-Lucy loop, the metric and the stop rule are
+written below in numpy, step by step, in the order the method states them.
+
+Passages followed (section / equation of the paper):
+
+* Richardson-Lucy deconvolution of the light-field image into a volume of axial
+  layers: sec. 1 (the method is named and attributed to Prevedel et al. 2014)
+  and sec. 2.1 (all iterations on the device, only the final volume returned).
+* The metric input is the maximum projection of each iterate along z: sec. 2.2
+  and the caption of Fig. 2(a).
+* Orthonormal 2-D DCT-II: Eqs. (1)-(4).
+* Shannon entropy over a region: Eq. (5); triangular region and its size:
+  Eq. (6); cutoff geometry: Eqs. (7), (9)-(11); DCT entropy: Eq. (12) with the
+  2-norm taken over the coefficient matrix.
+* Stopping: iterate until the DCT entropy starts to decrease and keep the
+  iterate at the maximum (sec. 2.2, after Eq. (12); Fig. 2(d)).
+
+Readings where the text is silent or garbled (each also listed in the design
+notes):
+
+* RL update: x <- x * A^T(y / A x) / A^T 1, with y/Ax := 0 where Ax <= 0 and
+  x := 0 where A^T 1 <= 0; ones initialisation.
+* Transposed PSF = exact adjoint of the forward projection.
+* DCT axes: Eq. (1) pairs u with the width and v with the height (X_S is the
+  width of the region, Eq. (6)); F is stored as F[v][u] (row frequency first).
+* "L2 of a matrix" = Frobenius norm of the whole DCT coefficient matrix.
+* "abslog2" = log2 of the absolute value, with 0 * log 0 = 0.
+* The prefactor of Eq. (12) = 1 / G_S = 2 / (X_S * Y_S).
+* Region S = {(u, v): u / X_S + v / Y_S < 1} (the upper-left triangle of Fig.
+  2(c)), with real-valued legs X_S, Y_S.
+* Eq. (8) is inverted relative to Eqs. (9)-(10); Eqs. (9)-(10) are used.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lfrl_oracle.c")
+_LIB = os.path.join(_HERE, "liblfrl_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C part of the oracle (gcc, OpenMP, generic x86-64)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
+               "-Wall", "-Wextra", "-o", tmp, _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+            lib = ctypes.CDLL(_LIB)
+            i, l = ctypes.c_int, ctypes.c_long
+            fp = ctypes.POINTER(ctypes.c_float)
+            dp = ctypes.POINTER(ctypes.c_double)
+            ip = ctypes.POINTER(ctypes.c_int)
+            lib.oracle_forward.argtypes = [i, i, i, i, i, fp, dp, dp]
+            lib.oracle_backward.argtypes = [i, i, i, i, i, fp, dp, dp]
+            lib.oracle_forward_at.argtypes = [i, i, i, i, i, fp, dp, l, ip, ip, dp]
+            lib.oracle_backward_at.argtypes = [i, i, i, i, i, fp, dp, l, ip, ip, ip, dp]
+            for f in (lib.oracle_forward, lib.oracle_backward,
+                      lib.oracle_forward_at, lib.oracle_backward_at):
+                f.restype = ctypes.c_int
+            lib.oracle_threads.restype = ctypes.c_int
+            _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _geom(psf: np.ndarray):
+    if psf.ndim != 5 or psf.shape[1] != psf.shape[2] or psf.shape[3] != psf.shape[4]:
+        raise ValueError("psf must be [nz][N][N][K][K]")
+    nz, n, _, k, _ = psf.shape
+    if k % 2 != 1:
+        raise ValueError("PSF support must be odd")
+    return nz, n, k
+
+
+def _f32(psf) -> np.ndarray:
+    return np.ascontiguousarray(psf, dtype=np.float32)
+
+
+def threads() -> int:
+    """OpenMP threads the C routines use."""
+    return int(_load().oracle_threads())
+
+
+def forward(psf, vol) -> np.ndarray:
+    """Light-field forward projection A x of a volume [nz][H][W] (float64)."""
+    psf = _f32(psf)
+    nz, n, k = _geom(psf)
+    vol = np.ascontiguousarray(vol, dtype=np.float64)
+    if vol.ndim != 3 or vol.shape[0] != nz:
+        raise ValueError("volume must be [nz][H][W]")
+    h, w = vol.shape[1:]
+    img = np.empty((h, w), dtype=np.float64)
+    rc = _load().oracle_forward(n, nz, k, h, w, _ptr(psf, ctypes.c_float),
+                                _ptr(vol, ctypes.c_double), _ptr(img, ctypes.c_double))
+    if rc != 0:
+        raise RuntimeError(f"oracle_forward failed ({rc})")
+    return img
+
+
+def backward(psf, img) -> np.ndarray:
+    """Back projection A^T y (exact adjoint of :func:`forward`)."""
+    psf = _f32(psf)
+    nz, n, k = _geom(psf)
+    img = np.ascontiguousarray(img, dtype=np.float64)
+    h, w = img.shape
+    vol = np.empty((nz, h, w), dtype=np.float64)
+    rc = _load().oracle_backward(n, nz, k, h, w, _ptr(psf, ctypes.c_float),
+                                 _ptr(img, ctypes.c_double), _ptr(vol, ctypes.c_double))
+    if rc != 0:
+        raise RuntimeError(f"oracle_backward failed ({rc})")
+    return vol
+
+
+def forward_at(psf, vol, rows, cols) -> np.ndarray:
+    """A x evaluated only at pixels (rows[i], cols[i])."""
+    psf = _f32(psf)
+    nz, n, k = _geom(psf)
+    vol = np.ascontiguousarray(vol, dtype=np.float64)
+    h, w = vol.shape[1:]
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    if rows.shape != cols.shape or rows.ndim != 1:
+        raise ValueError("rows/cols must be 1-D of equal length")
+    if rows.size and (rows.min() < 0 or rows.max() >= h or cols.min() < 0 or cols.max() >= w):
+        raise ValueError("pixel index out of range")
+    out = np.empty(rows.size, dtype=np.float64)
+    rc = _load().oracle_forward_at(n, nz, k, h, w, _ptr(psf, ctypes.c_float),
+                                   _ptr(vol, ctypes.c_double), rows.size,
+                                   _ptr(rows, ctypes.c_int), _ptr(cols, ctypes.c_int),
+                                   _ptr(out, ctypes.c_double))
+    if rc != 0:
+        raise RuntimeError(f"oracle_forward_at failed ({rc})")
+    return out
+
+
+def backward_at(psf, img, planes, rows, cols) -> np.ndarray:
+    """A^T y evaluated only at voxels (planes[i], rows[i], cols[i])."""
+    psf = _f32(psf)
+    nz, n, k = _geom(psf)
+    img = np.ascontiguousarray(img, dtype=np.float64)
+    h, w = img.shape
+    jj = np.ascontiguousarray(planes, dtype=np.int32)
+    rr = np.ascontiguousarray(rows, dtype=np.int32)
+    ss = np.ascontiguousarray(cols, dtype=np.int32)
+    if not (jj.shape == rr.shape == ss.shape) or jj.ndim != 1:
+        raise ValueError("index arrays must be 1-D of equal length")
+    if jj.size and (jj.min() < 0 or jj.max() >= nz or rr.min() < 0 or rr.max() >= h
+                    or ss.min() < 0 or ss.max() >= w):
+        raise ValueError("voxel index out of range")
+    out = np.empty(jj.size, dtype=np.float64)
+    rc = _load().oracle_backward_at(n, nz, k, h, w, _ptr(psf, ctypes.c_float),
+                                    _ptr(img, ctypes.c_double), jj.size,
+                                    _ptr(jj, ctypes.c_int), _ptr(rr, ctypes.c_int),
+                                    _ptr(ss, ctypes.c_int), _ptr(out, ctypes.c_double))
+    if rc != 0:
+        raise RuntimeError(f"oracle_backward_at failed ({rc})")
+    return out
+
+
+def sensitivity(psf, h: int, w: int) -> np.ndarray:
+    """c = A^T 1: the total weight each voxel sends into the image."""
+    return backward(psf, np.ones((h, w), dtype=np.float64))
+
+
+def normalize_psf(psf) -> np.ndarray:
+    """Scale every (j, a, b) kernel of a float32 PSF set to unit sum, the sums
+    taken in float64, the result rounded back to float32."""
+    p = np.asarray(psf, dtype=np.float32).astype(np.float64)
+    s = p.sum(axis=(-2, -1), keepdims=True)
+    return (p / s).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# Richardson-Lucy (sec. 1, sec. 2.1)
+# --------------------------------------------------------------------------
+def rl_step(psf, y, x, c):
+    """One Richardson-Lucy iteration; returns (x_new, yhat) where yhat = A x."""
+    yhat = forward(psf, x)
+    ratio = np.zeros_like(yhat)
+    pos = yhat > 0
+    ratio[pos] = y[pos] / yhat[pos]
+    b = backward(psf, ratio)
+    x_new = np.zeros_like(x)
+    ok = c > 0
+    x_new[ok] = x[ok] * b[ok] / c[ok]
+    return x_new, yhat
+
+
+def rl(psf, y, iters: int, x0=None, keep_all: bool = False):
+    """Run ``iters`` Richardson-Lucy iterations from ``x0`` (ones by default).
+
+    Returns the final iterate, or the list [x^0, x^1, ..., x^iters] when
+    ``keep_all``."""
+    y = np.asarray(y, dtype=np.float64)
+    nz = np.asarray(psf).shape[0]
+    h, w = y.shape
+    c = sensitivity(psf, h, w)
+    x = np.ones((nz, h, w)) if x0 is None else np.array(x0, dtype=np.float64)
+    out = [x]
+    for _ in range(iters):
+        x, _ = rl_step(psf, y, x, c)
+        out.append(x)
+    return out if keep_all else x
+
+
+def poisson_loglik(y, yhat) -> float:
+    """sum(y log yhat - yhat) over pixels with yhat > 0 (the objective RL ascends)."""
+    y = np.asarray(y, dtype=np.float64)
+    pos = yhat > 0
+    return float(np.sum(y[pos] * np.log(yhat[pos]) - yhat[pos]))
+
+
+# --------------------------------------------------------------------------
+# DCT-entropy metric (sec. 2.2, Eqs. 1-12)
+# --------------------------------------------------------------------------
+def mip(vol) -> np.ndarray:
+    """Maximum projection along z (sec. 2.2; Fig. 2(a))."""
+    return np.asarray(vol, dtype=np.float64).max(axis=0)
+
+
+def dct_basis(n: int) -> np.ndarray:
+    """C[k][x] = c(k, n) cos((2x + 1) pi k / (2n)), c = sqrt(1/n) for k = 0 and
+    sqrt(2/n) otherwise (Eqs. 2-4)."""
+    k = np.arange(n, dtype=np.float64)[:, None]
+    x = np.arange(n, dtype=np.float64)[None, :]
+    c = np.full((n, 1), np.sqrt(2.0 / n))
+    c[0, 0] = np.sqrt(1.0 / n)
+    return c * np.cos((2 * x + 1) * np.pi * k / (2 * n))
+
+
+def dct2(img) -> np.ndarray:
+    """F[v][u] = sum_{y,x} f[y][x] C_v(y, M) C_u(x, N) (Eq. 1): v is the row
+    (height) frequency, u the column (width) frequency."""
+    img = np.asarray(img, dtype=np.float64)
+    m, n = img.shape
+    return dct_basis(m) @ img @ dct_basis(n).T
+
+
+def triangle_mask(h: int, w: int, xs: float, ys: float) -> np.ndarray:
+    """Region S of Eq. (6): mask[v][u] = u / X_S + v / Y_S < 1."""
+    if not (xs > 0 and ys > 0):
+        raise ValueError("triangle legs must be positive")
+    v = np.arange(h, dtype=np.float64)[:, None]
+    u = np.arange(w, dtype=np.float64)[None, :]
+    return (u / xs + v / ys) < 1.0
+
+
+def dct_entropy(img, xs: float, ys: float) -> float:
+    """DCT entropy of a 2-D image (Eq. 12): with F the DCT of the image and
+    n = ||F|| (Frobenius, whole matrix), p = |F| / n over S and
+    e = -(2 / (X_S Y_S)) * sum_S p log2 p (0 log 0 = 0).  Returns 0 for an
+    all-zero image."""
+    f = dct2(img)
+    n = np.sqrt(np.sum(f * f))
+    if n == 0:
+        return 0.0
+    p = np.abs(f[triangle_mask(f.shape[0], f.shape[1], xs, ys)]) / n
+    p = p[p > 0]
+    return float(-(2.0 / (xs * ys)) * np.sum(p * np.log2(p)))
+
+
+def metric(vol, xs: float, ys: float) -> float:
+    """Per-iterate quality metric: DCT entropy of the z maximum projection."""
+    return dct_entropy(mip(vol), xs, ys)
+
+
+def stop_decision(trace, patience: int = 1):
+    """Apply the stopping rule to metric values trace[0] = e_1, trace[1] = e_2, ...
+
+    Stops at the first iteration k at which the last ``patience`` steps were all
+    strict decreases (e_i < e_{i-1}); ties are not decreases.  The iterate kept is
+    the one with the largest metric seen so far (ties go to the later iterate).
+
+    Returns (stopped, k_stop, best): ``stopped`` is False if the trace ran out
+    first (k_stop is then len(trace)); ``best`` is the 1-based iteration kept."""
+    if patience < 1:
+        raise ValueError("patience must be >= 1")
+    best, best_e, run = 0, -np.inf, 0
+    for i, e in enumerate(trace):
+        k = i + 1
+        if i > 0:
+            run = run + 1 if e < trace[i - 1] else 0
+        if e >= best_e:
+            best, best_e = k, e
+        if run >= patience:
+            return True, k, best
+    return False, len(trace), best
+
+
+def cutoff(d_ml: float, mag: float, nnum: int, wavelength: float, na: float,
+           h: int, w: int):
+    """Triangle legs from the optics: pixel size P_u = d_ML / (Q Nnum) (Eq. 7),
+    resolution limit d_psf = 1.22 lambda Nnum / NA (Eq. 11), X_S = P_u W / d_psf
+    (Eq. 9) and Y_S = P_u H / d_psf (Eq. 10).  Lengths in one unit."""
+    pu = d_ml / (mag * nnum)
+    dpsf = 1.22 * wavelength * nnum / na
+    return pu * w / dpsf, pu * h / dpsf
+
+
+def synthetic_cutoff(nnum: int, spot_radius: float, h: int, w: int):
+    """Triangle legs for synthetic PSFs given in pixel units: P_u = 1 and the
+    resolution limit is Nnum times the in-focus spot diameter (Eq. 11 with the
+    Airy unit replaced by the synthetic spot's diameter)."""
+    dpsf = nnum * 2.0 * spot_radius
+    return w / dpsf, h / dpsf
+
+
+def deconvolve(psf, y, max_iters: int, xs: float, ys: float, *, stop: bool = True,
+               patience: int = 1, x0=None):
+    """Richardson-Lucy with the metric evaluated on every iterate and the
+    stopping rule applied.  Returns (x_best, best_iter, iters_run, trace)."""
+    y = np.asarray(y, dtype=np.float64)
+    nz = np.asarray(psf).shape[0]
+    h, w = y.shape
+    c = sensitivity(psf, h, w)
+    x = np.ones((nz, h, w)) if x0 is None else np.array(x0, dtype=np.float64)
+    trace, iterates = [], {}
+    best_x = x
+    for k in range(1, max_iters + 1):
+        x, _ = rl_step(psf, y, x, c)
+        trace.append(metric(x, xs, ys))
+        iterates[k] = x
+        stopped, _, best = stop_decision(trace, patience)
+        best_x = iterates[best]
+        for kk in list(iterates):
+            if kk != best and kk != k:
+                del iterates[kk]
+        if stop and stopped:
+            return best_x, best, k, trace
+    _, _, best = stop_decision(trace, patience)
+    return iterates[best], best, max_iters, trace
