@@ -1,0 +1,194 @@
+/*
+ * lfrl.h - C ABI of the MI355X (gfx950) light-field Richardson-Lucy library.
+ *
+ * The library deconvolves a light-field microscopy image into a volume of
+ * axial layers with Richardson-Lucy iterations run entirely on the GPU, and
+ * scores each iterate with the DCT-entropy image-quality metric that picks the
+ * stopping iteration (AutoDeconJ, arXiv 2208.11422: sec. 1 and sec. 2.1 for
+ * the GPU-resident deconvolution, sec. 2.2 / Eqs. 1-12 for the metric).
+ *
+ * Conventions for every call:
+ *   - Pointers are DEVICE pointers on the plan's device unless marked [host].
+ *   - Arrays are row-major, contiguous float32 (metric results float64):
+ *       PSF    psf[nz][nnum][nnum][K][K]: image of a point source in depth plane
+ *              j whose pixel has row phase a = r mod nnum and column phase
+ *              b = s mod nnum; tap (u, v) lies at displacement (u - c0, v - c0)
+ *              from the source pixel, c0 = (K - 1) / 2, K odd.
+ *       volume vol[nz][h][w]; image img[h][w]; h and w multiples of nnum, the
+ *              lenslet grid starting at pixel (0, 0).
+ *   - Projections are linear with zero padding outside the image ("same" size,
+ *     not circular).
+ *   - Every call is asynchronous on `stream` (a hipStream_t passed as void*;
+ *     NULL = the null stream) unless stated otherwise.
+ *   - The caller owns every buffer it passes.  A plan owns its PSF spectra and
+ *     its workspace; after lfrl_plan returns, no call allocates device memory
+ *     except lfrl_metric (see there).
+ *   - One call at a time per plan (calls on one plan share its workspace).
+ *   - Calls return LFRL_OK or a negative lfrl_status and never throw.  Argument
+ *     errors are reported before anything is launched; lfrl_last_error() gives
+ *     a message (per thread).  Outputs are undefined after an error.
+ */
+#ifndef LFRL_H
+#define LFRL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lfrl_plan_s *lfrl_plan_t;
+
+typedef enum {
+    LFRL_OK = 0,
+    LFRL_ERR_ARG = -1,          /* bad argument or size */
+    LFRL_ERR_NOMEM = -2,        /* device allocation failed */
+    LFRL_ERR_DEVICE = -3,       /* HIP runtime / kernel launch error */
+    LFRL_ERR_UNSUPPORTED = -4,  /* valid request this build does not serve */
+    LFRL_ERR_NUMERIC = -5       /* non-finite value met where one is not allowed */
+} lfrl_status;
+
+typedef enum {
+    LFRL_FP32 = 0               /* spectra, DFTs and contraction in float32 */
+} lfrl_precision;
+
+/* Plan description.  Geometry of the PSF set and the largest image the plan
+ * serves (the memory estimate of Fig. 1 is made for that size). */
+typedef struct {
+    int32_t nnum;      /* pixels per lenslet per axis, N >= 1 */
+    int32_t nz;        /* depth planes, >= 1 */
+    int32_t ksize;     /* PSF support per axis, odd, >= 1 */
+    int32_t max_h;     /* largest image height served, multiple of nnum */
+    int32_t max_w;     /* largest image width served, multiple of nnum */
+    int32_t precision; /* lfrl_precision */
+    int32_t tile_q;    /* DFT tile side in lenslets; 0 = choose from the model */
+    uint32_t flags;    /* reserved, must be 0 */
+} lfrl_plan_desc;
+
+/* Read-only facts about a plan (all [host]). */
+typedef struct {
+    int32_t tile_q;        /* DFT tile side Q (lenslets) */
+    int32_t tile_out;      /* output lenslets per tile side T = Q - R + 1 */
+    int32_t taps;          /* polyphase taps per side R */
+    int32_t nfreq;         /* half-spectrum frequencies per tile, Q * (Q/2 + 1) */
+    int32_t max_tiles;     /* tiles at the plan's largest image */
+    int32_t split_k;       /* reduction split of the forward contraction */
+    size_t resident_bytes; /* spectra held for the plan's lifetime */
+    size_t workspace_bytes;/* per-call workspace at the largest image */
+} lfrl_plan_info_t;
+
+/* Memory estimate before allocation (Fig. 1: the required memory is
+ * estimated before anything is placed on the card).  [host], no device work.
+ * Either output pointer may be NULL. */
+int lfrl_plan_footprint(const lfrl_plan_desc *desc, size_t *resident_bytes,
+                        size_t *workspace_bytes);
+
+/* Build a plan: validate `desc`, allocate spectra and workspace, and turn the
+ * PSF set into the resident per-frequency spectra the projections stream
+ * (Fig. 1: the PSF is placed on the card once and used directly by every
+ * later reconstruction).  `psf` is [nz][nnum][nnum][K][K] float32; the caller
+ * may free it once the work queued on `stream` has completed.  On success
+ * *out receives the plan; on error *out is set to NULL. */
+int lfrl_plan(lfrl_plan_t *out, const lfrl_plan_desc *desc, const float *psf,
+              void *stream);
+
+/* Release a plan and everything it owns (synchronises its device first).
+ * NULL is accepted. */
+int lfrl_plan_destroy(lfrl_plan_t plan);
+
+/* Fill *info with the plan's tile shape and memory figures. */
+int lfrl_plan_get_info(lfrl_plan_t plan, lfrl_plan_info_t *info);
+
+/* Forward light-field projection img = A vol (sec. 1; the model behind RL):
+ * img[p] = sum_j sum_q vol[j][q] * psf[j][q mod N][p - q + c0]  (2-D indices),
+ * i.e. every depth and every lenslet-relative phase convolved with its own PSF
+ * and summed into one image.  vol [nz][h][w] -> img [h][w]; h <= max_h,
+ * w <= max_w, both multiples of nnum. */
+int lfrl_forward(lfrl_plan_t plan, int32_t h, int32_t w, const float *vol,
+                 float *img, void *stream);
+
+/* Back projection with the transposed PSFs, vol = A^T img, the exact adjoint
+ * of lfrl_forward: vol[j][q] = sum_p img[p] * psf[j][q mod N][p - q + c0].
+ * img [h][w] -> vol [nz][h][w]. */
+int lfrl_backward(lfrl_plan_t plan, int32_t h, int32_t w, const float *img,
+                  float *vol, void *stream);
+
+/* Stop modes of lfrl_deconvolve. */
+typedef enum {
+    LFRL_STOP_NONE = 0,   /* run max_iters iterations, no metric */
+    LFRL_STOP_METRIC = 1, /* metric every iteration; stop when it decreases */
+    LFRL_STOP_TRACK = 2   /* metric every iteration and keep the best iterate,
+                             but always run max_iters iterations */
+} lfrl_stop_mode;
+
+typedef struct {
+    int32_t max_iters; /* iteration cap, >= 1 */
+    int32_t stop;      /* lfrl_stop_mode */
+    int32_t patience;  /* consecutive strict decreases that stop (>= 1) */
+    int32_t init;      /* 0 = start from ones, 1 = start from the caller's vol */
+    double xs, ys;     /* legs of the triangular DCT region, in DCT bins:
+                          X_S along the width, Y_S along the height (Eq. 6) */
+} lfrl_rl_opts;
+
+typedef struct {
+    int32_t iters_run; /* iterations executed */
+    int32_t best_iter; /* iteration whose volume was returned */
+    int32_t stopped;   /* 1 if the stop rule fired before the cap */
+    int32_t reserved;
+    double *metric_trace; /* [host] array of max_iters or NULL: e_1, e_2, ... */
+    double *flux_trace;   /* [host] array of max_iters or NULL:
+                             <A^T 1, x^k> / sum(img) - 1 for each iterate */
+} lfrl_rl_report;
+
+/* Richardson-Lucy deconvolution (sec. 1; all iterations on the GPU and only
+ * the result handed back, sec. 2.1):
+ *   x^0 = 1 (or vol), c = A^T 1,
+ *   x^k = x^{k-1} * A^T( img / A x^{k-1} ) / c,
+ * with img / A x := 0 where A x <= 0 and x := 0 where c <= 0.
+ * With a metric stop mode, every iterate is scored by the DCT entropy of its
+ * z maximum projection (lfrl_metric) and the stop rule of sec. 2.2 applies:
+ * stop once the entropy has strictly decreased `patience` times in a row and
+ * return the iterate with the largest entropy seen (ties: the later one).
+ * img [h][w] -> vol [nz][h][w] (x^{best_iter}, or x^{max_iters} without a
+ * metric).  Synchronises `stream` before returning (the host needs the stop
+ * decision and the report).  `report` [host] may be NULL. */
+int lfrl_deconvolve(lfrl_plan_t plan, int32_t h, int32_t w, const float *img,
+                    float *vol, const lfrl_rl_opts *opts, lfrl_rl_report *report,
+                    void *stream);
+
+/* DCT entropy of a 2-D image (sec. 2.2, Eqs. 1-6 and 12): F = orthonormal
+ * DCT-II of img (Eqs. 1-4), n = Frobenius norm of F (the "2-norm of a matrix"),
+ * S = {(u, v): u / xs + v / ys < 1} with u the width and v the height
+ * frequency, and
+ *     *out = -(2 / (xs * ys)) * sum_{(u,v) in S} |F/n| log2 |F/n|
+ * with 0 log 0 = 0 (0 for an all-zero image).  Pass nz > 1 to score the z
+ * maximum projection of a volume img[nz][h][w] instead.  `out` is a device
+ * float64.  Uses a per-device scratch buffer that the library allocates on
+ * first use and grows when a larger image needs it. */
+int lfrl_metric(int32_t nz, int32_t h, int32_t w, const float *img, double xs,
+                double ys, double *out, void *stream);
+
+/* Triangle legs from the optics (Eqs. 7, 9-11), [host]:
+ * P_u = d_ml / (mag * nnum), d_psf = 1.22 * lambda * nnum / na,
+ * xs = P_u * w / d_psf, ys = P_u * h / d_psf.  Lengths in one unit. */
+int lfrl_metric_cutoff(double d_ml, double mag, int32_t nnum, double lambda,
+                       double na, int32_t h, int32_t w, double *xs, double *ys);
+
+/* Kernel timing with HIP events on the caller's stream, for benchmarks.
+ * While enabled, every launch of the two spectral contraction kernels is
+ * bracketed by events.  lfrl_profile_read synchronises and returns, for
+ * kernel "contract_fwd" or "contract_adj", the summed duration in ms and the
+ * number of launches since profiling was last enabled. */
+int lfrl_profile_enable(lfrl_plan_t plan, int32_t on);
+int lfrl_profile_read(lfrl_plan_t plan, const char *kernel, double *total_ms,
+                      int64_t *launches);
+
+/* Message describing the last error on this thread ("" if none). */
+const char *lfrl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LFRL_H */

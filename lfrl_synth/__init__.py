@@ -242,17 +242,37 @@ PRESETS = {
 }
 
 
-def preset(name: str, *, with_psf: bool = True) -> dict:
-    """Build the seeded inputs of a named workload: ``psf``, ``x_true`` and the
-    metadata needed to make the measurement (``peak``, ``background``,
-    ``noise_seed``).  The clean image itself must be projected by the caller."""
+def _cached(key: str, make, cache_dir: str | None):
+    """Load a generated array from ``cache_dir/key.npy`` or make and store it."""
+    if not cache_dir:
+        return make()
+    import os
+    os.makedirs(cache_dir, exist_ok=True)
+    path = os.path.join(cache_dir, key + ".npy")
+    if os.path.exists(path):
+        return np.load(path, allow_pickle=False)
+    arr = make()
+    tmp = f"{path}.{os.getpid()}.tmp.npy"
+    np.save(tmp, arr)
+    os.replace(tmp, path)
+    return arr
+
+
+def preset(name: str, *, with_psf: bool = True, cache_dir: str | None = None) -> dict:
+    """Build the seeded inputs of a named workload: ``psf_array``, ``x_true`` and
+    the metadata needed to make the measurement (``peak``, ``background``,
+    ``noise_seed``).  The clean image itself must be projected by the caller.
+    ``cache_dir`` keeps generated PSF sets on disk between processes."""
     p = dict(PRESETS[name])
     g: Geometry = p["geometry"]
     if with_psf:
+        key = f"psf_{p['psf']}_{g.nnum}_{g.nz}_{g.ksize}_{p['psf_seed']}"
         if p["psf"] == "gaussian":
-            p["psf_array"] = gaussian_psf(g.nnum, g.nz, g.ksize, p["psf_seed"])
+            p["psf_array"] = _cached(key, lambda: gaussian_psf(g.nnum, g.nz, g.ksize,
+                                                               p["psf_seed"]), cache_dir)
         else:
-            p["psf_array"] = disk_psf(g.nnum, g.nz, g.ksize, p["psf_seed"])
+            p["psf_array"] = _cached(key, lambda: disk_psf(g.nnum, g.nz, g.ksize,
+                                                           p["psf_seed"]), cache_dir)
     x = bead_volume(g.nz, g.h, g.w, p["beads"], p["vol_seed"])
     if p["filaments"]:
         x = add_filaments(x, p["filaments"], p["vol_seed"] + 1000)

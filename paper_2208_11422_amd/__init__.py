@@ -1,0 +1,293 @@
+"""Light-field Richardson-Lucy deconvolution on MI355X: Python binding.
+
+A thin ctypes layer over ``liblfrl.so`` (C ABI declared in include/lfrl.h).
+It only marshals arguments: every step of the computation runs in the
+library's HIP kernels.  PyTorch provides device memory and streams; importing
+torch first also loads the HIP runtime the library shares with it.
+
+The functions named ``lfrl_*`` mirror the C entry points one to one; the
+:class:`Plan` class is a small convenience wrapper over them.  There is no CPU
+fallback: if the library is missing every call raises :class:`LfrlError`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+__all__ = [
+    "LfrlError", "PlanDesc", "PlanInfo", "RlOpts", "RlReport",
+    "lfrl_plan_footprint", "lfrl_plan", "lfrl_plan_destroy", "lfrl_plan_get_info",
+    "lfrl_forward", "lfrl_backward", "lfrl_deconvolve", "lfrl_metric",
+    "lfrl_metric_cutoff", "lfrl_profile_enable", "lfrl_profile_read", "lfrl_last_error",
+    "Plan", "library_path", "STOP_NONE", "STOP_METRIC", "STOP_TRACK", "FP32",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liblfrl.so")
+
+FP32 = 0
+STOP_NONE, STOP_METRIC, STOP_TRACK = 0, 1, 2
+
+_STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_NOMEM", -3: "ERR_DEVICE",
+           -4: "ERR_UNSUPPORTED", -5: "ERR_NUMERIC"}
+
+
+class LfrlError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lfrl {_STATUS.get(code, code)} ({code}): {msg}")
+        self.code = code
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("nnum", ctypes.c_int32), ("nz", ctypes.c_int32), ("ksize", ctypes.c_int32),
+                ("max_h", ctypes.c_int32), ("max_w", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("tile_q", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("tile_q", ctypes.c_int32), ("tile_out", ctypes.c_int32),
+                ("taps", ctypes.c_int32), ("nfreq", ctypes.c_int32),
+                ("max_tiles", ctypes.c_int32), ("split_k", ctypes.c_int32),
+                ("resident_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t)]
+
+
+class RlOpts(ctypes.Structure):
+    _fields_ = [("max_iters", ctypes.c_int32), ("stop", ctypes.c_int32),
+                ("patience", ctypes.c_int32), ("init", ctypes.c_int32),
+                ("xs", ctypes.c_double), ("ys", ctypes.c_double)]
+
+
+class RlReport(ctypes.Structure):
+    _fields_ = [("iters_run", ctypes.c_int32), ("best_iter", ctypes.c_int32),
+                ("stopped", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("metric_trace", ctypes.POINTER(ctypes.c_double)),
+                ("flux_trace", ctypes.POINTER(ctypes.c_double))]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise LfrlError(-4, f"{_LIB_PATH} is not built (run __graft_entry__.build() or "
+                            "python paper_2208_11422_amd/build.py)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    sz = ctypes.POINTER(ctypes.c_size_t)
+    sig = {
+        "lfrl_plan_footprint": [ctypes.POINTER(PlanDesc), sz, sz],
+        "lfrl_plan": [ctypes.POINTER(vp), ctypes.POINTER(PlanDesc), vp, vp],
+        "lfrl_plan_destroy": [vp],
+        "lfrl_plan_get_info": [vp, ctypes.POINTER(PlanInfo)],
+        "lfrl_forward": [vp, i32, i32, vp, vp, vp],
+        "lfrl_backward": [vp, i32, i32, vp, vp, vp],
+        "lfrl_deconvolve": [vp, i32, i32, vp, vp, ctypes.POINTER(RlOpts),
+                            ctypes.POINTER(RlReport), vp],
+        "lfrl_metric": [i32, i32, i32, vp, dbl, dbl, vp, vp],
+        "lfrl_metric_cutoff": [dbl, dbl, i32, dbl, dbl, i32, i32,
+                               ctypes.POINTER(dbl), ctypes.POINTER(dbl)],
+        "lfrl_profile_enable": [vp, i32],
+        "lfrl_profile_read": [vp, ctypes.c_char_p, ctypes.POINTER(dbl),
+                              ctypes.POINTER(ctypes.c_int64)],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.lfrl_last_error.argtypes = []
+    lib.lfrl_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def lfrl_last_error() -> str:
+    return _load().lfrl_last_error().decode()
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        raise LfrlError(rc, lfrl_last_error())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _dev_f32(t: torch.Tensor, name: str, shape=None) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise LfrlError(-1, f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise LfrlError(-1, f"{name} must be contiguous float32")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise LfrlError(-1, f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.data_ptr()
+
+
+# ---------------------------------------------------------------------------
+# one-to-one wrappers of the C entry points
+# ---------------------------------------------------------------------------
+def lfrl_plan_footprint(desc: PlanDesc):
+    r, w = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(_load().lfrl_plan_footprint(ctypes.byref(desc), ctypes.byref(r), ctypes.byref(w)))
+    return r.value, w.value
+
+
+def lfrl_plan(desc: PlanDesc, psf: torch.Tensor, stream=None) -> int:
+    shape = (desc.nz, desc.nnum, desc.nnum, desc.ksize, desc.ksize)
+    ptr = _dev_f32(psf, "psf", shape)
+    h = ctypes.c_void_p()
+    _check(_load().lfrl_plan(ctypes.byref(h), ctypes.byref(desc), ptr, _stream(stream)))
+    return h.value
+
+
+def lfrl_plan_destroy(plan: int) -> None:
+    _check(_load().lfrl_plan_destroy(plan))
+
+
+def lfrl_plan_get_info(plan: int) -> dict:
+    info = PlanInfo()
+    _check(_load().lfrl_plan_get_info(plan, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in PlanInfo._fields_}
+
+
+def lfrl_forward(plan: int, h: int, w: int, vol: torch.Tensor, img: torch.Tensor,
+                 stream=None) -> None:
+    _check(_load().lfrl_forward(plan, h, w, _dev_f32(vol, "vol"), _dev_f32(img, "img"),
+                                _stream(stream)))
+
+
+def lfrl_backward(plan: int, h: int, w: int, img: torch.Tensor, vol: torch.Tensor,
+                  stream=None) -> None:
+    _check(_load().lfrl_backward(plan, h, w, _dev_f32(img, "img"), _dev_f32(vol, "vol"),
+                                 _stream(stream)))
+
+
+def lfrl_deconvolve(plan: int, h: int, w: int, img: torch.Tensor, vol: torch.Tensor,
+                    opts: RlOpts, want_metric: bool = True, want_flux: bool = False,
+                    stream=None) -> dict:
+    n = max(int(opts.max_iters), 1)
+    mt = (ctypes.c_double * n)() if want_metric else None
+    ft = (ctypes.c_double * n)() if want_flux else None
+    rep = RlReport()
+    rep.metric_trace = ctypes.cast(mt, ctypes.POINTER(ctypes.c_double)) if mt is not None else None
+    rep.flux_trace = ctypes.cast(ft, ctypes.POINTER(ctypes.c_double)) if ft is not None else None
+    _check(_load().lfrl_deconvolve(plan, h, w, _dev_f32(img, "img"), _dev_f32(vol, "vol"),
+                                   ctypes.byref(opts), ctypes.byref(rep), _stream(stream)))
+    k = rep.iters_run
+    out = {"iters_run": k, "best_iter": rep.best_iter, "stopped": bool(rep.stopped)}
+    if mt is not None and opts.stop != STOP_NONE:
+        out["metric_trace"] = list(mt[:k])
+    if ft is not None:
+        out["flux_trace"] = list(ft[:k])
+    return out
+
+
+def lfrl_metric(nz: int, h: int, w: int, img: torch.Tensor, xs: float, ys: float,
+                out: torch.Tensor, stream=None) -> None:
+    if not out.is_cuda or out.dtype != torch.float64 or out.numel() < 1:
+        raise LfrlError(-1, "out must be a CUDA float64 tensor")
+    _check(_load().lfrl_metric(nz, h, w, _dev_f32(img, "img"), float(xs), float(ys),
+                               out.data_ptr(), _stream(stream)))
+
+
+def lfrl_metric_cutoff(d_ml: float, mag: float, nnum: int, wavelength: float, na: float,
+                       h: int, w: int):
+    xs, ys = ctypes.c_double(), ctypes.c_double()
+    _check(_load().lfrl_metric_cutoff(d_ml, mag, nnum, wavelength, na, h, w,
+                                      ctypes.byref(xs), ctypes.byref(ys)))
+    return xs.value, ys.value
+
+
+def lfrl_profile_enable(plan: int, on: bool) -> None:
+    _check(_load().lfrl_profile_enable(plan, 1 if on else 0))
+
+
+def lfrl_profile_read(plan: int, kernel: str):
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(_load().lfrl_profile_read(plan, kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper
+# ---------------------------------------------------------------------------
+class Plan:
+    """Resident PSF spectra for one PSF set, serving images up to max_h x max_w."""
+
+    def __init__(self, psf: torch.Tensor, max_h: int, max_w: int, tile_q: int = 0,
+                 stream=None):
+        nz, n, n2, k, k2 = psf.shape
+        if n != n2 or k != k2:
+            raise LfrlError(-1, "psf must be [nz][N][N][K][K]")
+        self.desc = PlanDesc(nnum=n, nz=nz, ksize=k, max_h=max_h, max_w=max_w,
+                             precision=FP32, tile_q=tile_q, flags=0)
+        self.nnum, self.nz, self.ksize = n, nz, k
+        self.device = psf.device
+        self.handle = lfrl_plan(self.desc, psf, stream)
+        self.info = lfrl_plan_get_info(self.handle)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            lfrl_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, vol: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None):
+        _, h, w = vol.shape
+        if out is None:
+            out = torch.empty((h, w), dtype=torch.float32, device=vol.device)
+        lfrl_forward(self.handle, h, w, vol, out, stream)
+        return out
+
+    def backward(self, img: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None):
+        h, w = img.shape
+        if out is None:
+            out = torch.empty((self.nz, h, w), dtype=torch.float32, device=img.device)
+        lfrl_backward(self.handle, h, w, img, out, stream)
+        return out
+
+    def deconvolve(self, img: torch.Tensor, iters: int, *, stop: int = STOP_NONE,
+                   patience: int = 1, xs: float = 1.0, ys: float = 1.0,
+                   init: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                   want_flux: bool = False, stream=None):
+        h, w = img.shape
+        if out is None:
+            out = torch.empty((self.nz, h, w), dtype=torch.float32, device=img.device)
+        if init is not None:
+            out.copy_(init)
+        opts = RlOpts(max_iters=iters, stop=stop, patience=patience,
+                      init=0 if init is None else 1, xs=xs, ys=ys)
+        rep = lfrl_deconvolve(self.handle, h, w, img, out, opts, want_metric=True,
+                              want_flux=want_flux, stream=stream)
+        return out, rep
+
+
+def metric(img: torch.Tensor, xs: float, ys: float, stream=None) -> float:
+    """DCT entropy of a 2-D image, or of the z-MIP of a [nz][h][w] volume."""
+    if img.dim() == 2:
+        nz, (h, w) = 1, img.shape
+    else:
+        nz, h, w = img.shape
+    out = torch.empty(1, dtype=torch.float64, device=img.device)
+    lfrl_metric(nz, h, w, img, xs, ys, out, stream)
+    return float(out.item())

@@ -1,0 +1,1568 @@
+// lfrl.hip - light-field Richardson-Lucy deconvolution on MI355X (gfx950).
+//
+// The forward light-field projection (every depth plane and every lenslet-
+// relative phase convolved with its own PSF, summed into one image) is computed
+// on the lenslet grid.  Write a pixel index as p = N*L + c (lenslet L, phase c)
+// per axis.  Then
+//     y_c[L] = sum_{j,a} (G_{j,a->c} * x_{j,a})[L],
+//     G_{j,a->c}[D] = h[j][a][N*D + c - a + c0],
+// a sum of small 2-D convolutions on the lenslet grid with polyphase kernels
+// of R x R taps, R = 2*floor((c0 + N - 1)/N) + 1.  With overlap-save tiles of Q
+// lenslets and half-spectrum DFTs, every frequency k of a tile is a dense
+// complex contraction
+//     Y_k[c][tile] = sum_{(j,a)} G_k[(j,a)][c] X_k[(j,a)][tile]          (forward)
+//     B_k[(j,a)][tile] = sum_c conj(G_k[(j,a)][c]) R_k[c][tile]          (adjoint)
+// The spectra G_k are built once per PSF set (the PSF stays on the card and is
+// reused by every reconstruction, Fig. 1) and kept in two layouts, one per
+// direction, so each contraction streams them with unit-stride loads.
+//
+// Pipeline of one Richardson-Lucy iteration (sec. 1 / sec. 2.1, all on device):
+//   k_vol_r2c(x) -> k_contract_fwd -> k_c2r[ratio: rho = y / (A x)]
+//   k_vol_r2c(rho) -> k_contract_adj -> k_c2r[update: x *= A^T rho / A^T 1]
+//   metric (sec. 2.2): k_metric_partial -> k_metric_colsum -> k_metric_coeffs
+//                      -> k_metric_final (entropy + stop rule) -> k_cond_copy
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "lfrl.h"
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static int set_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return set_error(LFRL_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define LAUNCH_CHECK(name)                                                             \
+    do {                                                                               \
+        hipError_t e_ = hipGetLastError();                                             \
+        if (e_ != hipSuccess)                                                          \
+            return set_error(LFRL_ERR_DEVICE, "launch of %s failed: %s", name, hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// limits
+// ---------------------------------------------------------------------------
+static constexpr int kMaxQ = 64;        // DFT tile side
+static constexpr int kMaxNN = 256;      // nnum^2 (one thread per output phase)
+static constexpr int kMaxTrace = 4096;  // iterations recorded per deconvolve call
+static constexpr int kMetricChunks = 32;
+static constexpr int kMetricVBlock = 16;
+static constexpr int kMaxMetricLegs = 256;
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+struct Geo {
+    int N, Nz, K, c0, hD, R, Q, QH, T, nf, NN, KK;
+};
+
+static void geo_init(Geo &g, int N, int Nz, int K, int Q)
+{
+    g.N = N;
+    g.Nz = Nz;
+    g.K = K;
+    g.c0 = (K - 1) / 2;
+    g.hD = (g.c0 + N - 1) / N;
+    g.R = 2 * g.hD + 1;
+    g.Q = Q;
+    g.QH = Q / 2 + 1;
+    g.T = Q - g.R + 1;
+    g.nf = Q * g.QH;
+    g.NN = N * N;
+    g.KK = g.NN * Nz;
+}
+
+struct Tiles {
+    int Ly, Lx, ty, tx, nt;
+};
+
+static Tiles tiles_for(const Geo &g, int h, int w)
+{
+    Tiles t;
+    t.Ly = h / g.N;
+    t.Lx = w / g.N;
+    t.ty = (t.Ly + g.T - 1) / g.T;
+    t.tx = (t.Lx + g.T - 1) / g.T;
+    t.nt = t.ty * t.tx;
+    return t;
+}
+
+// LDS bytes of the r2c / c2r tile kernels.
+static size_t lds_r2c(const Geo &g)
+{
+    size_t in = (size_t)g.Q * g.Q * g.N;
+    in = (in + 1) & ~(size_t)1;
+    return in * 4 + (size_t)g.Q * g.QH * g.N * 8 + (size_t)g.Q * 8;
+}
+
+static size_t lds_c2r(const Geo &g)
+{
+    return (size_t)g.Q * g.QH * g.N * 8 + (size_t)g.T * g.QH * g.N * 8 + (size_t)g.Q * 8;
+}
+
+static int nt_template(int nt)
+{
+    int v = 1;
+    while (v < nt && v < 32)
+        v <<= 1;
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Row pass of a real Q x Q tile DFT for NP interleaved phases held in LDS as
+// raw pixel rows: in[i][l*NP + p].  Produces the half spectrum along the row:
+// Z[i][kv][p] = sum_l in[i][l*NP + p] * exp(-2 pi i l kv / Q), kv <= Q/2.
+__device__ __forceinline__ void dft_rows_r2c(const float *in, float2 *Z, const float2 *tw,
+                                             int Q, int QH, int NP)
+{
+    const int total = Q * QH * NP;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int p = idx % NP;
+        const int kv = (idx / NP) % QH;
+        const int i = idx / (NP * QH);
+        const float *row = in + (size_t)i * Q * NP + p;
+        float re = 0.f, im = 0.f;
+        int m = 0;
+        for (int l = 0; l < Q; ++l) {
+            const float v = row[l * NP];
+            const float2 w = tw[m];
+            re = fmaf(v, w.x, re);
+            im = fmaf(-v, w.y, im);
+            m += kv;
+            if (m >= Q)
+                m -= Q;
+        }
+        Z[idx] = make_float2(re, im);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// plan-time kernels
+// ---------------------------------------------------------------------------
+
+// Polyphase kernels of one (plane j, source phase a) for one output row phase
+// cr, all output column phases cc: the R x R taps G[D] = h[j][a][N*D + c - a + c0]
+// placed circularly (D mod Q) in a Q x Q tile, transformed, and written as
+// Gf[k][kk][c] with kk = j*N*N + a, c = cr*N + cc.
+__global__ void k_psf_r2c(const float *__restrict__ psf, int N, int K, int c0, int hD, int Q,
+                          int QH, int KK, int NN, float2 *__restrict__ Gf,
+                          const float2 *__restrict__ twg)
+{
+    extern __shared__ float smem[];
+    const int cr = blockIdx.x;
+    const int a = blockIdx.y;
+    const int j = blockIdx.z;
+    const int ar = a / N, ac = a % N;
+    const int rowlen = Q * N;
+    size_t in_n = (size_t)Q * rowlen;
+    in_n = (in_n + 1) & ~(size_t)1;
+    float *in = smem;
+    float2 *Z = reinterpret_cast<float2 *>(smem + in_n);
+    float2 *tw = Z + (size_t)Q * QH * N;
+    for (int i = threadIdx.x; i < Q; i += blockDim.x)
+        tw[i] = twg[i];
+    const float *hk = psf + (((size_t)j * N + ar) * N + ac) * (size_t)K * K;
+    for (int idx = threadIdx.x; idx < Q * rowlen; idx += blockDim.x) {
+        const int i = idx / rowlen, col = idx % rowlen;
+        const int l = col / N, cc = col % N;
+        const int Dr = (i <= hD) ? i : ((i >= Q - hD) ? i - Q : INT32_MIN);
+        const int Dc = (l <= hD) ? l : ((l >= Q - hD) ? l - Q : INT32_MIN);
+        float v = 0.f;
+        if (Dr != INT32_MIN && Dc != INT32_MIN) {
+            const int u = N * Dr + cr - ar + c0;
+            const int vv = N * Dc + cc - ac + c0;
+            if (u >= 0 && u < K && vv >= 0 && vv < K)
+                v = hk[(size_t)u * K + vv];
+        }
+        in[idx] = v;
+    }
+    __syncthreads();
+    dft_rows_r2c(in, Z, tw, Q, QH, N);
+    __syncthreads();
+    const size_t kk = (size_t)j * NN + a;
+    const int total = Q * QH * N;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int p = idx % N;
+        const int kv = (idx / N) % QH;
+        const int ku = idx / (N * QH);
+        float re = 0.f, im = 0.f;
+        int m = 0;
+        for (int i = 0; i < Q; ++i) {
+            const float2 z = Z[((size_t)i * QH + kv) * N + p];
+            const float2 w = tw[m];
+            re = fmaf(z.x, w.x, fmaf(z.y, w.y, re));
+            im = fmaf(z.y, w.x, fmaf(-z.x, w.y, im));
+            m += ku;
+            if (m >= Q)
+                m -= Q;
+        }
+        const size_t k = (size_t)ku * QH + kv;
+        Gf[(k * KK + kk) * NN + (size_t)cr * N + p] = make_float2(re, im);
+    }
+}
+
+// Gb[k][c][kk] = Gf[k][kk][c]: per-frequency transpose through LDS.
+__global__ void k_transpose_spec(const float2 *__restrict__ Gf, float2 *__restrict__ Gb,
+                                 int KK, int NN)
+{
+    __shared__ float2 tile[32][33];
+    const size_t k = blockIdx.z;
+    const int c0 = blockIdx.x * 32, kk0 = blockIdx.y * 32;
+    const float2 *src = Gf + k * (size_t)KK * NN;
+    float2 *dst = Gb + k * (size_t)KK * NN;
+    for (int r = threadIdx.y; r < 32; r += 8) {
+        const int kk = kk0 + r, c = c0 + threadIdx.x;
+        if (kk < KK && c < NN)
+            tile[r][threadIdx.x] = src[(size_t)kk * NN + c];
+    }
+    __syncthreads();
+    for (int r = threadIdx.y; r < 32; r += 8) {
+        const int c = c0 + r, kk = kk0 + threadIdx.x;
+        if (kk < KK && c < NN)
+            dst[(size_t)c * KK + kk] = tile[threadIdx.x][r];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-iteration kernels
+// ---------------------------------------------------------------------------
+
+// Gather one overlap-save tile of lenslet rows (plane j, row phase ar, all N
+// column phases) from a [planes][H][W] array and write its half spectrum:
+// out[k][tile][kk] with kk = j*N*N + ar*N + ac.  Lenslets outside the image
+// are zero (linear, not circular, convolution).
+__global__ void k_vol_r2c(const float *__restrict__ src, int H, int W, int N, int Q, int QH,
+                          int T, int hD, int tiles_x, int nt, int KKo,
+                          float2 *__restrict__ out, const float2 *__restrict__ twg)
+{
+    extern __shared__ float smem[];
+    const int tile = blockIdx.x;
+    const int j = blockIdx.y / N, ar = blockIdx.y % N;
+    const int ty = tile / tiles_x, tx = tile % tiles_x;
+    const int ly0 = ty * T - hD, lx0 = tx * T - hD;
+    const int rowlen = Q * N;
+    size_t in_n = (size_t)Q * rowlen;
+    in_n = (in_n + 1) & ~(size_t)1;
+    float *in = smem;
+    float2 *Z = reinterpret_cast<float2 *>(smem + in_n);
+    float2 *tw = Z + (size_t)Q * QH * N;
+    for (int i = threadIdx.x; i < Q; i += blockDim.x)
+        tw[i] = twg[i];
+    const float *plane = src + (size_t)j * H * W;
+    for (int idx = threadIdx.x; idx < Q * rowlen; idx += blockDim.x) {
+        const int i = idx / rowlen, col = idx % rowlen;
+        const int pr = N * (ly0 + i) + ar;
+        const int pc = N * lx0 + col;
+        float v = 0.f;
+        if (pr >= 0 && pr < H && pc >= 0 && pc < W)
+            v = plane[(size_t)pr * W + pc];
+        in[idx] = v;
+    }
+    __syncthreads();
+    dft_rows_r2c(in, Z, tw, Q, QH, N);
+    __syncthreads();
+    const size_t kkbase = (size_t)j * N * N + (size_t)ar * N;
+    const int total = Q * QH * N;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int p = idx % N;
+        const int kv = (idx / N) % QH;
+        const int ku = idx / (N * QH);
+        float re = 0.f, im = 0.f;
+        int m = 0;
+        for (int i = 0; i < Q; ++i) {
+            const float2 z = Z[((size_t)i * QH + kv) * N + p];
+            const float2 w = tw[m];
+            re = fmaf(z.x, w.x, fmaf(z.y, w.y, re));
+            im = fmaf(z.y, w.x, fmaf(-z.x, w.y, im));
+            m += ku;
+            if (m >= Q)
+                m -= Q;
+        }
+        const size_t k = (size_t)ku * QH + kv;
+        out[(k * nt + tile) * KKo + kkbase + p] = make_float2(re, im);
+    }
+}
+
+enum { EPI_STORE = 0, EPI_RATIO = 1, EPI_UPDATE = 2 };
+
+// Inverse tile DFT and scatter of the valid T x T lenslets of one tile for
+// plane j and row phase ar (all N column phases).  The spectrum is
+// sum_s spec[s*split_stride + (k*nt + tile)*KKo + kkbase + p] (split-K partials).
+// Epilogues:  STORE  dst[j][pr][pc] = v
+//             RATIO  dst[pr][pc] = v > 0 ? aux0[pr][pc] / v : 0   (rho = y / A x)
+//             UPDATE dst[j][pr][pc] = aux1 > 0 ? aux0 * v / aux1 : 0
+//                    (x_new = x_old * A^T rho / A^T 1)
+__global__ void k_c2r(const float2 *__restrict__ spec, size_t split_stride, int nsplit, int KKo,
+                      int N, int Q, int QH, int T, int hD, int tiles_x, int nt, int H, int W,
+                      int mode, float *__restrict__ dst, const float *__restrict__ aux0,
+                      const float *__restrict__ aux1, const float2 *__restrict__ twg)
+{
+    extern __shared__ float smem[];
+    const int tile = blockIdx.x;
+    const int j = blockIdx.y / N, ar = blockIdx.y % N;
+    const int ty = tile / tiles_x, tx = tile % tiles_x;
+    float2 *X = reinterpret_cast<float2 *>(smem);
+    float2 *Z = X + (size_t)Q * QH * N;
+    float2 *tw = Z + (size_t)T * QH * N;
+    for (int i = threadIdx.x; i < Q; i += blockDim.x)
+        tw[i] = twg[i];
+    const size_t kkbase = (size_t)j * N * N + (size_t)ar * N;
+    const int total = Q * QH * N;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int p = idx % N;
+        const size_t k = idx / N;
+        const size_t off = (k * nt + tile) * KKo + kkbase + p;
+        float2 acc = spec[off];
+        for (int s = 1; s < nsplit; ++s) {
+            const float2 v = spec[off + s * split_stride];
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+        X[idx] = acc;
+    }
+    __syncthreads();
+    // inverse DFT along the tile rows (ku -> i), only for the T valid rows
+    const int ztotal = T * QH * N;
+    for (int idx = threadIdx.x; idx < ztotal; idx += blockDim.x) {
+        const int p = idx % N;
+        const int kv = (idx / N) % QH;
+        const int ti = idx / (N * QH);
+        const int i = hD + ti;
+        float re = 0.f, im = 0.f;
+        int m = 0;
+        for (int ku = 0; ku < Q; ++ku) {
+            const float2 x = X[((size_t)ku * QH + kv) * N + p];
+            const float2 w = tw[m];
+            re = fmaf(x.x, w.x, fmaf(-x.y, w.y, re));
+            im = fmaf(x.x, w.y, fmaf(x.y, w.x, im));
+            m += i;
+            if (m >= Q)
+                m -= Q;
+        }
+        Z[idx] = make_float2(re, im);
+    }
+    __syncthreads();
+    // inverse real DFT along the tile columns (Hermitian half spectrum)
+    const float scale = 1.0f / (float)(Q * Q);
+    const int Ly = H / N, Lx = W / N;
+    const int otot = T * T * N;
+    for (int idx = threadIdx.x; idx < otot; idx += blockDim.x) {
+        const int p = idx % N;
+        const int tl = (idx / N) % T;
+        const int ti = idx / (N * T);
+        const int l = hD + tl;
+        const int Lr = ty * T + ti, Lc = tx * T + tl;
+        if (Lr >= Ly || Lc >= Lx)
+            continue;
+        float v = 0.f;
+        int m = 0;
+        for (int kv = 0; kv < QH; ++kv) {
+            const float2 z = Z[((size_t)ti * QH + kv) * N + p];
+            const float2 w = tw[m];
+            const float wt = (kv == 0 || 2 * kv == Q) ? 1.f : 2.f;
+            v = fmaf(wt, fmaf(z.x, w.x, -z.y * w.y), v);
+            m += l;
+            if (m >= Q)
+                m -= Q;
+        }
+        v *= scale;
+        const int pr = N * Lr + ar, pc = N * Lc + p;
+        const size_t pix = (size_t)pr * W + pc;
+        if (mode == EPI_STORE) {
+            dst[(size_t)j * H * W + pix] = v;
+        } else if (mode == EPI_RATIO) {
+            dst[pix] = v > 0.f ? aux0[pix] / v : 0.f;
+        } else {
+            const size_t o = (size_t)j * H * W + pix;
+            const float c = aux1[o];
+            dst[o] = c > 0.f ? aux0[o] * v / c : 0.f;
+        }
+    }
+}
+
+// Forward spectral contraction, one frequency k per block row:
+//   Yp[s][k][t][c] = sum_{kk in chunk s} Gf[k][kk][c] * X[k][t][kk]
+// One thread per output phase c keeps NT tile accumulators; the X chunk is
+// staged in LDS and read as a broadcast; Gf is streamed once, unit stride in c.
+template <int NT>
+__global__ __launch_bounds__(256) void k_contract_fwd(const float2 *__restrict__ Gf,
+                                                      const float2 *__restrict__ X,
+                                                      float2 *__restrict__ Yp, int NN, int KK,
+                                                      int nt, int nf, int kchunk)
+{
+    constexpr int KB = 64;
+    __shared__ float2 xs[KB][NT];
+    const int k = blockIdx.x, s = blockIdx.y, t0 = blockIdx.z * NT;
+    const int c = threadIdx.x;
+    const int kb0 = s * kchunk;
+    const int kb1 = min(KK, kb0 + kchunk);
+    float2 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+        acc[t] = make_float2(0.f, 0.f);
+    const float2 *g = Gf + (size_t)k * KK * NN + c;
+    const float2 *xk = X + (size_t)k * nt * KK;
+    for (int kb = kb0; kb < kb1; kb += KB) {
+        const int cnt = min(KB, kb1 - kb);
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < KB * NT; idx += blockDim.x) {
+            const int t = idx / KB, q = idx % KB;
+            float2 v = make_float2(0.f, 0.f);
+            if (q < cnt && t0 + t < nt)
+                v = xk[(size_t)(t0 + t) * KK + kb + q];
+            xs[q][t] = v;
+        }
+        __syncthreads();
+        if (c < NN) {
+            if (cnt == KB) {
+#pragma unroll 16
+                for (int q = 0; q < KB; ++q) {
+                    const float2 gv = g[(size_t)(kb + q) * NN];
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        const float2 xv = xs[q][t];
+                        acc[t].x = fmaf(gv.x, xv.x, fmaf(-gv.y, xv.y, acc[t].x));
+                        acc[t].y = fmaf(gv.x, xv.y, fmaf(gv.y, xv.x, acc[t].y));
+                    }
+                }
+            } else {
+                for (int q = 0; q < cnt; ++q) {
+                    const float2 gv = g[(size_t)(kb + q) * NN];
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        const float2 xv = xs[q][t];
+                        acc[t].x = fmaf(gv.x, xv.x, fmaf(-gv.y, xv.y, acc[t].x));
+                        acc[t].y = fmaf(gv.x, xv.y, fmaf(gv.y, xv.x, acc[t].y));
+                    }
+                }
+            }
+        }
+    }
+    if (c < NN) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            if (t0 + t < nt)
+                Yp[(((size_t)s * nf + k) * nt + t0 + t) * NN + c] = acc[t];
+    }
+}
+
+// Adjoint spectral contraction, one frequency k per block row:
+//   B[k][t][kk] = sum_c conj(Gb[k][c][kk]) * R[k][t][c]
+// One thread per (j, a) column kk; R for the frequency sits in LDS.
+template <int NT>
+__global__ __launch_bounds__(256) void k_contract_adj(const float2 *__restrict__ Gb,
+                                                      const float2 *__restrict__ Rs,
+                                                      float2 *__restrict__ B, int NN, int KK,
+                                                      int nt)
+{
+    extern __shared__ float2 rs[];  // [NN][NT]
+    const int k = blockIdx.x;
+    const int kk = blockIdx.y * blockDim.x + threadIdx.x;
+    const int t0 = blockIdx.z * NT;
+    for (int idx = threadIdx.x; idx < NN * NT; idx += blockDim.x) {
+        const int c = idx / NT, t = idx % NT;
+        float2 v = make_float2(0.f, 0.f);
+        if (t0 + t < nt)
+            v = Rs[((size_t)k * nt + t0 + t) * NN + c];
+        rs[idx] = v;
+    }
+    __syncthreads();
+    if (kk >= KK)
+        return;
+    float2 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+        acc[t] = make_float2(0.f, 0.f);
+    const float2 *g = Gb + (size_t)k * NN * KK + kk;
+#pragma unroll 8
+    for (int c = 0; c < NN; ++c) {
+        const float2 gv = g[(size_t)c * KK];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const float2 rv = rs[c * NT + t];
+            acc[t].x = fmaf(gv.x, rv.x, fmaf(gv.y, rv.y, acc[t].x));
+            acc[t].y = fmaf(gv.x, rv.y, fmaf(-gv.y, rv.x, acc[t].y));
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+        if (t0 + t < nt)
+            B[((size_t)k * nt + t0 + t) * KK + kk] = acc[t];
+}
+
+// ---------------------------------------------------------------------------
+// metric kernels (sec. 2.2)
+// ---------------------------------------------------------------------------
+
+// Orthonormal DCT-II basis value c(f, n) cos((2x + 1) pi f / (2n)) (Eqs. 2-4),
+// with the angle reduced exactly in integers before the cosine.
+__device__ __forceinline__ double dct_basis(int f, int x, int n)
+{
+    const long long num = ((long long)(2 * x + 1) * f) % (4LL * n);
+    const double c = (f == 0) ? sqrt(1.0 / n) : sqrt(2.0 / n);
+    return c * cospi((double)num / (2.0 * n));
+}
+
+// Row transform of the z maximum projection over a chunk of image rows:
+// T1[chunk][v][s] = sum_{r in chunk} C_H[v][r] * m[r][s],  m = max_j vol[j][r][s],
+// for row frequencies v in [v0, v0 + kMetricVBlock), and n2p[chunk][s] = sum m^2.
+__global__ void k_metric_partial(const float *__restrict__ vol, int nz, int H, int W, int nv,
+                                 int rows_per_chunk, double *__restrict__ T1,
+                                 double *__restrict__ n2p)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int chunk = blockIdx.y;
+    const int v0 = blockIdx.z * kMetricVBlock;
+    if (s >= W)
+        return;
+    const int r0 = chunk * rows_per_chunk;
+    const int r1 = min(H, r0 + rows_per_chunk);
+    double acc[kMetricVBlock];
+#pragma unroll
+    for (int q = 0; q < kMetricVBlock; ++q)
+        acc[q] = 0.0;
+    double n2 = 0.0;
+    for (int r = r0; r < r1; ++r) {
+        float m = vol[(size_t)r * W + s];
+        for (int j = 1; j < nz; ++j)
+            m = fmaxf(m, vol[((size_t)j * H + r) * W + s]);
+        const double md = (double)m;
+        n2 = fma(md, md, n2);
+#pragma unroll
+        for (int q = 0; q < kMetricVBlock; ++q)
+            if (v0 + q < nv)
+                acc[q] = fma(dct_basis(v0 + q, r, H), md, acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < kMetricVBlock; ++q)
+        if (v0 + q < nv)
+            T1[((size_t)chunk * nv + v0 + q) * W + s] = acc[q];
+    if (blockIdx.z == 0)
+        n2p[(size_t)chunk * W + s] = n2;
+}
+
+// Sum the row-chunk partials in a fixed order: T1[0][v][s] = sum_chunk T1[chunk][v][s].
+__global__ void k_metric_colsum(double *__restrict__ T1, int nchunks, int nv, int W)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nv * W)
+        return;
+    double acc = T1[idx];
+    for (int c = 1; c < nchunks; ++c)
+        acc += T1[(size_t)c * nv * W + idx];
+    T1[idx] = acc;
+}
+
+// One wave per candidate coefficient (v, u): F[v][u] = sum_s T1[v][s] C_W[u][s]
+// for (v, u) inside the triangle u / xs + v / ys < 1; |F| is written, -1 marks
+// coefficients outside the region.
+__global__ void k_metric_coeffs(const double *__restrict__ T1, int nv, int nu, int W, double xs,
+                                double ys, double *__restrict__ Fabs)
+{
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (wave >= nv * nu)
+        return;
+    const int v = wave / nu, u = wave % nu;
+    const bool inside = ((double)u / xs + (double)v / ys) < 1.0;
+    if (!inside) {
+        if (lane == 0)
+            Fabs[wave] = -1.0;
+        return;
+    }
+    double acc = 0.0;
+    for (int s = lane; s < W; s += 64)
+        acc = fma(T1[(size_t)v * W + s], dct_basis(u, s, W), acc);
+    for (int off = 32; off > 0; off >>= 1)
+        acc += __shfl_down(acc, off, 64);
+    if (lane == 0)
+        Fabs[wave] = fabs(acc);
+}
+
+// Device-side Richardson-Lucy stop state.
+struct StopState {
+    double best_e;
+    double prev_e;
+    double sum_img;
+    int best_k;
+    int run;
+    int stopped;
+    int stop_k;
+    int copy_flag;
+    int iter;
+};
+
+// Final entropy (Eq. 12 with the Frobenius norm from Parseval) and stop rule.
+// Single block.  out[0] = e.  When st != nullptr, iteration `k` is recorded:
+// trace[k-1] = e, the best iterate is tracked (ties: later) and the stop flag
+// raised after `patience` consecutive strict decreases.
+__global__ void k_metric_final(const double *__restrict__ n2p, int n2count,
+                               const double *__restrict__ Fabs, int ncoef, double xs, double ys,
+                               double *__restrict__ out, StopState *st, double *trace, int k,
+                               int patience)
+{
+    __shared__ double red[256];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n2count; i += blockDim.x)
+        a += n2p[i];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    const double n = sqrt(red[0]);
+    __syncthreads();
+    double e_part = 0.0;
+    if (n > 0.0) {
+        for (int i = threadIdx.x; i < ncoef; i += blockDim.x) {
+            const double f = Fabs[i];
+            if (f > 0.0) {
+                const double p = f / n;
+                e_part += p * log2(p);
+            }
+        }
+    }
+    red[threadIdx.x] = e_part;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double e = (n > 0.0) ? -(2.0 / (xs * ys)) * red[0] : 0.0;
+        out[0] = e;
+        if (st) {
+            if (trace)
+                trace[k - 1] = e;
+            st->iter = k;
+            if (k > 1)
+                st->run = (e < st->prev_e) ? st->run + 1 : 0;
+            st->copy_flag = (k == 1 || e >= st->best_e) ? 1 : 0;
+            if (st->copy_flag) {
+                st->best_e = e;
+                st->best_k = k;
+            }
+            st->prev_e = e;
+            if (!st->stopped && st->run >= patience) {
+                st->stopped = 1;
+                st->stop_k = k;
+            }
+        }
+    }
+}
+
+__global__ void k_state_reset(StopState *st)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->best_e = -1.0e300;
+        st->prev_e = 0.0;
+        st->sum_img = 0.0;
+        st->best_k = 0;
+        st->run = 0;
+        st->stopped = 0;
+        st->stop_k = 0;
+        st->copy_flag = 0;
+        st->iter = 0;
+    }
+}
+
+// dst = src when the stop state says the current iterate is the best so far.
+__global__ void k_cond_copy(const StopState *__restrict__ st, const float *__restrict__ src,
+                            float *__restrict__ dst, size_t n)
+{
+    if (!st->copy_flag)
+        return;
+    const size_t n4 = n / 4;
+    const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const float4 *s4 = reinterpret_cast<const float4 *>(src);
+    float4 *d4 = reinterpret_cast<float4 *>(dst);
+    for (size_t i = tid; i < n4; i += stride)
+        d4[i] = s4[i];
+    for (size_t i = n4 * 4 + tid; i < n; i += stride)
+        dst[i] = src[i];
+}
+
+__global__ void k_fill(float *__restrict__ p, size_t n, float v)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Per-block float64 partials of sum(a * b) (b == nullptr: sum(a)).
+__global__ void k_dot_partial(const float *__restrict__ a, const float *__restrict__ b, size_t n,
+                              double *__restrict__ part)
+{
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        acc += b ? (double)a[i] * (double)b[i] : (double)a[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = red[0];
+}
+
+// Fixed-order sum of the dot partials.  which = 0: store the image sum in the
+// stop state; which = 1: record the flux deviation <c, x^k> / sum(img) - 1.
+__global__ void k_dot_final(const double *__restrict__ part, int nparts, StopState *st,
+                            double *flux_trace, int k, int which)
+{
+    __shared__ double red[256];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x)
+        a += part[i];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (which == 0)
+            st->sum_img = red[0];
+        else
+            flux_trace[k - 1] = (st->sum_img != 0.0) ? red[0] / st->sum_img - 1.0 : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+static constexpr int kDotBlocks = 512;
+
+struct lfrl_plan_s {
+    int device = 0;
+    Geo g{};
+    int max_h = 0, max_w = 0, max_tiles = 0, split_k = 1;
+    size_t resident = 0, workspace = 0;
+    float2 *Gf = nullptr, *Gb = nullptr, *tw = nullptr;
+    float2 *X = nullptr, *Yp = nullptr, *Rs = nullptr;
+    float *img = nullptr, *sens = nullptr, *vol[3] = {nullptr, nullptr, nullptr};
+    double *T1 = nullptr, *n2p = nullptr, *Fabs = nullptr, *metric_out = nullptr;
+    double *trace = nullptr, *flux = nullptr, *dotp = nullptr;
+    StopState *state = nullptr;
+    StopState *state_host = nullptr;  // pinned
+    int sens_h = -1, sens_w = -1;
+    size_t lds_r2c_bytes = 0, lds_c2r_bytes = 0;
+    // profiling
+    bool prof = false;
+    std::vector<hipEvent_t> ev[2];
+    size_t ev_used[2] = {0, 0};
+};
+
+static int validate_desc(const lfrl_plan_desc *d)
+{
+    if (!d)
+        return set_error(LFRL_ERR_ARG, "desc is NULL");
+    if (d->nnum < 1 || d->nz < 1 || d->ksize < 1)
+        return set_error(LFRL_ERR_ARG, "nnum, nz and ksize must be >= 1");
+    if ((d->ksize & 1) == 0)
+        return set_error(LFRL_ERR_ARG, "ksize must be odd (got %d)", d->ksize);
+    if ((long long)d->nnum * d->nnum > kMaxNN)
+        return set_error(LFRL_ERR_UNSUPPORTED, "nnum^2 must be <= %d", kMaxNN);
+    if (d->max_h < d->nnum || d->max_w < d->nnum || d->max_h % d->nnum || d->max_w % d->nnum)
+        return set_error(LFRL_ERR_ARG, "max_h/max_w must be positive multiples of nnum");
+    if (d->precision != LFRL_FP32)
+        return set_error(LFRL_ERR_UNSUPPORTED, "precision %d not supported", d->precision);
+    if (d->flags != 0)
+        return set_error(LFRL_ERR_ARG, "flags must be 0");
+    if (d->tile_q < 0 || d->tile_q > kMaxQ)
+        return set_error(LFRL_ERR_ARG, "tile_q must be in [0, %d]", kMaxQ);
+    return LFRL_OK;
+}
+
+// Model of one iteration's time for tile side Q (bytes at a sustained HBM rate,
+// flops at a sustained FP32 rate, the contraction overlapping its two bounds).
+static double model_time(const Geo &g, const Tiles &t)
+{
+    const double spec = (double)g.nf * g.NN * g.KK * 8.0;
+    const double inter = (double)g.nf * t.nt * (g.KK + g.NN) * 8.0;
+    const double cflops = 8.0 * g.nf * (double)g.NN * g.KK * t.nt;
+    const double contract = 2.0 * std::max((spec + 2.0 * inter) / 5.0e12, cflops / 90.0e12);
+    const double dft = (double)(g.KK + g.NN) * t.nt * 6.0 * g.Q * g.Q * g.QH * 2.0 * 2.0 / 60.0e12;
+    return contract + dft;
+}
+
+static size_t lds_limit()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        v > 0)
+        return (size_t)v;
+    return 160 * 1024;
+}
+
+static int pick_q(const lfrl_plan_desc *d, size_t lds_max, int *q_out)
+{
+    Geo g;
+    geo_init(g, d->nnum, d->nz, d->ksize, 1);
+    const int R = g.R;
+    if (d->tile_q > 0) {
+        if (d->tile_q < R)
+            return set_error(LFRL_ERR_ARG, "tile_q %d smaller than the polyphase taps %d",
+                             d->tile_q, R);
+        Geo gq;
+        geo_init(gq, d->nnum, d->nz, d->ksize, d->tile_q);
+        if (lds_r2c(gq) > lds_max || lds_c2r(gq) > lds_max)
+            return set_error(LFRL_ERR_UNSUPPORTED, "tile_q %d needs more LDS than available",
+                             d->tile_q);
+        *q_out = d->tile_q;
+        return LFRL_OK;
+    }
+    double best = 1e300;
+    int bq = -1;
+    for (int q = std::max(R, 2); q <= kMaxQ; ++q) {
+        Geo gq;
+        geo_init(gq, d->nnum, d->nz, d->ksize, q);
+        if (lds_r2c(gq) > lds_max || lds_c2r(gq) > lds_max)
+            continue;
+        const Tiles t = tiles_for(gq, d->max_h, d->max_w);
+        const double tm = model_time(gq, t);
+        if (tm < best * 0.999) {
+            best = tm;
+            bq = q;
+        }
+    }
+    if (bq < 0)
+        return set_error(LFRL_ERR_UNSUPPORTED, "no DFT tile fits in %zu bytes of LDS", lds_max);
+    *q_out = bq;
+    return LFRL_OK;
+}
+
+static int pick_split(const Geo &g)
+{
+    int s = (2048 + g.nf - 1) / g.nf;
+    s = std::max(1, std::min(s, (g.KK + 255) / 256));
+    return s;
+}
+
+struct Sizes {
+    size_t Gf, tw, X, Yp, Rs, img, vol, T1, n2p, Fabs, trace, dotp;
+    size_t resident() const { return 2 * Gf + tw; }
+    size_t workspace() const
+    {
+        return X + Yp + Rs + img + 4 * vol + T1 + n2p + Fabs + 2 * trace + dotp + 256;
+    }
+};
+
+static Sizes sizes_for(const Geo &g, int max_h, int max_w, int split)
+{
+    const Tiles t = tiles_for(g, max_h, max_w);
+    Sizes s;
+    s.Gf = (size_t)g.nf * g.NN * g.KK * sizeof(float2);
+    s.tw = (size_t)g.Q * sizeof(float2);
+    s.X = (size_t)g.nf * t.nt * g.KK * sizeof(float2);
+    s.Yp = (size_t)split * g.nf * t.nt * g.NN * sizeof(float2);
+    s.Rs = (size_t)g.nf * t.nt * g.NN * sizeof(float2);
+    s.img = (size_t)max_h * max_w * sizeof(float);
+    s.vol = (size_t)g.Nz * max_h * max_w * sizeof(float);
+    s.T1 = (size_t)kMetricChunks * kMaxMetricLegs * max_w * sizeof(double);
+    s.n2p = (size_t)kMetricChunks * max_w * sizeof(double);
+    s.Fabs = (size_t)kMaxMetricLegs * kMaxMetricLegs * sizeof(double);
+    s.trace = (size_t)kMaxTrace * sizeof(double);
+    s.dotp = (size_t)kDotBlocks * sizeof(double);
+    return s;
+}
+
+// Check that [ptr, ptr + bytes) lies inside one device allocation, so a host
+// pointer or a short buffer is reported as an argument error instead of
+// faulting the GPU.
+static int check_buf(const void *ptr, size_t bytes, const char *name)
+{
+    if (!ptr)
+        return set_error(LFRL_ERR_ARG, "%s is NULL", name);
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    hipError_t e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)ptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(LFRL_ERR_ARG, "%s is not a device allocation", name);
+    }
+    const char *b = (const char *)base, *q = (const char *)ptr;
+    if (q < b || (size_t)(q - b) + bytes > size)
+        return set_error(LFRL_ERR_ARG, "%s: %zu bytes do not fit in its allocation", name, bytes);
+    return LFRL_OK;
+}
+
+extern "C" int lfrl_plan_footprint(const lfrl_plan_desc *desc, size_t *resident_bytes,
+                                   size_t *workspace_bytes)
+{
+    int rc = validate_desc(desc);
+    if (rc)
+        return rc;
+    int q = 0;
+    rc = pick_q(desc, 160 * 1024, &q);
+    if (rc)
+        return rc;
+    Geo g;
+    geo_init(g, desc->nnum, desc->nz, desc->ksize, q);
+    const Sizes s = sizes_for(g, desc->max_h, desc->max_w, pick_split(g));
+    if (resident_bytes)
+        *resident_bytes = s.resident();
+    if (workspace_bytes)
+        *workspace_bytes = s.workspace();
+    return LFRL_OK;
+}
+
+static void free_plan(lfrl_plan_s *p)
+{
+    if (!p)
+        return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    void *bufs[] = {p->Gf, p->Gb, p->tw, p->X, p->Yp, p->Rs, p->img, p->sens,
+                    p->vol[0], p->vol[1], p->vol[2], p->T1, p->n2p, p->Fabs,
+                    p->metric_out, p->trace, p->flux, p->dotp, p->state};
+    for (void *b : bufs)
+        if (b)
+            (void)hipFree(b);
+    if (p->state_host)
+        (void)hipHostFree(p->state_host);
+    for (auto &v : p->ev)
+        for (hipEvent_t e : v)
+            (void)hipEventDestroy(e);
+    (void)hipSetDevice(cur);
+    delete p;
+}
+
+template <typename T>
+static int dalloc(T **ptr, size_t bytes)
+{
+    hipError_t e = hipMalloc((void **)ptr, bytes ? bytes : 16);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        (void)hipGetLastError();
+        return set_error(LFRL_ERR_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    return LFRL_OK;
+}
+
+#define TRY(expr)              \
+    do {                       \
+        int rc_ = (expr);      \
+        if (rc_ != LFRL_OK) {  \
+            free_plan(p);      \
+            return rc_;        \
+        }                      \
+    } while (0)
+
+static void set_lds_attrs(size_t lds)
+{
+    (void)hipFuncSetAttribute((const void *)k_psf_r2c, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void *)k_vol_r2c, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void *)k_c2r, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+extern "C" int lfrl_plan(lfrl_plan_t *out, const lfrl_plan_desc *desc, const float *psf,
+                         void *stream)
+{
+    if (!out)
+        return set_error(LFRL_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = validate_desc(desc);
+    if (rc)
+        return rc;
+    if (!psf)
+        return set_error(LFRL_ERR_ARG, "psf is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t lmax = lds_limit();
+    int q = 0;
+    rc = pick_q(desc, lmax, &q);
+    if (rc)
+        return rc;
+    rc = check_buf(psf, (size_t)desc->nz * desc->nnum * desc->nnum * desc->ksize * desc->ksize *
+                            sizeof(float), "psf");
+    if (rc)
+        return rc;
+    lfrl_plan_s *p = new lfrl_plan_s();
+    {
+        hipError_t e0 = hipGetDevice(&p->device);
+        if (e0 != hipSuccess) {
+            delete p;
+            return set_error(LFRL_ERR_DEVICE, "hipGetDevice failed: %s", hipGetErrorString(e0));
+        }
+    }
+    geo_init(p->g, desc->nnum, desc->nz, desc->ksize, q);
+    const Geo &g = p->g;
+    p->max_h = desc->max_h;
+    p->max_w = desc->max_w;
+    p->max_tiles = tiles_for(g, desc->max_h, desc->max_w).nt;
+    p->split_k = pick_split(g);
+    const Sizes s = sizes_for(g, p->max_h, p->max_w, p->split_k);
+    p->resident = s.resident();
+    p->workspace = s.workspace();
+    p->lds_r2c_bytes = lds_r2c(g);
+    p->lds_c2r_bytes = lds_c2r(g);
+    TRY(dalloc(&p->Gf, s.Gf));
+    TRY(dalloc(&p->Gb, s.Gf));
+    TRY(dalloc(&p->tw, s.tw));
+    TRY(dalloc(&p->X, s.X));
+    TRY(dalloc(&p->Yp, s.Yp));
+    TRY(dalloc(&p->Rs, s.Rs));
+    TRY(dalloc(&p->img, s.img));
+    TRY(dalloc(&p->sens, s.vol));
+    for (int i = 0; i < 3; ++i)
+        TRY(dalloc(&p->vol[i], s.vol));
+    TRY(dalloc(&p->T1, s.T1));
+    TRY(dalloc(&p->n2p, s.n2p));
+    TRY(dalloc(&p->Fabs, s.Fabs));
+    TRY(dalloc(&p->metric_out, 64));
+    TRY(dalloc(&p->trace, s.trace));
+    TRY(dalloc(&p->flux, s.trace));
+    TRY(dalloc(&p->dotp, s.dotp));
+    TRY(dalloc(&p->state, sizeof(StopState)));
+    {
+        hipError_t e = hipHostMalloc((void **)&p->state_host, sizeof(StopState), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            p->state_host = nullptr;
+            free_plan(p);
+            return set_error(LFRL_ERR_NOMEM, "hipHostMalloc failed: %s", hipGetErrorString(e));
+        }
+    }
+    // twiddles exp(2 pi i m / Q), computed in double, rounded once
+    std::vector<float2> tw(g.Q);
+    for (int m = 0; m < g.Q; ++m) {
+        const double th = 2.0 * M_PI * (double)m / (double)g.Q;
+        tw[m] = make_float2((float)std::cos(th), (float)std::sin(th));
+    }
+    set_lds_attrs(std::max(p->lds_r2c_bytes, p->lds_c2r_bytes));
+    hipError_t e = hipMemcpyAsync(p->tw, tw.data(), g.Q * sizeof(float2), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        dim3 grid(g.N, g.NN, g.Nz);
+        hipLaunchKernelGGL(k_psf_r2c, grid, dim3(256), p->lds_r2c_bytes, st, psf, g.N, g.K, g.c0,
+                           g.hD, g.Q, g.QH, g.KK, g.NN, p->Gf, p->tw);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        dim3 grid((g.NN + 31) / 32, (g.KK + 31) / 32, g.nf);
+        hipLaunchKernelGGL(k_transpose_spec, grid, dim3(32, 8), 0, st, p->Gf, p->Gb, g.KK, g.NN);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);  // the tw staging vector goes out of scope
+    if (e != hipSuccess) {
+        free_plan(p);
+        return set_error(LFRL_ERR_DEVICE, "plan build failed: %s", hipGetErrorString(e));
+    }
+    *out = p;
+    return LFRL_OK;
+}
+
+#undef TRY
+
+extern "C" int lfrl_plan_destroy(lfrl_plan_t plan)
+{
+    free_plan(plan);
+    return LFRL_OK;
+}
+
+extern "C" int lfrl_plan_get_info(lfrl_plan_t p, lfrl_plan_info_t *info)
+{
+    if (!p || !info)
+        return set_error(LFRL_ERR_ARG, "NULL argument");
+    info->tile_q = p->g.Q;
+    info->tile_out = p->g.T;
+    info->taps = p->g.R;
+    info->nfreq = p->g.nf;
+    info->max_tiles = p->max_tiles;
+    info->split_k = p->split_k;
+    info->resident_bytes = p->resident;
+    info->workspace_bytes = p->workspace;
+    return LFRL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// internal launches
+// ---------------------------------------------------------------------------
+struct DevGuard {
+    int prev = -1;
+    explicit DevGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess)
+            prev = -1;
+        if (prev != dev)
+            (void)hipSetDevice(dev);
+    }
+    ~DevGuard()
+    {
+        if (prev >= 0)
+            (void)hipSetDevice(prev);
+    }
+};
+
+static int check_hw(lfrl_plan_s *p, int h, int w)
+{
+    if (h < p->g.N || w < p->g.N || h % p->g.N || w % p->g.N)
+        return set_error(LFRL_ERR_ARG, "h=%d, w=%d must be positive multiples of nnum=%d", h, w, p->g.N);
+    if (h > p->max_h || w > p->max_w)
+        return set_error(LFRL_ERR_ARG, "image %dx%d exceeds the plan maximum %dx%d", h, w,
+                         p->max_h, p->max_w);
+    return LFRL_OK;
+}
+
+static int prof_event(lfrl_plan_s *p, int which, hipStream_t st)
+{
+    auto &v = p->ev[which];
+    size_t &used = p->ev_used[which];
+    if (used == v.size()) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        v.push_back(e);
+    }
+    HIP_TRY(hipEventRecord(v[used++], st));
+    return LFRL_OK;
+}
+
+#define DISPATCH_NT(NTV, ...)                                  \
+    switch (NTV) {                                             \
+    case 1: { constexpr int NT_ = 1; __VA_ARGS__; } break;     \
+    case 2: { constexpr int NT_ = 2; __VA_ARGS__; } break;     \
+    case 4: { constexpr int NT_ = 4; __VA_ARGS__; } break;     \
+    case 8: { constexpr int NT_ = 8; __VA_ARGS__; } break;     \
+    case 16: { constexpr int NT_ = 16; __VA_ARGS__; } break;   \
+    default: { constexpr int NT_ = 32; __VA_ARGS__; } break;   \
+    }
+
+// vol [Nz][h][w] -> img [h][w]: plain projection (mode STORE) or the RL ratio
+// y / (A x) written into `dst` (mode RATIO, y = aux).
+static int run_forward(lfrl_plan_s *p, int h, int w, const float *vol, float *dst, int mode,
+                       const float *aux, hipStream_t st)
+{
+    const Geo &g = p->g;
+    const Tiles t = tiles_for(g, h, w);
+    hipLaunchKernelGGL(k_vol_r2c, dim3(t.nt, g.Nz * g.N), dim3(256), p->lds_r2c_bytes, st, vol, h,
+                       w, g.N, g.Q, g.QH, g.T, g.hD, t.tx, t.nt, g.KK, p->X, p->tw);
+    LAUNCH_CHECK("k_vol_r2c");
+    const int NTV = nt_template(t.nt);
+    const int ntg = (t.nt + NTV - 1) / NTV;
+    int kchunk = (g.KK + p->split_k - 1) / p->split_k;
+    kchunk = (kchunk + 63) / 64 * 64;
+    const int split = (g.KK + kchunk - 1) / kchunk;
+    const int block = std::min(256, (g.NN + 63) / 64 * 64);
+    if (p->prof) {
+        int rc = prof_event(p, 0, st);
+        if (rc)
+            return rc;
+    }
+    DISPATCH_NT(NTV, hipLaunchKernelGGL(k_contract_fwd<NT_>, dim3(g.nf, split, ntg), dim3(block),
+                                        0, st, p->Gf, p->X, p->Yp, g.NN, g.KK, t.nt, g.nf, kchunk));
+    LAUNCH_CHECK("k_contract_fwd");
+    if (p->prof) {
+        int rc = prof_event(p, 0, st);
+        if (rc)
+            return rc;
+    }
+    const size_t split_stride = (size_t)g.nf * t.nt * g.NN;
+    hipLaunchKernelGGL(k_c2r, dim3(t.nt, g.N), dim3(256), p->lds_c2r_bytes, st, p->Yp,
+                       split_stride, split, g.NN, g.N, g.Q, g.QH, g.T, g.hD, t.tx, t.nt, h, w,
+                       mode, dst, aux, (const float *)nullptr, p->tw);
+    LAUNCH_CHECK("k_c2r(forward)");
+    return LFRL_OK;
+}
+
+// img [h][w] -> vol [Nz][h][w]: plain back projection (STORE) or the RL update
+// dst = x_old * A^T img / sens (UPDATE, x_old = aux0, sens = aux1).
+static int run_backward(lfrl_plan_s *p, int h, int w, const float *img, float *dst, int mode,
+                        const float *aux0, const float *aux1, hipStream_t st)
+{
+    const Geo &g = p->g;
+    const Tiles t = tiles_for(g, h, w);
+    hipLaunchKernelGGL(k_vol_r2c, dim3(t.nt, g.N), dim3(256), p->lds_r2c_bytes, st, img, h, w,
+                       g.N, g.Q, g.QH, g.T, g.hD, t.tx, t.nt, g.NN, p->Rs, p->tw);
+    LAUNCH_CHECK("k_vol_r2c(image)");
+    const int NTV = nt_template(t.nt);
+    const int ntg = (t.nt + NTV - 1) / NTV;
+    if (p->prof) {
+        int rc = prof_event(p, 1, st);
+        if (rc)
+            return rc;
+    }
+    DISPATCH_NT(NTV, hipLaunchKernelGGL(k_contract_adj<NT_>, dim3(g.nf, (g.KK + 255) / 256, ntg),
+                                        dim3(256), (size_t)g.NN * NT_ * sizeof(float2), st, p->Gb,
+                                        p->Rs, p->X, g.NN, g.KK, t.nt));
+    LAUNCH_CHECK("k_contract_adj");
+    if (p->prof) {
+        int rc = prof_event(p, 1, st);
+        if (rc)
+            return rc;
+    }
+    hipLaunchKernelGGL(k_c2r, dim3(t.nt, g.Nz * g.N), dim3(256), p->lds_c2r_bytes, st, p->X,
+                       (size_t)0, 1, g.KK, g.N, g.Q, g.QH, g.T, g.hD, t.tx, t.nt, h, w, mode, dst,
+                       aux0, aux1, p->tw);
+    LAUNCH_CHECK("k_c2r(backward)");
+    return LFRL_OK;
+}
+
+static int launch_fill(float *ptr, size_t n, float v, hipStream_t st)
+{
+    const int blocks = (int)std::min<size_t>(4096, (n + 255) / 256 + 1);
+    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, st, ptr, n, v);
+    LAUNCH_CHECK("k_fill");
+    return LFRL_OK;
+}
+
+static int legs_count(double legs, int n)
+{
+    const double c = std::ceil(legs);
+    return (int)std::min<double>((double)n, c);
+}
+
+// DCT entropy of the z-MIP of vol[nz][h][w] (nz = 1: the image itself) into
+// out[0]; optional stop-state update for iteration k.
+static int run_metric(int nz, int h, int w, const float *vol, double xs, double ys, double *out,
+                      double *T1, double *n2p, double *Fabs, StopState *st_dev, double *trace,
+                      int k, int patience, hipStream_t st)
+{
+    const int nv = legs_count(ys, h), nu = legs_count(xs, w);
+    const int chunks = std::min(kMetricChunks, h);
+    const int rpc = (h + chunks - 1) / chunks;
+    const int nchunks = (h + rpc - 1) / rpc;
+    dim3 grid((w + 255) / 256, nchunks, (nv + kMetricVBlock - 1) / kMetricVBlock);
+    hipLaunchKernelGGL(k_metric_partial, grid, dim3(256), 0, st, vol, nz, h, w, nv, rpc, T1, n2p);
+    LAUNCH_CHECK("k_metric_partial");
+    hipLaunchKernelGGL(k_metric_colsum, dim3((nv * w + 255) / 256), dim3(256), 0, st, T1, nchunks,
+                       nv, w);
+    LAUNCH_CHECK("k_metric_colsum");
+    const int ncoef = nv * nu;
+    hipLaunchKernelGGL(k_metric_coeffs, dim3((ncoef + 3) / 4), dim3(256), 0, st, (const double *)T1,
+                       nv, nu, w, xs, ys, Fabs);
+    LAUNCH_CHECK("k_metric_coeffs");
+    hipLaunchKernelGGL(k_metric_final, dim3(1), dim3(256), 0, st, (const double *)n2p, nchunks * w,
+                       (const double *)Fabs, ncoef, xs, ys, out, st_dev, trace, k, patience);
+    LAUNCH_CHECK("k_metric_final");
+    return LFRL_OK;
+}
+
+static int check_legs(double xs, double ys)
+{
+    if (!(xs > 0.0) || !(ys > 0.0) || !std::isfinite(xs) || !std::isfinite(ys))
+        return set_error(LFRL_ERR_ARG, "triangle legs xs=%g, ys=%g must be positive", xs, ys);
+    if (std::ceil(xs) > kMaxMetricLegs || std::ceil(ys) > kMaxMetricLegs)
+        return set_error(LFRL_ERR_UNSUPPORTED, "triangle legs above %d bins", kMaxMetricLegs);
+    return LFRL_OK;
+}
+
+static int ensure_sensitivity(lfrl_plan_s *p, int h, int w, hipStream_t st)
+{
+    if (p->sens_h == h && p->sens_w == w)
+        return LFRL_OK;
+    p->sens_h = p->sens_w = -1;
+    int rc = launch_fill(p->img, (size_t)h * w, 1.0f, st);
+    if (rc)
+        return rc;
+    rc = run_backward(p, h, w, p->img, p->sens, EPI_STORE, nullptr, nullptr, st);
+    if (rc)
+        return rc;
+    p->sens_h = h;
+    p->sens_w = w;
+    return LFRL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// public entry points
+// ---------------------------------------------------------------------------
+extern "C" int lfrl_forward(lfrl_plan_t p, int32_t h, int32_t w, const float *vol, float *img,
+                            void *stream)
+{
+    if (!p || !vol || !img)
+        return set_error(LFRL_ERR_ARG, "NULL argument");
+    int rc = check_hw(p, h, w);
+    if (rc)
+        return rc;
+    DevGuard dg(p->device);
+    const size_t npx = (size_t)h * w;
+    if ((rc = check_buf(vol, npx * p->g.Nz * sizeof(float), "vol")) ||
+        (rc = check_buf(img, npx * sizeof(float), "img")))
+        return rc;
+    return run_forward(p, h, w, vol, img, EPI_STORE, nullptr, (hipStream_t)stream);
+}
+
+extern "C" int lfrl_backward(lfrl_plan_t p, int32_t h, int32_t w, const float *img, float *vol,
+                             void *stream)
+{
+    if (!p || !vol || !img)
+        return set_error(LFRL_ERR_ARG, "NULL argument");
+    int rc = check_hw(p, h, w);
+    if (rc)
+        return rc;
+    DevGuard dg(p->device);
+    const size_t npx = (size_t)h * w;
+    if ((rc = check_buf(vol, npx * p->g.Nz * sizeof(float), "vol")) ||
+        (rc = check_buf(img, npx * sizeof(float), "img")))
+        return rc;
+    return run_backward(p, h, w, img, vol, EPI_STORE, nullptr, nullptr, (hipStream_t)stream);
+}
+
+static int dot_into(lfrl_plan_s *p, const float *a, const float *b, size_t n, double *flux,
+                    int k, int which, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, a, b, n, p->dotp);
+    LAUNCH_CHECK("k_dot_partial");
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, st, (const double *)p->dotp, kDotBlocks,
+                       p->state, flux, k, which);
+    LAUNCH_CHECK("k_dot_final");
+    return LFRL_OK;
+}
+
+extern "C" int lfrl_deconvolve(lfrl_plan_t p, int32_t h, int32_t w, const float *img, float *vol,
+                               const lfrl_rl_opts *opts, lfrl_rl_report *report, void *stream)
+{
+    if (!p || !img || !vol || !opts)
+        return set_error(LFRL_ERR_ARG, "NULL argument");
+    int rc = check_hw(p, h, w);
+    if (rc)
+        return rc;
+    if (opts->max_iters < 1 || opts->max_iters > kMaxTrace)
+        return set_error(LFRL_ERR_ARG, "max_iters must be in [1, %d]", kMaxTrace);
+    if (opts->stop < LFRL_STOP_NONE || opts->stop > LFRL_STOP_TRACK)
+        return set_error(LFRL_ERR_ARG, "unknown stop mode %d", opts->stop);
+    if (opts->init != 0 && opts->init != 1)
+        return set_error(LFRL_ERR_ARG, "init must be 0 or 1");
+    const bool use_metric = opts->stop != LFRL_STOP_NONE;
+    if (use_metric) {
+        if (opts->patience < 1)
+            return set_error(LFRL_ERR_ARG, "patience must be >= 1");
+        rc = check_legs(opts->xs, opts->ys);
+        if (rc)
+            return rc;
+    }
+    DevGuard dg(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t nvox = (size_t)p->g.Nz * h * w;
+    if ((rc = check_buf(vol, nvox * sizeof(float), "vol")) ||
+        (rc = check_buf(img, (size_t)h * w * sizeof(float), "img")))
+        return rc;
+    const bool want_flux = report && report->flux_trace;
+    rc = ensure_sensitivity(p, h, w, st);
+    if (rc)
+        return rc;
+    float *V[2] = {p->vol[0], p->vol[1]};
+    float *VB = p->vol[2];
+    if (opts->init == 1) {
+        HIP_TRY(hipMemcpyAsync(V[0], vol, nvox * sizeof(float), hipMemcpyDeviceToDevice, st));
+    } else {
+        rc = launch_fill(V[0], nvox, 1.0f, st);
+        if (rc)
+            return rc;
+    }
+    hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(1), 0, st, p->state);
+    LAUNCH_CHECK("k_state_reset");
+    if (want_flux) {
+        rc = dot_into(p, img, nullptr, (size_t)h * w, nullptr, 0, 0, st);
+        if (rc)
+            return rc;
+    }
+    int iters = 0;
+    bool stopped = false;
+    for (int k = 1; k <= opts->max_iters; ++k) {
+        float *cur = V[(k - 1) & 1], *nxt = V[k & 1];
+        rc = run_forward(p, h, w, cur, p->img, EPI_RATIO, img, st);
+        if (rc)
+            return rc;
+        rc = run_backward(p, h, w, p->img, nxt, EPI_UPDATE, cur, p->sens, st);
+        if (rc)
+            return rc;
+        iters = k;
+        if (use_metric) {
+            rc = run_metric(p->g.Nz, h, w, nxt, opts->xs, opts->ys, p->metric_out, p->T1, p->n2p,
+                            p->Fabs, p->state, p->trace, k, opts->patience, st);
+            if (rc)
+                return rc;
+            hipLaunchKernelGGL(k_cond_copy, dim3(1024), dim3(256), 0, st, (const StopState *)p->state,
+                               (const float *)nxt, VB, nvox);
+            LAUNCH_CHECK("k_cond_copy");
+        }
+        if (want_flux) {
+            rc = dot_into(p, p->sens, nxt, nvox, p->flux, k, 1, st);
+            if (rc)
+                return rc;
+        }
+        if (opts->stop == LFRL_STOP_METRIC) {
+            HIP_TRY(hipMemcpyAsync(p->state_host, p->state, sizeof(StopState), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if (p->state_host->stopped) {
+                stopped = true;
+                break;
+            }
+        }
+    }
+    int best = iters;
+    if (use_metric) {
+        HIP_TRY(hipMemcpyAsync(p->state_host, p->state, sizeof(StopState), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        best = p->state_host->best_k;
+        HIP_TRY(hipMemcpyAsync(vol, VB, nvox * sizeof(float), hipMemcpyDeviceToDevice, st));
+    } else {
+        HIP_TRY(hipMemcpyAsync(vol, V[iters & 1], nvox * sizeof(float), hipMemcpyDeviceToDevice, st));
+    }
+    if (report) {
+        if (use_metric && report->metric_trace)
+            HIP_TRY(hipMemcpyAsync(report->metric_trace, p->trace, iters * sizeof(double),
+                                   hipMemcpyDeviceToHost, st));
+        if (want_flux)
+            HIP_TRY(hipMemcpyAsync(report->flux_trace, p->flux, iters * sizeof(double),
+                                   hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    if (report) {
+        report->iters_run = iters;
+        report->best_iter = best;
+        report->stopped = stopped ? 1 : 0;
+    }
+    return LFRL_OK;
+}
+
+// Scratch for the plan-less metric entry point: one growable set per device.
+struct MetricScratch {
+    double *T1 = nullptr, *n2p = nullptr, *Fabs = nullptr;
+    size_t w_cap = 0;
+};
+static std::mutex g_metric_mu;
+static std::vector<MetricScratch> g_metric_scratch;
+
+extern "C" int lfrl_metric(int32_t nz, int32_t h, int32_t w, const float *img, double xs,
+                           double ys, double *out, void *stream)
+{
+    if (!img || !out)
+        return set_error(LFRL_ERR_ARG, "NULL argument");
+    if (nz < 1 || h < 1 || w < 1)
+        return set_error(LFRL_ERR_ARG, "nz, h, w must be >= 1");
+    int rc = check_legs(xs, ys);
+    if (rc)
+        return rc;
+    if ((rc = check_buf(img, (size_t)nz * h * w * sizeof(float), "img")) ||
+        (rc = check_buf(out, sizeof(double), "out")))
+        return rc;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_metric_mu);
+    if ((int)g_metric_scratch.size() <= dev)
+        g_metric_scratch.resize(dev + 1);
+    MetricScratch &ms = g_metric_scratch[dev];
+    if (ms.w_cap < (size_t)w) {
+        if (ms.T1) {
+            HIP_TRY(hipDeviceSynchronize());
+            (void)hipFree(ms.T1);
+            (void)hipFree(ms.n2p);
+            (void)hipFree(ms.Fabs);
+            ms = MetricScratch();
+        }
+        const size_t wc = std::max<size_t>(w, 1024);
+        rc = dalloc(&ms.T1, (size_t)kMetricChunks * kMaxMetricLegs * wc * sizeof(double));
+        if (!rc)
+            rc = dalloc(&ms.n2p, (size_t)kMetricChunks * wc * sizeof(double));
+        if (!rc)
+            rc = dalloc(&ms.Fabs, (size_t)kMaxMetricLegs * kMaxMetricLegs * sizeof(double));
+        if (rc) {
+            if (ms.T1) (void)hipFree(ms.T1);
+            if (ms.n2p) (void)hipFree(ms.n2p);
+            if (ms.Fabs) (void)hipFree(ms.Fabs);
+            ms = MetricScratch();
+            return rc;
+        }
+        ms.w_cap = wc;
+    }
+    return run_metric(nz, h, w, img, xs, ys, out, ms.T1, ms.n2p, ms.Fabs, nullptr, nullptr, 0, 1,
+                      (hipStream_t)stream);
+}
+
+extern "C" int lfrl_metric_cutoff(double d_ml, double mag, int32_t nnum, double lambda, double na,
+                                  int32_t h, int32_t w, double *xs, double *ys)
+{
+    if (!xs || !ys)
+        return set_error(LFRL_ERR_ARG, "NULL argument");
+    if (!(d_ml > 0) || !(mag > 0) || nnum < 1 || !(lambda > 0) || !(na > 0) || h < 1 || w < 1)
+        return set_error(LFRL_ERR_ARG, "optics parameters must be positive");
+    const double pu = d_ml / (mag * nnum);
+    const double dpsf = 1.22 * lambda * nnum / na;
+    *xs = pu * w / dpsf;
+    *ys = pu * h / dpsf;
+    return LFRL_OK;
+}
+
+extern "C" int lfrl_profile_enable(lfrl_plan_t p, int32_t on)
+{
+    if (!p)
+        return set_error(LFRL_ERR_ARG, "NULL plan");
+    p->prof = on != 0;
+    p->ev_used[0] = p->ev_used[1] = 0;
+    return LFRL_OK;
+}
+
+extern "C" int lfrl_profile_read(lfrl_plan_t p, const char *kernel, double *total_ms,
+                                 int64_t *launches)
+{
+    if (!p || !kernel || !total_ms || !launches)
+        return set_error(LFRL_ERR_ARG, "NULL argument");
+    int which = -1;
+    if (!strcmp(kernel, "contract_fwd"))
+        which = 0;
+    else if (!strcmp(kernel, "contract_adj"))
+        which = 1;
+    if (which < 0)
+        return set_error(LFRL_ERR_ARG, "unknown kernel '%s'", kernel);
+    DevGuard dg(p->device);
+    double tot = 0.0;
+    const size_t used = p->ev_used[which];
+    for (size_t i = 0; i + 1 < used; i += 2) {
+        HIP_TRY(hipEventSynchronize(p->ev[which][i + 1]));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, p->ev[which][i], p->ev[which][i + 1]));
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = (int64_t)(used / 2);
+    return LFRL_OK;
+}
+
+extern "C" const char *lfrl_last_error(void)
+{
+    return g_last_error.c_str();
+}

@@ -1,0 +1,236 @@
+"""Parity of the HIP path with the CPU oracle (needs an MI355X).
+
+Every call goes through the C ABI (the ctypes binding only marshals
+arguments).  Sizes span several DFT tiles with a ragged last tile, several
+tile groups in the contraction, non-square images, images smaller than the
+plan maximum, Nnum = 1 and Nnum = 15.  Floating-point bar: relative L2 error
+<= 1e-5 against the float64 oracle on the same float32 inputs."""
+import numpy as np
+import pytest
+
+import lfrl_synth as S
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def lf():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2208_11422_amd as lf
+    import os
+    assert os.path.exists(lf.library_path()), "liblfrl.so missing: build first"
+    return lf
+
+
+def dev():
+    import torch
+    return torch.device("cuda:0")
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev())
+
+
+def rel_l2(got, want):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    return float(np.linalg.norm(got - want) / np.linalg.norm(want))
+
+
+def random_psf(nz, n, k, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.0, 1.0, size=(nz, n, n, k, k)).astype(np.float32)
+
+
+# (name, nnum, lenslets_y, lenslets_x, nz, ksize, psf kind, tile_q list)
+GEOMS = [
+    ("small-N5", 5, 11, 11, 5, 25, "gauss", [0, 10, 7]),
+    ("nonsquare-N3", 3, 5, 8, 2, 9, "rand", [0, 6]),
+    ("nnum1", 1, 20, 17, 3, 7, "rand", [0, 9]),
+    ("N15", 15, 4, 4, 2, 31, "gauss", [0]),
+    ("delta-N2", 2, 6, 7, 1, 1, "rand", [0, 3]),
+]
+
+
+def make_psf(n, nz, k, kind, seed):
+    if kind == "gauss":
+        return S.gaussian_psf(n, nz, k, seed=seed, shift_scale=None)
+    return random_psf(nz, n, k, seed)
+
+
+def cases():
+    for name, n, ly, lx, nz, k, kind, qs in GEOMS:
+        for q in qs:
+            yield pytest.param(n, ly, lx, nz, k, kind, q, id=f"{name}-Q{q}")
+
+
+@pytest.mark.parametrize("n,ly,lx,nz,k,kind,q", list(cases()))
+def test_forward_backward_parity(lf, n, ly, lx, nz, k, kind, q):
+    import torch
+    psf = make_psf(n, nz, k, kind, seed=100 + n)
+    h, w = n * ly, n * lx
+    rng = np.random.default_rng(7)
+    x = rng.uniform(0.0, 1.0, size=(nz, h, w)).astype(np.float32)
+    y = rng.uniform(0.0, 1.0, size=(h, w)).astype(np.float32)
+    print(f"case N={n} {h}x{w} nz={nz} K={k} Q={q}", flush=True)
+    # plan sized for a larger image than the one used
+    plan = lf.Plan(to_dev(psf), h + 2 * n, w + n, tile_q=q)
+    try:
+        fx = plan.forward(to_dev(x))
+        by = plan.backward(to_dev(y))
+        torch.cuda.synchronize()
+        assert rel_l2(fx.cpu().numpy(), oracle.forward(psf, x)) <= TOL
+        assert rel_l2(by.cpu().numpy(), oracle.backward(psf, y)) <= TOL
+    finally:
+        plan.close()
+
+
+def test_adjointness_on_gpu(lf):
+    import torch
+    n, ly, lx, nz, k = 3, 9, 7, 3, 11
+    psf = random_psf(nz, n, k, seed=3)
+    h, w = n * ly, n * lx
+    rng = np.random.default_rng(4)
+    x = rng.normal(size=(nz, h, w)).astype(np.float32)
+    y = rng.normal(size=(h, w)).astype(np.float32)
+    plan = lf.Plan(to_dev(psf), h, w, tile_q=7)
+    try:
+        ax = plan.forward(to_dev(x)).cpu().numpy().astype(np.float64)
+        aty = plan.backward(to_dev(y)).cpu().numpy().astype(np.float64)
+    finally:
+        plan.close()
+    lhs = np.sum(ax * y.astype(np.float64))
+    rhs = np.sum(x.astype(np.float64) * aty)
+    assert abs(lhs - rhs) <= 1e-5 * np.sqrt(np.sum(ax ** 2) * np.sum(y.astype(np.float64) ** 2))
+
+
+def test_delta_voxel_reproduces_psf(lf):
+    import torch
+    n, ly, nz, k = 5, 9, 3, 13
+    psf = random_psf(nz, n, k, seed=5)
+    h = w = n * ly
+    c0 = (k - 1) // 2
+    plan = lf.Plan(to_dev(psf), h, w, tile_q=9)
+    try:
+        for (j, r, s) in [(1, 22, 21), (2, 20, 24), (0, 23, 19)]:
+            x = np.zeros((nz, h, w), dtype=np.float32)
+            x[j, r, s] = 1.0
+            img = plan.forward(to_dev(x)).cpu().numpy()
+            want = np.zeros((h, w))
+            want[r - c0:r + c0 + 1, s - c0:s + c0 + 1] = psf[j, r % n, s % n]
+            assert np.max(np.abs(img - want)) <= 1e-6 * psf.max()
+    finally:
+        plan.close()
+
+
+def small_problem():
+    p = S.preset("small")
+    g = p["geometry"]
+    psf = p["psf_array"]
+    y = S.measure(oracle.forward(psf, p["x_true"]), p["peak"], p["background"], p["noise_seed"])
+    xs, ys = oracle.synthetic_cutoff(g.nnum, p["spot_radius"], g.h, g.w)
+    return p, psf, y, xs, ys
+
+
+def test_rl_iterates_match_oracle(lf):
+    """Each of the first 5 iterates of the Nnum 5, 55 x 55, 5-plane workload."""
+    import torch
+    p, psf, y, xs, ys = small_problem()
+    g = p["geometry"]
+    ref = oracle.rl(psf, y, p["iters"], keep_all=True)
+    plan = lf.Plan(to_dev(psf), g.h, g.w)
+    try:
+        for k in range(1, p["iters"] + 1):
+            vol, rep = plan.deconvolve(to_dev(y), k, stop=lf.STOP_NONE)
+            torch.cuda.synchronize()
+            assert rep["iters_run"] == k
+            err = rel_l2(vol.cpu().numpy(), ref[k])
+            print(f"iter {k}: rel L2 {err:.2e}", flush=True)
+            assert err <= TOL
+    finally:
+        plan.close()
+
+
+def test_rl_with_metric_matches_oracle(lf):
+    """Metric trace, best iterate and stop decision over 30 iterations."""
+    import torch
+    p, psf, y, xs, ys = small_problem()
+    g = p["geometry"]
+    iters = 30
+    ref_x, ref_best, ref_run, ref_trace = oracle.deconvolve(psf, y, iters, xs, ys, stop=False)
+    plan = lf.Plan(to_dev(psf), g.h, g.w)
+    try:
+        vol, rep = plan.deconvolve(to_dev(y), iters, stop=lf.STOP_TRACK, xs=xs, ys=ys,
+                                   want_flux=True)
+        torch.cuda.synchronize()
+        tr = np.array(rep["metric_trace"])
+        np.testing.assert_allclose(tr, ref_trace, rtol=TOL)
+        assert rep["best_iter"] == ref_best
+        assert rel_l2(vol.cpu().numpy(), ref_x) <= TOL
+        # flux invariant <A^T 1, x^k> = sum(y) (every predicted pixel is positive here)
+        assert np.max(np.abs(rep["flux_trace"])) <= 1e-5
+        # early stop: same stop iteration as the oracle's rule on the same trace
+        stopped, k_stop, best = oracle.stop_decision(list(ref_trace), 1)
+        vol2, rep2 = plan.deconvolve(to_dev(y), iters, stop=lf.STOP_METRIC, xs=xs, ys=ys)
+        torch.cuda.synchronize()
+        assert rep2["stopped"] == stopped
+        assert rep2["iters_run"] == k_stop
+        assert rep2["best_iter"] == best
+        ref_best_x = oracle.rl(psf, y, best)
+        assert rel_l2(vol2.cpu().numpy(), ref_best_x) <= TOL
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("nz,h,w,xs,ys", [(1, 55, 55, 5.5, 5.5), (3, 40, 64, 7.3, 3.9),
+                                         (1, 600, 600, 10.0, 10.0), (5, 31, 17, 2.0, 30.0)])
+def test_metric_matches_oracle(lf, nz, h, w, xs, ys):
+    rng = np.random.default_rng(h * w + nz)
+    vol = rng.uniform(0.0, 1.0, size=(nz, h, w)).astype(np.float32)
+    vol[:, h // 3:h // 2, w // 4:w // 2] += 3.0
+    img = vol[0] if nz == 1 else vol
+    got = lf.metric(to_dev(img), xs, ys)
+    want = oracle.metric(vol, xs, ys)
+    assert got == pytest.approx(want, rel=1e-9)
+
+
+def test_metric_zero_image(lf):
+    assert lf.metric(to_dev(np.zeros((15, 20))), 3.0, 3.0) == 0.0
+
+
+def test_deterministic(lf):
+    import torch
+    p, psf, y, xs, ys = small_problem()
+    g = p["geometry"]
+    plan = lf.Plan(to_dev(psf), g.h, g.w, tile_q=10)
+    try:
+        a, _ = plan.deconvolve(to_dev(y), 3, stop=lf.STOP_TRACK, xs=xs, ys=ys)
+        b, _ = plan.deconvolve(to_dev(y), 3, stop=lf.STOP_TRACK, xs=xs, ys=ys)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+    finally:
+        plan.close()
+
+
+def test_argument_errors(lf):
+    import torch
+    psf = random_psf(2, 3, 5, seed=1)
+    plan = lf.Plan(to_dev(psf), 12, 12)
+    try:
+        with pytest.raises(lf.LfrlError):
+            plan.forward(to_dev(np.zeros((2, 15, 12))))      # exceeds max_h
+        with pytest.raises(lf.LfrlError):
+            plan.forward(to_dev(np.zeros((2, 10, 12))))      # not a multiple of nnum
+        with pytest.raises(lf.LfrlError):
+            plan.deconvolve(to_dev(np.ones((12, 12))), 0)    # max_iters < 1
+        with pytest.raises(lf.LfrlError):
+            plan.deconvolve(to_dev(np.ones((12, 12))), 2, stop=lf.STOP_METRIC, xs=-1.0)
+    finally:
+        plan.close()
+    with pytest.raises(lf.LfrlError):
+        lf.Plan(to_dev(random_psf(2, 3, 4, seed=1)), 12, 12)  # even support
