@@ -135,7 +135,9 @@ typedef struct {
     int32_t iters_run; /* iterations executed */
     int32_t best_iter; /* iteration whose volume was returned */
     int32_t stopped;   /* 1 if the stop rule fired before the cap */
-    int32_t reserved;
+    int32_t weak_voxels; /* voxels updated by exact float64 window sums (their
+                            A^T 1 is below 1e-2 of the largest, so the tile-DFT
+                            values would be dominated by round-off) */
     double *metric_trace; /* [host] array of max_iters or NULL: e_1, e_2, ... */
     double *flux_trace;   /* [host] array of max_iters or NULL:
                              <A^T 1, x^k> / sum(img) - 1 for each iterate */

@@ -63,7 +63,7 @@ class RlOpts(ctypes.Structure):
 
 class RlReport(ctypes.Structure):
     _fields_ = [("iters_run", ctypes.c_int32), ("best_iter", ctypes.c_int32),
-                ("stopped", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("stopped", ctypes.c_int32), ("weak_voxels", ctypes.c_int32),
                 ("metric_trace", ctypes.POINTER(ctypes.c_double)),
                 ("flux_trace", ctypes.POINTER(ctypes.c_double))]
 
@@ -189,7 +189,8 @@ def lfrl_deconvolve(plan: int, h: int, w: int, img: torch.Tensor, vol: torch.Ten
     _check(_load().lfrl_deconvolve(plan, h, w, _dev_f32(img, "img"), _dev_f32(vol, "vol"),
                                    ctypes.byref(opts), ctypes.byref(rep), _stream(stream)))
     k = rep.iters_run
-    out = {"iters_run": k, "best_iter": rep.best_iter, "stopped": bool(rep.stopped)}
+    out = {"iters_run": k, "best_iter": rep.best_iter, "stopped": bool(rep.stopped),
+           "weak_voxels": rep.weak_voxels}
     if mt is not None and opts.stop != STOP_NONE:
         out["metric_trace"] = list(mt[:k])
     if ft is not None:

@@ -33,6 +33,7 @@
 #include <vector>
 
 #include "lfrl.h"
+#include "tile_fft.hpp"
 
 // ---------------------------------------------------------------------------
 // errors
@@ -73,6 +74,7 @@ static constexpr int kMaxTrace = 4096;  // iterations recorded per deconvolve ca
 static constexpr int kMetricChunks = 32;
 static constexpr int kMetricVBlock = 16;
 static constexpr int kMaxMetricLegs = 256;
+static constexpr float kWeakThreshold = 1e-2f;  // weak voxel: A^T 1 < this * max A^T 1
 
 // ---------------------------------------------------------------------------
 // geometry
@@ -770,6 +772,235 @@ __global__ void k_dot_final(const double *__restrict__ part, int nparts, StopSta
 }
 
 // ---------------------------------------------------------------------------
+// FFT tile kernels: supported sizes and dispatch
+// ---------------------------------------------------------------------------
+// Tile sides with an FFT kernel (7-smooth, register-resident).  Other sides use
+// the direct-sum DFT kernels above.
+#define LFRL_FFT_Q_LIST(X) \
+    X(8) X(9) X(10) X(12) X(14) X(15) X(16) X(18) X(20) X(21) X(24) X(25) X(27) X(28) X(30) \
+    X(32) X(35) X(36) X(40) X(42) X(45) X(48)
+
+static bool fft_supported(int Q)
+{
+    switch (Q) {
+#define LFRL_CASE(q) case q:
+        LFRL_FFT_Q_LIST(LFRL_CASE)
+#undef LFRL_CASE
+        return true;
+    default:
+        return false;
+    }
+}
+
+static size_t lds_r2c_fft(const Geo &g)
+{
+    const size_t a = (size_t)g.Q * g.Q * g.N * 4, b = (size_t)g.Q * g.QH * g.N * 8;
+    return std::max(a, b) + (size_t)g.Q * 8;
+}
+
+static size_t lds_c2r_fft(const Geo &g)
+{
+    return (size_t)g.Q * g.QH * g.N * 8 + (size_t)g.T * g.QH * g.N * 8 + (size_t)g.Q * 8;
+}
+
+static int round64(int v)
+{
+    return (v + 63) / 64 * 64;
+}
+
+// One thread per row pair / column of a tile; the kernels are built for at
+// most kFftMaxThreads threads per block (which leaves 256 VGPRs per thread).
+static constexpr int kFftMaxThreads = 512;
+
+static int threads_r2c_fft(const Geo &g)
+{
+    return round64(std::max((g.Q * g.N + 1) / 2, g.QH * g.N));
+}
+
+static int threads_c2r_fft(const Geo &g)
+{
+    return round64(std::max(g.QH * g.N, (g.T * g.N + 1) / 2));
+}
+
+static bool fft_usable(const Geo &g, size_t lds_max)
+{
+    return fft_supported(g.Q) && threads_r2c_fft(g) <= kFftMaxThreads &&
+           threads_c2r_fft(g) <= kFftMaxThreads && lds_r2c_fft(g) <= lds_max &&
+           lds_c2r_fft(g) <= lds_max;
+}
+
+static void set_fft_lds_attrs(int Q, size_t lds)
+{
+    switch (Q) {
+#define LFRL_CASE(q)                                                                        \
+    case q:                                                                                 \
+        (void)hipFuncSetAttribute((const void *)k_r2c_fft<q>,                               \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);    \
+        (void)hipFuncSetAttribute((const void *)k_c2r_fft<q>,                               \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);    \
+        break;
+        LFRL_FFT_Q_LIST(LFRL_CASE)
+#undef LFRL_CASE
+    default:
+        break;
+    }
+}
+
+static void launch_r2c_fft(int Q, dim3 grid, int block, size_t lds, hipStream_t st, int mode,
+                           const float *src, int H, int W, int N, int T, int hD, int tiles_x,
+                           int nt, int KKo, int K, int c0, int KK, float2 *out, const float2 *tw)
+{
+    switch (Q) {
+#define LFRL_CASE(q)                                                                        \
+    case q:                                                                                 \
+        hipLaunchKernelGGL(k_r2c_fft<q>, grid, dim3(block), lds, st, mode, src, H, W, N, T,  \
+                           hD, tiles_x, nt, KKo, K, c0, KK, out, tw);                        \
+        break;
+        LFRL_FFT_Q_LIST(LFRL_CASE)
+#undef LFRL_CASE
+    default:
+        break;
+    }
+}
+
+static void launch_c2r_fft(int Q, dim3 grid, int block, size_t lds, hipStream_t st,
+                           const float2 *spec, size_t split_stride, int nsplit, int KKo, int N,
+                           int T, int hD, int tiles_x, int nt, int H, int W, int mode, float *dst,
+                           const float *aux0, const float *aux1, const float2 *tw)
+{
+    switch (Q) {
+#define LFRL_CASE(q)                                                                        \
+    case q:                                                                                 \
+        hipLaunchKernelGGL(k_c2r_fft<q>, grid, dim3(block), lds, st, spec, split_stride,     \
+                           nsplit, KKo, N, T, hD, tiles_x, nt, H, W, mode, dst, aux0, aux1,  \
+                           tw);                                                             \
+        break;
+        LFRL_FFT_Q_LIST(LFRL_CASE)
+#undef LFRL_CASE
+    default:
+        break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// weakly observed voxels
+// ---------------------------------------------------------------------------
+// A voxel whose PSF footprint barely overlaps the image has a tiny sensitivity
+// c = A^T 1, and the update x * (A^T rho) / c divides two small numbers whose
+// float32 tile-DFT values carry absolute round-off of the image's scale.  Such
+// voxels (c below a small fraction of the largest c) are listed once per image
+// size and their window sums are evaluated directly in float64 instead.
+
+// Per-block maxima of max(a, 0).
+__global__ void k_max_partial(const float *__restrict__ a, size_t n, float *__restrict__ part)
+{
+    __shared__ float red[256];
+    float m = 0.f;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, a[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = red[0];
+}
+
+__global__ void k_max_final(const float *__restrict__ part, int nparts, float *__restrict__ out,
+                            unsigned *__restrict__ count)
+{
+    __shared__ float red[256];
+    float m = 0.f;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x)
+        m = fmaxf(m, part[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = red[0];
+        *count = 0u;
+    }
+}
+
+// Append voxels with sens < thr_rel * max to `list` (order not significant);
+// *count ends as the number found, which may exceed cap (extra entries dropped).
+__global__ void k_weak_select(const float *__restrict__ sens, size_t n,
+                              const float *__restrict__ cmax, float thr_rel,
+                              unsigned *__restrict__ list, unsigned *__restrict__ count,
+                              unsigned cap)
+{
+    const float thr = thr_rel * cmax[0];
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        if (sens[i] < thr) {
+            const unsigned slot = atomicAdd(count, 1u);
+            if (slot < cap)
+                list[slot] = (unsigned)i;
+        }
+    }
+}
+
+__global__ void k_zero_u32(unsigned *p)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *p = 0u;
+}
+
+enum { WEAK_SENS = 0, WEAK_UPDATE = 1 };
+
+// One block per listed voxel (j, r, s): the exact window sum
+//   acc = sum_{taps inside the image} h[j][r mod N][s mod N][u][v] * img[r+u-c0][s+v-c0]
+// in float64 (img == nullptr stands for an all-ones image, i.e. A^T 1).
+//   WEAK_SENS:   sens[vox] = acc
+//   WEAK_UPDATE: dst[vox] = sens[vox] > 0 ? src[vox] * acc / sens[vox] : 0
+__global__ void k_weak_exact(const unsigned *__restrict__ list, const float *__restrict__ psf,
+                             int N, int K, int H, int W, const float *__restrict__ img,
+                             float *__restrict__ sens, const float *__restrict__ src,
+                             float *__restrict__ dst, int mode)
+{
+    __shared__ double red[256];
+    const unsigned vox = list[blockIdx.x];
+    const size_t hw = (size_t)H * W;
+    const int j = (int)(vox / hw);
+    const int r = (int)((vox % hw) / W), s = (int)(vox % W);
+    const int c0 = (K - 1) / 2;
+    const int u0 = max(0, c0 - r), u1 = min(K, H - r + c0);
+    const int v0 = max(0, c0 - s), v1 = min(K, W - s + c0);
+    const int wu = max(0, u1 - u0), wv = max(0, v1 - v0);
+    const float *hk = psf + (((size_t)j * N + r % N) * N + s % N) * (size_t)K * K;
+    double acc = 0.0;
+    const int total = wu * wv;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int u = u0 + idx / wv, v = v0 + idx % wv;
+        const double hv = (double)hk[(size_t)u * K + v];
+        acc += img ? hv * (double)img[(size_t)(r + u - c0) * W + (s + v - c0)] : hv;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (mode == WEAK_SENS) {
+            sens[vox] = (float)red[0];
+        } else {
+            const float c = sens[vox];
+            dst[vox] = c > 0.f ? (float)((double)src[vox] * red[0] / (double)c) : 0.f;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
 static constexpr int kDotBlocks = 512;
@@ -786,8 +1017,16 @@ struct lfrl_plan_s {
     double *trace = nullptr, *flux = nullptr, *dotp = nullptr;
     StopState *state = nullptr;
     StopState *state_host = nullptr;  // pinned
+    float *psf = nullptr;             // resident copy of the PSF set (weak-voxel sums)
+    unsigned *weak = nullptr;         // weakly observed voxel list
+    unsigned *weak_count = nullptr;   // device counter
+    unsigned *weak_count_host = nullptr;  // pinned
+    float *cmax = nullptr;            // [kDotBlocks + 1] max partials, max at [kDotBlocks]
+    unsigned weak_cap = 0, nweak = 0;
     int sens_h = -1, sens_w = -1;
     size_t lds_r2c_bytes = 0, lds_c2r_bytes = 0;
+    bool use_fft = false;  // tile DFTs by the register FFT kernels
+    int thr_r2c = 256, thr_c2r = 256;
     // profiling
     bool prof = false;
     std::vector<hipEvent_t> ev[2];
@@ -817,14 +1056,20 @@ static int validate_desc(const lfrl_plan_desc *d)
 
 // Model of one iteration's time for tile side Q (bytes at a sustained HBM rate,
 // flops at a sustained FP32 rate, the contraction overlapping its two bounds).
+static bool fft_supported(int Q);
+
 static double model_time(const Geo &g, const Tiles &t)
 {
     const double spec = (double)g.nf * g.NN * g.KK * 8.0;
     const double inter = (double)g.nf * t.nt * (g.KK + g.NN) * 8.0;
     const double cflops = 8.0 * g.nf * (double)g.NN * g.KK * t.nt;
     const double contract = 2.0 * std::max((spec + 2.0 * inter) / 5.0e12, cflops / 90.0e12);
-    const double dft = (double)(g.KK + g.NN) * t.nt * 6.0 * g.Q * g.Q * g.QH * 2.0 * 2.0 / 60.0e12;
-    return contract + dft;
+    // tile transforms: both directions, volume side and image side
+    const double tiles = (double)(g.KK + g.NN) * t.nt * 2.0;
+    const double per_tile = fft_supported(g.Q)
+                                ? 10.0 * g.Q * g.Q * std::log2((double)g.Q) / 40.0e12
+                                : 12.0 * g.Q * g.Q * g.QH / 60.0e12;
+    return contract + tiles * per_tile;
 }
 
 static size_t lds_limit()
@@ -882,13 +1127,18 @@ static int pick_split(const Geo &g)
 }
 
 struct Sizes {
-    size_t Gf, tw, X, Yp, Rs, img, vol, T1, n2p, Fabs, trace, dotp;
-    size_t resident() const { return 2 * Gf + tw; }
+    size_t Gf, tw, psf, X, Yp, Rs, img, vol, T1, n2p, Fabs, trace, dotp, weak;
+    size_t resident() const { return 2 * Gf + tw + psf; }
     size_t workspace() const
     {
-        return X + Yp + Rs + img + 4 * vol + T1 + n2p + Fabs + 2 * trace + dotp + 256;
+        return X + Yp + Rs + img + 4 * vol + T1 + n2p + Fabs + 2 * trace + 2 * dotp + weak + 512;
     }
 };
+
+static unsigned weak_cap_for(size_t nvox)
+{
+    return (unsigned)std::min<size_t>(nvox, (size_t)1 << 20);
+}
 
 static Sizes sizes_for(const Geo &g, int max_h, int max_w, int split)
 {
@@ -906,6 +1156,8 @@ static Sizes sizes_for(const Geo &g, int max_h, int max_w, int split)
     s.Fabs = (size_t)kMaxMetricLegs * kMaxMetricLegs * sizeof(double);
     s.trace = (size_t)kMaxTrace * sizeof(double);
     s.dotp = (size_t)kDotBlocks * sizeof(double);
+    s.psf = (size_t)g.Nz * g.NN * g.K * g.K * sizeof(float);
+    s.weak = (size_t)weak_cap_for((size_t)g.Nz * max_h * max_w) * sizeof(unsigned);
     return s;
 }
 
@@ -959,12 +1211,15 @@ static void free_plan(lfrl_plan_s *p)
     (void)hipDeviceSynchronize();
     void *bufs[] = {p->Gf, p->Gb, p->tw, p->X, p->Yp, p->Rs, p->img, p->sens,
                     p->vol[0], p->vol[1], p->vol[2], p->T1, p->n2p, p->Fabs,
-                    p->metric_out, p->trace, p->flux, p->dotp, p->state};
+                    p->metric_out, p->trace, p->flux, p->dotp, p->state,
+                    p->psf, p->weak, p->weak_count, p->cmax};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
     if (p->state_host)
         (void)hipHostFree(p->state_host);
+    if (p->weak_count_host)
+        (void)hipHostFree(p->weak_count_host);
     for (auto &v : p->ev)
         for (hipEvent_t e : v)
             (void)hipEventDestroy(e);
@@ -1038,8 +1293,16 @@ extern "C" int lfrl_plan(lfrl_plan_t *out, const lfrl_plan_desc *desc, const flo
     const Sizes s = sizes_for(g, p->max_h, p->max_w, p->split_k);
     p->resident = s.resident();
     p->workspace = s.workspace();
-    p->lds_r2c_bytes = lds_r2c(g);
-    p->lds_c2r_bytes = lds_c2r(g);
+    p->use_fft = fft_usable(g, lmax);
+    if (p->use_fft) {
+        p->lds_r2c_bytes = lds_r2c_fft(g);
+        p->lds_c2r_bytes = lds_c2r_fft(g);
+        p->thr_r2c = threads_r2c_fft(g);
+        p->thr_c2r = threads_c2r_fft(g);
+    } else {
+        p->lds_r2c_bytes = lds_r2c(g);
+        p->lds_c2r_bytes = lds_c2r(g);
+    }
     TRY(dalloc(&p->Gf, s.Gf));
     TRY(dalloc(&p->Gb, s.Gf));
     TRY(dalloc(&p->tw, s.tw));
@@ -1058,10 +1321,16 @@ extern "C" int lfrl_plan(lfrl_plan_t *out, const lfrl_plan_desc *desc, const flo
     TRY(dalloc(&p->flux, s.trace));
     TRY(dalloc(&p->dotp, s.dotp));
     TRY(dalloc(&p->state, sizeof(StopState)));
+    TRY(dalloc(&p->psf, s.psf));
+    p->weak_cap = weak_cap_for((size_t)g.Nz * p->max_h * p->max_w);
+    TRY(dalloc(&p->weak, s.weak));
+    TRY(dalloc(&p->weak_count, sizeof(unsigned)));
+    TRY(dalloc(&p->cmax, (kDotBlocks + 1) * sizeof(float)));
     {
         hipError_t e = hipHostMalloc((void **)&p->state_host, sizeof(StopState), hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void **)&p->weak_count_host, sizeof(unsigned), hipHostMallocDefault);
         if (e != hipSuccess) {
-            p->state_host = nullptr;
             free_plan(p);
             return set_error(LFRL_ERR_NOMEM, "hipHostMalloc failed: %s", hipGetErrorString(e));
         }
@@ -1073,11 +1342,19 @@ extern "C" int lfrl_plan(lfrl_plan_t *out, const lfrl_plan_desc *desc, const flo
         tw[m] = make_float2((float)std::cos(th), (float)std::sin(th));
     }
     set_lds_attrs(std::max(p->lds_r2c_bytes, p->lds_c2r_bytes));
+    if (p->use_fft)
+        set_fft_lds_attrs(g.Q, std::max(p->lds_r2c_bytes, p->lds_c2r_bytes));
     hipError_t e = hipMemcpyAsync(p->tw, tw.data(), g.Q * sizeof(float2), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->psf, psf, s.psf, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) {
         dim3 grid(g.N, g.NN, g.Nz);
-        hipLaunchKernelGGL(k_psf_r2c, grid, dim3(256), p->lds_r2c_bytes, st, psf, g.N, g.K, g.c0,
-                           g.hD, g.Q, g.QH, g.KK, g.NN, p->Gf, p->tw);
+        if (p->use_fft)
+            launch_r2c_fft(g.Q, grid, p->thr_r2c, p->lds_r2c_bytes, st, SRC_PSF, psf, 0, 0, g.N,
+                           g.T, g.hD, 0, 0, 0, g.K, g.c0, g.KK, p->Gf, p->tw);
+        else
+            hipLaunchKernelGGL(k_psf_r2c, grid, dim3(256), p->lds_r2c_bytes, st, psf, g.N, g.K,
+                               g.c0, g.hD, g.Q, g.QH, g.KK, g.NN, p->Gf, p->tw);
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
@@ -1177,8 +1454,12 @@ static int run_forward(lfrl_plan_s *p, int h, int w, const float *vol, float *ds
 {
     const Geo &g = p->g;
     const Tiles t = tiles_for(g, h, w);
-    hipLaunchKernelGGL(k_vol_r2c, dim3(t.nt, g.Nz * g.N), dim3(256), p->lds_r2c_bytes, st, vol, h,
-                       w, g.N, g.Q, g.QH, g.T, g.hD, t.tx, t.nt, g.KK, p->X, p->tw);
+    if (p->use_fft)
+        launch_r2c_fft(g.Q, dim3(t.nt, g.Nz * g.N), p->thr_r2c, p->lds_r2c_bytes, st, SRC_PLANES,
+                       vol, h, w, g.N, g.T, g.hD, t.tx, t.nt, g.KK, g.K, g.c0, g.KK, p->X, p->tw);
+    else
+        hipLaunchKernelGGL(k_vol_r2c, dim3(t.nt, g.Nz * g.N), dim3(256), p->lds_r2c_bytes, st, vol,
+                           h, w, g.N, g.Q, g.QH, g.T, g.hD, t.tx, t.nt, g.KK, p->X, p->tw);
     LAUNCH_CHECK("k_vol_r2c");
     const int NTV = nt_template(t.nt);
     const int ntg = (t.nt + NTV - 1) / NTV;
@@ -1200,9 +1481,14 @@ static int run_forward(lfrl_plan_s *p, int h, int w, const float *vol, float *ds
             return rc;
     }
     const size_t split_stride = (size_t)g.nf * t.nt * g.NN;
-    hipLaunchKernelGGL(k_c2r, dim3(t.nt, g.N), dim3(256), p->lds_c2r_bytes, st, p->Yp,
-                       split_stride, split, g.NN, g.N, g.Q, g.QH, g.T, g.hD, t.tx, t.nt, h, w,
-                       mode, dst, aux, (const float *)nullptr, p->tw);
+    if (p->use_fft)
+        launch_c2r_fft(g.Q, dim3(t.nt, g.N), p->thr_c2r, p->lds_c2r_bytes, st, p->Yp, split_stride,
+                       split, g.NN, g.N, g.T, g.hD, t.tx, t.nt, h, w, mode, dst, aux,
+                       (const float *)nullptr, p->tw);
+    else
+        hipLaunchKernelGGL(k_c2r, dim3(t.nt, g.N), dim3(256), p->lds_c2r_bytes, st, p->Yp,
+                           split_stride, split, g.NN, g.N, g.Q, g.QH, g.T, g.hD, t.tx, t.nt, h, w,
+                           mode, dst, aux, (const float *)nullptr, p->tw);
     LAUNCH_CHECK("k_c2r(forward)");
     return LFRL_OK;
 }
@@ -1214,8 +1500,12 @@ static int run_backward(lfrl_plan_s *p, int h, int w, const float *img, float *d
 {
     const Geo &g = p->g;
     const Tiles t = tiles_for(g, h, w);
-    hipLaunchKernelGGL(k_vol_r2c, dim3(t.nt, g.N), dim3(256), p->lds_r2c_bytes, st, img, h, w,
-                       g.N, g.Q, g.QH, g.T, g.hD, t.tx, t.nt, g.NN, p->Rs, p->tw);
+    if (p->use_fft)
+        launch_r2c_fft(g.Q, dim3(t.nt, g.N), p->thr_r2c, p->lds_r2c_bytes, st, SRC_PLANES, img, h,
+                       w, g.N, g.T, g.hD, t.tx, t.nt, g.NN, g.K, g.c0, g.KK, p->Rs, p->tw);
+    else
+        hipLaunchKernelGGL(k_vol_r2c, dim3(t.nt, g.N), dim3(256), p->lds_r2c_bytes, st, img, h,
+                           w, g.N, g.Q, g.QH, g.T, g.hD, t.tx, t.nt, g.NN, p->Rs, p->tw);
     LAUNCH_CHECK("k_vol_r2c(image)");
     const int NTV = nt_template(t.nt);
     const int ntg = (t.nt + NTV - 1) / NTV;
@@ -1233,9 +1523,14 @@ static int run_backward(lfrl_plan_s *p, int h, int w, const float *img, float *d
         if (rc)
             return rc;
     }
-    hipLaunchKernelGGL(k_c2r, dim3(t.nt, g.Nz * g.N), dim3(256), p->lds_c2r_bytes, st, p->X,
-                       (size_t)0, 1, g.KK, g.N, g.Q, g.QH, g.T, g.hD, t.tx, t.nt, h, w, mode, dst,
-                       aux0, aux1, p->tw);
+    if (p->use_fft)
+        launch_c2r_fft(g.Q, dim3(t.nt, g.Nz * g.N), p->thr_c2r, p->lds_c2r_bytes, st, p->X,
+                       (size_t)0, 1, g.KK, g.N, g.T, g.hD, t.tx, t.nt, h, w, mode, dst, aux0, aux1,
+                       p->tw);
+    else
+        hipLaunchKernelGGL(k_c2r, dim3(t.nt, g.Nz * g.N), dim3(256), p->lds_c2r_bytes, st, p->X,
+                           (size_t)0, 1, g.KK, g.N, g.Q, g.QH, g.T, g.hD, t.tx, t.nt, h, w, mode,
+                           dst, aux0, aux1, p->tw);
     LAUNCH_CHECK("k_c2r(backward)");
     return LFRL_OK;
 }
@@ -1289,17 +1584,54 @@ static int check_legs(double xs, double ys)
     return LFRL_OK;
 }
 
+// c = A^T 1 for an h x w image, through the tile-DFT path, then made exact
+// (float64 window sums) at the weakly observed voxels, which are listed for the
+// per-iteration fix-up.  Runs once per image size; synchronises the stream.
 static int ensure_sensitivity(lfrl_plan_s *p, int h, int w, hipStream_t st)
 {
     if (p->sens_h == h && p->sens_w == w)
         return LFRL_OK;
     p->sens_h = p->sens_w = -1;
+    p->nweak = 0;
     int rc = launch_fill(p->img, (size_t)h * w, 1.0f, st);
     if (rc)
         return rc;
     rc = run_backward(p, h, w, p->img, p->sens, EPI_STORE, nullptr, nullptr, st);
     if (rc)
         return rc;
+    const size_t nvox = (size_t)p->g.Nz * h * w;
+    hipLaunchKernelGGL(k_max_partial, dim3(kDotBlocks), dim3(256), 0, st, (const float *)p->sens,
+                       nvox, p->cmax);
+    LAUNCH_CHECK("k_max_partial");
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, st, (const float *)p->cmax, kDotBlocks,
+                       p->cmax + kDotBlocks, p->weak_count);
+    LAUNCH_CHECK("k_max_final");
+    float thr = kWeakThreshold;
+    unsigned found = 0;
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        if (attempt > 0) {
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, p->weak_count);
+            LAUNCH_CHECK("k_zero_u32");
+        }
+        hipLaunchKernelGGL(k_weak_select, dim3(2048), dim3(256), 0, st, (const float *)p->sens,
+                           nvox, (const float *)(p->cmax + kDotBlocks), thr, p->weak,
+                           p->weak_count, p->weak_cap);
+        LAUNCH_CHECK("k_weak_select");
+        HIP_TRY(hipMemcpyAsync(p->weak_count_host, p->weak_count, sizeof(unsigned),
+                               hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        found = *p->weak_count_host;
+        if (found <= p->weak_cap)
+            break;
+        thr *= 0.1f;
+    }
+    p->nweak = std::min(found, p->weak_cap);
+    if (p->nweak) {
+        hipLaunchKernelGGL(k_weak_exact, dim3(p->nweak), dim3(256), 0, st, (const unsigned *)p->weak,
+                           (const float *)p->psf, p->g.N, p->g.K, h, w, (const float *)nullptr,
+                           p->sens, (const float *)nullptr, (float *)nullptr, (int)WEAK_SENS);
+        LAUNCH_CHECK("k_weak_exact(sens)");
+    }
     p->sens_h = h;
     p->sens_w = w;
     return LFRL_OK;
@@ -1409,6 +1741,13 @@ extern "C" int lfrl_deconvolve(lfrl_plan_t p, int32_t h, int32_t w, const float 
         rc = run_backward(p, h, w, p->img, nxt, EPI_UPDATE, cur, p->sens, st);
         if (rc)
             return rc;
+        if (p->nweak) {
+            hipLaunchKernelGGL(k_weak_exact, dim3(p->nweak), dim3(256), 0, st,
+                               (const unsigned *)p->weak, (const float *)p->psf, p->g.N, p->g.K,
+                               h, w, (const float *)p->img, p->sens, (const float *)cur, nxt,
+                               (int)WEAK_UPDATE);
+            LAUNCH_CHECK("k_weak_exact(update)");
+        }
         iters = k;
         if (use_metric) {
             rc = run_metric(p->g.Nz, h, w, nxt, opts->xs, opts->ys, p->metric_out, p->T1, p->n2p,
@@ -1455,6 +1794,7 @@ extern "C" int lfrl_deconvolve(lfrl_plan_t p, int32_t h, int32_t w, const float 
         report->iters_run = iters;
         report->best_iter = best;
         report->stopped = stopped ? 1 : 0;
+        report->weak_voxels = (int32_t)p->nweak;
     }
     return LFRL_OK;
 }

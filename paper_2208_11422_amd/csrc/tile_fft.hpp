@@ -1,0 +1,360 @@
+// tile_fft.hpp - Q x Q tile DFTs as mixed-radix FFTs held in registers.
+//
+// One thread transforms one length-Q sequence (or two real sequences packed
+// as one complex one) entirely in registers.  Q is a template parameter, so
+// every radix stage is unrolled with compile-time indices; twiddles
+// exp(2 pi i m / Q) come from a Q-entry table read with uniform (scalar)
+// loads.  Stages follow the Stockham autosort ordering (each radix-R stage
+// multiplies by exp(-+2 pi i k r / (Ns R)) and writes its outputs Ns apart),
+// so no digit reversal is needed.  Tiles live in LDS between the row pass
+// and the column pass, exactly as in the direct-sum kernels they replace.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace tfft {
+
+template <int L>
+constexpr int radix_of()
+{
+    return (L % 4 == 0 && L != 8) ? 4 : (L % 2 == 0) ? 2 : (L % 3 == 0) ? 3 : (L % 5 == 0) ? 5
+                                                         : (L % 7 == 0) ? 7 : L;
+}
+
+// exp(SIGN * 2 pi i m / Q) from the table tw[m] = (cos, sin)(2 pi m / Q)
+template <int SIGN>
+__device__ __forceinline__ float2 twid(const float2 *__restrict__ tw, int m)
+{
+    const float2 t = tw[m];
+    return SIGN > 0 ? t : make_float2(t.x, -t.y);
+}
+
+__device__ __forceinline__ float2 cmulf(float2 a, float2 b)
+{
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+
+// In-place R-point DFT, natural order: v[p] <- sum_q v[q] exp(SIGN 2 pi i p q / R).
+template <int R, int SIGN, int Q>
+__device__ __forceinline__ void dft_small(float2 (&v)[R], const float2 *__restrict__ tw)
+{
+    if constexpr (R == 2) {
+        const float2 a = v[0], b = v[1];
+        v[0] = make_float2(a.x + b.x, a.y + b.y);
+        v[1] = make_float2(a.x - b.x, a.y - b.y);
+    } else if constexpr (R == 4) {
+        const float2 a = v[0], b = v[1], c = v[2], d = v[3];
+        const float2 s0 = make_float2(a.x + c.x, a.y + c.y), s1 = make_float2(a.x - c.x, a.y - c.y);
+        const float2 s2 = make_float2(b.x + d.x, b.y + d.y), s3 = make_float2(b.x - d.x, b.y - d.y);
+        // s3 * (SIGN i)
+        const float2 s3r = SIGN > 0 ? make_float2(-s3.y, s3.x) : make_float2(s3.y, -s3.x);
+        v[0] = make_float2(s0.x + s2.x, s0.y + s2.y);
+        v[2] = make_float2(s0.x - s2.x, s0.y - s2.y);
+        v[1] = make_float2(s1.x + s3r.x, s1.y + s3r.y);
+        v[3] = make_float2(s1.x - s3r.x, s1.y - s3r.y);
+    } else {
+        float2 o[R];
+#pragma unroll
+        for (int p = 0; p < R; ++p) {
+            float2 acc = v[0];
+#pragma unroll
+            for (int q = 1; q < R; ++q) {
+                const float2 w = twid<SIGN>(tw, ((p * q) % R) * (Q / R));
+                acc.x = fmaf(v[q].x, w.x, fmaf(-v[q].y, w.y, acc.x));
+                acc.y = fmaf(v[q].x, w.y, fmaf(v[q].y, w.x, acc.y));
+            }
+            o[p] = acc;
+        }
+#pragma unroll
+        for (int p = 0; p < R; ++p)
+            v[p] = o[p];
+    }
+}
+
+// One Stockham stage of radix R with span Ns: in -> out.
+template <int Q, int R, int Ns, int SIGN>
+__device__ __forceinline__ void stage(const float2 (&in)[Q], float2 (&out)[Q],
+                                      const float2 *__restrict__ tw)
+{
+#pragma unroll
+    for (int j = 0; j < Q / R; ++j) {
+        float2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            v[r] = in[j + r * (Q / R)];
+        const int k = j % Ns;
+        if (k != 0) {
+#pragma unroll
+            for (int r = 1; r < R; ++r)
+                v[r] = cmulf(v[r], twid<SIGN>(tw, (k * r * (Q / (Ns * R))) % Q));
+        }
+        dft_small<R, SIGN, Q>(v, tw);
+        const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            out[base + r * Ns] = v[r];
+    }
+}
+
+template <int Q, int Ns, int SIGN>
+__device__ __forceinline__ void stages(float2 (&a)[Q], float2 (&b)[Q], const float2 *__restrict__ tw)
+{
+    if constexpr (Ns < Q) {
+        constexpr int R = radix_of<Q / Ns>();
+        stage<Q, R, Ns, SIGN>(a, b, tw);
+        stages<Q, Ns * R, SIGN>(b, a, tw);
+    }
+}
+
+template <int Q, int Ns>
+constexpr int stage_count()
+{
+    if constexpr (Ns < Q)
+        return 1 + stage_count<Q, Ns * radix_of<Q / Ns>()>();
+    else
+        return 0;
+}
+
+// v <- sum_m v[m] exp(SIGN 2 pi i k m / Q)  (unnormalised)
+template <int Q, int SIGN>
+__device__ __forceinline__ void fft(float2 (&v)[Q], const float2 *__restrict__ tw)
+{
+    float2 t[Q];
+    stages<Q, 1, SIGN>(v, t, tw);
+    if constexpr (stage_count<Q, 1>() % 2 == 1) {
+#pragma unroll
+        for (int m = 0; m < Q; ++m)
+            v[m] = t[m];
+    }
+}
+
+}  // namespace tfft
+
+enum { SRC_PLANES = 0, SRC_PSF = 1 };
+
+// Forward real tile DFT of N interleaved phases, written as a half spectrum:
+// out[obase + k * kstride + p], k = ku * (Q/2 + 1) + kv.
+//   SRC_PLANES: one overlap-save tile of lenslet rows (plane j, row phase ar)
+//               of a [planes][H][W] array; blockIdx = (tile, j*N + ar).
+//               obase = (tile * KKo + j*N*N + ar*N), kstride = nt * KKo.
+//   SRC_PSF:    the polyphase kernels G_{j,a->c}[D] = h[j][a][N*D + c - a + c0]
+//               for output row phase cr and all column phases, placed
+//               circularly in the tile; blockIdx = (cr, a, j).
+//               obase = ((j*N*N + a) * N*N + cr*N), kstride = KK * N*N.
+template <int Q>
+__global__ __launch_bounds__(512) void k_r2c_fft(int mode, const float *__restrict__ src, int H,
+                                                  int W, int N, int T, int hD, int tiles_x, int nt,
+                                                  int KKo, int K, int c0, int KK,
+                                                  float2 *__restrict__ out,
+                                                  const float2 *__restrict__ twg)
+{
+    constexpr int QH = Q / 2 + 1;
+    extern __shared__ float smem[];
+    float2 *tw = reinterpret_cast<float2 *>(smem);
+    float *buf = smem + 2 * Q;
+    float2 *Z = reinterpret_cast<float2 *>(buf);
+    const int tid = threadIdx.x;
+    for (int i = tid; i < Q; i += blockDim.x)
+        tw[i] = twg[i];
+    const int rowlen = Q * N;
+    size_t obase, kstride;
+    if (mode == SRC_PLANES) {
+        const int tile = blockIdx.x;
+        const int j = blockIdx.y / N, ar = blockIdx.y % N;
+        const int ly0 = (tile / tiles_x) * T - hD, lx0 = (tile % tiles_x) * T - hD;
+        const float *plane = src + (size_t)j * H * W;
+        for (int idx = tid; idx < Q * rowlen; idx += blockDim.x) {
+            const int i = idx / rowlen, col = idx % rowlen;
+            const int pr = N * (ly0 + i) + ar;
+            const int pc = N * lx0 + col;
+            float v = 0.f;
+            if (pr >= 0 && pr < H && pc >= 0 && pc < W)
+                v = plane[(size_t)pr * W + pc];
+            buf[idx] = v;
+        }
+        obase = (size_t)tile * KKo + (size_t)j * N * N + (size_t)ar * N;
+        kstride = (size_t)nt * KKo;
+    } else {
+        const int cr = blockIdx.x, a = blockIdx.y, j = blockIdx.z;
+        const int ar = a / N, ac = a % N;
+        const float *hk = src + (((size_t)j * N + ar) * N + ac) * (size_t)K * K;
+        for (int idx = tid; idx < Q * rowlen; idx += blockDim.x) {
+            const int i = idx / rowlen, col = idx % rowlen;
+            const int l = col / N, cc = col % N;
+            const int Dr = (i <= hD) ? i : ((i >= Q - hD) ? i - Q : INT32_MIN);
+            const int Dc = (l <= hD) ? l : ((l >= Q - hD) ? l - Q : INT32_MIN);
+            float v = 0.f;
+            if (Dr != INT32_MIN && Dc != INT32_MIN) {
+                const int u = N * Dr + cr - ar + c0;
+                const int vv = N * Dc + cc - ac + c0;
+                if (u >= 0 && u < K && vv >= 0 && vv < K)
+                    v = hk[(size_t)u * K + vv];
+            }
+            buf[idx] = v;
+        }
+        const size_t NN = (size_t)N * N;
+        obase = ((size_t)j * NN + a) * NN + (size_t)cr * N;
+        kstride = (size_t)KK * NN;
+    }
+    __syncthreads();
+    // row pass: two real rows per thread packed as one complex sequence
+    const int nseq = Q * N;
+    const int npairs = (nseq + 1) / 2;
+    float2 v[Q];
+    int s0 = -1, s1 = -1;
+    if (tid < npairs) {
+        s0 = 2 * tid;
+        s1 = (2 * tid + 1 < nseq) ? 2 * tid + 1 : -1;
+        const int i0 = s0 / N, p0 = s0 % N;
+        const int i1 = s1 >= 0 ? s1 / N : 0, p1 = s1 >= 0 ? s1 % N : 0;
+#pragma unroll
+        for (int l = 0; l < Q; ++l) {
+            const float a = buf[(size_t)i0 * rowlen + l * N + p0];
+            const float b = s1 >= 0 ? buf[(size_t)i1 * rowlen + l * N + p1] : 0.f;
+            v[l] = make_float2(a, b);
+        }
+    }
+    __syncthreads();  // every row is in registers: Z may now overwrite buf
+    if (tid < npairs) {
+        tfft::fft<Q, -1>(v, tw);
+        const int i0 = s0 / N, p0 = s0 % N;
+#pragma unroll
+        for (int k = 0; k < QH; ++k) {
+            const float2 zk = v[k], zm = v[(Q - k) % Q];
+            // A = (Z[k] + conj(Z[-k])) / 2,  B = (Z[k] - conj(Z[-k])) / (2i)
+            Z[((size_t)i0 * QH + k) * N + p0] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+            if (s1 >= 0) {
+                const int i1 = s1 / N, p1 = s1 % N;
+                Z[((size_t)i1 * QH + k) * N + p1] =
+                    make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+            }
+        }
+    }
+    __syncthreads();
+    // column pass: one complex column (kv, p) per thread
+    if (tid < QH * N) {
+        const int kv = tid / N, p = tid % N;
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            v[i] = Z[((size_t)i * QH + kv) * N + p];
+        tfft::fft<Q, -1>(v, tw);
+#pragma unroll
+        for (int ku = 0; ku < Q; ++ku)
+            out[obase + (size_t)(ku * QH + kv) * kstride + p] = v[ku];
+    }
+}
+
+// Inverse tile DFT of N interleaved phases with the crop to the T x T valid
+// lenslets and the per-pixel epilogue (see k_c2r for the modes).  The spectrum
+// is sum_s spec[s * split_stride + (k * nt + tile) * KKo + j*N*N + ar*N + p].
+template <int Q>
+__global__ __launch_bounds__(512) void k_c2r_fft(const float2 *__restrict__ spec,
+                                                  size_t split_stride, int nsplit, int KKo, int N,
+                                                  int T, int hD, int tiles_x, int nt, int H, int W,
+                                                  int mode, float *__restrict__ dst,
+                                                  const float *__restrict__ aux0,
+                                                  const float *__restrict__ aux1,
+                                                  const float2 *__restrict__ twg)
+{
+    constexpr int QH = Q / 2 + 1;
+    extern __shared__ float smem[];
+    float2 *tw = reinterpret_cast<float2 *>(smem);
+    float2 *X = tw + Q;
+    float2 *Zs = X + (size_t)Q * QH * N;
+    float *obuf = reinterpret_cast<float *>(X);  // reused once X is consumed
+    const int tid = threadIdx.x;
+    const int tile = blockIdx.x;
+    const int j = blockIdx.y / N, ar = blockIdx.y % N;
+    const int ty = tile / tiles_x, tx = tile % tiles_x;
+    for (int i = tid; i < Q; i += blockDim.x)
+        tw[i] = twg[i];
+    const size_t kkbase = (size_t)j * N * N + (size_t)ar * N;
+    const int total = Q * QH * N;
+    for (int idx = tid; idx < total; idx += blockDim.x) {
+        const int p = idx % N;
+        const size_t k = idx / N;
+        const size_t off = (k * nt + tile) * KKo + kkbase + p;
+        float2 acc = spec[off];
+        for (int s = 1; s < nsplit; ++s) {
+            const float2 v = spec[off + s * split_stride];
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+        X[idx] = acc;
+    }
+    __syncthreads();
+    float2 v[Q];
+    // inverse along tile rows (ku -> i), keeping the T valid rows
+    if (tid < QH * N) {
+        const int kv = tid / N, p = tid % N;
+#pragma unroll
+        for (int ku = 0; ku < Q; ++ku)
+            v[ku] = X[((size_t)ku * QH + kv) * N + p];
+        tfft::fft<Q, 1>(v, tw);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int ti = i - hD;
+            if (ti >= 0 && ti < T)
+                Zs[((size_t)ti * QH + kv) * N + p] = v[i];
+        }
+    }
+    __syncthreads();
+    // inverse real transform along tile columns: two Hermitian rows per thread
+    const int nrow = T * N;
+    const int npairs = (nrow + 1) / 2;
+    const float scale = 1.0f / (float)(Q * Q);
+    if (tid < npairs) {
+        const int r0 = 2 * tid, r1 = (2 * tid + 1 < nrow) ? 2 * tid + 1 : -1;
+        const int ti0 = r0 / N, p0 = r0 % N;
+        const int ti1 = r1 >= 0 ? r1 / N : 0, p1 = r1 >= 0 ? r1 % N : 0;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            const bool lo = k < QH;
+            const int kk = lo ? k : Q - k;
+            float2 a = Zs[((size_t)ti0 * QH + kk) * N + p0];
+            float2 b = r1 >= 0 ? Zs[((size_t)ti1 * QH + kk) * N + p1] : make_float2(0.f, 0.f);
+            if (k == 0 || 2 * k == Q) {
+                a.y = 0.f;
+                b.y = 0.f;
+            }
+            if (!lo) {
+                a.y = -a.y;
+                b.y = -b.y;
+            }
+            // a + i b
+            v[k] = make_float2(a.x - b.y, a.y + b.x);
+        }
+        tfft::fft<Q, 1>(v, tw);
+#pragma unroll
+        for (int l = 0; l < Q; ++l) {
+            const int tl = l - hD;
+            if (tl >= 0 && tl < T) {
+                obuf[((size_t)ti0 * T + tl) * N + p0] = v[l].x * scale;
+                if (r1 >= 0)
+                    obuf[((size_t)ti1 * T + tl) * N + p1] = v[l].y * scale;
+            }
+        }
+    }
+    __syncthreads();
+    // coalesced epilogue over whole pixel rows of the tile
+    const int Ly = H / N, Lx = W / N;
+    const int rowpix = T * N;
+    for (int idx = tid; idx < T * rowpix; idx += blockDim.x) {
+        const int ti = idx / rowpix, rem = idx % rowpix;
+        const int Lr = ty * T + ti, Lc = tx * T + rem / N;
+        if (Lr >= Ly || Lc >= Lx)
+            continue;
+        const float val = obuf[idx];
+        const int pr = N * Lr + ar, pc = N * tx * T + rem;
+        const size_t pix = (size_t)pr * W + pc;
+        if (mode == 0) {
+            dst[(size_t)j * H * W + pix] = val;
+        } else if (mode == 1) {
+            dst[pix] = val > 0.f ? aux0[pix] / val : 0.f;
+        } else {
+            const size_t o = (size_t)j * H * W + pix;
+            const float c = aux1[o];
+            dst[o] = c > 0.f ? aux0[o] * val / c : 0.f;
+        }
+    }
+}

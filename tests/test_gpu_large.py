@@ -1,0 +1,150 @@
+"""Full-size parity at the benchmark workload (needs an MI355X).
+
+Nnum 15, 40 x 40 lenslets (600 x 600), 31 planes, 255 x 255 PSF, with the
+plan built exactly as bench.py builds it.  The oracle cannot run whole
+iterations at this size, so it is compared on sampled outputs it computes one
+by one (forward at random and border pixels, back projection at random and
+border voxels), and whole RL runs are checked through invariants that hold at
+any size (flux, non-negativity, likelihood ascent, determinism)."""
+import numpy as np
+import pytest
+
+import lfrl_synth as S
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+CACHE = "/tmp/lfrl_synth_cache"
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2208_11422_amd as lf
+    p = S.preset("large", cache_dir=CACHE)
+    g = p["geometry"]
+    dev = torch.device("cuda:0")
+    print(f"large workload: N={g.nnum} {g.h}x{g.w} nz={g.nz} K={g.ksize}", flush=True)
+    plan = lf.Plan(torch.from_numpy(p["psf_array"]).to(dev), g.h, g.w)
+    print(f"plan: {plan.info}", flush=True)
+    yield lf, p, plan, dev
+    plan.close()
+
+
+def sample_pixels(h, w, n, seed):
+    rng = np.random.default_rng(seed)
+    rr = np.concatenate([rng.integers(0, h, n), [0, 0, h - 1, h - 1, 7, h - 8]])
+    cc = np.concatenate([rng.integers(0, w, n), [0, w - 1, 0, w - 1, w - 9, 3]])
+    return rr, cc
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_forward_sampled(setup):
+    import torch
+    lf, p, plan, dev = setup
+    g = p["geometry"]
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0.0, 1.0, size=(g.nz, g.h, g.w)).astype(np.float32)
+    img = plan.forward(torch.from_numpy(x).to(dev)).cpu().numpy()
+    rr, cc = sample_pixels(g.h, g.w, 150, 6)
+    want = oracle.forward_at(p["psf_array"], x, rr, cc)
+    err = rel_l2(img[rr, cc], want)
+    print(f"forward sampled rel L2 {err:.2e}", flush=True)
+    assert err <= TOL
+
+
+def test_backward_sampled(setup):
+    import torch
+    lf, p, plan, dev = setup
+    g = p["geometry"]
+    y = np.random.default_rng(7).uniform(10.0, 2000.0, size=(g.h, g.w)).astype(np.float32)
+    vol = plan.backward(torch.from_numpy(y).to(dev)).cpu().numpy()
+    rng = np.random.default_rng(8)
+    rr, cc = sample_pixels(g.h, g.w, 1500, 9)
+    jj = rng.integers(0, g.nz, rr.size)
+    jj[-6:] = [0, g.nz - 1, 0, g.nz - 1, g.nz // 2, 1]
+    want = oracle.backward_at(p["psf_array"], y, jj, rr, cc)
+    err = rel_l2(vol[jj, rr, cc], want)
+    print(f"backward sampled rel L2 {err:.2e}", flush=True)
+    assert err <= TOL
+
+
+def test_rl_invariants_full_size(setup):
+    """Two bench-configuration RL runs on oracle-projected data: flux matches
+    sum(y) to float32 accuracy, volumes are non-negative, the Poisson
+    log-likelihood rises, and repeated runs are bitwise identical."""
+    import torch
+    lf, p, plan, dev = setup
+    g = p["geometry"]
+    clean = oracle.forward(p["psf_array"], p["x_true"])       # sparse volume: fast scatter
+    y = S.measure(clean, p["peak"], p["background"], p["noise_seed"])
+    y_d = torch.from_numpy(y).to(dev)
+    xs = ys = g.w / (g.nnum * 2.0 * p["spot_radius"])
+    lls = []
+    for k in (1, 2, 4):
+        vol, rep = plan.deconvolve(y_d, k, stop=lf.STOP_TRACK, xs=xs, ys=ys, want_flux=True)
+        assert max(abs(f) for f in rep["flux_trace"]) <= 1e-5
+        assert float(vol.min()) >= -1e-6 * float(vol.max())
+        assert rep["weak_voxels"] > 0
+        tr = rep["metric_trace"]
+        assert all(np.isfinite(tr))
+        # the tracked best iterate is the argmax of the trace (ties -> later)
+        best = max(range(len(tr)), key=lambda i: (tr[i], i)) + 1
+        assert rep["best_iter"] == best
+        vol_k, _ = plan.deconvolve(y_d, k, stop=lf.STOP_NONE)
+        yhat = plan.forward(vol_k).double().cpu().numpy()
+        lls.append(oracle.poisson_loglik(y, yhat))
+    assert lls[0] < lls[1] < lls[2]
+    a, _ = plan.deconvolve(y_d, 2, stop=lf.STOP_TRACK, xs=xs, ys=ys)
+    a = a.clone()
+    b, _ = plan.deconvolve(y_d, 2, stop=lf.STOP_TRACK, xs=xs, ys=ys)
+    assert torch.equal(a, b)
+
+
+def test_first_iterate_sampled(setup):
+    """x^1 = A^T(y / A 1) / A^T 1 at sampled voxels.  A 1 is needed over each
+    sampled voxel's whole PSF footprint, so the oracle evaluates it at every
+    pixel of a small window and the voxels are drawn where their footprint
+    lies inside that window: a PSF set cropped to a 31 x 31 support around the
+    centre keeps this cheap while using the bench plan's DFT tile size."""
+    import torch
+    lf, p, plan, dev = setup
+    g = p["geometry"]
+    k = 31
+    c0, h0 = (g.ksize - 1) // 2, (k - 1) // 2
+    psf = np.ascontiguousarray(p["psf_array"][:, :, :, c0 - h0:c0 + h0 + 1, c0 - h0:c0 + h0 + 1])
+    small = lf.Plan(torch.from_numpy(psf).to(dev), g.h, g.w, tile_q=plan.info["tile_q"])
+    try:
+        y = np.random.default_rng(3).uniform(10.0, 2000.0, size=(g.h, g.w)).astype(np.float32)
+        vol, _ = small.deconvolve(torch.from_numpy(y).to(dev), 1, stop=lf.STOP_NONE)
+        vol = vol.cpu().numpy()
+    finally:
+        small.close()
+    # window of pixels where A 1 is needed: voxels in rows/cols [r0, r1) need
+    # pixels [r0 - h0, r1 + h0)
+    r0, r1, s0, s1 = 280, 296, 140, 156
+    pr = np.arange(r0 - h0, r1 + h0)
+    pc = np.arange(s0 - h0, s1 + h0)
+    grid_r, grid_c = np.meshgrid(pr, pc, indexing="ij")
+    ones = np.ones((g.nz, g.h, g.w))
+    a1 = oracle.forward_at(psf, ones, grid_r.ravel(), grid_c.ravel()).reshape(grid_r.shape)
+    ratio = np.zeros((g.h, g.w))
+    ratio[r0 - h0:r1 + h0, s0 - h0:s1 + h0] = y[r0 - h0:r1 + h0, s0 - h0:s1 + h0] / a1
+    rng = np.random.default_rng(4)
+    n = 300
+    jj = rng.integers(0, g.nz, n)
+    rr = rng.integers(r0, r1, n)
+    ss = rng.integers(s0, s1, n)
+    b = oracle.backward_at(psf, ratio, jj, rr, ss)
+    c = oracle.backward_at(psf, np.ones((g.h, g.w)), jj, rr, ss)
+    want = b / c
+    err = rel_l2(vol[jj, rr, ss], want)
+    print(f"first iterate sampled rel L2 {err:.2e}", flush=True)
+    assert err <= TOL
