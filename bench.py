@@ -122,6 +122,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--tile-q", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-split", action="store_true",
+                    help="skip the split-FP16 measurement")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one 1 GiB device-to-device copy (reference kernel of known "
+                         "size for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the z-sharded "
@@ -138,6 +143,12 @@ def main() -> int:
     import paper_2208_11422_amd as lf
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t_setup = time.perf_counter()
     p = S.preset("large", cache_dir=CACHE)
     g = p["geometry"]
@@ -229,6 +240,39 @@ def main() -> int:
         },
         "kernels": kern,
     }
+    if not args.no_split:
+        vol32 = vol.clone()
+        plan.close()
+        torch.cuda.empty_cache()
+        psf_d = torch.from_numpy(p["psf_array"]).to(dev)
+        plan16 = lf.Plan(psf_d, h, w, tile_q=args.tile_q, precision=lf.SPLIT_FP16)
+        del psf_d
+        torch.cuda.synchronize()
+        opts16 = lf.RlOpts(max_iters=args.warmup if args.warmup > 0 else 1, stop=lf.STOP_TRACK,
+                           patience=1, init=0, xs=xs, ys=ys)
+        lf.lfrl_deconvolve(plan16.handle, h, w, y_d, vol, opts16)
+        lf.lfrl_profile_enable(plan16.handle, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        opts16.max_iters = args.steps
+        lf.lfrl_deconvolve(plan16.handle, h, w, y_d, vol, opts16)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof16 = {k: lf.lfrl_profile_read(plan16.handle, k)
+                  for k in ("contract_fwd", "contract_adj")}
+        ms16 = (t1 - t0) * 1000.0 / args.steps
+        diff = float(torch.linalg.vector_norm(vol - vol32) / torch.linalg.vector_norm(vol32))
+        out["split_fp16"] = {
+            "value": 1000.0 / ms16, "unit": "iters/s", "ms_per_step": ms16,
+            "dtype": "f16 spectra, hi/lo f16 tile spectra, f32 accumulate",
+            "rel_l2_vs_fp32_after_steps": diff,
+            "speedup_vs_fp32": ms_per_step / ms16,
+            "kernels": {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]}
+                        for k, v in prof16.items()},
+        }
+        log(f"bench: split FP16 {ms16:.3f} ms/iter ({1000.0 / ms16:.1f} it/s), "
+            f"rel L2 vs FP32 {diff:.2e}")
+        plan = plan16
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle, bounded sample)")
         # oracle inputs come from the generators, never from the GPU path; the

@@ -50,7 +50,13 @@ typedef enum {
 } lfrl_status;
 
 typedef enum {
-    LFRL_FP32 = 0               /* spectra, DFTs and contraction in float32 */
+    LFRL_FP32 = 0,        /* spectra, tile DFTs and contractions in float32 */
+    LFRL_SPLIT_FP16 = 1   /* PSF spectra stored in FP16 (per-frequency power-of-two
+                             scale; half the bytes streamed per projection); tile
+                             spectra split into hi + lo FP16 parts, products on
+                             FP16 matrix cores with FP32 accumulation; tile DFTs,
+                             ratio and update in float32.  Relative error of a
+                             projection about 1e-4 instead of 1e-7. */
 } lfrl_precision;
 
 /* Plan description.  Geometry of the PSF set and the largest image the plan

@@ -22,13 +22,13 @@ __all__ = [
     "lfrl_plan_footprint", "lfrl_plan", "lfrl_plan_destroy", "lfrl_plan_get_info",
     "lfrl_forward", "lfrl_backward", "lfrl_deconvolve", "lfrl_metric",
     "lfrl_metric_cutoff", "lfrl_profile_enable", "lfrl_profile_read", "lfrl_last_error",
-    "Plan", "library_path", "STOP_NONE", "STOP_METRIC", "STOP_TRACK", "FP32",
+    "Plan", "library_path", "STOP_NONE", "STOP_METRIC", "STOP_TRACK", "FP32", "SPLIT_FP16",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liblfrl.so")
 
-FP32 = 0
+FP32, SPLIT_FP16 = 0, 1
 STOP_NONE, STOP_METRIC, STOP_TRACK = 0, 1, 2
 
 _STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_NOMEM", -3: "ERR_DEVICE",
@@ -231,12 +231,12 @@ class Plan:
     """Resident PSF spectra for one PSF set, serving images up to max_h x max_w."""
 
     def __init__(self, psf: torch.Tensor, max_h: int, max_w: int, tile_q: int = 0,
-                 stream=None):
+                 precision: int = FP32, stream=None):
         nz, n, n2, k, k2 = psf.shape
         if n != n2 or k != k2:
             raise LfrlError(-1, "psf must be [nz][N][N][K][K]")
         self.desc = PlanDesc(nnum=n, nz=nz, ksize=k, max_h=max_h, max_w=max_w,
-                             precision=FP32, tile_q=tile_q, flags=0)
+                             precision=precision, tile_q=tile_q, flags=0)
         self.nnum, self.nz, self.ksize = n, nz, k
         self.device = psf.device
         self.handle = lfrl_plan(self.desc, psf, stream)

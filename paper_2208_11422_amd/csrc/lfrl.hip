@@ -19,7 +19,7 @@
 // Pipeline of one Richardson-Lucy iteration (sec. 1 / sec. 2.1, all on device):
 //   k_vol_r2c(x) -> k_contract_fwd -> k_c2r[ratio: rho = y / (A x)]
 //   k_vol_r2c(rho) -> k_contract_adj -> k_c2r[update: x *= A^T rho / A^T 1]
-//   metric (sec. 2.2): k_metric_partial -> k_metric_colsum -> k_metric_coeffs
+//   metric (sec. 2.2): k_mip -> k_dct_rows -> k_metric_coeffs
 //                      -> k_metric_final (entropy + stop rule) -> k_cond_copy
 #include <hip/hip_runtime.h>
 
@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -71,8 +72,7 @@ static int set_error(int code, const char *fmt, ...)
 static constexpr int kMaxQ = 64;        // DFT tile side
 static constexpr int kMaxNN = 256;      // nnum^2 (one thread per output phase)
 static constexpr int kMaxTrace = 4096;  // iterations recorded per deconvolve call
-static constexpr int kMetricChunks = 32;
-static constexpr int kMetricVBlock = 16;
+static constexpr int kMetricChunks = 8;   // row chunks of the DCT row transform
 static constexpr int kMaxMetricLegs = 256;
 static constexpr float kWeakThreshold = 1e-2f;  // weak voxel: A^T 1 < this * max A^T 1
 
@@ -80,7 +80,7 @@ static constexpr float kWeakThreshold = 1e-2f;  // weak voxel: A^T 1 < this * ma
 // geometry
 // ---------------------------------------------------------------------------
 struct Geo {
-    int N, Nz, K, c0, hD, R, Q, QH, T, nf, NN, KK;
+    int N, Nz, K, c0, hD, R, Q, QH, T, nf, NN, NNp, KK, KKs;
 };
 
 static void geo_init(Geo &g, int N, int Nz, int K, int Q)
@@ -96,7 +96,9 @@ static void geo_init(Geo &g, int N, int Nz, int K, int Q)
     g.T = Q - g.R + 1;
     g.nf = Q * g.QH;
     g.NN = N * N;
+    g.NNp = (g.NN + 15) / 16 * 16;  // forward spectra row stride (aligned 16-column blocks)
     g.KK = g.NN * Nz;
+    g.KKs = (g.KK + 31) / 32 * 32;  // row stride of the volume tile spectra
 }
 
 struct Tiles {
@@ -127,13 +129,6 @@ static size_t lds_c2r(const Geo &g)
     return (size_t)g.Q * g.QH * g.N * 8 + (size_t)g.T * g.QH * g.N * 8 + (size_t)g.Q * 8;
 }
 
-static int nt_template(int nt)
-{
-    int v = 1;
-    while (v < nt && v < 32)
-        v <<= 1;
-    return v;
-}
 
 // ---------------------------------------------------------------------------
 // device helpers
@@ -177,9 +172,9 @@ __device__ __forceinline__ void dft_rows_r2c(const float *in, float2 *Z, const f
 // Polyphase kernels of one (plane j, source phase a) for one output row phase
 // cr, all output column phases cc: the R x R taps G[D] = h[j][a][N*D + c - a + c0]
 // placed circularly (D mod Q) in a Q x Q tile, transformed, and written as
-// Gf[k][kk][c] with kk = j*N*N + a, c = cr*N + cc.
+// Gf[k][kk][c] with kk = j*N*N + a, c = cr*N + cc (rows of NNp >= N*N entries).
 __global__ void k_psf_r2c(const float *__restrict__ psf, int N, int K, int c0, int hD, int Q,
-                          int QH, int KK, int NN, float2 *__restrict__ Gf,
+                          int QH, int KK, int NNp, float2 *__restrict__ Gf,
                           const float2 *__restrict__ twg)
 {
     extern __shared__ float smem[];
@@ -213,7 +208,7 @@ __global__ void k_psf_r2c(const float *__restrict__ psf, int N, int K, int c0, i
     __syncthreads();
     dft_rows_r2c(in, Z, tw, Q, QH, N);
     __syncthreads();
-    const size_t kk = (size_t)j * NN + a;
+    const size_t kk = (size_t)j * N * N + a;
     const int total = Q * QH * N;
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
         const int p = idx % N;
@@ -231,23 +226,24 @@ __global__ void k_psf_r2c(const float *__restrict__ psf, int N, int K, int c0, i
                 m -= Q;
         }
         const size_t k = (size_t)ku * QH + kv;
-        Gf[(k * KK + kk) * NN + (size_t)cr * N + p] = make_float2(re, im);
+        Gf[(k * KK + kk) * NNp + (size_t)cr * N + p] = make_float2(re, im);
     }
 }
 
-// Gb[k][c][kk] = Gf[k][kk][c]: per-frequency transpose through LDS.
+// Gb[k][c][kk] = Gf[k][kk][c]: per-frequency transpose through LDS (Gf rows
+// hold NNp entries, Gb rows KK).
 __global__ void k_transpose_spec(const float2 *__restrict__ Gf, float2 *__restrict__ Gb,
-                                 int KK, int NN)
+                                 int KK, int NN, int NNp)
 {
     __shared__ float2 tile[32][33];
     const size_t k = blockIdx.z;
     const int c0 = blockIdx.x * 32, kk0 = blockIdx.y * 32;
-    const float2 *src = Gf + k * (size_t)KK * NN;
+    const float2 *src = Gf + k * (size_t)KK * NNp;
     float2 *dst = Gb + k * (size_t)KK * NN;
     for (int r = threadIdx.y; r < 32; r += 8) {
         const int kk = kk0 + r, c = c0 + threadIdx.x;
         if (kk < KK && c < NN)
-            tile[r][threadIdx.x] = src[(size_t)kk * NN + c];
+            tile[r][threadIdx.x] = src[(size_t)kk * NNp + c];
     }
     __syncthreads();
     for (int r = threadIdx.y; r < 32; r += 8) {
@@ -320,14 +316,16 @@ __global__ void k_vol_r2c(const float *__restrict__ src, int H, int W, int N, in
 enum { EPI_STORE = 0, EPI_RATIO = 1, EPI_UPDATE = 2 };
 
 // Inverse tile DFT and scatter of the valid T x T lenslets of one tile for
-// plane j and row phase ar (all N column phases).  The spectrum is
-// sum_s spec[s*split_stride + (k*nt + tile)*KKo + kkbase + p] (split-K partials).
+// plane j and row phase ar (all N column phases).  The spectrum of column
+// index q = j*N*N + ar*N + p at frequency k is
+// sum_s spec[s*split_stride + k*sk + tile*stile + q*sc] (split-K partials).
 // Epilogues:  STORE  dst[j][pr][pc] = v
 //             RATIO  dst[pr][pc] = v > 0 ? aux0[pr][pc] / v : 0   (rho = y / A x)
 //             UPDATE dst[j][pr][pc] = aux1 > 0 ? aux0 * v / aux1 : 0
 //                    (x_new = x_old * A^T rho / A^T 1)
-__global__ void k_c2r(const float2 *__restrict__ spec, size_t split_stride, int nsplit, int KKo,
-                      int N, int Q, int QH, int T, int hD, int tiles_x, int nt, int H, int W,
+__global__ void k_c2r(const float2 *__restrict__ spec, size_t split_stride, int nsplit, size_t sk,
+                      size_t stile, size_t sc, int N, int Q, int QH, int T, int hD, int tiles_x,
+                      int H, int W,
                       int mode, float *__restrict__ dst, const float *__restrict__ aux0,
                       const float *__restrict__ aux1, const float2 *__restrict__ twg)
 {
@@ -345,7 +343,7 @@ __global__ void k_c2r(const float2 *__restrict__ spec, size_t split_stride, int 
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
         const int p = idx % N;
         const size_t k = idx / N;
-        const size_t off = (k * nt + tile) * KKo + kkbase + p;
+        const size_t off = k * sk + tile * stile + (kkbase + p) * sc;
         float2 acc = spec[off];
         for (int s = 1; s < nsplit; ++s) {
             const float2 v = spec[off + s * split_stride];
@@ -414,114 +412,208 @@ __global__ void k_c2r(const float2 *__restrict__ spec, size_t split_stride, int 
     }
 }
 
-// Forward spectral contraction, one frequency k per block row:
-//   Yp[s][k][t][c] = sum_{kk in chunk s} Gf[k][kk][c] * X[k][t][kk]
-// One thread per output phase c keeps NT tile accumulators; the X chunk is
-// staged in LDS and read as a broadcast; Gf is streamed once, unit stride in c.
-template <int NT>
-__global__ __launch_bounds__(256) void k_contract_fwd(const float2 *__restrict__ Gf,
-                                                      const float2 *__restrict__ X,
-                                                      float2 *__restrict__ Yp, int NN, int KK,
-                                                      int nt, int nf, int kchunk)
+// ---------------------------------------------------------------------------
+// spectral contractions on FP32 matrix cores
+// ---------------------------------------------------------------------------
+// Each complex product is four real v_mfma_f32_16x16x4f32 products (full FP32
+// inputs, FP32 accumulation).  Fragment layouts of that instruction (wave64):
+//   A (16 x 4):  lane l holds A[l % 16][l / 16]
+//   B (4 x 16):  lane l holds B[l / 16][l % 16]
+//   D (16 x 16): lane l holds D[4 * (l / 16) + i][l % 16] in element i.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c)
 {
-    constexpr int KB = 64;
-    __shared__ float2 xs[KB][NT];
-    const int k = blockIdx.x, s = blockIdx.y, t0 = blockIdx.z * NT;
-    const int c = threadIdx.x;
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+#include "contract_f16.hpp"
+
+// Forward contraction for one frequency k and one reduction chunk s, computed
+// transposed so that tiles are the MFMA rows:
+//   Yp[s][k][t][c] = sum_{kk in chunk} X[k][t][kk] * Gf[k][kk][c]
+// A = X (16 tiles x 4 kk, loaded straight from HBM), B = Gf (4 kk x 16 c per
+// block of c, CB blocks per wave).  Gf rows are padded to NNp (a multiple of
+// 16, zero filled) so each 16-column block is one aligned 128-byte line that
+// no other wave touches.  Register groups of U steps are double-buffered: the
+// loads of group g+1 are in flight while group g runs on the matrix cores.
+// Every load is unconditional (clamped index; kk past the chunk end is zeroed
+// in X by a multiply); outputs for t >= nt or c >= NN are simply not stored.
+template <int CB, int U>
+__global__ __launch_bounds__(512) void k_contract_fwd(const float2 *__restrict__ Gf,
+                                                      const float2 *__restrict__ X,
+                                                      float2 *__restrict__ Yp, int NN, int NNp,
+                                                      int KK, int KKs, int nt, int nf, int kchunk)
+{
+    const int k = blockIdx.x, s = blockIdx.y, t0 = blockIdx.z * 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
     const int kb0 = s * kchunk;
     const int kb1 = min(KK, kb0 + kchunk);
-    float2 acc[NT];
+    const int nsteps = (kb1 - kb0 + 3) / 4;
+    const int ngroups = (nsteps + U - 1) / U;
+    const int t = t0 + col;
+    const float2 *xrow = X + ((size_t)k * nt + min(t, nt - 1)) * KKs;
+    const float2 *gk = Gf + (size_t)k * KK * NNp;
+    int cidx[CB];
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
-        acc[t] = make_float2(0.f, 0.f);
-    const float2 *g = Gf + (size_t)k * KK * NN + c;
-    const float2 *xk = X + (size_t)k * nt * KK;
-    for (int kb = kb0; kb < kb1; kb += KB) {
-        const int cnt = min(KB, kb1 - kb);
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < KB * NT; idx += blockDim.x) {
-            const int t = idx / KB, q = idx % KB;
-            float2 v = make_float2(0.f, 0.f);
-            if (q < cnt && t0 + t < nt)
-                v = xk[(size_t)(t0 + t) * KK + kb + q];
-            xs[q][t] = v;
+    for (int b = 0; b < CB; ++b)
+        cidx[b] = min(16 * (wave * CB + b) + col, NNp - 1);
+    f32x4 accr[CB], acci[CB];
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+        accr[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        acci[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    float2 xa0[U], xa1[U], gb0[U][CB], gb1[U][CB];
+    auto load_group = [&](int grp, float2(&xa)[U], float2(&gb)[U][CB]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int kk = kb0 + 4 * (grp * U + u) + kq;
+            const float m = kk < kb1 ? 1.f : 0.f;
+            const int kkc = min(kk, kb1 - 1);
+            const float2 xv = xrow[kkc];
+            xa[u] = make_float2(xv.x * m, xv.y * m);
+#pragma unroll
+            for (int b = 0; b < CB; ++b)
+                gb[u][b] = gk[(size_t)kkc * NNp + cidx[b]];
         }
-        __syncthreads();
-        if (c < NN) {
-            if (cnt == KB) {
-#pragma unroll 16
-                for (int q = 0; q < KB; ++q) {
-                    const float2 gv = g[(size_t)(kb + q) * NN];
+    };
+    auto compute_group = [&](const float2(&xa)[U], const float2(&gb)[U][CB]) {
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) {
-                        const float2 xv = xs[q][t];
-                        acc[t].x = fmaf(gv.x, xv.x, fmaf(-gv.y, xv.y, acc[t].x));
-                        acc[t].y = fmaf(gv.x, xv.y, fmaf(gv.y, xv.x, acc[t].y));
-                    }
-                }
-            } else {
-                for (int q = 0; q < cnt; ++q) {
-                    const float2 gv = g[(size_t)(kb + q) * NN];
+        for (int u = 0; u < U; ++u) {
+            const float2 a = xa[u];
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) {
-                        const float2 xv = xs[q][t];
-                        acc[t].x = fmaf(gv.x, xv.x, fmaf(-gv.y, xv.y, acc[t].x));
-                        acc[t].y = fmaf(gv.x, xv.y, fmaf(gv.y, xv.x, acc[t].y));
-                    }
-                }
+            for (int b = 0; b < CB; ++b) {
+                const float2 g = gb[u][b];
+                accr[b] = mfma4(a.x, g.x, accr[b]);
+                accr[b] = mfma4(-a.y, g.y, accr[b]);
+                acci[b] = mfma4(a.x, g.y, acci[b]);
+                acci[b] = mfma4(a.y, g.x, acci[b]);
             }
         }
+    };
+    if (ngroups > 0)
+        load_group(0, xa0, gb0);
+    for (int grp = 0; grp < ngroups; grp += 2) {
+        if (grp + 1 < ngroups)
+            load_group(grp + 1, xa1, gb1);
+        compute_group(xa0, gb0);
+        if (grp + 1 < ngroups) {
+            if (grp + 2 < ngroups)
+                load_group(grp + 2, xa0, gb0);
+            compute_group(xa1, gb1);
+        }
     }
-    if (c < NN) {
+    // D[t][c]: lane holds tiles t0 + 4 * kq + i, column c of each block
+    float2 *yk = Yp + ((size_t)s * nf + k) * nt * NN;
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
-            if (t0 + t < nt)
-                Yp[(((size_t)s * nf + k) * nt + t0 + t) * NN + c] = acc[t];
+    for (int b = 0; b < CB; ++b) {
+        const int c = 16 * (wave * CB + b) + col;
+        if (c >= NN)
+            continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int tt = t0 + 4 * kq + i;
+            if (tt < nt)
+                yk[(size_t)tt * NN + c] = make_float2(accr[b][i], acci[b][i]);
+        }
     }
 }
 
-// Adjoint spectral contraction, one frequency k per block row:
-//   B[k][t][kk] = sum_c conj(Gb[k][c][kk]) * R[k][t][c]
-// One thread per (j, a) column kk; R for the frequency sits in LDS.
-template <int NT>
+// Adjoint contraction for one frequency k and a range of kk, computed
+// transposed so that tiles are the MFMA rows:
+//   B[k][t][kk] = sum_c R[k][t][c] * conj(Gb[k][c][kk])
+// A = R (16 tiles x 4 c, staged once per block in LDS as rs[c][t]),
+// B = conj(Gb) (4 c x 16 kk per block of kk, CB blocks per wave), with the same
+// double-buffered (groups of U steps), unconditional loads as the forward
+// contraction.
+template <int CB, int U>
 __global__ __launch_bounds__(256) void k_contract_adj(const float2 *__restrict__ Gb,
                                                       const float2 *__restrict__ Rs,
                                                       float2 *__restrict__ B, int NN, int KK,
                                                       int nt)
 {
-    extern __shared__ float2 rs[];  // [NN][NT]
-    const int k = blockIdx.x;
-    const int kk = blockIdx.y * blockDim.x + threadIdx.x;
-    const int t0 = blockIdx.z * NT;
-    for (int idx = threadIdx.x; idx < NN * NT; idx += blockDim.x) {
-        const int c = idx / NT, t = idx % NT;
+    extern __shared__ float2 rs[];  // [NN rounded up to 4 * U][16], zero padded
+    const int k = blockIdx.x, t0 = blockIdx.z * 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const int NCp = (NN + 4 * U - 1) / (4 * U) * (4 * U);
+    for (int idx = threadIdx.x; idx < NCp * 16; idx += blockDim.x) {
+        const int c = idx / 16, tt = idx % 16;
         float2 v = make_float2(0.f, 0.f);
-        if (t0 + t < nt)
-            v = Rs[((size_t)k * nt + t0 + t) * NN + c];
+        if (c < NN && t0 + tt < nt)
+            v = Rs[((size_t)k * nt + t0 + tt) * NN + c];
         rs[idx] = v;
     }
     __syncthreads();
-    if (kk >= KK)
-        return;
-    float2 acc[NT];
+    const float2 *gk = Gb + (size_t)k * NN * KK;
+    int kidx[CB];
+    bool k_ok[CB];
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
-        acc[t] = make_float2(0.f, 0.f);
-    const float2 *g = Gb + (size_t)k * NN * KK + kk;
-#pragma unroll 8
-    for (int c = 0; c < NN; ++c) {
-        const float2 gv = g[(size_t)c * KK];
+    for (int b = 0; b < CB; ++b) {
+        const int kk = 16 * ((blockIdx.y * nwaves + wave) * CB + b) + col;
+        k_ok[b] = kk < KK;
+        kidx[b] = k_ok[b] ? kk : KK - 1;
+    }
+    f32x4 accr[CB], acci[CB];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const float2 rv = rs[c * NT + t];
-            acc[t].x = fmaf(gv.x, rv.x, fmaf(gv.y, rv.y, acc[t].x));
-            acc[t].y = fmaf(gv.x, rv.y, fmaf(-gv.y, rv.x, acc[t].y));
+    for (int b = 0; b < CB; ++b) {
+        accr[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        acci[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    const int ngroups = NCp / (4 * U);
+    float2 gb0[U][CB], gb1[U][CB];
+    // rows c >= NN read a valid row (clamped) that meets a zero in rs; columns
+    // kk >= KK only feed outputs that are not stored
+    auto load_group = [&](int grp, float2(&gb)[U][CB]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int cc = min(4 * (grp * U + u) + kq, NN - 1);
+#pragma unroll
+            for (int b = 0; b < CB; ++b)
+                gb[u][b] = gk[(size_t)cc * KK + kidx[b]];
+        }
+    };
+    auto compute_group = [&](int grp, const float2(&gb)[U][CB]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const float2 am = rs[(4 * (grp * U + u) + kq) * 16 + col];
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                const float2 g = gb[u][b];
+                accr[b] = mfma4(am.x, g.x, accr[b]);
+                accr[b] = mfma4(am.y, g.y, accr[b]);
+                acci[b] = mfma4(am.y, g.x, acci[b]);
+                acci[b] = mfma4(-am.x, g.y, acci[b]);
+            }
+        }
+    };
+    if (ngroups > 0)
+        load_group(0, gb0);
+    for (int grp = 0; grp < ngroups; grp += 2) {
+        if (grp + 1 < ngroups)
+            load_group(grp + 1, gb1);
+        compute_group(grp, gb0);
+        if (grp + 1 < ngroups) {
+            if (grp + 2 < ngroups)
+                load_group(grp + 2, gb0);
+            compute_group(grp + 1, gb1);
         }
     }
+    // D[t][kk]: lane holds tiles t0 + 4 * kq + i, column kk of each block
+    float2 *bk = B + (size_t)k * nt * KK;
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
-        if (t0 + t < nt)
-            B[((size_t)k * nt + t0 + t) * KK + kk] = acc[t];
+    for (int b = 0; b < CB; ++b) {
+        if (!k_ok[b])
+            continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int tt = t0 + 4 * kq + i;
+            if (tt < nt)
+                bk[(size_t)tt * KK + kidx[b]] = make_float2(accr[b][i], acci[b][i]);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -537,61 +629,65 @@ __device__ __forceinline__ double dct_basis(int f, int x, int n)
     return c * cospi((double)num / (2.0 * n));
 }
 
-// Row transform of the z maximum projection over a chunk of image rows:
-// T1[chunk][v][s] = sum_{r in chunk} C_H[v][r] * m[r][s],  m = max_j vol[j][r][s],
-// for row frequencies v in [v0, v0 + kMetricVBlock), and n2p[chunk][s] = sum m^2.
-__global__ void k_metric_partial(const float *__restrict__ vol, int nz, int H, int W, int nv,
-                                 int rows_per_chunk, double *__restrict__ T1,
-                                 double *__restrict__ n2p)
-{
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    const int chunk = blockIdx.y;
-    const int v0 = blockIdx.z * kMetricVBlock;
-    if (s >= W)
-        return;
-    const int r0 = chunk * rows_per_chunk;
-    const int r1 = min(H, r0 + rows_per_chunk);
-    double acc[kMetricVBlock];
-#pragma unroll
-    for (int q = 0; q < kMetricVBlock; ++q)
-        acc[q] = 0.0;
-    double n2 = 0.0;
-    for (int r = r0; r < r1; ++r) {
-        float m = vol[(size_t)r * W + s];
-        for (int j = 1; j < nz; ++j)
-            m = fmaxf(m, vol[((size_t)j * H + r) * W + s]);
-        const double md = (double)m;
-        n2 = fma(md, md, n2);
-#pragma unroll
-        for (int q = 0; q < kMetricVBlock; ++q)
-            if (v0 + q < nv)
-                acc[q] = fma(dct_basis(v0 + q, r, H), md, acc[q]);
-    }
-#pragma unroll
-    for (int q = 0; q < kMetricVBlock; ++q)
-        if (v0 + q < nv)
-            T1[((size_t)chunk * nv + v0 + q) * W + s] = acc[q];
-    if (blockIdx.z == 0)
-        n2p[(size_t)chunk * W + s] = n2;
-}
-
-// Sum the row-chunk partials in a fixed order: T1[0][v][s] = sum_chunk T1[chunk][v][s].
-__global__ void k_metric_colsum(double *__restrict__ T1, int nchunks, int nv, int W)
+// tab[f][x] = c(f, n) cos((2x + 1) pi f / (2n)), f < nfreq, x < n (Eqs. 2-4).
+__global__ void k_dct_table(double *__restrict__ tab, int n, int nfreq)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= nv * W)
-        return;
-    double acc = T1[idx];
-    for (int c = 1; c < nchunks; ++c)
-        acc += T1[(size_t)c * nv * W + idx];
-    T1[idx] = acc;
+    if (idx < n * nfreq)
+        tab[idx] = dct_basis(idx / n, idx % n, n);
 }
 
-// One wave per candidate coefficient (v, u): F[v][u] = sum_s T1[v][s] C_W[u][s]
-// for (v, u) inside the triangle u / xs + v / ys < 1; |F| is written, -1 marks
-// coefficients outside the region.
-__global__ void k_metric_coeffs(const double *__restrict__ T1, int nv, int nu, int W, double xs,
-                                double ys, double *__restrict__ Fabs)
+// z maximum projection m[r][s] = max_j vol[j][r][s] (sec. 2.2, Fig. 2(a)) with
+// per-block float64 partial sums of m^2 (Parseval: sum m^2 = ||F||_F^2).
+__global__ void k_mip(const float *__restrict__ vol, int nz, size_t hw, float *__restrict__ mip,
+                      double *__restrict__ n2p)
+{
+    __shared__ double red[256];
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    double sq = 0.0;
+    if (i < hw) {
+        float m = vol[i];
+        for (int j = 1; j < nz; ++j)
+            m = fmaxf(m, vol[(size_t)j * hw + i]);
+        mip[i] = m;
+        sq = (double)m * (double)m;
+    }
+    red[threadIdx.x] = sq;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        n2p[blockIdx.x] = red[0];
+}
+
+// Row transform over a chunk of image rows:
+// T1[chunk][v][s] = sum_{r in chunk} C_H[v][r] m[r][s]  (float64).
+__global__ void k_dct_rows(const float *__restrict__ mip, int H, int W,
+                           const double *__restrict__ tabH, int nv, int rows_per_chunk,
+                           double *__restrict__ T1)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int chunk = blockIdx.y;
+    if (idx >= nv * W)
+        return;
+    const int v = idx / W, s = idx % W;
+    const int r0 = chunk * rows_per_chunk, r1 = min(H, r0 + rows_per_chunk);
+    const double *tv = tabH + (size_t)v * H;
+    double acc = 0.0;
+    for (int r = r0; r < r1; ++r)
+        acc = fma(tv[r], (double)mip[(size_t)r * W + s], acc);
+    T1[(size_t)chunk * nv * W + idx] = acc;
+}
+
+// One wave per candidate coefficient (v, u):
+// F[v][u] = sum_chunk sum_s T1[chunk][v][s] C_W[u][s] for (v, u) inside the
+// triangle u / xs + v / ys < 1; |F| is written, -1 marks coefficients outside.
+__global__ void k_metric_coeffs(const double *__restrict__ T1, int nchunks, int nv, int nu, int W,
+                                const double *__restrict__ tabW, double xs, double ys,
+                                double *__restrict__ Fabs)
 {
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
@@ -604,9 +700,14 @@ __global__ void k_metric_coeffs(const double *__restrict__ T1, int nv, int nu, i
             Fabs[wave] = -1.0;
         return;
     }
+    const double *tu = tabW + (size_t)u * W;
     double acc = 0.0;
-    for (int s = lane; s < W; s += 64)
-        acc = fma(T1[(size_t)v * W + s], dct_basis(u, s, W), acc);
+    for (int s = lane; s < W; s += 64) {
+        double t = 0.0;
+        for (int c = 0; c < nchunks; ++c)
+            t += T1[((size_t)c * nv + v) * W + s];
+        acc = fma(t, tu[s], acc);
+    }
     for (int off = 32; off > 0; off >>= 1)
         acc += __shfl_down(acc, off, 64);
     if (lane == 0)
@@ -720,6 +821,13 @@ __global__ void k_cond_copy(const StopState *__restrict__ st, const float *__res
         dst[i] = src[i];
 }
 
+__global__ void k_zero_u32n(unsigned *__restrict__ p, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
 __global__ void k_fill(float *__restrict__ p, size_t n, float v)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
@@ -795,7 +903,7 @@ static bool fft_supported(int Q)
 static size_t lds_r2c_fft(const Geo &g)
 {
     const size_t a = (size_t)g.Q * g.Q * g.N * 4, b = (size_t)g.Q * g.QH * g.N * 8;
-    return std::max(a, b) + (size_t)g.Q * 8;
+    return std::max(a, b) + (size_t)g.Q * 8 + (size_t)g.Q * g.QH * 4;  // + row maxima
 }
 
 static size_t lds_c2r_fft(const Geo &g)
@@ -848,13 +956,14 @@ static void set_fft_lds_attrs(int Q, size_t lds)
 
 static void launch_r2c_fft(int Q, dim3 grid, int block, size_t lds, hipStream_t st, int mode,
                            const float *src, int H, int W, int N, int T, int hD, int tiles_x,
-                           int nt, int KKo, int K, int c0, int KK, float2 *out, const float2 *tw)
+                           int nt, int KKo, int K, int c0, int KK, float2 *out, const float2 *tw,
+                           unsigned *rowmax = nullptr)
 {
     switch (Q) {
 #define LFRL_CASE(q)                                                                        \
     case q:                                                                                 \
         hipLaunchKernelGGL(k_r2c_fft<q>, grid, dim3(block), lds, st, mode, src, H, W, N, T,  \
-                           hD, tiles_x, nt, KKo, K, c0, KK, out, tw);                        \
+                           hD, tiles_x, nt, KKo, K, c0, KK, out, tw, rowmax);                \
         break;
         LFRL_FFT_Q_LIST(LFRL_CASE)
 #undef LFRL_CASE
@@ -864,16 +973,17 @@ static void launch_r2c_fft(int Q, dim3 grid, int block, size_t lds, hipStream_t 
 }
 
 static void launch_c2r_fft(int Q, dim3 grid, int block, size_t lds, hipStream_t st,
-                           const float2 *spec, size_t split_stride, int nsplit, int KKo, int N,
-                           int T, int hD, int tiles_x, int nt, int H, int W, int mode, float *dst,
-                           const float *aux0, const float *aux1, const float2 *tw)
+                           const float2 *spec, size_t split_stride, int nsplit, size_t sk,
+                           size_t stile, size_t sc, int N, int planes, int T, int hD, int tiles_x,
+                           int H, int W, int mode, float *dst, const float *aux0,
+                           const float *aux1, const float2 *tw)
 {
     switch (Q) {
 #define LFRL_CASE(q)                                                                        \
     case q:                                                                                 \
         hipLaunchKernelGGL(k_c2r_fft<q>, grid, dim3(block), lds, st, spec, split_stride,     \
-                           nsplit, KKo, N, T, hD, tiles_x, nt, H, W, mode, dst, aux0, aux1,  \
-                           tw);                                                             \
+                           nsplit, sk, stile, sc, N, planes, T, hD, tiles_x, H, W, mode, dst, \
+                           aux0, aux1, tw);                                                 \
         break;
         LFRL_FFT_Q_LIST(LFRL_CASE)
 #undef LFRL_CASE
@@ -1014,6 +1124,9 @@ struct lfrl_plan_s {
     float2 *X = nullptr, *Yp = nullptr, *Rs = nullptr;
     float *img = nullptr, *sens = nullptr, *vol[3] = {nullptr, nullptr, nullptr};
     double *T1 = nullptr, *n2p = nullptr, *Fabs = nullptr, *metric_out = nullptr;
+    double *tabH = nullptr, *tabW = nullptr;  // DCT basis rows (Eqs. 2-4)
+    float *mip = nullptr;
+    int tab_h = -1, tab_nv = -1, tab_w = -1, tab_nu = -1;
     double *trace = nullptr, *flux = nullptr, *dotp = nullptr;
     StopState *state = nullptr;
     StopState *state_host = nullptr;  // pinned
@@ -1026,6 +1139,12 @@ struct lfrl_plan_s {
     int sens_h = -1, sens_w = -1;
     size_t lds_r2c_bytes = 0, lds_c2r_bytes = 0;
     bool use_fft = false;  // tile DFTs by the register FFT kernels
+    int fwd_cb = 3, fwd_u = 4, adj_cb = 4, adj_u = 4;  // contraction launch shapes
+    bool split = false;                 // split FP16 spectra (LFRL_SPLIT_FP16)
+    int hfwd_cb = 3, hfwd_u = 1, hadj_cb = 4, hadj_u = 2;  // their contraction shapes
+    half2c *Hf = nullptr, *Hb = nullptr;  // FP16 spectra in fragment order
+    int *gexp = nullptr;                // per-frequency exponents of the FP16 spectra
+    unsigned *xmax = nullptr, *rmax = nullptr;  // per-(frequency, tile) maxima of tile spectra
     int thr_r2c = 256, thr_c2r = 256;
     // profiling
     bool prof = false;
@@ -1045,7 +1164,7 @@ static int validate_desc(const lfrl_plan_desc *d)
         return set_error(LFRL_ERR_UNSUPPORTED, "nnum^2 must be <= %d", kMaxNN);
     if (d->max_h < d->nnum || d->max_w < d->nnum || d->max_h % d->nnum || d->max_w % d->nnum)
         return set_error(LFRL_ERR_ARG, "max_h/max_w must be positive multiples of nnum");
-    if (d->precision != LFRL_FP32)
+    if (d->precision != LFRL_FP32 && d->precision != LFRL_SPLIT_FP16)
         return set_error(LFRL_ERR_UNSUPPORTED, "precision %d not supported", d->precision);
     if (d->flags != 0)
         return set_error(LFRL_ERR_ARG, "flags must be 0");
@@ -1096,6 +1215,9 @@ static int pick_q(const lfrl_plan_desc *d, size_t lds_max, int *q_out)
         if (lds_r2c(gq) > lds_max || lds_c2r(gq) > lds_max)
             return set_error(LFRL_ERR_UNSUPPORTED, "tile_q %d needs more LDS than available",
                              d->tile_q);
+        if (d->precision == LFRL_SPLIT_FP16 && !fft_usable(gq, lds_max))
+            return set_error(LFRL_ERR_UNSUPPORTED, "split FP16 needs an FFT tile size (tile_q %d)",
+                             d->tile_q);
         *q_out = d->tile_q;
         return LFRL_OK;
     }
@@ -1106,6 +1228,8 @@ static int pick_q(const lfrl_plan_desc *d, size_t lds_max, int *q_out)
         geo_init(gq, d->nnum, d->nz, d->ksize, q);
         if (lds_r2c(gq) > lds_max || lds_c2r(gq) > lds_max)
             continue;
+        if (d->precision == LFRL_SPLIT_FP16 && !fft_usable(gq, lds_max))
+            continue;  // the split path takes its row scales from the FFT tile kernels
         const Tiles t = tiles_for(gq, d->max_h, d->max_w);
         const double tm = model_time(gq, t);
         if (tm < best * 0.999) {
@@ -1126,12 +1250,46 @@ static int pick_split(const Geo &g)
     return s;
 }
 
+// Launch shapes of the two contractions: 16-column blocks per wave (CB) and
+// prefetch depth in 4-deep reduction steps (U).  The forward spreads its
+// NNp / 16 column blocks over at most 8 waves; the adjoint uses 4 waves.
+static constexpr int kAdjWaves = 4;
+
+static bool fwd_cb_ok(int cb) { return cb == 1 || cb == 2 || cb == 3 || cb == 4 || cb == 5 || cb == 8; }
+static bool adj_cb_ok(int cb) { return cb == 1 || cb == 2 || cb == 4 || cb == 8; }
+static bool u_ok(int u) { return u == 2 || u == 4 || u == 8; }
+
+static void default_shapes(const Geo &g, int *fcb, int *fu, int *acb, int *au)
+{
+    const int ncb = g.NNp / 16;
+    int cb = std::min(5, (ncb + 4) / 5);
+    while (!fwd_cb_ok(cb) || (ncb + cb - 1) / cb > 8)
+        ++cb;
+    *fcb = cb;
+    *fu = 4;
+    *acb = 4;
+    *au = 4;
+    // tuning override: LFRL_CONTRACT_SHAPE="fwd_cb,fwd_u,adj_cb,adj_u"
+    const char *env = getenv("LFRL_CONTRACT_SHAPE");
+    int a = 0, b = 0, c = 0, d = 0;
+    if (env && sscanf(env, "%d,%d,%d,%d", &a, &b, &c, &d) == 4 && fwd_cb_ok(a) &&
+        (ncb + a - 1) / a <= 8 && u_ok(b) && !(a == 8 && b == 8) && adj_cb_ok(c) && u_ok(d)) {
+        *fcb = a;
+        *fu = b;
+        *acb = c;
+        *au = d;
+    }
+}
+
 struct Sizes {
-    size_t Gf, tw, psf, X, Yp, Rs, img, vol, T1, n2p, Fabs, trace, dotp, weak;
-    size_t resident() const { return 2 * Gf + tw + psf; }
+    size_t Gf, Gb, tw, psf, X, Yp, Rs, img, vol, T1, n2p, Fabs, trace, dotp, weak, tabH, tabW;
+    size_t Hf = 0, Hb = 0, gexp = 0, rowmax = 0;  // split FP16 only
+    bool split = false;
+    size_t resident() const { return (split ? Hf + Hb + gexp : Gf + Gb) + tw + psf; }
     size_t workspace() const
     {
-        return X + Yp + Rs + img + 4 * vol + T1 + n2p + Fabs + 2 * trace + 2 * dotp + weak + 512;
+        return X + Yp + Rs + 2 * img + 4 * vol + T1 + n2p + Fabs + 2 * trace + 2 * dotp + weak +
+               tabH + tabW + 2 * rowmax + 512;
     }
 };
 
@@ -1140,24 +1298,34 @@ static unsigned weak_cap_for(size_t nvox)
     return (unsigned)std::min<size_t>(nvox, (size_t)1 << 20);
 }
 
-static Sizes sizes_for(const Geo &g, int max_h, int max_w, int split)
+static Sizes sizes_for(const Geo &g, int max_h, int max_w, int split, bool f16 = false)
 {
     const Tiles t = tiles_for(g, max_h, max_w);
     Sizes s;
-    s.Gf = (size_t)g.nf * g.NN * g.KK * sizeof(float2);
+    s.Gf = (size_t)g.nf * g.NNp * g.KK * sizeof(float2);
+    s.Gb = (size_t)g.nf * g.NN * g.KK * sizeof(float2);
     s.tw = (size_t)g.Q * sizeof(float2);
-    s.X = (size_t)g.nf * t.nt * g.KK * sizeof(float2);
+    s.X = (size_t)g.nf * t.nt * g.KKs * sizeof(float2);
     s.Yp = (size_t)split * g.nf * t.nt * g.NN * sizeof(float2);
     s.Rs = (size_t)g.nf * t.nt * g.NN * sizeof(float2);
     s.img = (size_t)max_h * max_w * sizeof(float);
     s.vol = (size_t)g.Nz * max_h * max_w * sizeof(float);
     s.T1 = (size_t)kMetricChunks * kMaxMetricLegs * max_w * sizeof(double);
-    s.n2p = (size_t)kMetricChunks * max_w * sizeof(double);
+    s.n2p = ((size_t)max_h * max_w + 255) / 256 * sizeof(double);
+    s.tabH = (size_t)kMaxMetricLegs * max_h * sizeof(double);
+    s.tabW = (size_t)kMaxMetricLegs * max_w * sizeof(double);
     s.Fabs = (size_t)kMaxMetricLegs * kMaxMetricLegs * sizeof(double);
     s.trace = (size_t)kMaxTrace * sizeof(double);
     s.dotp = (size_t)kDotBlocks * sizeof(double);
     s.psf = (size_t)g.Nz * g.NN * g.K * g.K * sizeof(float);
     s.weak = (size_t)weak_cap_for((size_t)g.Nz * max_h * max_w) * sizeof(unsigned);
+    if (f16) {
+        s.split = true;
+        s.Hf = (size_t)g.nf * g.KKs * g.NNp * sizeof(half2c);
+        s.Hb = (size_t)g.nf * g.NNp * ((g.KK + 15) / 16 * 16) * sizeof(half2c);
+        s.gexp = (size_t)g.nf * sizeof(int);
+        s.rowmax = (size_t)g.nf * t.nt * sizeof(unsigned);
+    }
     return s;
 }
 
@@ -1193,7 +1361,8 @@ extern "C" int lfrl_plan_footprint(const lfrl_plan_desc *desc, size_t *resident_
         return rc;
     Geo g;
     geo_init(g, desc->nnum, desc->nz, desc->ksize, q);
-    const Sizes s = sizes_for(g, desc->max_h, desc->max_w, pick_split(g));
+    const Sizes s = sizes_for(g, desc->max_h, desc->max_w, pick_split(g),
+                              desc->precision == LFRL_SPLIT_FP16);
     if (resident_bytes)
         *resident_bytes = s.resident();
     if (workspace_bytes)
@@ -1211,8 +1380,10 @@ static void free_plan(lfrl_plan_s *p)
     (void)hipDeviceSynchronize();
     void *bufs[] = {p->Gf, p->Gb, p->tw, p->X, p->Yp, p->Rs, p->img, p->sens,
                     p->vol[0], p->vol[1], p->vol[2], p->T1, p->n2p, p->Fabs,
+                    p->tabH, p->tabW, p->mip,
                     p->metric_out, p->trace, p->flux, p->dotp, p->state,
-                    p->psf, p->weak, p->weak_count, p->cmax};
+                    p->psf, p->weak, p->weak_count, p->cmax, p->Hf, p->Hb, p->gexp,
+                    p->xmax, p->rmax};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -1290,10 +1461,30 @@ extern "C" int lfrl_plan(lfrl_plan_t *out, const lfrl_plan_desc *desc, const flo
     p->max_w = desc->max_w;
     p->max_tiles = tiles_for(g, desc->max_h, desc->max_w).nt;
     p->split_k = pick_split(g);
-    const Sizes s = sizes_for(g, p->max_h, p->max_w, p->split_k);
+    p->split = desc->precision == LFRL_SPLIT_FP16;
+    const Sizes s = sizes_for(g, p->max_h, p->max_w, p->split_k, p->split);
     p->resident = s.resident();
     p->workspace = s.workspace();
     p->use_fft = fft_usable(g, lmax);
+    default_shapes(g, &p->fwd_cb, &p->fwd_u, &p->adj_cb, &p->adj_u);
+    {
+        // split FP16 shapes; tuning override LFRL_CONTRACT_SHAPE_F16="fcb,fu,acb,au"
+        const int ncb = g.NNp / 16;
+        p->hfwd_cb = ncb > 8 ? 2 : 1;
+        if ((ncb + p->hfwd_cb - 1) / p->hfwd_cb > 8)
+            p->hfwd_cb = 3;
+        const char *env = getenv("LFRL_CONTRACT_SHAPE_F16");
+        int a = 0, b = 0, c = 0, d = 0;
+        // (only shapes whose registers fit without spilling)
+        if (env && sscanf(env, "%d,%d,%d,%d", &a, &b, &c, &d) == 4 &&
+            ((a == 1 || a == 2) ? (b == 1 || b == 2) : (a == 3 && b == 1)) &&
+            (ncb + a - 1) / a <= 8 && (c == 2 || c == 4) && (d == 2 || d == 4)) {
+            p->hfwd_cb = a;
+            p->hfwd_u = b;
+            p->hadj_cb = c;
+            p->hadj_u = d;
+        }
+    }
     if (p->use_fft) {
         p->lds_r2c_bytes = lds_r2c_fft(g);
         p->lds_c2r_bytes = lds_c2r_fft(g);
@@ -1304,7 +1495,7 @@ extern "C" int lfrl_plan(lfrl_plan_t *out, const lfrl_plan_desc *desc, const flo
         p->lds_c2r_bytes = lds_c2r(g);
     }
     TRY(dalloc(&p->Gf, s.Gf));
-    TRY(dalloc(&p->Gb, s.Gf));
+    TRY(dalloc(&p->Gb, s.Gb));
     TRY(dalloc(&p->tw, s.tw));
     TRY(dalloc(&p->X, s.X));
     TRY(dalloc(&p->Yp, s.Yp));
@@ -1315,6 +1506,9 @@ extern "C" int lfrl_plan(lfrl_plan_t *out, const lfrl_plan_desc *desc, const flo
         TRY(dalloc(&p->vol[i], s.vol));
     TRY(dalloc(&p->T1, s.T1));
     TRY(dalloc(&p->n2p, s.n2p));
+    TRY(dalloc(&p->tabH, s.tabH));
+    TRY(dalloc(&p->tabW, s.tabW));
+    TRY(dalloc(&p->mip, s.img));
     TRY(dalloc(&p->Fabs, s.Fabs));
     TRY(dalloc(&p->metric_out, 64));
     TRY(dalloc(&p->trace, s.trace));
@@ -1326,6 +1520,13 @@ extern "C" int lfrl_plan(lfrl_plan_t *out, const lfrl_plan_desc *desc, const flo
     TRY(dalloc(&p->weak, s.weak));
     TRY(dalloc(&p->weak_count, sizeof(unsigned)));
     TRY(dalloc(&p->cmax, (kDotBlocks + 1) * sizeof(float)));
+    if (p->split) {
+        TRY(dalloc(&p->Hf, s.Hf));
+        TRY(dalloc(&p->Hb, s.Hb));
+        TRY(dalloc(&p->gexp, s.gexp));
+        TRY(dalloc(&p->xmax, s.rowmax));
+        TRY(dalloc(&p->rmax, s.rowmax));
+    }
     {
         hipError_t e = hipHostMalloc((void **)&p->state_host, sizeof(StopState), hipHostMallocDefault);
         if (e == hipSuccess)
@@ -1347,20 +1548,43 @@ extern "C" int lfrl_plan(lfrl_plan_t *out, const lfrl_plan_desc *desc, const flo
     hipError_t e = hipMemcpyAsync(p->tw, tw.data(), g.Q * sizeof(float2), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(p->psf, psf, s.psf, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && g.NNp != g.NN)
+        e = hipMemsetAsync(p->Gf, 0, s.Gf, st);  // zero the row padding
     if (e == hipSuccess) {
         dim3 grid(g.N, g.NN, g.Nz);
         if (p->use_fft)
             launch_r2c_fft(g.Q, grid, p->thr_r2c, p->lds_r2c_bytes, st, SRC_PSF, psf, 0, 0, g.N,
-                           g.T, g.hD, 0, 0, 0, g.K, g.c0, g.KK, p->Gf, p->tw);
+                           g.T, g.hD, 0, 0, g.NNp, g.K, g.c0, g.KK, p->Gf, p->tw);
         else
             hipLaunchKernelGGL(k_psf_r2c, grid, dim3(256), p->lds_r2c_bytes, st, psf, g.N, g.K,
-                               g.c0, g.hD, g.Q, g.QH, g.KK, g.NN, p->Gf, p->tw);
+                               g.c0, g.hD, g.Q, g.QH, g.KK, g.NNp, p->Gf, p->tw);
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
         dim3 grid((g.NN + 31) / 32, (g.KK + 31) / 32, g.nf);
-        hipLaunchKernelGGL(k_transpose_spec, grid, dim3(32, 8), 0, st, p->Gf, p->Gb, g.KK, g.NN);
+        hipLaunchKernelGGL(k_transpose_spec, grid, dim3(32, 8), 0, st, p->Gf, p->Gb, g.KK, g.NN,
+                           g.NNp);
         e = hipGetLastError();
+    }
+    if (e == hipSuccess && p->split) {
+        // FP16 fragments with per-frequency power-of-two scales, then drop the
+        // FP32 spectra
+        hipLaunchKernelGGL(k_spec_exp, dim3(g.nf), dim3(256), 0, st, (const float2 *)p->Gf,
+                           (size_t)g.KK * g.NNp, p->gexp);
+        const size_t nhf = s.Hf / sizeof(half2c), nhb = s.Hb / sizeof(half2c);
+        hipLaunchKernelGGL(k_pack_fwd_f16, dim3(8192), dim3(256), 0, st, (const float2 *)p->Gf,
+                           g.KK, g.NNp, g.KKs / 32, (const int *)p->gexp, p->Hf, nhf);
+        hipLaunchKernelGGL(k_pack_adj_f16, dim3(8192), dim3(256), 0, st, (const float2 *)p->Gb,
+                           g.NN, g.KK, g.NNp / 16, (g.KK + 15) / 16, (const int *)p->gexp, p->Hb,
+                           nhb);
+        e = hipGetLastError();
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e == hipSuccess) {
+            (void)hipFree(p->Gf);
+            (void)hipFree(p->Gb);
+            p->Gf = p->Gb = nullptr;
+        }
     }
     if (e == hipSuccess)
         e = hipStreamSynchronize(st);  // the tw staging vector goes out of scope
@@ -1437,15 +1661,29 @@ static int prof_event(lfrl_plan_s *p, int which, hipStream_t st)
     return LFRL_OK;
 }
 
-#define DISPATCH_NT(NTV, ...)                                  \
-    switch (NTV) {                                             \
-    case 1: { constexpr int NT_ = 1; __VA_ARGS__; } break;     \
-    case 2: { constexpr int NT_ = 2; __VA_ARGS__; } break;     \
-    case 4: { constexpr int NT_ = 4; __VA_ARGS__; } break;     \
-    case 8: { constexpr int NT_ = 8; __VA_ARGS__; } break;     \
-    case 16: { constexpr int NT_ = 16; __VA_ARGS__; } break;   \
-    default: { constexpr int NT_ = 32; __VA_ARGS__; } break;   \
+#define LFRL_FWD_CASE(CBV, UV)                                                                   \
+    if (p->fwd_cb == CBV && p->fwd_u == UV) {                                                    \
+        hipLaunchKernelGGL((k_contract_fwd<CBV, UV>), grid, block, 0, st, p->Gf, p->X, p->Yp,    \
+                           g.NN, g.NNp, g.KK, g.KKs, t.nt, g.nf, kchunk);                        \
+        launched = true;                                                                         \
     }
+#define LFRL_FWD_CASES(CBV) LFRL_FWD_CASE(CBV, 2) LFRL_FWD_CASE(CBV, 4) LFRL_FWD_CASE(CBV, 8)
+#define LFRL_ADJ_CASE(CBV, UV)                                                                   \
+    if (p->adj_cb == CBV && p->adj_u == UV) {                                                    \
+        hipLaunchKernelGGL((k_contract_adj<CBV, UV>), grid, dim3(64 * kAdjWaves), lds, st, p->Gb, \
+                           p->Rs, p->X, g.NN, g.KK, t.nt);                                       \
+        launched = true;                                                                         \
+    }
+#define LFRL_ADJ_CASES(CBV) LFRL_ADJ_CASE(CBV, 2) LFRL_ADJ_CASE(CBV, 4) LFRL_ADJ_CASE(CBV, 8)
+
+static int contraction_split(const lfrl_plan_s *p, int *kchunk)
+{
+    const Geo &g = p->g;
+    int kc = (g.KK + p->split_k - 1) / p->split_k;
+    kc = (kc + 63) / 64 * 64;
+    *kchunk = kc;
+    return (g.KK + kc - 1) / kc;
+}
 
 // vol [Nz][h][w] -> img [h][w]: plain projection (mode STORE) or the RL ratio
 // y / (A x) written into `dst` (mode RATIO, y = aux).
@@ -1454,41 +1692,68 @@ static int run_forward(lfrl_plan_s *p, int h, int w, const float *vol, float *ds
 {
     const Geo &g = p->g;
     const Tiles t = tiles_for(g, h, w);
+    if (p->split) {
+        hipLaunchKernelGGL(k_zero_u32n, dim3(64), dim3(256), 0, st, p->xmax, (size_t)g.nf * t.nt);
+        LAUNCH_CHECK("k_zero_u32n");
+    }
     if (p->use_fft)
-        launch_r2c_fft(g.Q, dim3(t.nt, g.Nz * g.N), p->thr_r2c, p->lds_r2c_bytes, st, SRC_PLANES,
-                       vol, h, w, g.N, g.T, g.hD, t.tx, t.nt, g.KK, g.K, g.c0, g.KK, p->X, p->tw);
+        launch_r2c_fft(g.Q, dim3(t.nt * g.Nz * g.N), p->thr_r2c, p->lds_r2c_bytes, st, SRC_PLANES,
+                       vol, h, w, g.N, g.T, g.hD, t.tx, t.nt, g.KKs, g.K, g.c0, g.KK, p->X, p->tw,
+                       p->split ? p->xmax : nullptr);
     else
         hipLaunchKernelGGL(k_vol_r2c, dim3(t.nt, g.Nz * g.N), dim3(256), p->lds_r2c_bytes, st, vol,
-                           h, w, g.N, g.Q, g.QH, g.T, g.hD, t.tx, t.nt, g.KK, p->X, p->tw);
+                           h, w, g.N, g.Q, g.QH, g.T, g.hD, t.tx, t.nt, g.KKs, p->X, p->tw);
     LAUNCH_CHECK("k_vol_r2c");
-    const int NTV = nt_template(t.nt);
-    const int ntg = (t.nt + NTV - 1) / NTV;
-    int kchunk = (g.KK + p->split_k - 1) / p->split_k;
-    kchunk = (kchunk + 63) / 64 * 64;
-    const int split = (g.KK + kchunk - 1) / kchunk;
-    const int block = std::min(256, (g.NN + 63) / 64 * 64);
+    int kchunk = 0;
+    const int split = contraction_split(p, &kchunk);
+    if (p->split)
+        kchunk = (kchunk + 31) / 32 * 32;
+    const int split2 = (g.KK + kchunk - 1) / kchunk;
+    const int fcb = p->split ? p->hfwd_cb : p->fwd_cb;
+    const int nwaves = (g.NNp / 16 + fcb - 1) / fcb;
+    const dim3 grid(g.nf, split2, (t.nt + 15) / 16);
+    const dim3 block(64 * nwaves);
     if (p->prof) {
         int rc = prof_event(p, 0, st);
         if (rc)
             return rc;
     }
-    DISPATCH_NT(NTV, hipLaunchKernelGGL(k_contract_fwd<NT_>, dim3(g.nf, split, ntg), dim3(block),
-                                        0, st, p->Gf, p->X, p->Yp, g.NN, g.KK, t.nt, g.nf, kchunk));
+    bool launched = false;
+    if (p->split) {
+#define LFRL_HFWD_CASE(CBV, UV)                                                                  \
+    if (p->hfwd_cb == CBV && p->hfwd_u == UV) {                                                  \
+        hipLaunchKernelGGL((k_contract_fwd_f16<CBV, UV>), grid, block, 0, st,                    \
+                           (const half2c *)p->Hf, (const float2 *)p->X, (const unsigned *)p->xmax,\
+                           (const int *)p->gexp, p->Yp, g.NN, g.NNp, g.KK, g.KKs, g.KKs / 32,    \
+                           t.nt, g.nf, kchunk);                                                  \
+        launched = true;                                                                         \
+    }
+        LFRL_HFWD_CASE(1, 1) LFRL_HFWD_CASE(1, 2) LFRL_HFWD_CASE(2, 1) LFRL_HFWD_CASE(2, 2)
+        LFRL_HFWD_CASE(3, 1)
+#undef LFRL_HFWD_CASE
+    } else {
+    LFRL_FWD_CASES(1) LFRL_FWD_CASES(2) LFRL_FWD_CASES(3) LFRL_FWD_CASES(4) LFRL_FWD_CASES(5)
+    LFRL_FWD_CASE(8, 2) LFRL_FWD_CASE(8, 4)
+    }
+    if (!launched)
+        return set_error(LFRL_ERR_UNSUPPORTED, "no forward contraction for shape %d/%d",
+                         p->fwd_cb, p->fwd_u);
     LAUNCH_CHECK("k_contract_fwd");
     if (p->prof) {
         int rc = prof_event(p, 0, st);
         if (rc)
             return rc;
     }
-    const size_t split_stride = (size_t)g.nf * t.nt * g.NN;
+    // partials Yp[s][k][t][c]
+    const size_t sk = (size_t)g.NN * t.nt, split_stride = (size_t)g.nf * sk;
     if (p->use_fft)
-        launch_c2r_fft(g.Q, dim3(t.nt, g.N), p->thr_c2r, p->lds_c2r_bytes, st, p->Yp, split_stride,
-                       split, g.NN, g.N, g.T, g.hD, t.tx, t.nt, h, w, mode, dst, aux,
+        launch_c2r_fft(g.Q, dim3(t.nt * g.N), p->thr_c2r, p->lds_c2r_bytes, st, p->Yp, split_stride,
+                       split2, sk, g.NN, 1, g.N, 1, g.T, g.hD, t.tx, h, w, mode, dst, aux,
                        (const float *)nullptr, p->tw);
     else
         hipLaunchKernelGGL(k_c2r, dim3(t.nt, g.N), dim3(256), p->lds_c2r_bytes, st, p->Yp,
-                           split_stride, split, g.NN, g.N, g.Q, g.QH, g.T, g.hD, t.tx, t.nt, h, w,
-                           mode, dst, aux, (const float *)nullptr, p->tw);
+                           split_stride, split2, sk, (size_t)g.NN, (size_t)1, g.N, g.Q, g.QH, g.T,
+                           g.hD, t.tx, h, w, mode, dst, aux, (const float *)nullptr, p->tw);
     LAUNCH_CHECK("k_c2r(forward)");
     return LFRL_OK;
 }
@@ -1500,37 +1765,62 @@ static int run_backward(lfrl_plan_s *p, int h, int w, const float *img, float *d
 {
     const Geo &g = p->g;
     const Tiles t = tiles_for(g, h, w);
+    if (p->split) {
+        hipLaunchKernelGGL(k_zero_u32n, dim3(64), dim3(256), 0, st, p->rmax, (size_t)g.nf * t.nt);
+        LAUNCH_CHECK("k_zero_u32n");
+    }
     if (p->use_fft)
-        launch_r2c_fft(g.Q, dim3(t.nt, g.N), p->thr_r2c, p->lds_r2c_bytes, st, SRC_PLANES, img, h,
-                       w, g.N, g.T, g.hD, t.tx, t.nt, g.NN, g.K, g.c0, g.KK, p->Rs, p->tw);
+        launch_r2c_fft(g.Q, dim3(t.nt * g.N), p->thr_r2c, p->lds_r2c_bytes, st, SRC_PLANES, img, h,
+                       w, g.N, g.T, g.hD, t.tx, t.nt, g.NN, g.K, g.c0, g.KK, p->Rs, p->tw,
+                       p->split ? p->rmax : nullptr);
     else
         hipLaunchKernelGGL(k_vol_r2c, dim3(t.nt, g.N), dim3(256), p->lds_r2c_bytes, st, img, h,
                            w, g.N, g.Q, g.QH, g.T, g.hD, t.tx, t.nt, g.NN, p->Rs, p->tw);
     LAUNCH_CHECK("k_vol_r2c(image)");
-    const int NTV = nt_template(t.nt);
-    const int ntg = (t.nt + NTV - 1) / NTV;
+    const int acb = p->split ? p->hadj_cb : p->adj_cb;
+    const int kk_per_block = 16 * acb * kAdjWaves;
+    const dim3 grid(g.nf, (g.KK + kk_per_block - 1) / kk_per_block, (t.nt + 15) / 16);
+    const int ustep = 4 * p->adj_u;
+    const size_t lds = p->split ? (size_t)(g.NNp / 16) * 64 * 16 * sizeof(_Float16)
+                                : (size_t)(g.NN + ustep - 1) / ustep * ustep * 16 * sizeof(float2);
     if (p->prof) {
         int rc = prof_event(p, 1, st);
         if (rc)
             return rc;
     }
-    DISPATCH_NT(NTV, hipLaunchKernelGGL(k_contract_adj<NT_>, dim3(g.nf, (g.KK + 255) / 256, ntg),
-                                        dim3(256), (size_t)g.NN * NT_ * sizeof(float2), st, p->Gb,
-                                        p->Rs, p->X, g.NN, g.KK, t.nt));
+    bool launched = false;
+    if (p->split) {
+#define LFRL_HADJ_CASE(CBV, UV)                                                                  \
+    if (p->hadj_cb == CBV && p->hadj_u == UV) {                                                  \
+        hipLaunchKernelGGL((k_contract_adj_f16<CBV, UV>), grid, dim3(64 * kAdjWaves), lds, st,   \
+                           (const half2c *)p->Hb, (const float2 *)p->Rs, (const unsigned *)p->rmax,\
+                           (const int *)p->gexp, p->X, g.NN, g.NNp, g.KK, (g.KK + 15) / 16, t.nt);\
+        launched = true;                                                                         \
+    }
+        LFRL_HADJ_CASE(2, 2) LFRL_HADJ_CASE(2, 4) LFRL_HADJ_CASE(4, 2) LFRL_HADJ_CASE(4, 4)
+#undef LFRL_HADJ_CASE
+    } else {
+    LFRL_ADJ_CASES(1) LFRL_ADJ_CASES(2) LFRL_ADJ_CASES(4) LFRL_ADJ_CASES(8)
+    }
+    if (!launched)
+        return set_error(LFRL_ERR_UNSUPPORTED, "no adjoint contraction for shape %d/%d",
+                         p->adj_cb, p->adj_u);
     LAUNCH_CHECK("k_contract_adj");
     if (p->prof) {
         int rc = prof_event(p, 1, st);
         if (rc)
             return rc;
     }
+    // B[k][t][kk]
+    const size_t sk = (size_t)g.KK * t.nt;
     if (p->use_fft)
-        launch_c2r_fft(g.Q, dim3(t.nt, g.Nz * g.N), p->thr_c2r, p->lds_c2r_bytes, st, p->X,
-                       (size_t)0, 1, g.KK, g.N, g.T, g.hD, t.tx, t.nt, h, w, mode, dst, aux0, aux1,
-                       p->tw);
+        launch_c2r_fft(g.Q, dim3(t.nt * g.Nz * g.N), p->thr_c2r, p->lds_c2r_bytes, st, p->X,
+                       (size_t)0, 1, sk, g.KK, 1, g.N, g.Nz, g.T, g.hD, t.tx, h, w, mode, dst,
+                       aux0, aux1, p->tw);
     else
         hipLaunchKernelGGL(k_c2r, dim3(t.nt, g.Nz * g.N), dim3(256), p->lds_c2r_bytes, st, p->X,
-                           (size_t)0, 1, g.KK, g.N, g.Q, g.QH, g.T, g.hD, t.tx, t.nt, h, w, mode,
-                           dst, aux0, aux1, p->tw);
+                           (size_t)0, 1, sk, (size_t)g.KK, (size_t)1, g.N, g.Q, g.QH, g.T, g.hD,
+                           t.tx, h, w, mode, dst, aux0, aux1, p->tw);
     LAUNCH_CHECK("k_c2r(backward)");
     return LFRL_OK;
 }
@@ -1549,28 +1839,51 @@ static int legs_count(double legs, int n)
     return (int)std::min<double>((double)n, c);
 }
 
+// Scratch of one metric evaluation.
+struct MetricBufs {
+    float *mip;
+    double *tabH, *tabW, *T1, *n2p, *Fabs;
+    int *tab_h, *tab_nv, *tab_w, *tab_nu;  // cached table shapes (may be null: rebuild)
+};
+
 // DCT entropy of the z-MIP of vol[nz][h][w] (nz = 1: the image itself) into
 // out[0]; optional stop-state update for iteration k.
 static int run_metric(int nz, int h, int w, const float *vol, double xs, double ys, double *out,
-                      double *T1, double *n2p, double *Fabs, StopState *st_dev, double *trace,
-                      int k, int patience, hipStream_t st)
+                      const MetricBufs &mb, StopState *st_dev, double *trace, int k, int patience,
+                      hipStream_t st)
 {
     const int nv = legs_count(ys, h), nu = legs_count(xs, w);
+    const bool cached = mb.tab_h && *mb.tab_h == h && *mb.tab_nv >= nv && *mb.tab_w == w &&
+                        *mb.tab_nu >= nu;
+    if (!cached) {
+        hipLaunchKernelGGL(k_dct_table, dim3((h * nv + 255) / 256), dim3(256), 0, st, mb.tabH, h, nv);
+        LAUNCH_CHECK("k_dct_table(H)");
+        hipLaunchKernelGGL(k_dct_table, dim3((w * nu + 255) / 256), dim3(256), 0, st, mb.tabW, w, nu);
+        LAUNCH_CHECK("k_dct_table(W)");
+        if (mb.tab_h) {
+            *mb.tab_h = h;
+            *mb.tab_nv = nv;
+            *mb.tab_w = w;
+            *mb.tab_nu = nu;
+        }
+    }
+    const size_t hw = (size_t)h * w;
+    const int nblk = (int)((hw + 255) / 256);
+    hipLaunchKernelGGL(k_mip, dim3(nblk), dim3(256), 0, st, vol, nz, hw, mb.mip, mb.n2p);
+    LAUNCH_CHECK("k_mip");
     const int chunks = std::min(kMetricChunks, h);
     const int rpc = (h + chunks - 1) / chunks;
     const int nchunks = (h + rpc - 1) / rpc;
-    dim3 grid((w + 255) / 256, nchunks, (nv + kMetricVBlock - 1) / kMetricVBlock);
-    hipLaunchKernelGGL(k_metric_partial, grid, dim3(256), 0, st, vol, nz, h, w, nv, rpc, T1, n2p);
-    LAUNCH_CHECK("k_metric_partial");
-    hipLaunchKernelGGL(k_metric_colsum, dim3((nv * w + 255) / 256), dim3(256), 0, st, T1, nchunks,
-                       nv, w);
-    LAUNCH_CHECK("k_metric_colsum");
+    hipLaunchKernelGGL(k_dct_rows, dim3((nv * w + 255) / 256, nchunks), dim3(256), 0, st,
+                       (const float *)mb.mip, h, w, (const double *)mb.tabH, nv, rpc, mb.T1);
+    LAUNCH_CHECK("k_dct_rows");
     const int ncoef = nv * nu;
-    hipLaunchKernelGGL(k_metric_coeffs, dim3((ncoef + 3) / 4), dim3(256), 0, st, (const double *)T1,
-                       nv, nu, w, xs, ys, Fabs);
+    hipLaunchKernelGGL(k_metric_coeffs, dim3((ncoef + 3) / 4), dim3(256), 0, st,
+                       (const double *)mb.T1, nchunks, nv, nu, w, (const double *)mb.tabW, xs, ys,
+                       mb.Fabs);
     LAUNCH_CHECK("k_metric_coeffs");
-    hipLaunchKernelGGL(k_metric_final, dim3(1), dim3(256), 0, st, (const double *)n2p, nchunks * w,
-                       (const double *)Fabs, ncoef, xs, ys, out, st_dev, trace, k, patience);
+    hipLaunchKernelGGL(k_metric_final, dim3(1), dim3(256), 0, st, (const double *)mb.n2p, nblk,
+                       (const double *)mb.Fabs, ncoef, xs, ys, out, st_dev, trace, k, patience);
     LAUNCH_CHECK("k_metric_final");
     return LFRL_OK;
 }
@@ -1750,8 +2063,10 @@ extern "C" int lfrl_deconvolve(lfrl_plan_t p, int32_t h, int32_t w, const float 
         }
         iters = k;
         if (use_metric) {
-            rc = run_metric(p->g.Nz, h, w, nxt, opts->xs, opts->ys, p->metric_out, p->T1, p->n2p,
-                            p->Fabs, p->state, p->trace, k, opts->patience, st);
+            const MetricBufs mb{p->mip, p->tabH, p->tabW, p->T1, p->n2p, p->Fabs,
+                                &p->tab_h, &p->tab_nv, &p->tab_w, &p->tab_nu};
+            rc = run_metric(p->g.Nz, h, w, nxt, opts->xs, opts->ys, p->metric_out, mb, p->state,
+                            p->trace, k, opts->patience, st);
             if (rc)
                 return rc;
             hipLaunchKernelGGL(k_cond_copy, dim3(1024), dim3(256), 0, st, (const StopState *)p->state,
@@ -1801,11 +2116,21 @@ extern "C" int lfrl_deconvolve(lfrl_plan_t p, int32_t h, int32_t w, const float 
 
 // Scratch for the plan-less metric entry point: one growable set per device.
 struct MetricScratch {
-    double *T1 = nullptr, *n2p = nullptr, *Fabs = nullptr;
-    size_t w_cap = 0;
+    float *mip = nullptr;
+    double *tabH = nullptr, *tabW = nullptr, *T1 = nullptr, *n2p = nullptr, *Fabs = nullptr;
+    size_t h_cap = 0, w_cap = 0;
 };
 static std::mutex g_metric_mu;
 static std::vector<MetricScratch> g_metric_scratch;
+
+static void free_metric_scratch(MetricScratch &ms)
+{
+    void *b[] = {ms.mip, ms.tabH, ms.tabW, ms.T1, ms.n2p, ms.Fabs};
+    for (void *q : b)
+        if (q)
+            (void)hipFree(q);
+    ms = MetricScratch();
+}
 
 extern "C" int lfrl_metric(int32_t nz, int32_t h, int32_t w, const float *img, double xs,
                            double ys, double *out, void *stream)
@@ -1826,31 +2151,28 @@ extern "C" int lfrl_metric(int32_t nz, int32_t h, int32_t w, const float *img, d
     if ((int)g_metric_scratch.size() <= dev)
         g_metric_scratch.resize(dev + 1);
     MetricScratch &ms = g_metric_scratch[dev];
-    if (ms.w_cap < (size_t)w) {
-        if (ms.T1) {
+    if (ms.h_cap < (size_t)h || ms.w_cap < (size_t)w) {
+        if (ms.mip) {
             HIP_TRY(hipDeviceSynchronize());
-            (void)hipFree(ms.T1);
-            (void)hipFree(ms.n2p);
-            (void)hipFree(ms.Fabs);
-            ms = MetricScratch();
+            free_metric_scratch(ms);
         }
-        const size_t wc = std::max<size_t>(w, 1024);
-        rc = dalloc(&ms.T1, (size_t)kMetricChunks * kMaxMetricLegs * wc * sizeof(double));
-        if (!rc)
-            rc = dalloc(&ms.n2p, (size_t)kMetricChunks * wc * sizeof(double));
-        if (!rc)
-            rc = dalloc(&ms.Fabs, (size_t)kMaxMetricLegs * kMaxMetricLegs * sizeof(double));
+        const size_t hc = std::max<size_t>(h, 1024), wc = std::max<size_t>(w, 1024);
+        rc = dalloc(&ms.mip, hc * wc * sizeof(float));
+        if (!rc) rc = dalloc(&ms.tabH, (size_t)kMaxMetricLegs * hc * sizeof(double));
+        if (!rc) rc = dalloc(&ms.tabW, (size_t)kMaxMetricLegs * wc * sizeof(double));
+        if (!rc) rc = dalloc(&ms.T1, (size_t)kMetricChunks * kMaxMetricLegs * wc * sizeof(double));
+        if (!rc) rc = dalloc(&ms.n2p, (hc * wc + 255) / 256 * sizeof(double));
+        if (!rc) rc = dalloc(&ms.Fabs, (size_t)kMaxMetricLegs * kMaxMetricLegs * sizeof(double));
         if (rc) {
-            if (ms.T1) (void)hipFree(ms.T1);
-            if (ms.n2p) (void)hipFree(ms.n2p);
-            if (ms.Fabs) (void)hipFree(ms.Fabs);
-            ms = MetricScratch();
+            free_metric_scratch(ms);
             return rc;
         }
+        ms.h_cap = hc;
         ms.w_cap = wc;
     }
-    return run_metric(nz, h, w, img, xs, ys, out, ms.T1, ms.n2p, ms.Fabs, nullptr, nullptr, 0, 1,
-                      (hipStream_t)stream);
+    const MetricBufs mb{ms.mip, ms.tabH, ms.tabW, ms.T1, ms.n2p, ms.Fabs,
+                        nullptr, nullptr, nullptr, nullptr};
+    return run_metric(nz, h, w, img, xs, ys, out, mb, nullptr, nullptr, 0, 1, (hipStream_t)stream);
 }
 
 extern "C" int lfrl_metric_cutoff(double d_ml, double mag, int32_t nnum, double lambda, double na,

@@ -132,35 +132,60 @@ __device__ __forceinline__ void fft(float2 (&v)[Q], const float2 *__restrict__ t
 
 enum { SRC_PLANES = 0, SRC_PSF = 1 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Remap the linear block id so that every XCD works through one contiguous
+// range of work items: items that share cache lines then share an L2.
+__device__ __forceinline__ int xcd_item(int bid, int n)
+{
+    constexpr int kXcds = 8;
+    const int xcd = bid % kXcds, local = bid / kXcds;
+    const int base = n / kXcds, rem = n % kXcds;
+    return xcd * base + min(xcd, rem) + local;
+}
+
 // Forward real tile DFT of N interleaved phases, written as a half spectrum:
 // out[obase + k * kstride + p], k = ku * (Q/2 + 1) + kv.
 //   SRC_PLANES: one overlap-save tile of lenslet rows (plane j, row phase ar)
-//               of a [planes][H][W] array; blockIdx = (tile, j*N + ar).
+//               of a [planes][H][W] array; 1-D grid of nt * planes * N blocks,
+//               work item = (j*N + ar) * nt + tile (tiles of one row phase,
+//               which overlap, land on one XCD).
 //               obase = (tile * KKo + j*N*N + ar*N), kstride = nt * KKo.
 //   SRC_PSF:    the polyphase kernels G_{j,a->c}[D] = h[j][a][N*D + c - a + c0]
 //               for output row phase cr and all column phases, placed
-//               circularly in the tile; blockIdx = (cr, a, j).
-//               obase = ((j*N*N + a) * N*N + cr*N), kstride = KK * N*N.
+//               circularly in the tile; blockIdx = (cr, a, j); KKo is the row
+//               stride NNp of the spectra.
+//               obase = ((j*N*N + a) * NNp + cr*N), kstride = KK * NNp.
+//   rowmax (SRC_PLANES, may be null): rowmax[k * nt + tile] is raised (atomic
+//   max on the float bits) to the largest |re| or |im| the block writes at
+//   frequency k; the caller zeroes it first.
 template <int Q>
 __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const float *__restrict__ src, int H,
                                                   int W, int N, int T, int hD, int tiles_x, int nt,
                                                   int KKo, int K, int c0, int KK,
                                                   float2 *__restrict__ out,
-                                                  const float2 *__restrict__ twg)
+                                                  const float2 *__restrict__ twg,
+                                                  unsigned *__restrict__ rowmax)
 {
     constexpr int QH = Q / 2 + 1;
     extern __shared__ float smem[];
     float2 *tw = reinterpret_cast<float2 *>(smem);
     float *buf = smem + 2 * Q;
     float2 *Z = reinterpret_cast<float2 *>(buf);
+    const size_t buf_floats = (size_t)Q * Q * N > (size_t)2 * Q * QH * N ? (size_t)Q * Q * N
+                                                                         : (size_t)2 * Q * QH * N;
+    unsigned *kmax = reinterpret_cast<unsigned *>(buf + buf_floats);  // [Q * QH]
     const int tid = threadIdx.x;
     for (int i = tid; i < Q; i += blockDim.x)
         tw[i] = twg[i];
+    if (rowmax)
+        for (int i = tid; i < Q * QH; i += blockDim.x)
+            kmax[i] = 0u;
     const int rowlen = Q * N;
     size_t obase, kstride;
     if (mode == SRC_PLANES) {
-        const int tile = blockIdx.x;
-        const int j = blockIdx.y / N, ar = blockIdx.y % N;
+        const int item = xcd_item(blockIdx.x, gridDim.x);
+        const int tile = item % nt, jar = item / nt;
+        const int j = jar / N, ar = jar % N;
         const int ly0 = (tile / tiles_x) * T - hD, lx0 = (tile % tiles_x) * T - hD;
         const float *plane = src + (size_t)j * H * W;
         for (int idx = tid; idx < Q * rowlen; idx += blockDim.x) {
@@ -192,9 +217,8 @@ __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const float *__restri
             }
             buf[idx] = v;
         }
-        const size_t NN = (size_t)N * N;
-        obase = ((size_t)j * NN + a) * NN + (size_t)cr * N;
-        kstride = (size_t)KK * NN;
+        obase = ((size_t)j * N * N + a) * (size_t)KKo + (size_t)cr * N;
+        kstride = (size_t)KK * KKo;
     }
     __syncthreads();
     // row pass: two real rows per thread packed as one complex sequence
@@ -241,16 +265,33 @@ __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const float *__restri
 #pragma unroll
         for (int ku = 0; ku < Q; ++ku)
             out[obase + (size_t)(ku * QH + kv) * kstride + p] = v[ku];
+        if (rowmax) {
+#pragma unroll
+            for (int ku = 0; ku < Q; ++ku)
+                atomicMax(&kmax[ku * QH + kv],
+                          __float_as_uint(fmaxf(fabsf(v[ku].x), fabsf(v[ku].y))));
+        }
+    }
+    if (rowmax) {
+        __syncthreads();
+        const int tile = xcd_item(blockIdx.x, gridDim.x) % nt;
+        for (int i = tid; i < Q * QH; i += blockDim.x)
+            if (kmax[i])
+                atomicMax(&rowmax[(size_t)i * nt + tile], kmax[i]);
     }
 }
 
 // Inverse tile DFT of N interleaved phases with the crop to the T x T valid
 // lenslets and the per-pixel epilogue (see k_c2r for the modes).  The spectrum
-// is sum_s spec[s * split_stride + (k * nt + tile) * KKo + j*N*N + ar*N + p].
+// of column q = j*N*N + ar*N + p at frequency k is
+// sum_s spec[s * split_stride + k * sk + tile * stile + q * sc].
+// 1-D grid of nt * planes * N blocks, work item = tile * (planes * N) + j*N + ar
+// (consecutive phases of one tile read adjacent spectra and share an XCD).
 template <int Q>
 __global__ __launch_bounds__(512) void k_c2r_fft(const float2 *__restrict__ spec,
-                                                  size_t split_stride, int nsplit, int KKo, int N,
-                                                  int T, int hD, int tiles_x, int nt, int H, int W,
+                                                  size_t split_stride, int nsplit, size_t sk,
+                                                  size_t stile, size_t sc, int N, int planes,
+                                                  int T, int hD, int tiles_x, int H, int W,
                                                   int mode, float *__restrict__ dst,
                                                   const float *__restrict__ aux0,
                                                   const float *__restrict__ aux1,
@@ -263,8 +304,9 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const float2 *__restrict__ spec
     float2 *Zs = X + (size_t)Q * QH * N;
     float *obuf = reinterpret_cast<float *>(X);  // reused once X is consumed
     const int tid = threadIdx.x;
-    const int tile = blockIdx.x;
-    const int j = blockIdx.y / N, ar = blockIdx.y % N;
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    const int tile = item / (planes * N), jar = item % (planes * N);
+    const int j = jar / N, ar = jar % N;
     const int ty = tile / tiles_x, tx = tile % tiles_x;
     for (int i = tid; i < Q; i += blockDim.x)
         tw[i] = twg[i];
@@ -273,7 +315,7 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const float2 *__restrict__ spec
     for (int idx = tid; idx < total; idx += blockDim.x) {
         const int p = idx % N;
         const size_t k = idx / N;
-        const size_t off = (k * nt + tile) * KKo + kkbase + p;
+        const size_t off = k * sk + tile * stile + (kkbase + p) * sc;
         float2 acc = spec[off];
         for (int s = 1; s < nsplit; ++s) {
             const float2 v = spec[off + s * split_stride];

@@ -39,9 +39,10 @@ def test_footprint_and_cutoff_without_gpu():
                     tile_q=28, flags=0)
     res, ws = lf.lfrl_plan_footprint(d)
     nf = 28 * 15
-    spec = nf * 225 * 225 * 31 * 8          # one layout of the per-frequency spectra
+    kk = 225 * 31
+    spec = nf * kk * (240 + 225) * 8        # both layouts; forward rows padded to 240
     psf_copy = 31 * 225 * 255 * 255 * 4     # the PSF kept for exact weak-voxel sums
-    assert 2 * spec + psf_copy <= res < 2 * spec + psf_copy + 4096
+    assert spec + psf_copy <= res < spec + psf_copy + 4096
     assert ws > nf * 16 * 225 * 31 * 8      # tile spectra of the volume
     # monotone in image size
     d2 = lf.PlanDesc(nnum=15, nz=31, ksize=255, max_h=900, max_w=900, precision=0,
