@@ -132,6 +132,18 @@ __device__ __forceinline__ void fft(float2 (&v)[Q], const float2 *__restrict__ t
 
 enum { SRC_PLANES = 0, SRC_PSF = 1 };
 
+// Loads in these kernels are issued in batches of kLoadBatch per thread before
+// any of them is consumed, so a thread keeps that many requests in flight
+// instead of waiting out the memory latency once per element.  Addresses are
+// clamped to valid elements and unwanted values cleared with a bit mask (not a
+// select, which the compiler would turn into a branch around the load).
+static constexpr int kLoadBatch = 8;
+
+__device__ __forceinline__ float keep_if(float v, bool keep)
+{
+    return __uint_as_float(__float_as_uint(v) & (keep ? 0xffffffffu : 0u));
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
 // Remap the linear block id so that every XCD works through one contiguous
 // range of work items: items that share cache lines then share an L2.
@@ -188,14 +200,25 @@ __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const float *__restri
         const int j = jar / N, ar = jar % N;
         const int ly0 = (tile / tiles_x) * T - hD, lx0 = (tile % tiles_x) * T - hD;
         const float *plane = src + (size_t)j * H * W;
-        for (int idx = tid; idx < Q * rowlen; idx += blockDim.x) {
-            const int i = idx / rowlen, col = idx % rowlen;
-            const int pr = N * (ly0 + i) + ar;
-            const int pc = N * lx0 + col;
-            float v = 0.f;
-            if (pr >= 0 && pr < H && pc >= 0 && pc < W)
-                v = plane[(size_t)pr * W + pc];
-            buf[idx] = v;
+        const int total = Q * rowlen;
+        for (int base = tid; base < total; base += kLoadBatch * blockDim.x) {
+            float v[kLoadBatch];
+#pragma unroll
+            for (int b = 0; b < kLoadBatch; ++b) {
+                const int idx = min(base + b * (int)blockDim.x, total - 1);
+                const int i = idx / rowlen, col = idx % rowlen;
+                const int pr = N * (ly0 + i) + ar;
+                const int pc = N * lx0 + col;
+                const bool ok = pr >= 0 && pr < H && pc >= 0 && pc < W;
+                const float x = plane[(size_t)min(max(pr, 0), H - 1) * W + min(max(pc, 0), W - 1)];
+                v[b] = keep_if(x, ok);
+            }
+#pragma unroll
+            for (int b = 0; b < kLoadBatch; ++b) {
+                const int idx = base + b * (int)blockDim.x;
+                if (idx < total)
+                    buf[idx] = v[b];
+            }
         }
         obase = (size_t)tile * KKo + (size_t)j * N * N + (size_t)ar * N;
         kstride = (size_t)nt * KKo;
@@ -312,17 +335,34 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const float2 *__restrict__ spec
         tw[i] = twg[i];
     const size_t kkbase = (size_t)j * N * N + (size_t)ar * N;
     const int total = Q * QH * N;
-    for (int idx = tid; idx < total; idx += blockDim.x) {
-        const int p = idx % N;
-        const size_t k = idx / N;
-        const size_t off = k * sk + tile * stile + (kkbase + p) * sc;
-        float2 acc = spec[off];
-        for (int s = 1; s < nsplit; ++s) {
-            const float2 v = spec[off + s * split_stride];
-            acc.x += v.x;
-            acc.y += v.y;
+    for (int base = tid; base < total; base += kLoadBatch * blockDim.x) {
+        float2 acc[kLoadBatch];
+        size_t off[kLoadBatch];
+#pragma unroll
+        for (int b = 0; b < kLoadBatch; ++b) {
+            const int idx = min(base + b * (int)blockDim.x, total - 1);
+            const int p = idx % N;
+            const size_t k = idx / N;
+            off[b] = k * sk + tile * stile + (kkbase + p) * sc;
+            acc[b] = spec[off[b]];
         }
-        X[idx] = acc;
+        for (int s = 1; s < nsplit; ++s) {
+            float2 part[kLoadBatch];
+#pragma unroll
+            for (int b = 0; b < kLoadBatch; ++b)
+                part[b] = spec[off[b] + s * split_stride];
+#pragma unroll
+            for (int b = 0; b < kLoadBatch; ++b) {
+                acc[b].x += part[b].x;
+                acc[b].y += part[b].y;
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < kLoadBatch; ++b) {
+            const int idx = base + b * (int)blockDim.x;
+            if (idx < total)
+                X[idx] = acc[b];
+        }
     }
     __syncthreads();
     float2 v[Q];
@@ -381,22 +421,34 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const float2 *__restrict__ spec
     // coalesced epilogue over whole pixel rows of the tile
     const int Ly = H / N, Lx = W / N;
     const int rowpix = T * N;
-    for (int idx = tid; idx < T * rowpix; idx += blockDim.x) {
-        const int ti = idx / rowpix, rem = idx % rowpix;
-        const int Lr = ty * T + ti, Lc = tx * T + rem / N;
-        if (Lr >= Ly || Lc >= Lx)
-            continue;
-        const float val = obuf[idx];
-        const int pr = N * Lr + ar, pc = N * tx * T + rem;
-        const size_t pix = (size_t)pr * W + pc;
-        if (mode == 0) {
-            dst[(size_t)j * H * W + pix] = val;
-        } else if (mode == 1) {
-            dst[pix] = val > 0.f ? aux0[pix] / val : 0.f;
-        } else {
-            const size_t o = (size_t)j * H * W + pix;
-            const float c = aux1[o];
-            dst[o] = c > 0.f ? aux0[o] * val / c : 0.f;
+    const int ototal = T * rowpix;
+    for (int base = tid; base < ototal; base += kLoadBatch * blockDim.x) {
+        size_t o[kLoadBatch];
+        bool ok[kLoadBatch];
+        float a0[kLoadBatch], a1[kLoadBatch];
+#pragma unroll
+        for (int b = 0; b < kLoadBatch; ++b) {
+            const int idx = min(base + b * (int)blockDim.x, ototal - 1);
+            const int ti = idx / rowpix, rem = idx % rowpix;
+            const int Lr = ty * T + ti, Lc = tx * T + rem / N;
+            ok[b] = base + b * (int)blockDim.x < ototal && Lr < Ly && Lc < Lx;
+            const int pr = min(N * Lr + ar, H - 1), pc = min(N * tx * T + rem, W - 1);
+            const size_t pix = (size_t)pr * W + pc;
+            o[b] = (mode == 1 ? 0 : (size_t)j * H * W) + pix;
+            a0[b] = (mode != 0) ? aux0[o[b]] : 0.f;
+            a1[b] = (mode == 2) ? aux1[o[b]] : 0.f;
+        }
+#pragma unroll
+        for (int b = 0; b < kLoadBatch; ++b) {
+            if (!ok[b])
+                continue;
+            const float val = obuf[base + b * (int)blockDim.x];
+            if (mode == 0)
+                dst[o[b]] = val;
+            else if (mode == 1)
+                dst[o[b]] = val > 0.f ? a0[b] / val : 0.f;
+            else
+                dst[o[b]] = a1[b] > 0.f ? a0[b] * val / a1[b] : 0.f;
         }
     }
 }
