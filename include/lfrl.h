@@ -22,7 +22,8 @@
  *     NULL = the null stream) unless stated otherwise.
  *   - The caller owns every buffer it passes.  A plan owns its PSF spectra and
  *     its workspace; after lfrl_plan returns, no call allocates device memory
- *     except lfrl_metric (see there).
+ *     except lfrl_metric (see there) and the job calls (a job's state is
+ *     allocated by lfrl_job_create, sized by lfrl_job_footprint).
  *   - One call at a time per plan (calls on one plan share its workspace).
  *   - Calls return LFRL_OK or a negative lfrl_status and never throw.  Argument
  *     errors are reported before anything is launched; lfrl_last_error() gives
@@ -70,6 +71,9 @@ typedef struct {
     int32_t precision; /* lfrl_precision */
     int32_t tile_q;    /* DFT tile side in lenslets; 0 = choose from the model */
     uint32_t flags;    /* reserved, must be 0 */
+    int32_t max_batch; /* frames of max_h x max_w whose tiles one batched
+                          projection covers (lfrl_job_step); 0 or 1 = one
+                          frame, at most 16.  Workspace grows with it. */
 } lfrl_plan_desc;
 
 /* Read-only facts about a plan (all [host]). */
@@ -78,10 +82,12 @@ typedef struct {
     int32_t tile_out;      /* output lenslets per tile side T = Q - R + 1 */
     int32_t taps;          /* polyphase taps per side R */
     int32_t nfreq;         /* half-spectrum frequencies per tile, Q * (Q/2 + 1) */
-    int32_t max_tiles;     /* tiles at the plan's largest image */
+    int32_t max_tiles;     /* tiles one projection covers: max_batch frames of
+                              the plan's largest image */
     int32_t split_k;       /* reduction split of the forward contraction */
     size_t resident_bytes; /* spectra held for the plan's lifetime */
-    size_t workspace_bytes;/* per-call workspace at the largest image */
+    size_t workspace_bytes;/* workspace: tile spectra for max_tiles tiles plus
+                              the frame state of lfrl_deconvolve */
 } lfrl_plan_info_t;
 
 /* Memory estimate before allocation (Fig. 1: the required memory is
@@ -164,6 +170,64 @@ typedef struct {
 int lfrl_deconvolve(lfrl_plan_t plan, int32_t h, int32_t w, const float *img,
                     float *vol, const lfrl_rl_opts *opts, lfrl_rl_report *report,
                     void *stream);
+
+/* ---- batched and served deconvolution --------------------------------------
+ * A job is one frame's Richardson-Lucy run (the iteration and stop rule of
+ * lfrl_deconvolve) held on the device between calls: its own copy of the
+ * image, the iterates, A^T 1 with its weakly observed voxels, and the metric
+ * and stop state.  lfrl_job_step advances many jobs by one iteration each.
+ * Jobs on one plan share every launch of the projections: their tiles are
+ * concatenated along the contraction's tile dimension, so the plan's spectra
+ * stream from memory once per projection for the whole batch (up to
+ * max_batch largest frames, or 16 frames, per launch).  Jobs on different
+ * plans run side by side on internal streams.  A job's iterates do not depend
+ * on which other jobs share its steps.  Calls on jobs of one plan, and that
+ * plan's other calls, must not overlap (they share its workspace). */
+typedef struct lfrl_job_s *lfrl_job_t;
+
+enum { LFRL_JOB_FLUX = 1u << 0 }; /* record the flux trace of the report */
+
+/* Device bytes lfrl_job_create allocates for an h x w frame on `plan` (the
+ * admission figure of a serving loop, in the spirit of Fig. 1's estimate
+ * before allocation).  [host], no device work. */
+int lfrl_job_footprint(lfrl_plan_t plan, int32_t h, int32_t w, size_t *bytes);
+
+/* Create a job for image img [h][w] (copied; the caller may reuse img once
+ * the call returns) with the options of lfrl_deconvolve.  vol0 [nz][h][w] is
+ * the start volume when opts->init == 1 (copied), else ignored.  Computes A^T 1
+ * for the frame and synchronises `stream`.  Returns LFRL_ERR_NUMERIC, and
+ * creates nothing, when img holds a negative or non-finite value;
+ * LFRL_ERR_NOMEM when the job's memory cannot be allocated. */
+int lfrl_job_create(lfrl_job_t *out, lfrl_plan_t plan, int32_t h, int32_t w,
+                    const float *img, const float *vol0, const lfrl_rl_opts *opts,
+                    uint32_t flags, void *stream);
+
+/* One Richardson-Lucy iteration for every listed job that is not done (a job
+ * is done at its iteration cap, or, with LFRL_STOP_METRIC, once the stop rule
+ * fired).  Synchronises `stream` when a listed job uses LFRL_STOP_METRIC (the
+ * host needs the decision); otherwise only queues work.  *active (may be
+ * NULL) receives the number of listed jobs not yet done. */
+int lfrl_job_step(const lfrl_job_t *jobs, int32_t njobs, int32_t *active, void *stream);
+
+/* Host-side state as of the last step: done flag and iterations run. */
+int lfrl_job_poll(lfrl_job_t job, int32_t *done, int32_t *iters_run);
+
+/* Copy the job's result (the iterate lfrl_deconvolve would return after the
+ * same iterations) into vol [nz][h][w] (may be NULL) and fill `report` [host]
+ * (may be NULL).  Synchronises `stream`. */
+int lfrl_job_result(lfrl_job_t job, float *vol, lfrl_rl_report *report, void *stream);
+
+/* Release a job (NULL accepted).  Call once no queued work uses it
+ * (lfrl_job_result synchronises its stream), and before destroying its plan. */
+int lfrl_job_destroy(lfrl_job_t job);
+
+/* Deconvolve n frames, each on its own plan (plans may repeat) and size, as
+ * jobs stepped together until all are done; vols[i] [nz_i][h_i][w_i] receives
+ * frame i's result and reports[i] (array may be NULL) its report.  Allocates
+ * the jobs' state for the duration of the call; synchronises `stream`. */
+int lfrl_deconvolve_batch(const lfrl_plan_t *plans, int32_t n, const int32_t *h,
+                          const int32_t *w, const float *const *imgs, float *const *vols,
+                          const lfrl_rl_opts *opts, lfrl_rl_report *reports, void *stream);
 
 /* DCT entropy of a 2-D image (sec. 2.2, Eqs. 1-6 and 12): F = orthonormal
  * DCT-II of img (Eqs. 1-4), n = Frobenius norm of F (the "2-norm of a matrix"),

@@ -45,7 +45,7 @@ class PlanDesc(ctypes.Structure):
     _fields_ = [("nnum", ctypes.c_int32), ("nz", ctypes.c_int32), ("ksize", ctypes.c_int32),
                 ("max_h", ctypes.c_int32), ("max_w", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("tile_q", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("max_batch", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -97,6 +97,16 @@ def _load():
         "lfrl_metric": [i32, i32, i32, vp, dbl, dbl, vp, vp],
         "lfrl_metric_cutoff": [dbl, dbl, i32, dbl, dbl, i32, i32,
                                ctypes.POINTER(dbl), ctypes.POINTER(dbl)],
+        "lfrl_job_footprint": [vp, i32, i32, sz],
+        "lfrl_job_create": [ctypes.POINTER(vp), vp, i32, i32, vp, vp, ctypes.POINTER(RlOpts),
+                            ctypes.c_uint32, vp],
+        "lfrl_job_step": [ctypes.POINTER(vp), i32, ctypes.POINTER(i32), vp],
+        "lfrl_job_poll": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "lfrl_job_result": [vp, vp, ctypes.POINTER(RlReport), vp],
+        "lfrl_job_destroy": [vp],
+        "lfrl_deconvolve_batch": [ctypes.POINTER(vp), i32, ctypes.POINTER(i32),
+                                  ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                  ctypes.POINTER(RlOpts), ctypes.POINTER(RlReport), vp],
         "lfrl_profile_enable": [vp, i32],
         "lfrl_profile_read": [vp, ctypes.c_char_p, ctypes.POINTER(dbl),
                               ctypes.POINTER(ctypes.c_int64)],
@@ -180,22 +190,10 @@ def lfrl_backward(plan: int, h: int, w: int, img: torch.Tensor, vol: torch.Tenso
 def lfrl_deconvolve(plan: int, h: int, w: int, img: torch.Tensor, vol: torch.Tensor,
                     opts: RlOpts, want_metric: bool = True, want_flux: bool = False,
                     stream=None) -> dict:
-    n = max(int(opts.max_iters), 1)
-    mt = (ctypes.c_double * n)() if want_metric else None
-    ft = (ctypes.c_double * n)() if want_flux else None
-    rep = RlReport()
-    rep.metric_trace = ctypes.cast(mt, ctypes.POINTER(ctypes.c_double)) if mt is not None else None
-    rep.flux_trace = ctypes.cast(ft, ctypes.POINTER(ctypes.c_double)) if ft is not None else None
+    rep, mt, ft = _report_buffers(max(int(opts.max_iters), 1), want_metric, want_flux)
     _check(_load().lfrl_deconvolve(plan, h, w, _dev_f32(img, "img"), _dev_f32(vol, "vol"),
                                    ctypes.byref(opts), ctypes.byref(rep), _stream(stream)))
-    k = rep.iters_run
-    out = {"iters_run": k, "best_iter": rep.best_iter, "stopped": bool(rep.stopped),
-           "weak_voxels": rep.weak_voxels}
-    if mt is not None and opts.stop != STOP_NONE:
-        out["metric_trace"] = list(mt[:k])
-    if ft is not None:
-        out["flux_trace"] = list(ft[:k])
-    return out
+    return _report_dict(rep, mt, ft, opts.stop)
 
 
 def lfrl_metric(nz: int, h: int, w: int, img: torch.Tensor, xs: float, ys: float,
@@ -212,6 +210,88 @@ def lfrl_metric_cutoff(d_ml: float, mag: float, nnum: int, wavelength: float, na
     _check(_load().lfrl_metric_cutoff(d_ml, mag, nnum, wavelength, na, h, w,
                                       ctypes.byref(xs), ctypes.byref(ys)))
     return xs.value, ys.value
+
+
+JOB_FLUX = 1
+
+
+def _report_buffers(n: int, want_metric: bool, want_flux: bool):
+    mt = (ctypes.c_double * n)() if want_metric else None
+    ft = (ctypes.c_double * n)() if want_flux else None
+    rep = RlReport()
+    rep.metric_trace = ctypes.cast(mt, ctypes.POINTER(ctypes.c_double)) if mt is not None else None
+    rep.flux_trace = ctypes.cast(ft, ctypes.POINTER(ctypes.c_double)) if ft is not None else None
+    return rep, mt, ft
+
+
+def _report_dict(rep: RlReport, mt, ft, stop: int) -> dict:
+    k = rep.iters_run
+    out = {"iters_run": k, "best_iter": rep.best_iter, "stopped": bool(rep.stopped),
+           "weak_voxels": rep.weak_voxels}
+    if mt is not None and stop != STOP_NONE:
+        out["metric_trace"] = list(mt[:k])
+    if ft is not None:
+        out["flux_trace"] = list(ft[:k])
+    return out
+
+
+def lfrl_job_footprint(plan: int, h: int, w: int) -> int:
+    b = ctypes.c_size_t()
+    _check(_load().lfrl_job_footprint(plan, h, w, ctypes.byref(b)))
+    return b.value
+
+
+def lfrl_job_create(plan: int, h: int, w: int, img: torch.Tensor, opts: RlOpts,
+                    vol0: Optional[torch.Tensor] = None, flags: int = 0, stream=None) -> int:
+    j = ctypes.c_void_p()
+    v0 = _dev_f32(vol0, "vol0") if vol0 is not None else None
+    _check(_load().lfrl_job_create(ctypes.byref(j), plan, h, w, _dev_f32(img, "img"), v0,
+                                   ctypes.byref(opts), flags, _stream(stream)))
+    return j.value
+
+
+def lfrl_job_step(jobs, stream=None) -> int:
+    arr = (ctypes.c_void_p * max(len(jobs), 1))(*jobs)
+    active = ctypes.c_int32()
+    _check(_load().lfrl_job_step(arr, len(jobs), ctypes.byref(active), _stream(stream)))
+    return active.value
+
+
+def lfrl_job_poll(job: int):
+    d, k = ctypes.c_int32(), ctypes.c_int32()
+    _check(_load().lfrl_job_poll(job, ctypes.byref(d), ctypes.byref(k)))
+    return bool(d.value), k.value
+
+
+def lfrl_job_result(job: int, vol: Optional[torch.Tensor], max_iters: int, stop: int,
+                    want_metric: bool = True, want_flux: bool = False, stream=None) -> dict:
+    rep, mt, ft = _report_buffers(max(max_iters, 1), want_metric, want_flux)
+    _check(_load().lfrl_job_result(job, _dev_f32(vol, "vol") if vol is not None else None,
+                                   ctypes.byref(rep), _stream(stream)))
+    return _report_dict(rep, mt, ft, stop)
+
+
+def lfrl_job_destroy(job: int) -> None:
+    _check(_load().lfrl_job_destroy(job))
+
+
+def lfrl_deconvolve_batch(plans, hs, ws, imgs, vols, opts, want_flux: bool = False,
+                          stream=None) -> list:
+    n = len(plans)
+    P = (ctypes.c_void_p * n)(*plans)
+    H = (ctypes.c_int32 * n)(*hs)
+    W = (ctypes.c_int32 * n)(*ws)
+    I = (ctypes.c_void_p * n)(*[_dev_f32(t, "img") for t in imgs])
+    V = (ctypes.c_void_p * n)(*[_dev_f32(t, "vol") for t in vols])
+    O = (RlOpts * n)(*opts)
+    R = (RlReport * n)()
+    keep = []
+    for i in range(n):
+        rep, mt, ft = _report_buffers(max(int(opts[i].max_iters), 1), True, want_flux)
+        R[i] = rep
+        keep.append((mt, ft))
+    _check(_load().lfrl_deconvolve_batch(P, n, H, W, I, V, O, R, _stream(stream)))
+    return [_report_dict(R[i], keep[i][0], keep[i][1], opts[i].stop) for i in range(n)]
 
 
 def lfrl_profile_enable(plan: int, on: bool) -> None:
@@ -231,12 +311,13 @@ class Plan:
     """Resident PSF spectra for one PSF set, serving images up to max_h x max_w."""
 
     def __init__(self, psf: torch.Tensor, max_h: int, max_w: int, tile_q: int = 0,
-                 precision: int = FP32, stream=None):
+                 precision: int = FP32, max_batch: int = 1, stream=None):
         nz, n, n2, k, k2 = psf.shape
         if n != n2 or k != k2:
             raise LfrlError(-1, "psf must be [nz][N][N][K][K]")
         self.desc = PlanDesc(nnum=n, nz=nz, ksize=k, max_h=max_h, max_w=max_w,
-                             precision=precision, tile_q=tile_q, flags=0)
+                             precision=precision, tile_q=tile_q, flags=0,
+                             max_batch=max_batch)
         self.nnum, self.nz, self.ksize = n, nz, k
         self.device = psf.device
         self.handle = lfrl_plan(self.desc, psf, stream)
@@ -281,6 +362,48 @@ class Plan:
         rep = lfrl_deconvolve(self.handle, h, w, img, out, opts, want_metric=True,
                               want_flux=want_flux, stream=stream)
         return out, rep
+
+
+class Job:
+    """One frame's Richardson-Lucy run held on the device (see lfrl_job_create)."""
+
+    def __init__(self, plan: Plan, img: torch.Tensor, iters: int, *, stop: int = STOP_NONE,
+                 patience: int = 1, xs: float = 1.0, ys: float = 1.0,
+                 init: Optional[torch.Tensor] = None, want_flux: bool = False, stream=None):
+        self.plan = plan
+        self.h, self.w = img.shape
+        self.opts = RlOpts(max_iters=iters, stop=stop, patience=patience,
+                           init=0 if init is None else 1, xs=xs, ys=ys)
+        self.want_flux = want_flux
+        self.handle = lfrl_job_create(plan.handle, self.h, self.w, img, self.opts, vol0=init,
+                                      flags=JOB_FLUX if want_flux else 0, stream=stream)
+
+    @staticmethod
+    def step(jobs, stream=None) -> int:
+        """One iteration for every job not done; returns how many are not done."""
+        return lfrl_job_step([j.handle for j in jobs], stream)
+
+    def poll(self):
+        return lfrl_job_poll(self.handle)
+
+    def result(self, out: Optional[torch.Tensor] = None, stream=None):
+        if out is None:
+            out = torch.empty((self.plan.nz, self.h, self.w), dtype=torch.float32,
+                              device=self.plan.device)
+        rep = lfrl_job_result(self.handle, out, int(self.opts.max_iters), int(self.opts.stop),
+                              want_flux=self.want_flux, stream=stream)
+        return out, rep
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            lfrl_job_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def metric(img: torch.Tensor, xs: float, ys: float, stream=None) -> float:

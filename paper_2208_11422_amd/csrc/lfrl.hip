@@ -261,14 +261,15 @@ __global__ void k_transpose_spec(const float2 *__restrict__ Gf, float2 *__restri
 // column phases) from a [planes][H][W] array and write its half spectrum:
 // out[k][tile][kk] with kk = j*N*N + ar*N + ac.  Lenslets outside the image
 // are zero (linear, not circular, convolution).
-__global__ void k_vol_r2c(const float *__restrict__ src, int H, int W, int N, int Q, int QH,
-                          int T, int hD, int tiles_x, int nt, int KKo,
-                          float2 *__restrict__ out, const float2 *__restrict__ twg)
+__global__ void k_vol_r2c(const TileBatch batch, int N, int Q, int QH, int T, int hD, int nt,
+                          int KKo, float2 *__restrict__ out, const float2 *__restrict__ twg)
 {
     extern __shared__ float smem[];
     const int tile = blockIdx.x;
     const int j = blockIdx.y / N, ar = blockIdx.y % N;
-    const int ty = tile / tiles_x, tx = tile % tiles_x;
+    const TileJob &fj = batch.job[batch_job(batch, tile)];
+    const int H = fj.H, W = fj.W, lt = tile - fj.tile0;
+    const int ty = lt / fj.tiles_x, tx = lt % fj.tiles_x;
     const int ly0 = ty * T - hD, lx0 = tx * T - hD;
     const int rowlen = Q * N;
     size_t in_n = (size_t)Q * rowlen;
@@ -278,7 +279,7 @@ __global__ void k_vol_r2c(const float *__restrict__ src, int H, int W, int N, in
     float2 *tw = Z + (size_t)Q * QH * N;
     for (int i = threadIdx.x; i < Q; i += blockDim.x)
         tw[i] = twg[i];
-    const float *plane = src + (size_t)j * H * W;
+    const float *plane = fj.src + (size_t)j * H * W;
     for (int idx = threadIdx.x; idx < Q * rowlen; idx += blockDim.x) {
         const int i = idx / rowlen, col = idx % rowlen;
         const int pr = N * (ly0 + i) + ar;
@@ -323,16 +324,19 @@ enum { EPI_STORE = 0, EPI_RATIO = 1, EPI_UPDATE = 2 };
 //             RATIO  dst[pr][pc] = v > 0 ? aux0[pr][pc] / v : 0   (rho = y / A x)
 //             UPDATE dst[j][pr][pc] = aux1 > 0 ? aux0 * v / aux1 : 0
 //                    (x_new = x_old * A^T rho / A^T 1)
-__global__ void k_c2r(const float2 *__restrict__ spec, size_t split_stride, int nsplit, size_t sk,
-                      size_t stile, size_t sc, int N, int Q, int QH, int T, int hD, int tiles_x,
-                      int H, int W,
-                      int mode, float *__restrict__ dst, const float *__restrict__ aux0,
-                      const float *__restrict__ aux1, const float2 *__restrict__ twg)
+__global__ void k_c2r(const TileBatch batch, const float2 *__restrict__ spec, size_t split_stride,
+                      int nsplit, size_t sk, size_t stile, size_t sc, int N, int Q, int QH, int T,
+                      int hD, int mode, const float2 *__restrict__ twg)
 {
     extern __shared__ float smem[];
     const int tile = blockIdx.x;
     const int j = blockIdx.y / N, ar = blockIdx.y % N;
-    const int ty = tile / tiles_x, tx = tile % tiles_x;
+    const TileJob &fj = batch.job[batch_job(batch, tile)];
+    const int H = fj.H, W = fj.W, lt = tile - fj.tile0;
+    const int ty = lt / fj.tiles_x, tx = lt % fj.tiles_x;
+    float *__restrict__ dst = fj.dst;
+    const float *__restrict__ aux0 = fj.aux0;
+    const float *__restrict__ aux1 = fj.aux1;
     float2 *X = reinterpret_cast<float2 *>(smem);
     float2 *Z = X + (size_t)Q * QH * N;
     float2 *tw = Z + (size_t)T * QH * N;
@@ -955,15 +959,15 @@ static void set_fft_lds_attrs(int Q, size_t lds)
 }
 
 static void launch_r2c_fft(int Q, dim3 grid, int block, size_t lds, hipStream_t st, int mode,
-                           const float *src, int H, int W, int N, int T, int hD, int tiles_x,
-                           int nt, int KKo, int K, int c0, int KK, float2 *out, const float2 *tw,
+                           const TileBatch &batch, const float *src, int N, int T, int hD, int nt,
+                           int KKo, int K, int c0, int KK, float2 *out, const float2 *tw,
                            unsigned *rowmax = nullptr)
 {
     switch (Q) {
 #define LFRL_CASE(q)                                                                        \
     case q:                                                                                 \
-        hipLaunchKernelGGL(k_r2c_fft<q>, grid, dim3(block), lds, st, mode, src, H, W, N, T,  \
-                           hD, tiles_x, nt, KKo, K, c0, KK, out, tw, rowmax);                \
+        hipLaunchKernelGGL(k_r2c_fft<q>, grid, dim3(block), lds, st, mode, batch, src, N, T, \
+                           hD, nt, KKo, K, c0, KK, out, tw, rowmax);                         \
         break;
         LFRL_FFT_Q_LIST(LFRL_CASE)
 #undef LFRL_CASE
@@ -973,17 +977,15 @@ static void launch_r2c_fft(int Q, dim3 grid, int block, size_t lds, hipStream_t 
 }
 
 static void launch_c2r_fft(int Q, dim3 grid, int block, size_t lds, hipStream_t st,
-                           const float2 *spec, size_t split_stride, int nsplit, size_t sk,
-                           size_t stile, size_t sc, int N, int planes, int T, int hD, int tiles_x,
-                           int H, int W, int mode, float *dst, const float *aux0,
-                           const float *aux1, const float2 *tw)
+                           const TileBatch &batch, const float2 *spec, size_t split_stride,
+                           int nsplit, size_t sk, size_t stile, size_t sc, int N, int planes,
+                           int T, int hD, int mode, const float2 *tw)
 {
     switch (Q) {
 #define LFRL_CASE(q)                                                                        \
     case q:                                                                                 \
-        hipLaunchKernelGGL(k_c2r_fft<q>, grid, dim3(block), lds, st, spec, split_stride,     \
-                           nsplit, sk, stile, sc, N, planes, T, hD, tiles_x, H, W, mode, dst, \
-                           aux0, aux1, tw);                                                 \
+        hipLaunchKernelGGL(k_c2r_fft<q>, grid, dim3(block), lds, st, batch, spec,            \
+                           split_stride, nsplit, sk, stile, sc, N, planes, T, hD, mode, tw);  \
         break;
         LFRL_FFT_Q_LIST(LFRL_CASE)
 #undef LFRL_CASE
@@ -1115,27 +1117,64 @@ __global__ void k_weak_exact(const unsigned *__restrict__ list, const float *__r
 // ---------------------------------------------------------------------------
 static constexpr int kDotBlocks = 512;
 
+// Raise *flag when any of the n values is negative or not finite (an image RL
+// cannot take: the ratio y / A x and the multiplicative update assume y >= 0).
+__global__ void k_check_image(const float *__restrict__ a, size_t n, unsigned *__restrict__ flag)
+{
+    bool bad = false;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const float v = a[i];
+        bad |= !(v >= 0.f) || !(v <= 3.402823466e38f);
+    }
+    if (bad)
+        atomicOr(flag, 1u);
+}
+
+// Device state of one frame's Richardson-Lucy run: the measured image, the
+// ratio image, the iterates, A^T 1 with its weakly observed voxels, and the
+// metric / stop state.  The plan holds one for lfrl_deconvolve; every job
+// holds its own.  All device buffers are carved from one allocation.
+struct Frame {
+    int h = 0, w = 0;
+    const float *y = nullptr;          // measured image [h][w]
+    float *y_own = nullptr;            // the job's copy of it (jobs only)
+    float *rho = nullptr;              // y / A x; the ones image while A^T 1 is formed
+    float *V[2] = {nullptr, nullptr};  // x^{k-1} and x^k (ping-pong)
+    float *VB = nullptr;               // best iterate under a metric stop mode
+    float *sens = nullptr;             // A^T 1 [Nz][h][w]
+    unsigned *weak = nullptr;          // weakly observed voxels
+    unsigned *counters = nullptr;      // [0] weak count, [1] bad-input flag
+    unsigned *counters_host = nullptr; // pinned copy
+    float *cmax = nullptr;             // [kDotBlocks + 1] max partials, max at [kDotBlocks]
+    unsigned weak_cap = 0, nweak = 0;
+    float *mip = nullptr;
+    double *tabH = nullptr, *tabW = nullptr, *T1 = nullptr, *n2p = nullptr, *Fabs = nullptr;
+    double *metric_out = nullptr, *trace = nullptr, *flux = nullptr, *dotp = nullptr;
+    StopState *state = nullptr;
+    StopState *state_host = nullptr;   // pinned
+    int tab_h = -1, tab_nv = -1, tab_w = -1, tab_nu = -1;
+    void *block = nullptr;             // the device allocation (owned by the job or plan)
+    size_t block_bytes = 0;
+    // run state
+    lfrl_rl_opts opts{};
+    bool want_flux = false;
+    int iters = 0;
+    bool done = false, stopped = false;
+};
+
 struct lfrl_plan_s {
     int device = 0;
     Geo g{};
-    int max_h = 0, max_w = 0, max_tiles = 0, split_k = 1;
+    int max_h = 0, max_w = 0;
+    int frame_tiles = 0;  // tiles of a max_h x max_w frame
+    int max_tiles = 0;    // tiles one batched launch covers
+    int split_k = 1;
     size_t resident = 0, workspace = 0;
     float2 *Gf = nullptr, *Gb = nullptr, *tw = nullptr;
     float2 *X = nullptr, *Yp = nullptr, *Rs = nullptr;
-    float *img = nullptr, *sens = nullptr, *vol[3] = {nullptr, nullptr, nullptr};
-    double *T1 = nullptr, *n2p = nullptr, *Fabs = nullptr, *metric_out = nullptr;
-    double *tabH = nullptr, *tabW = nullptr;  // DCT basis rows (Eqs. 2-4)
-    float *mip = nullptr;
-    int tab_h = -1, tab_nv = -1, tab_w = -1, tab_nu = -1;
-    double *trace = nullptr, *flux = nullptr, *dotp = nullptr;
-    StopState *state = nullptr;
-    StopState *state_host = nullptr;  // pinned
-    float *psf = nullptr;             // resident copy of the PSF set (weak-voxel sums)
-    unsigned *weak = nullptr;         // weakly observed voxel list
-    unsigned *weak_count = nullptr;   // device counter
-    unsigned *weak_count_host = nullptr;  // pinned
-    float *cmax = nullptr;            // [kDotBlocks + 1] max partials, max at [kDotBlocks]
-    unsigned weak_cap = 0, nweak = 0;
+    float *psf = nullptr;  // resident copy of the PSF set (weak-voxel sums)
+    Frame fr;              // frame state of lfrl_deconvolve (sized for max_h x max_w)
     int sens_h = -1, sens_w = -1;
     size_t lds_r2c_bytes = 0, lds_c2r_bytes = 0;
     bool use_fft = false;  // tile DFTs by the register FFT kernels
@@ -1170,6 +1209,8 @@ static int validate_desc(const lfrl_plan_desc *d)
         return set_error(LFRL_ERR_ARG, "flags must be 0");
     if (d->tile_q < 0 || d->tile_q > kMaxQ)
         return set_error(LFRL_ERR_ARG, "tile_q must be in [0, %d]", kMaxQ);
+    if (d->max_batch < 0 || d->max_batch > kMaxBatchJobs)
+        return set_error(LFRL_ERR_ARG, "max_batch must be in [0, %d]", kMaxBatchJobs);
     return LFRL_OK;
 }
 
@@ -1281,50 +1322,106 @@ static void default_shapes(const Geo &g, int *fcb, int *fu, int *acb, int *au)
     }
 }
 
-struct Sizes {
-    size_t Gf, Gb, tw, psf, X, Yp, Rs, img, vol, T1, n2p, Fabs, trace, dotp, weak, tabH, tabW;
-    size_t Hf = 0, Hb = 0, gexp = 0, rowmax = 0;  // split FP16 only
-    bool split = false;
-    size_t resident() const { return (split ? Hf + Hb + gexp : Gf + Gb) + tw + psf; }
-    size_t workspace() const
-    {
-        return X + Yp + Rs + 2 * img + 4 * vol + T1 + n2p + Fabs + 2 * trace + 2 * dotp + weak +
-               tabH + tabW + 2 * rowmax + 512;
-    }
-};
-
 static unsigned weak_cap_for(size_t nvox)
 {
     return (unsigned)std::min<size_t>(nvox, (size_t)1 << 20);
 }
 
-static Sizes sizes_for(const Geo &g, int max_h, int max_w, int split, bool f16 = false)
+// Device buffers of one Frame, in the order they are carved from its block.
+enum {
+    FB_Y, FB_RHO, FB_V0, FB_V1, FB_VB, FB_SENS, FB_WEAK, FB_COUNTERS, FB_CMAX, FB_MIP, FB_TABH,
+    FB_TABW, FB_T1, FB_N2P, FB_FABS, FB_MOUT, FB_TRACE, FB_FLUX, FB_DOTP, FB_STATE, FB_COUNT
+};
+
+// Byte offsets (256-byte aligned) of a Frame's buffers for an h x w image;
+// returns the block size.  own_y: the frame keeps its own copy of the image.
+static size_t frame_layout(const Geo &g, int h, int w, bool own_y, size_t off[FB_COUNT])
 {
-    const Tiles t = tiles_for(g, max_h, max_w);
+    const size_t hw = (size_t)h * w, nvox = (size_t)g.Nz * hw;
+    const size_t legs_h = std::min(h, kMaxMetricLegs), legs_w = std::min(w, kMaxMetricLegs);
+    size_t bytes[FB_COUNT];
+    bytes[FB_Y] = own_y ? hw * sizeof(float) : 0;
+    bytes[FB_RHO] = hw * sizeof(float);
+    bytes[FB_V0] = bytes[FB_V1] = bytes[FB_VB] = bytes[FB_SENS] = nvox * sizeof(float);
+    bytes[FB_WEAK] = (size_t)weak_cap_for(nvox) * sizeof(unsigned);
+    bytes[FB_COUNTERS] = 2 * sizeof(unsigned);
+    bytes[FB_CMAX] = (kDotBlocks + 1) * sizeof(float);
+    bytes[FB_MIP] = hw * sizeof(float);
+    bytes[FB_TABH] = legs_h * h * sizeof(double);
+    bytes[FB_TABW] = legs_w * w * sizeof(double);
+    bytes[FB_T1] = (size_t)kMetricChunks * legs_h * w * sizeof(double);
+    bytes[FB_N2P] = (hw + 255) / 256 * sizeof(double);
+    bytes[FB_FABS] = legs_h * legs_w * sizeof(double);
+    bytes[FB_MOUT] = sizeof(double);
+    bytes[FB_TRACE] = bytes[FB_FLUX] = (size_t)kMaxTrace * sizeof(double);
+    bytes[FB_DOTP] = (size_t)kDotBlocks * sizeof(double);
+    bytes[FB_STATE] = sizeof(StopState);
+    size_t total = 0;
+    for (int i = 0; i < FB_COUNT; ++i) {
+        off[i] = total;
+        total += (bytes[i] + 255) / 256 * 256;
+    }
+    return total;
+}
+
+static void frame_bind(Frame &f, const Geo &g, int h, int w, void *block, const size_t off[FB_COUNT],
+                       bool own_y)
+{
+    char *b = (char *)block;
+    f.h = h;
+    f.w = w;
+    f.y_own = own_y ? (float *)(b + off[FB_Y]) : nullptr;
+    f.rho = (float *)(b + off[FB_RHO]);
+    f.V[0] = (float *)(b + off[FB_V0]);
+    f.V[1] = (float *)(b + off[FB_V1]);
+    f.VB = (float *)(b + off[FB_VB]);
+    f.sens = (float *)(b + off[FB_SENS]);
+    f.weak = (unsigned *)(b + off[FB_WEAK]);
+    f.counters = (unsigned *)(b + off[FB_COUNTERS]);
+    f.cmax = (float *)(b + off[FB_CMAX]);
+    f.mip = (float *)(b + off[FB_MIP]);
+    f.tabH = (double *)(b + off[FB_TABH]);
+    f.tabW = (double *)(b + off[FB_TABW]);
+    f.T1 = (double *)(b + off[FB_T1]);
+    f.n2p = (double *)(b + off[FB_N2P]);
+    f.Fabs = (double *)(b + off[FB_FABS]);
+    f.metric_out = (double *)(b + off[FB_MOUT]);
+    f.trace = (double *)(b + off[FB_TRACE]);
+    f.flux = (double *)(b + off[FB_FLUX]);
+    f.dotp = (double *)(b + off[FB_DOTP]);
+    f.state = (StopState *)(b + off[FB_STATE]);
+    f.weak_cap = weak_cap_for((size_t)g.Nz * h * w);
+    f.nweak = 0;
+    f.tab_h = f.tab_nv = f.tab_w = f.tab_nu = -1;
+}
+
+struct Sizes {
+    size_t Gf, Gb, tw, psf, X, Yp, Rs, frame;
+    size_t Hf = 0, Hb = 0, gexp = 0, rowmax = 0;  // split FP16 only
+    bool split = false;
+    size_t resident() const { return (split ? Hf + Hb + gexp : Gf + Gb) + tw + psf; }
+    size_t workspace() const { return X + Yp + Rs + 2 * rowmax + frame; }
+};
+
+static Sizes sizes_for(const Geo &g, int max_h, int max_w, int max_batch, int split, bool f16)
+{
+    const int nt = tiles_for(g, max_h, max_w).nt * std::max(1, max_batch);
     Sizes s;
     s.Gf = (size_t)g.nf * g.NNp * g.KK * sizeof(float2);
     s.Gb = (size_t)g.nf * g.NN * g.KK * sizeof(float2);
     s.tw = (size_t)g.Q * sizeof(float2);
-    s.X = (size_t)g.nf * t.nt * g.KKs * sizeof(float2);
-    s.Yp = (size_t)split * g.nf * t.nt * g.NN * sizeof(float2);
-    s.Rs = (size_t)g.nf * t.nt * g.NN * sizeof(float2);
-    s.img = (size_t)max_h * max_w * sizeof(float);
-    s.vol = (size_t)g.Nz * max_h * max_w * sizeof(float);
-    s.T1 = (size_t)kMetricChunks * kMaxMetricLegs * max_w * sizeof(double);
-    s.n2p = ((size_t)max_h * max_w + 255) / 256 * sizeof(double);
-    s.tabH = (size_t)kMaxMetricLegs * max_h * sizeof(double);
-    s.tabW = (size_t)kMaxMetricLegs * max_w * sizeof(double);
-    s.Fabs = (size_t)kMaxMetricLegs * kMaxMetricLegs * sizeof(double);
-    s.trace = (size_t)kMaxTrace * sizeof(double);
-    s.dotp = (size_t)kDotBlocks * sizeof(double);
+    s.X = (size_t)g.nf * nt * g.KKs * sizeof(float2);
+    s.Yp = (size_t)split * g.nf * nt * g.NN * sizeof(float2);
+    s.Rs = (size_t)g.nf * nt * g.NN * sizeof(float2);
     s.psf = (size_t)g.Nz * g.NN * g.K * g.K * sizeof(float);
-    s.weak = (size_t)weak_cap_for((size_t)g.Nz * max_h * max_w) * sizeof(unsigned);
+    size_t off[FB_COUNT];
+    s.frame = frame_layout(g, max_h, max_w, false, off);
     if (f16) {
         s.split = true;
         s.Hf = (size_t)g.nf * g.KKs * g.NNp * sizeof(half2c);
         s.Hb = (size_t)g.nf * g.NNp * ((g.KK + 15) / 16 * 16) * sizeof(half2c);
         s.gexp = (size_t)g.nf * sizeof(int);
-        s.rowmax = (size_t)g.nf * t.nt * sizeof(unsigned);
+        s.rowmax = (size_t)g.nf * nt * sizeof(unsigned);
     }
     return s;
 }
@@ -1361,13 +1458,26 @@ extern "C" int lfrl_plan_footprint(const lfrl_plan_desc *desc, size_t *resident_
         return rc;
     Geo g;
     geo_init(g, desc->nnum, desc->nz, desc->ksize, q);
-    const Sizes s = sizes_for(g, desc->max_h, desc->max_w, pick_split(g),
+    const Sizes s = sizes_for(g, desc->max_h, desc->max_w, desc->max_batch, pick_split(g),
                               desc->precision == LFRL_SPLIT_FP16);
     if (resident_bytes)
         *resident_bytes = s.resident();
     if (workspace_bytes)
         *workspace_bytes = s.workspace();
     return LFRL_OK;
+}
+
+static void free_frame(Frame &f)
+{
+    if (f.block)
+        (void)hipFree(f.block);
+    if (f.state_host)
+        (void)hipHostFree(f.state_host);
+    if (f.counters_host)
+        (void)hipHostFree(f.counters_host);
+    f.block = nullptr;
+    f.state_host = nullptr;
+    f.counters_host = nullptr;
 }
 
 static void free_plan(lfrl_plan_s *p)
@@ -1378,19 +1488,12 @@ static void free_plan(lfrl_plan_s *p)
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
-    void *bufs[] = {p->Gf, p->Gb, p->tw, p->X, p->Yp, p->Rs, p->img, p->sens,
-                    p->vol[0], p->vol[1], p->vol[2], p->T1, p->n2p, p->Fabs,
-                    p->tabH, p->tabW, p->mip,
-                    p->metric_out, p->trace, p->flux, p->dotp, p->state,
-                    p->psf, p->weak, p->weak_count, p->cmax, p->Hf, p->Hb, p->gexp,
-                    p->xmax, p->rmax};
+    void *bufs[] = {p->Gf, p->Gb, p->tw, p->X, p->Yp, p->Rs, p->psf,
+                    p->Hf, p->Hb, p->gexp, p->xmax, p->rmax};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
-    if (p->state_host)
-        (void)hipHostFree(p->state_host);
-    if (p->weak_count_host)
-        (void)hipHostFree(p->weak_count_host);
+    free_frame(p->fr);
     for (auto &v : p->ev)
         for (hipEvent_t e : v)
             (void)hipEventDestroy(e);
@@ -1406,6 +1509,27 @@ static int dalloc(T **ptr, size_t bytes)
         *ptr = nullptr;
         (void)hipGetLastError();
         return set_error(LFRL_ERR_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    return LFRL_OK;
+}
+
+// Allocate and bind a Frame's device block and pinned host words.
+static int frame_alloc(Frame &f, const Geo &g, int h, int w, bool own_y)
+{
+    size_t off[FB_COUNT];
+    const size_t bytes = frame_layout(g, h, w, own_y, off);
+    int rc = dalloc((char **)&f.block, bytes);
+    if (rc)
+        return rc;
+    f.block_bytes = bytes;
+    frame_bind(f, g, h, w, f.block, off, own_y);
+    hipError_t e = hipHostMalloc((void **)&f.state_host, sizeof(StopState), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&f.counters_host, 2 * sizeof(unsigned), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_frame(f);
+        return set_error(LFRL_ERR_NOMEM, "hipHostMalloc failed: %s", hipGetErrorString(e));
     }
     return LFRL_OK;
 }
@@ -1459,10 +1583,11 @@ extern "C" int lfrl_plan(lfrl_plan_t *out, const lfrl_plan_desc *desc, const flo
     const Geo &g = p->g;
     p->max_h = desc->max_h;
     p->max_w = desc->max_w;
-    p->max_tiles = tiles_for(g, desc->max_h, desc->max_w).nt;
+    p->frame_tiles = tiles_for(g, desc->max_h, desc->max_w).nt;
+    p->max_tiles = p->frame_tiles * std::max(1, (int)desc->max_batch);
     p->split_k = pick_split(g);
     p->split = desc->precision == LFRL_SPLIT_FP16;
-    const Sizes s = sizes_for(g, p->max_h, p->max_w, p->split_k, p->split);
+    const Sizes s = sizes_for(g, p->max_h, p->max_w, desc->max_batch, p->split_k, p->split);
     p->resident = s.resident();
     p->workspace = s.workspace();
     p->use_fft = fft_usable(g, lmax);
@@ -1500,41 +1625,14 @@ extern "C" int lfrl_plan(lfrl_plan_t *out, const lfrl_plan_desc *desc, const flo
     TRY(dalloc(&p->X, s.X));
     TRY(dalloc(&p->Yp, s.Yp));
     TRY(dalloc(&p->Rs, s.Rs));
-    TRY(dalloc(&p->img, s.img));
-    TRY(dalloc(&p->sens, s.vol));
-    for (int i = 0; i < 3; ++i)
-        TRY(dalloc(&p->vol[i], s.vol));
-    TRY(dalloc(&p->T1, s.T1));
-    TRY(dalloc(&p->n2p, s.n2p));
-    TRY(dalloc(&p->tabH, s.tabH));
-    TRY(dalloc(&p->tabW, s.tabW));
-    TRY(dalloc(&p->mip, s.img));
-    TRY(dalloc(&p->Fabs, s.Fabs));
-    TRY(dalloc(&p->metric_out, 64));
-    TRY(dalloc(&p->trace, s.trace));
-    TRY(dalloc(&p->flux, s.trace));
-    TRY(dalloc(&p->dotp, s.dotp));
-    TRY(dalloc(&p->state, sizeof(StopState)));
     TRY(dalloc(&p->psf, s.psf));
-    p->weak_cap = weak_cap_for((size_t)g.Nz * p->max_h * p->max_w);
-    TRY(dalloc(&p->weak, s.weak));
-    TRY(dalloc(&p->weak_count, sizeof(unsigned)));
-    TRY(dalloc(&p->cmax, (kDotBlocks + 1) * sizeof(float)));
+    TRY(frame_alloc(p->fr, g, p->max_h, p->max_w, false));
     if (p->split) {
         TRY(dalloc(&p->Hf, s.Hf));
         TRY(dalloc(&p->Hb, s.Hb));
         TRY(dalloc(&p->gexp, s.gexp));
         TRY(dalloc(&p->xmax, s.rowmax));
         TRY(dalloc(&p->rmax, s.rowmax));
-    }
-    {
-        hipError_t e = hipHostMalloc((void **)&p->state_host, sizeof(StopState), hipHostMallocDefault);
-        if (e == hipSuccess)
-            e = hipHostMalloc((void **)&p->weak_count_host, sizeof(unsigned), hipHostMallocDefault);
-        if (e != hipSuccess) {
-            free_plan(p);
-            return set_error(LFRL_ERR_NOMEM, "hipHostMalloc failed: %s", hipGetErrorString(e));
-        }
     }
     // twiddles exp(2 pi i m / Q), computed in double, rounded once
     std::vector<float2> tw(g.Q);
@@ -1553,8 +1651,8 @@ extern "C" int lfrl_plan(lfrl_plan_t *out, const lfrl_plan_desc *desc, const flo
     if (e == hipSuccess) {
         dim3 grid(g.N, g.NN, g.Nz);
         if (p->use_fft)
-            launch_r2c_fft(g.Q, grid, p->thr_r2c, p->lds_r2c_bytes, st, SRC_PSF, psf, 0, 0, g.N,
-                           g.T, g.hD, 0, 0, g.NNp, g.K, g.c0, g.KK, p->Gf, p->tw);
+            launch_r2c_fft(g.Q, grid, p->thr_r2c, p->lds_r2c_bytes, st, SRC_PSF, TileBatch{}, psf,
+                           g.N, g.T, g.hD, 0, g.NNp, g.K, g.c0, g.KK, p->Gf, p->tw);
         else
             hipLaunchKernelGGL(k_psf_r2c, grid, dim3(256), p->lds_r2c_bytes, st, psf, g.N, g.K,
                                g.c0, g.hD, g.Q, g.QH, g.KK, g.NNp, p->Gf, p->tw);
@@ -1664,14 +1762,14 @@ static int prof_event(lfrl_plan_s *p, int which, hipStream_t st)
 #define LFRL_FWD_CASE(CBV, UV)                                                                   \
     if (p->fwd_cb == CBV && p->fwd_u == UV) {                                                    \
         hipLaunchKernelGGL((k_contract_fwd<CBV, UV>), grid, block, 0, st, p->Gf, p->X, p->Yp,    \
-                           g.NN, g.NNp, g.KK, g.KKs, t.nt, g.nf, kchunk);                        \
+                           g.NN, g.NNp, g.KK, g.KKs, nt, g.nf, kchunk);                          \
         launched = true;                                                                         \
     }
 #define LFRL_FWD_CASES(CBV) LFRL_FWD_CASE(CBV, 2) LFRL_FWD_CASE(CBV, 4) LFRL_FWD_CASE(CBV, 8)
 #define LFRL_ADJ_CASE(CBV, UV)                                                                   \
     if (p->adj_cb == CBV && p->adj_u == UV) {                                                    \
         hipLaunchKernelGGL((k_contract_adj<CBV, UV>), grid, dim3(64 * kAdjWaves), lds, st, p->Gb, \
-                           p->Rs, p->X, g.NN, g.KK, t.nt);                                       \
+                           p->Rs, p->X, g.NN, g.KK, nt);                                         \
         launched = true;                                                                         \
     }
 #define LFRL_ADJ_CASES(CBV) LFRL_ADJ_CASE(CBV, 2) LFRL_ADJ_CASE(CBV, 4) LFRL_ADJ_CASE(CBV, 8)
@@ -1685,33 +1783,68 @@ static int contraction_split(const lfrl_plan_s *p, int *kchunk)
     return (g.KK + kc - 1) / kc;
 }
 
-// vol [Nz][h][w] -> img [h][w]: plain projection (mode STORE) or the RL ratio
-// y / (A x) written into `dst` (mode RATIO, y = aux).
-static int run_forward(lfrl_plan_s *p, int h, int w, const float *vol, float *dst, int mode,
-                       const float *aux, hipStream_t st)
+// One frame of a batched tile launch: its size, the array the forward tile
+// transform reads, and the inverse transform's destination and epilogue inputs.
+struct FrameIO {
+    int h, w;
+    const float *src;
+    float *dst;
+    const float *aux0, *aux1;
+};
+
+// Concatenate the frames' tiles into one tile index space; returns the total.
+static int make_batch(const Geo &g, const FrameIO *io, int n, TileBatch *b)
+{
+    int nt = 0;
+    b->njobs = n;
+    for (int i = 0; i < n; ++i) {
+        const Tiles t = tiles_for(g, io[i].h, io[i].w);
+        TileJob &j = b->job[i];
+        j.src = io[i].src;
+        j.dst = io[i].dst;
+        j.aux0 = io[i].aux0;
+        j.aux1 = io[i].aux1;
+        j.H = io[i].h;
+        j.W = io[i].w;
+        j.tiles_x = t.tx;
+        j.tile0 = nt;
+        nt += t.nt;
+    }
+    return nt;
+}
+
+// Forward projection of n frames in one pass: vol [Nz][h][w] -> img [h][w]
+// per frame, stored (mode STORE) or turned into the RL ratio y / (A x)
+// (mode RATIO, y = aux0).  The frames' tiles share every launch; their total
+// must not exceed the plan's tile capacity.
+static int run_forward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipStream_t st)
 {
     const Geo &g = p->g;
-    const Tiles t = tiles_for(g, h, w);
+    TileBatch batch;
+    const int nt = make_batch(g, io, n, &batch);
+    if (nt > p->max_tiles)
+        return set_error(LFRL_ERR_ARG, "batch of %d tiles exceeds the plan capacity %d", nt,
+                         p->max_tiles);
     if (p->split) {
-        hipLaunchKernelGGL(k_zero_u32n, dim3(64), dim3(256), 0, st, p->xmax, (size_t)g.nf * t.nt);
+        hipLaunchKernelGGL(k_zero_u32n, dim3(64), dim3(256), 0, st, p->xmax, (size_t)g.nf * nt);
         LAUNCH_CHECK("k_zero_u32n");
     }
     if (p->use_fft)
-        launch_r2c_fft(g.Q, dim3(t.nt * g.Nz * g.N), p->thr_r2c, p->lds_r2c_bytes, st, SRC_PLANES,
-                       vol, h, w, g.N, g.T, g.hD, t.tx, t.nt, g.KKs, g.K, g.c0, g.KK, p->X, p->tw,
+        launch_r2c_fft(g.Q, dim3(nt * g.Nz * g.N), p->thr_r2c, p->lds_r2c_bytes, st, SRC_PLANES,
+                       batch, nullptr, g.N, g.T, g.hD, nt, g.KKs, g.K, g.c0, g.KK, p->X, p->tw,
                        p->split ? p->xmax : nullptr);
     else
-        hipLaunchKernelGGL(k_vol_r2c, dim3(t.nt, g.Nz * g.N), dim3(256), p->lds_r2c_bytes, st, vol,
-                           h, w, g.N, g.Q, g.QH, g.T, g.hD, t.tx, t.nt, g.KKs, p->X, p->tw);
+        hipLaunchKernelGGL(k_vol_r2c, dim3(nt, g.Nz * g.N), dim3(256), p->lds_r2c_bytes, st, batch,
+                           g.N, g.Q, g.QH, g.T, g.hD, nt, g.KKs, p->X, p->tw);
     LAUNCH_CHECK("k_vol_r2c");
     int kchunk = 0;
-    const int split = contraction_split(p, &kchunk);
+    (void)contraction_split(p, &kchunk);
     if (p->split)
         kchunk = (kchunk + 31) / 32 * 32;
     const int split2 = (g.KK + kchunk - 1) / kchunk;
     const int fcb = p->split ? p->hfwd_cb : p->fwd_cb;
     const int nwaves = (g.NNp / 16 + fcb - 1) / fcb;
-    const dim3 grid(g.nf, split2, (t.nt + 15) / 16);
+    const dim3 grid(g.nf, split2, (nt + 15) / 16);
     const dim3 block(64 * nwaves);
     if (p->prof) {
         int rc = prof_event(p, 0, st);
@@ -1725,7 +1858,7 @@ static int run_forward(lfrl_plan_s *p, int h, int w, const float *vol, float *ds
         hipLaunchKernelGGL((k_contract_fwd_f16<CBV, UV>), grid, block, 0, st,                    \
                            (const half2c *)p->Hf, (const float2 *)p->X, (const unsigned *)p->xmax,\
                            (const int *)p->gexp, p->Yp, g.NN, g.NNp, g.KK, g.KKs, g.KKs / 32,    \
-                           t.nt, g.nf, kchunk);                                                  \
+                           nt, g.nf, kchunk);                                                    \
         launched = true;                                                                         \
     }
         LFRL_HFWD_CASE(1, 1) LFRL_HFWD_CASE(1, 2) LFRL_HFWD_CASE(2, 1) LFRL_HFWD_CASE(2, 2)
@@ -1745,41 +1878,44 @@ static int run_forward(lfrl_plan_s *p, int h, int w, const float *vol, float *ds
             return rc;
     }
     // partials Yp[s][k][t][c]
-    const size_t sk = (size_t)g.NN * t.nt, split_stride = (size_t)g.nf * sk;
+    const size_t sk = (size_t)g.NN * nt, split_stride = (size_t)g.nf * sk;
     if (p->use_fft)
-        launch_c2r_fft(g.Q, dim3(t.nt * g.N), p->thr_c2r, p->lds_c2r_bytes, st, p->Yp, split_stride,
-                       split2, sk, g.NN, 1, g.N, 1, g.T, g.hD, t.tx, h, w, mode, dst, aux,
-                       (const float *)nullptr, p->tw);
+        launch_c2r_fft(g.Q, dim3(nt * g.N), p->thr_c2r, p->lds_c2r_bytes, st, batch, p->Yp,
+                       split_stride, split2, sk, g.NN, 1, g.N, 1, g.T, g.hD, mode, p->tw);
     else
-        hipLaunchKernelGGL(k_c2r, dim3(t.nt, g.N), dim3(256), p->lds_c2r_bytes, st, p->Yp,
+        hipLaunchKernelGGL(k_c2r, dim3(nt, g.N), dim3(256), p->lds_c2r_bytes, st, batch, p->Yp,
                            split_stride, split2, sk, (size_t)g.NN, (size_t)1, g.N, g.Q, g.QH, g.T,
-                           g.hD, t.tx, h, w, mode, dst, aux, (const float *)nullptr, p->tw);
+                           g.hD, mode, p->tw);
     LAUNCH_CHECK("k_c2r(forward)");
     return LFRL_OK;
 }
 
-// img [h][w] -> vol [Nz][h][w]: plain back projection (STORE) or the RL update
+// Back projection of n frames in one pass: img [h][w] -> vol [Nz][h][w] per
+// frame, stored (STORE) or applied as the RL update
 // dst = x_old * A^T img / sens (UPDATE, x_old = aux0, sens = aux1).
-static int run_backward(lfrl_plan_s *p, int h, int w, const float *img, float *dst, int mode,
-                        const float *aux0, const float *aux1, hipStream_t st)
+static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipStream_t st)
 {
     const Geo &g = p->g;
-    const Tiles t = tiles_for(g, h, w);
+    TileBatch batch;
+    const int nt = make_batch(g, io, n, &batch);
+    if (nt > p->max_tiles)
+        return set_error(LFRL_ERR_ARG, "batch of %d tiles exceeds the plan capacity %d", nt,
+                         p->max_tiles);
     if (p->split) {
-        hipLaunchKernelGGL(k_zero_u32n, dim3(64), dim3(256), 0, st, p->rmax, (size_t)g.nf * t.nt);
+        hipLaunchKernelGGL(k_zero_u32n, dim3(64), dim3(256), 0, st, p->rmax, (size_t)g.nf * nt);
         LAUNCH_CHECK("k_zero_u32n");
     }
     if (p->use_fft)
-        launch_r2c_fft(g.Q, dim3(t.nt * g.N), p->thr_r2c, p->lds_r2c_bytes, st, SRC_PLANES, img, h,
-                       w, g.N, g.T, g.hD, t.tx, t.nt, g.NN, g.K, g.c0, g.KK, p->Rs, p->tw,
+        launch_r2c_fft(g.Q, dim3(nt * g.N), p->thr_r2c, p->lds_r2c_bytes, st, SRC_PLANES, batch,
+                       nullptr, g.N, g.T, g.hD, nt, g.NN, g.K, g.c0, g.KK, p->Rs, p->tw,
                        p->split ? p->rmax : nullptr);
     else
-        hipLaunchKernelGGL(k_vol_r2c, dim3(t.nt, g.N), dim3(256), p->lds_r2c_bytes, st, img, h,
-                           w, g.N, g.Q, g.QH, g.T, g.hD, t.tx, t.nt, g.NN, p->Rs, p->tw);
+        hipLaunchKernelGGL(k_vol_r2c, dim3(nt, g.N), dim3(256), p->lds_r2c_bytes, st, batch, g.N,
+                           g.Q, g.QH, g.T, g.hD, nt, g.NN, p->Rs, p->tw);
     LAUNCH_CHECK("k_vol_r2c(image)");
     const int acb = p->split ? p->hadj_cb : p->adj_cb;
     const int kk_per_block = 16 * acb * kAdjWaves;
-    const dim3 grid(g.nf, (g.KK + kk_per_block - 1) / kk_per_block, (t.nt + 15) / 16);
+    const dim3 grid(g.nf, (g.KK + kk_per_block - 1) / kk_per_block, (nt + 15) / 16);
     const int ustep = 4 * p->adj_u;
     const size_t lds = p->split ? (size_t)(g.NNp / 16) * 64 * 16 * sizeof(_Float16)
                                 : (size_t)(g.NN + ustep - 1) / ustep * ustep * 16 * sizeof(float2);
@@ -1794,7 +1930,7 @@ static int run_backward(lfrl_plan_s *p, int h, int w, const float *img, float *d
     if (p->hadj_cb == CBV && p->hadj_u == UV) {                                                  \
         hipLaunchKernelGGL((k_contract_adj_f16<CBV, UV>), grid, dim3(64 * kAdjWaves), lds, st,   \
                            (const half2c *)p->Hb, (const float2 *)p->Rs, (const unsigned *)p->rmax,\
-                           (const int *)p->gexp, p->X, g.NN, g.NNp, g.KK, (g.KK + 15) / 16, t.nt);\
+                           (const int *)p->gexp, p->X, g.NN, g.NNp, g.KK, (g.KK + 15) / 16, nt); \
         launched = true;                                                                         \
     }
         LFRL_HADJ_CASE(2, 2) LFRL_HADJ_CASE(2, 4) LFRL_HADJ_CASE(4, 2) LFRL_HADJ_CASE(4, 4)
@@ -1812,15 +1948,14 @@ static int run_backward(lfrl_plan_s *p, int h, int w, const float *img, float *d
             return rc;
     }
     // B[k][t][kk]
-    const size_t sk = (size_t)g.KK * t.nt;
+    const size_t sk = (size_t)g.KK * nt;
     if (p->use_fft)
-        launch_c2r_fft(g.Q, dim3(t.nt * g.Nz * g.N), p->thr_c2r, p->lds_c2r_bytes, st, p->X,
-                       (size_t)0, 1, sk, g.KK, 1, g.N, g.Nz, g.T, g.hD, t.tx, h, w, mode, dst,
-                       aux0, aux1, p->tw);
+        launch_c2r_fft(g.Q, dim3(nt * g.Nz * g.N), p->thr_c2r, p->lds_c2r_bytes, st, batch, p->X,
+                       (size_t)0, 1, sk, g.KK, 1, g.N, g.Nz, g.T, g.hD, mode, p->tw);
     else
-        hipLaunchKernelGGL(k_c2r, dim3(t.nt, g.Nz * g.N), dim3(256), p->lds_c2r_bytes, st, p->X,
-                           (size_t)0, 1, sk, (size_t)g.KK, (size_t)1, g.N, g.Q, g.QH, g.T, g.hD,
-                           t.tx, h, w, mode, dst, aux0, aux1, p->tw);
+        hipLaunchKernelGGL(k_c2r, dim3(nt, g.Nz * g.N), dim3(256), p->lds_c2r_bytes, st, batch,
+                           p->X, (size_t)0, 1, sk, (size_t)g.KK, (size_t)1, g.N, g.Q, g.QH, g.T,
+                           g.hD, mode, p->tw);
     LAUNCH_CHECK("k_c2r(backward)");
     return LFRL_OK;
 }
@@ -1897,56 +2032,244 @@ static int check_legs(double xs, double ys)
     return LFRL_OK;
 }
 
-// c = A^T 1 for an h x w image, through the tile-DFT path, then made exact
-// (float64 window sums) at the weakly observed voxels, which are listed for the
-// per-iteration fix-up.  Runs once per image size; synchronises the stream.
+static MetricBufs frame_metric_bufs(Frame &f)
+{
+    return MetricBufs{f.mip, f.tabH, f.tabW, f.T1, f.n2p, f.Fabs,
+                      &f.tab_h, &f.tab_nv, &f.tab_w, &f.tab_nu};
+}
+
+// c = A^T 1 for the frame's image size, through the tile-DFT path, then made
+// exact (float64 window sums) at the weakly observed voxels, which are listed
+// for the per-iteration fix-up.  With check_input, the frame's image is also
+// checked for negative or non-finite values (LFRL_ERR_NUMERIC).  Synchronises
+// the stream.
+static int frame_sensitivity(lfrl_plan_s *p, Frame &f, bool check_input, hipStream_t st)
+{
+    const int h = f.h, w = f.w;
+    const size_t hw = (size_t)h * w, nvox = (size_t)p->g.Nz * hw;
+    f.nweak = 0;
+    int rc = launch_fill(f.rho, hw, 1.0f, st);
+    if (rc)
+        return rc;
+    const FrameIO io{h, w, f.rho, f.sens, nullptr, nullptr};
+    rc = run_backward(p, &io, 1, EPI_STORE, st);
+    if (rc)
+        return rc;
+    hipLaunchKernelGGL(k_max_partial, dim3(kDotBlocks), dim3(256), 0, st, (const float *)f.sens,
+                       nvox, f.cmax);
+    LAUNCH_CHECK("k_max_partial");
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, st, (const float *)f.cmax, kDotBlocks,
+                       f.cmax + kDotBlocks, f.counters);
+    LAUNCH_CHECK("k_max_final");
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, f.counters + 1);
+    LAUNCH_CHECK("k_zero_u32");
+    if (check_input) {
+        hipLaunchKernelGGL(k_check_image, dim3(256), dim3(256), 0, st, f.y, hw, f.counters + 1);
+        LAUNCH_CHECK("k_check_image");
+    }
+    float thr = kWeakThreshold;
+    unsigned found = 0;
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        if (attempt > 0) {
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, f.counters);
+            LAUNCH_CHECK("k_zero_u32");
+        }
+        hipLaunchKernelGGL(k_weak_select, dim3(2048), dim3(256), 0, st, (const float *)f.sens,
+                           nvox, (const float *)(f.cmax + kDotBlocks), thr, f.weak, f.counters,
+                           f.weak_cap);
+        LAUNCH_CHECK("k_weak_select");
+        HIP_TRY(hipMemcpyAsync(f.counters_host, f.counters, 2 * sizeof(unsigned),
+                               hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        found = f.counters_host[0];
+        if (found <= f.weak_cap)
+            break;
+        thr *= 0.1f;
+    }
+    if (check_input && f.counters_host[1])
+        return set_error(LFRL_ERR_NUMERIC, "image has negative or non-finite values");
+    f.nweak = std::min(found, f.weak_cap);
+    if (f.nweak) {
+        hipLaunchKernelGGL(k_weak_exact, dim3(f.nweak), dim3(256), 0, st, (const unsigned *)f.weak,
+                           (const float *)p->psf, p->g.N, p->g.K, h, w, (const float *)nullptr,
+                           f.sens, (const float *)nullptr, (float *)nullptr, (int)WEAK_SENS);
+        LAUNCH_CHECK("k_weak_exact(sens)");
+    }
+    return LFRL_OK;
+}
+
+// Sensitivity of the plan's own frame, cached per image size.
 static int ensure_sensitivity(lfrl_plan_s *p, int h, int w, hipStream_t st)
 {
     if (p->sens_h == h && p->sens_w == w)
         return LFRL_OK;
     p->sens_h = p->sens_w = -1;
-    p->nweak = 0;
-    int rc = launch_fill(p->img, (size_t)h * w, 1.0f, st);
+    p->fr.h = h;
+    p->fr.w = w;
+    int rc = frame_sensitivity(p, p->fr, false, st);
     if (rc)
         return rc;
-    rc = run_backward(p, h, w, p->img, p->sens, EPI_STORE, nullptr, nullptr, st);
-    if (rc)
-        return rc;
-    const size_t nvox = (size_t)p->g.Nz * h * w;
-    hipLaunchKernelGGL(k_max_partial, dim3(kDotBlocks), dim3(256), 0, st, (const float *)p->sens,
-                       nvox, p->cmax);
-    LAUNCH_CHECK("k_max_partial");
-    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, st, (const float *)p->cmax, kDotBlocks,
-                       p->cmax + kDotBlocks, p->weak_count);
-    LAUNCH_CHECK("k_max_final");
-    float thr = kWeakThreshold;
-    unsigned found = 0;
-    for (int attempt = 0; attempt < 8; ++attempt) {
-        if (attempt > 0) {
-            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, p->weak_count);
-            LAUNCH_CHECK("k_zero_u32");
-        }
-        hipLaunchKernelGGL(k_weak_select, dim3(2048), dim3(256), 0, st, (const float *)p->sens,
-                           nvox, (const float *)(p->cmax + kDotBlocks), thr, p->weak,
-                           p->weak_count, p->weak_cap);
-        LAUNCH_CHECK("k_weak_select");
-        HIP_TRY(hipMemcpyAsync(p->weak_count_host, p->weak_count, sizeof(unsigned),
-                               hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        found = *p->weak_count_host;
-        if (found <= p->weak_cap)
-            break;
-        thr *= 0.1f;
-    }
-    p->nweak = std::min(found, p->weak_cap);
-    if (p->nweak) {
-        hipLaunchKernelGGL(k_weak_exact, dim3(p->nweak), dim3(256), 0, st, (const unsigned *)p->weak,
-                           (const float *)p->psf, p->g.N, p->g.K, h, w, (const float *)nullptr,
-                           p->sens, (const float *)nullptr, (float *)nullptr, (int)WEAK_SENS);
-        LAUNCH_CHECK("k_weak_exact(sens)");
-    }
     p->sens_h = h;
     p->sens_w = w;
+    return LFRL_OK;
+}
+
+// Float64 sum(a * b) (b == nullptr: sum(a)) into the frame's stop state
+// (which = 0: the image sum) or its flux trace at iteration k (which = 1).
+static int frame_dot(Frame &f, const float *a, const float *b, size_t n, int k, int which,
+                     hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, a, b, n, f.dotp);
+    LAUNCH_CHECK("k_dot_partial");
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, st, (const double *)f.dotp, kDotBlocks,
+                       f.state, f.flux, k, which);
+    LAUNCH_CHECK("k_dot_final");
+    return LFRL_OK;
+}
+
+static int check_opts(const lfrl_rl_opts *opts)
+{
+    if (opts->max_iters < 1 || opts->max_iters > kMaxTrace)
+        return set_error(LFRL_ERR_ARG, "max_iters must be in [1, %d]", kMaxTrace);
+    if (opts->stop < LFRL_STOP_NONE || opts->stop > LFRL_STOP_TRACK)
+        return set_error(LFRL_ERR_ARG, "unknown stop mode %d", opts->stop);
+    if (opts->init != 0 && opts->init != 1)
+        return set_error(LFRL_ERR_ARG, "init must be 0 or 1");
+    if (opts->stop != LFRL_STOP_NONE) {
+        if (opts->patience < 1)
+            return set_error(LFRL_ERR_ARG, "patience must be >= 1");
+        return check_legs(opts->xs, opts->ys);
+    }
+    return LFRL_OK;
+}
+
+// x^0 (ones, or a copy of vol0), a fresh stop state, and the image sum for the
+// flux trace.
+static int frame_start(Frame &f, int nz, const float *vol0, hipStream_t st)
+{
+    const size_t nvox = (size_t)nz * f.h * f.w;
+    if (vol0) {
+        HIP_TRY(hipMemcpyAsync(f.V[0], vol0, nvox * sizeof(float), hipMemcpyDeviceToDevice, st));
+    } else {
+        int rc = launch_fill(f.V[0], nvox, 1.0f, st);
+        if (rc)
+            return rc;
+    }
+    hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(1), 0, st, f.state);
+    LAUNCH_CHECK("k_state_reset");
+    if (f.want_flux) {
+        int rc = frame_dot(f, f.y, nullptr, (size_t)f.h * f.w, 0, 0, st);
+        if (rc)
+            return rc;
+    }
+    f.iters = 0;
+    f.done = f.stopped = false;
+    return LFRL_OK;
+}
+
+// One Richardson-Lucy iteration for n frames of plan p, their projections
+// batched: x^k = x^{k-1} * A^T(y / A x^{k-1}) / c, the exact update at the
+// weakly observed voxels, then the metric, best-iterate copy and flux of each
+// frame.  Queued on `st` without synchronising.
+static int step_frames(lfrl_plan_s *p, Frame *const *fr, int n, hipStream_t st)
+{
+    FrameIO io[kMaxBatchJobs];
+    for (int i = 0; i < n; ++i) {
+        Frame &f = *fr[i];
+        const int k = f.iters + 1;
+        io[i] = FrameIO{f.h, f.w, f.V[(k - 1) & 1], f.rho, f.y, nullptr};
+    }
+    int rc = run_forward(p, io, n, EPI_RATIO, st);
+    if (rc)
+        return rc;
+    for (int i = 0; i < n; ++i) {
+        Frame &f = *fr[i];
+        const int k = f.iters + 1;
+        io[i] = FrameIO{f.h, f.w, f.rho, f.V[k & 1], f.V[(k - 1) & 1], f.sens};
+    }
+    rc = run_backward(p, io, n, EPI_UPDATE, st);
+    if (rc)
+        return rc;
+    for (int i = 0; i < n; ++i) {
+        Frame &f = *fr[i];
+        const int k = f.iters + 1;
+        const float *cur = f.V[(k - 1) & 1];
+        float *nxt = f.V[k & 1];
+        const size_t nvox = (size_t)p->g.Nz * f.h * f.w;
+        if (f.nweak) {
+            hipLaunchKernelGGL(k_weak_exact, dim3(f.nweak), dim3(256), 0, st,
+                               (const unsigned *)f.weak, (const float *)p->psf, p->g.N, p->g.K,
+                               f.h, f.w, (const float *)f.rho, f.sens, cur, nxt, (int)WEAK_UPDATE);
+            LAUNCH_CHECK("k_weak_exact(update)");
+        }
+        if (f.opts.stop != LFRL_STOP_NONE) {
+            rc = run_metric(p->g.Nz, f.h, f.w, nxt, f.opts.xs, f.opts.ys, f.metric_out,
+                            frame_metric_bufs(f), f.state, f.trace, k, f.opts.patience, st);
+            if (rc)
+                return rc;
+            hipLaunchKernelGGL(k_cond_copy, dim3(1024), dim3(256), 0, st,
+                               (const StopState *)f.state, (const float *)nxt, f.VB, nvox);
+            LAUNCH_CHECK("k_cond_copy");
+        }
+        if (f.want_flux) {
+            rc = frame_dot(f, f.sens, nxt, nvox, k, 1, st);
+            if (rc)
+                return rc;
+        }
+        f.iters = k;
+    }
+    return LFRL_OK;
+}
+
+// After a step: queue the copy of the stop state a METRIC frame needs.
+static int frame_queue_poll(Frame &f, hipStream_t st)
+{
+    if (f.opts.stop == LFRL_STOP_METRIC)
+        HIP_TRY(hipMemcpyAsync(f.state_host, f.state, sizeof(StopState), hipMemcpyDeviceToHost, st));
+    return LFRL_OK;
+}
+
+// After the stream has reached the polled state: the frame is done at the cap
+// or once the stop rule fired.
+static void frame_update_done(Frame &f)
+{
+    if (f.opts.stop == LFRL_STOP_METRIC && f.state_host->stopped)
+        f.stopped = true;
+    f.done = f.stopped || f.iters >= f.opts.max_iters;
+}
+
+// Copy x^{best} (metric modes) or the last iterate into vol, and fill the
+// report.  Synchronises the stream.
+static int frame_result(Frame &f, int nz, float *vol, lfrl_rl_report *report, hipStream_t st)
+{
+    const size_t nvox = (size_t)nz * f.h * f.w;
+    const bool use_metric = f.opts.stop != LFRL_STOP_NONE;
+    int best = f.iters;
+    if (use_metric) {
+        HIP_TRY(hipMemcpyAsync(f.state_host, f.state, sizeof(StopState), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        best = f.state_host->best_k;
+    }
+    if (vol && f.iters > 0)
+        HIP_TRY(hipMemcpyAsync(vol, use_metric ? f.VB : f.V[f.iters & 1], nvox * sizeof(float),
+                               hipMemcpyDeviceToDevice, st));
+    else if (vol)
+        HIP_TRY(hipMemcpyAsync(vol, f.V[0], nvox * sizeof(float), hipMemcpyDeviceToDevice, st));
+    if (report && f.iters > 0) {
+        if (use_metric && report->metric_trace)
+            HIP_TRY(hipMemcpyAsync(report->metric_trace, f.trace, f.iters * sizeof(double),
+                                   hipMemcpyDeviceToHost, st));
+        if (f.want_flux && report->flux_trace)
+            HIP_TRY(hipMemcpyAsync(report->flux_trace, f.flux, f.iters * sizeof(double),
+                                   hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    if (report) {
+        report->iters_run = f.iters;
+        report->best_iter = best;
+        report->stopped = f.stopped ? 1 : 0;
+        report->weak_voxels = (int32_t)f.nweak;
+    }
     return LFRL_OK;
 }
 
@@ -1966,7 +2289,8 @@ extern "C" int lfrl_forward(lfrl_plan_t p, int32_t h, int32_t w, const float *vo
     if ((rc = check_buf(vol, npx * p->g.Nz * sizeof(float), "vol")) ||
         (rc = check_buf(img, npx * sizeof(float), "img")))
         return rc;
-    return run_forward(p, h, w, vol, img, EPI_STORE, nullptr, (hipStream_t)stream);
+    const FrameIO io{h, w, vol, img, nullptr, nullptr};
+    return run_forward(p, &io, 1, EPI_STORE, (hipStream_t)stream);
 }
 
 extern "C" int lfrl_backward(lfrl_plan_t p, int32_t h, int32_t w, const float *img, float *vol,
@@ -1982,18 +2306,8 @@ extern "C" int lfrl_backward(lfrl_plan_t p, int32_t h, int32_t w, const float *i
     if ((rc = check_buf(vol, npx * p->g.Nz * sizeof(float), "vol")) ||
         (rc = check_buf(img, npx * sizeof(float), "img")))
         return rc;
-    return run_backward(p, h, w, img, vol, EPI_STORE, nullptr, nullptr, (hipStream_t)stream);
-}
-
-static int dot_into(lfrl_plan_s *p, const float *a, const float *b, size_t n, double *flux,
-                    int k, int which, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, a, b, n, p->dotp);
-    LAUNCH_CHECK("k_dot_partial");
-    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, st, (const double *)p->dotp, kDotBlocks,
-                       p->state, flux, k, which);
-    LAUNCH_CHECK("k_dot_final");
-    return LFRL_OK;
+    const FrameIO io{h, w, img, vol, nullptr, nullptr};
+    return run_backward(p, &io, 1, EPI_STORE, (hipStream_t)stream);
 }
 
 extern "C" int lfrl_deconvolve(lfrl_plan_t p, int32_t h, int32_t w, const float *img, float *vol,
@@ -2004,114 +2318,303 @@ extern "C" int lfrl_deconvolve(lfrl_plan_t p, int32_t h, int32_t w, const float 
     int rc = check_hw(p, h, w);
     if (rc)
         return rc;
-    if (opts->max_iters < 1 || opts->max_iters > kMaxTrace)
-        return set_error(LFRL_ERR_ARG, "max_iters must be in [1, %d]", kMaxTrace);
-    if (opts->stop < LFRL_STOP_NONE || opts->stop > LFRL_STOP_TRACK)
-        return set_error(LFRL_ERR_ARG, "unknown stop mode %d", opts->stop);
-    if (opts->init != 0 && opts->init != 1)
-        return set_error(LFRL_ERR_ARG, "init must be 0 or 1");
-    const bool use_metric = opts->stop != LFRL_STOP_NONE;
-    if (use_metric) {
-        if (opts->patience < 1)
-            return set_error(LFRL_ERR_ARG, "patience must be >= 1");
-        rc = check_legs(opts->xs, opts->ys);
-        if (rc)
-            return rc;
-    }
+    if ((rc = check_opts(opts)))
+        return rc;
     DevGuard dg(p->device);
     hipStream_t st = (hipStream_t)stream;
     const size_t nvox = (size_t)p->g.Nz * h * w;
     if ((rc = check_buf(vol, nvox * sizeof(float), "vol")) ||
         (rc = check_buf(img, (size_t)h * w * sizeof(float), "img")))
         return rc;
-    const bool want_flux = report && report->flux_trace;
-    rc = ensure_sensitivity(p, h, w, st);
+    if ((rc = ensure_sensitivity(p, h, w, st)))
+        return rc;
+    Frame &f = p->fr;
+    f.y = img;
+    f.opts = *opts;
+    f.want_flux = report && report->flux_trace;
+    if ((rc = frame_start(f, p->g.Nz, opts->init == 1 ? vol : nullptr, st)))
+        return rc;
+    Frame *one[1] = {&f};
+    while (!f.done) {
+        if ((rc = step_frames(p, one, 1, st)) || (rc = frame_queue_poll(f, st)))
+            return rc;
+        if (f.opts.stop == LFRL_STOP_METRIC)
+            HIP_TRY(hipStreamSynchronize(st));
+        frame_update_done(f);
+    }
+    return frame_result(f, p->g.Nz, vol, report, st);
+}
+
+// ---------------------------------------------------------------------------
+// jobs: batched and served deconvolution
+// ---------------------------------------------------------------------------
+struct lfrl_job_s {
+    lfrl_plan_s *plan = nullptr;  // must outlive the job
+    int device = 0;
+    Frame f;
+};
+
+extern "C" int lfrl_job_footprint(lfrl_plan_t p, int32_t h, int32_t w, size_t *bytes)
+{
+    if (!p || !bytes)
+        return set_error(LFRL_ERR_ARG, "NULL argument");
+    int rc = check_hw(p, h, w);
     if (rc)
         return rc;
-    float *V[2] = {p->vol[0], p->vol[1]};
-    float *VB = p->vol[2];
-    if (opts->init == 1) {
-        HIP_TRY(hipMemcpyAsync(V[0], vol, nvox * sizeof(float), hipMemcpyDeviceToDevice, st));
-    } else {
-        rc = launch_fill(V[0], nvox, 1.0f, st);
-        if (rc)
-            return rc;
+    size_t off[FB_COUNT];
+    *bytes = frame_layout(p->g, h, w, true, off);
+    return LFRL_OK;
+}
+
+static void free_job(lfrl_job_s *j)
+{
+    if (!j)
+        return;
+    DevGuard dg(j->device);
+    free_frame(j->f);
+    delete j;
+}
+
+extern "C" int lfrl_job_create(lfrl_job_t *out, lfrl_plan_t p, int32_t h, int32_t w,
+                               const float *img, const float *vol0, const lfrl_rl_opts *opts,
+                               uint32_t flags, void *stream)
+{
+    if (!out)
+        return set_error(LFRL_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!p || !img || !opts)
+        return set_error(LFRL_ERR_ARG, "NULL argument");
+    int rc = check_hw(p, h, w);
+    if (rc)
+        return rc;
+    if ((rc = check_opts(opts)))
+        return rc;
+    if (flags & ~(uint32_t)LFRL_JOB_FLUX)
+        return set_error(LFRL_ERR_ARG, "unknown job flags 0x%x", flags);
+    if (opts->init == 1 && !vol0)
+        return set_error(LFRL_ERR_ARG, "init = 1 needs vol0");
+    DevGuard dg(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t hw = (size_t)h * w;
+    if ((rc = check_buf(img, hw * sizeof(float), "img")))
+        return rc;
+    if (opts->init == 1 && (rc = check_buf(vol0, hw * p->g.Nz * sizeof(float), "vol0")))
+        return rc;
+    lfrl_job_s *j = new lfrl_job_s();
+    j->plan = p;
+    j->device = p->device;
+    Frame &f = j->f;
+    if ((rc = frame_alloc(f, p->g, h, w, true))) {
+        delete j;
+        return rc;
     }
-    hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(1), 0, st, p->state);
-    LAUNCH_CHECK("k_state_reset");
-    if (want_flux) {
-        rc = dot_into(p, img, nullptr, (size_t)h * w, nullptr, 0, 0, st);
-        if (rc)
-            return rc;
+    f.opts = *opts;
+    f.want_flux = (flags & LFRL_JOB_FLUX) != 0;
+    hipError_t e = hipMemcpyAsync(f.y_own, img, hw * sizeof(float), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) {
+        free_job(j);
+        return set_error(LFRL_ERR_DEVICE, "image copy failed: %s", hipGetErrorString(e));
     }
-    int iters = 0;
-    bool stopped = false;
-    for (int k = 1; k <= opts->max_iters; ++k) {
-        float *cur = V[(k - 1) & 1], *nxt = V[k & 1];
-        rc = run_forward(p, h, w, cur, p->img, EPI_RATIO, img, st);
-        if (rc)
-            return rc;
-        rc = run_backward(p, h, w, p->img, nxt, EPI_UPDATE, cur, p->sens, st);
-        if (rc)
-            return rc;
-        if (p->nweak) {
-            hipLaunchKernelGGL(k_weak_exact, dim3(p->nweak), dim3(256), 0, st,
-                               (const unsigned *)p->weak, (const float *)p->psf, p->g.N, p->g.K,
-                               h, w, (const float *)p->img, p->sens, (const float *)cur, nxt,
-                               (int)WEAK_UPDATE);
-            LAUNCH_CHECK("k_weak_exact(update)");
+    f.y = f.y_own;
+    if ((rc = frame_sensitivity(p, f, true, st)) ||
+        (rc = frame_start(f, p->g.Nz, opts->init == 1 ? vol0 : nullptr, st))) {
+        const std::string msg = lfrl_last_error();
+        (void)hipStreamSynchronize(st);
+        free_job(j);
+        set_error(rc, "%s", msg.c_str());
+        return rc;
+    }
+    *out = j;
+    return LFRL_OK;
+}
+
+// Internal streams that run the jobs of different plans side by side (default
+// priority, non-blocking), one set per device.
+struct StreamPool {
+    std::vector<hipStream_t> s;
+    std::vector<hipEvent_t> done;
+    hipEvent_t fork = nullptr;
+};
+static constexpr int kPoolStreams = 4;
+static std::mutex g_pool_mu;
+static std::vector<StreamPool> g_pools;
+
+static int get_pool(int dev, StreamPool **out)
+{
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if ((int)g_pools.size() <= dev)
+        g_pools.resize(dev + 1);
+    StreamPool &sp = g_pools[dev];
+    if (sp.s.empty()) {
+        HIP_TRY(hipEventCreateWithFlags(&sp.fork, hipEventDisableTiming));
+        for (int i = 0; i < kPoolStreams; ++i) {
+            hipStream_t s;
+            hipEvent_t e;
+            HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            sp.s.push_back(s);
+            sp.done.push_back(e);
         }
-        iters = k;
-        if (use_metric) {
-            const MetricBufs mb{p->mip, p->tabH, p->tabW, p->T1, p->n2p, p->Fabs,
-                                &p->tab_h, &p->tab_nv, &p->tab_w, &p->tab_nu};
-            rc = run_metric(p->g.Nz, h, w, nxt, opts->xs, opts->ys, p->metric_out, mb, p->state,
-                            p->trace, k, opts->patience, st);
-            if (rc)
-                return rc;
-            hipLaunchKernelGGL(k_cond_copy, dim3(1024), dim3(256), 0, st, (const StopState *)p->state,
-                               (const float *)nxt, VB, nvox);
-            LAUNCH_CHECK("k_cond_copy");
-        }
-        if (want_flux) {
-            rc = dot_into(p, p->sens, nxt, nvox, p->flux, k, 1, st);
-            if (rc)
-                return rc;
-        }
-        if (opts->stop == LFRL_STOP_METRIC) {
-            HIP_TRY(hipMemcpyAsync(p->state_host, p->state, sizeof(StopState), hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            if (p->state_host->stopped) {
-                stopped = true;
+    }
+    *out = &sp;
+    return LFRL_OK;
+}
+
+// Queue one iteration of the jobs on plan p, in launches of at most
+// kMaxBatchJobs frames and the plan's tile capacity.
+static int step_plan_group(lfrl_plan_s *p, std::vector<Frame *> &fr, hipStream_t st)
+{
+    size_t i = 0;
+    while (i < fr.size()) {
+        int n = 0, tiles = 0;
+        while (i + n < fr.size() && n < kMaxBatchJobs) {
+            const int t = tiles_for(p->g, fr[i + n]->h, fr[i + n]->w).nt;
+            if (n > 0 && tiles + t > p->max_tiles)
                 break;
-            }
+            tiles += t;
+            ++n;
         }
-    }
-    int best = iters;
-    if (use_metric) {
-        HIP_TRY(hipMemcpyAsync(p->state_host, p->state, sizeof(StopState), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        best = p->state_host->best_k;
-        HIP_TRY(hipMemcpyAsync(vol, VB, nvox * sizeof(float), hipMemcpyDeviceToDevice, st));
-    } else {
-        HIP_TRY(hipMemcpyAsync(vol, V[iters & 1], nvox * sizeof(float), hipMemcpyDeviceToDevice, st));
-    }
-    if (report) {
-        if (use_metric && report->metric_trace)
-            HIP_TRY(hipMemcpyAsync(report->metric_trace, p->trace, iters * sizeof(double),
-                                   hipMemcpyDeviceToHost, st));
-        if (want_flux)
-            HIP_TRY(hipMemcpyAsync(report->flux_trace, p->flux, iters * sizeof(double),
-                                   hipMemcpyDeviceToHost, st));
-    }
-    HIP_TRY(hipStreamSynchronize(st));
-    if (report) {
-        report->iters_run = iters;
-        report->best_iter = best;
-        report->stopped = stopped ? 1 : 0;
-        report->weak_voxels = (int32_t)p->nweak;
+        int rc = step_frames(p, fr.data() + i, n, st);
+        if (rc)
+            return rc;
+        for (int k = 0; k < n; ++k)
+            if ((rc = frame_queue_poll(*fr[i + k], st)))
+                return rc;
+        i += n;
     }
     return LFRL_OK;
+}
+
+extern "C" int lfrl_job_step(const lfrl_job_t *jobs, int32_t njobs, int32_t *active, void *stream)
+{
+    if (njobs < 0 || (njobs > 0 && !jobs))
+        return set_error(LFRL_ERR_ARG, "bad job list");
+    std::vector<lfrl_plan_s *> plans;
+    std::vector<std::vector<Frame *>> groups;
+    bool any_metric = false;
+    int dev = -1;
+    for (int i = 0; i < njobs; ++i) {
+        if (!jobs[i])
+            return set_error(LFRL_ERR_ARG, "job %d is NULL", i);
+        lfrl_job_s *j = jobs[i];
+        if (dev < 0)
+            dev = j->plan->device;
+        else if (j->plan->device != dev)
+            return set_error(LFRL_ERR_ARG, "jobs on different devices");
+        for (int k = 0; k < i; ++k)
+            if (jobs[k] == j)
+                return set_error(LFRL_ERR_ARG, "job %d listed twice", i);
+        if (j->f.done)
+            continue;
+        size_t g = 0;
+        while (g < plans.size() && plans[g] != j->plan)
+            ++g;
+        if (g == plans.size()) {
+            plans.push_back(j->plan);
+            groups.emplace_back();
+        }
+        groups[g].push_back(&j->f);
+        any_metric |= j->f.opts.stop == LFRL_STOP_METRIC;
+    }
+    int rc = LFRL_OK;
+    if (!plans.empty()) {
+        DevGuard dg(dev);
+        hipStream_t st = (hipStream_t)stream;
+        if (plans.size() == 1) {
+            rc = step_plan_group(plans[0], groups[0], st);
+        } else {
+            StreamPool *sp = nullptr;
+            if ((rc = get_pool(dev, &sp)))
+                return rc;
+            HIP_TRY(hipEventRecord(sp->fork, st));
+            const int nw = (int)std::min<size_t>(plans.size(), sp->s.size());
+            for (int w = 0; w < nw; ++w)
+                HIP_TRY(hipStreamWaitEvent(sp->s[w], sp->fork, 0));
+            for (size_t g = 0; g < plans.size() && rc == LFRL_OK; ++g)
+                rc = step_plan_group(plans[g], groups[g], sp->s[g % nw]);
+            for (int w = 0; w < nw; ++w) {
+                HIP_TRY(hipEventRecord(sp->done[w], sp->s[w]));
+                HIP_TRY(hipStreamWaitEvent(st, sp->done[w], 0));
+            }
+        }
+        if (rc)
+            return rc;
+        if (any_metric)
+            HIP_TRY(hipStreamSynchronize(st));
+        for (auto &gr : groups)
+            for (Frame *f : gr)
+                frame_update_done(*f);
+    }
+    if (active) {
+        int n = 0;
+        for (int i = 0; i < njobs; ++i)
+            n += jobs[i]->f.done ? 0 : 1;
+        *active = n;
+    }
+    return LFRL_OK;
+}
+
+extern "C" int lfrl_job_poll(lfrl_job_t j, int32_t *done, int32_t *iters_run)
+{
+    if (!j)
+        return set_error(LFRL_ERR_ARG, "job is NULL");
+    if (done)
+        *done = j->f.done ? 1 : 0;
+    if (iters_run)
+        *iters_run = j->f.iters;
+    return LFRL_OK;
+}
+
+extern "C" int lfrl_job_result(lfrl_job_t j, float *vol, lfrl_rl_report *report, void *stream)
+{
+    if (!j)
+        return set_error(LFRL_ERR_ARG, "job is NULL");
+    DevGuard dg(j->plan->device);
+    int rc;
+    if (vol && (rc = check_buf(vol, (size_t)j->plan->g.Nz * j->f.h * j->f.w * sizeof(float), "vol")))
+        return rc;
+    return frame_result(j->f, j->plan->g.Nz, vol, report, (hipStream_t)stream);
+}
+
+extern "C" int lfrl_job_destroy(lfrl_job_t j)
+{
+    free_job(j);
+    return LFRL_OK;
+}
+
+extern "C" int lfrl_deconvolve_batch(const lfrl_plan_t *plans, int32_t n, const int32_t *h,
+                                     const int32_t *w, const float *const *imgs,
+                                     float *const *vols, const lfrl_rl_opts *opts,
+                                     lfrl_rl_report *reports, void *stream)
+{
+    if (n < 0 || (n > 0 && (!plans || !h || !w || !imgs || !vols || !opts)))
+        return set_error(LFRL_ERR_ARG, "NULL argument");
+    std::vector<lfrl_job_t> jobs(n, nullptr);
+    auto cleanup = [&]() {
+        for (lfrl_job_t j : jobs)
+            free_job(j);
+    };
+    int rc = LFRL_OK;
+    for (int i = 0; i < n && rc == LFRL_OK; ++i) {
+        if (!plans[i] || !vols[i]) {
+            rc = set_error(LFRL_ERR_ARG, "frame %d: NULL plan or vol", i);
+            break;
+        }
+        const uint32_t fl = (reports && reports[i].flux_trace) ? LFRL_JOB_FLUX : 0u;
+        rc = lfrl_job_create(&jobs[i], plans[i], h[i], w[i], imgs[i],
+                             opts[i].init == 1 ? vols[i] : nullptr, &opts[i], fl, stream);
+        if (rc == LFRL_OK)
+            rc = check_buf(vols[i], (size_t)plans[i]->g.Nz * h[i] * w[i] * sizeof(float), "vol");
+    }
+    int active = n;
+    while (rc == LFRL_OK && active > 0)
+        rc = lfrl_job_step(jobs.data(), n, &active, stream);
+    for (int i = 0; i < n && rc == LFRL_OK; ++i)
+        rc = lfrl_job_result(jobs[i], vols[i], reports ? &reports[i] : nullptr, stream);
+    if (rc != LFRL_OK)
+        (void)hipStreamSynchronize((hipStream_t)stream);
+    cleanup();
+    return rc;
 }
 
 // Scratch for the plan-less metric entry point: one growable set per device.

@@ -139,6 +139,33 @@ enum { SRC_PLANES = 0, SRC_PSF = 1 };
 // select, which the compiler would turn into a branch around the load).
 static constexpr int kLoadBatch = 8;
 
+// Frames whose tiles one launch covers.  Tiles of all frames are numbered
+// consecutively (frame f owns tiles [tile0, tile0 + its tile count)); the
+// contraction between the transforms treats them as one tile dimension, so the
+// spectra stream once for the whole batch.
+static constexpr int kMaxBatchJobs = 16;
+
+struct TileJob {
+    const float *src;   // forward transform: source planes [planes][H][W]
+    float *dst;         // inverse transform: destination (planes or image)
+    const float *aux0;  // inverse transform: y (ratio) or x_old (update)
+    const float *aux1;  // inverse transform: A^T 1 (update)
+    int H, W, tiles_x, tile0;
+};
+
+struct TileBatch {
+    int njobs;
+    TileJob job[kMaxBatchJobs];
+};
+
+__device__ __forceinline__ int batch_job(const TileBatch &b, int tile)
+{
+    int f = 0;
+    while (f + 1 < b.njobs && tile >= b.job[f + 1].tile0)
+        ++f;
+    return f;
+}
+
 __device__ __forceinline__ float keep_if(float v, bool keep)
 {
     return __uint_as_float(__float_as_uint(v) & (keep ? 0xffffffffu : 0u));
@@ -158,22 +185,23 @@ __device__ __forceinline__ int xcd_item(int bid, int n)
 // Forward real tile DFT of N interleaved phases, written as a half spectrum:
 // out[obase + k * kstride + p], k = ku * (Q/2 + 1) + kv.
 //   SRC_PLANES: one overlap-save tile of lenslet rows (plane j, row phase ar)
-//               of a [planes][H][W] array; 1-D grid of nt * planes * N blocks,
+//               of a frame's [planes][H][W] array (frames and tiles from
+//               `batch`; `src` unused); 1-D grid of nt * planes * N blocks,
 //               work item = (j*N + ar) * nt + tile (tiles of one row phase,
 //               which overlap, land on one XCD).
 //               obase = (tile * KKo + j*N*N + ar*N), kstride = nt * KKo.
 //   SRC_PSF:    the polyphase kernels G_{j,a->c}[D] = h[j][a][N*D + c - a + c0]
 //               for output row phase cr and all column phases, placed
-//               circularly in the tile; blockIdx = (cr, a, j); KKo is the row
-//               stride NNp of the spectra.
+//               circularly in the tile; blockIdx = (cr, a, j); `src` is the
+//               PSF; KKo is the row stride NNp of the spectra.
 //               obase = ((j*N*N + a) * NNp + cr*N), kstride = KK * NNp.
 //   rowmax (SRC_PLANES, may be null): rowmax[k * nt + tile] is raised (atomic
 //   max on the float bits) to the largest |re| or |im| the block writes at
 //   frequency k; the caller zeroes it first.
 template <int Q>
-__global__ __launch_bounds__(512) void k_r2c_fft(int mode, const float *__restrict__ src, int H,
-                                                  int W, int N, int T, int hD, int tiles_x, int nt,
-                                                  int KKo, int K, int c0, int KK,
+__global__ __launch_bounds__(512) void k_r2c_fft(int mode, const TileBatch batch,
+                                                  const float *__restrict__ src, int N, int T,
+                                                  int hD, int nt, int KKo, int K, int c0, int KK,
                                                   float2 *__restrict__ out,
                                                   const float2 *__restrict__ twg,
                                                   unsigned *__restrict__ rowmax)
@@ -198,8 +226,10 @@ __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const float *__restri
         const int item = xcd_item(blockIdx.x, gridDim.x);
         const int tile = item % nt, jar = item / nt;
         const int j = jar / N, ar = jar % N;
-        const int ly0 = (tile / tiles_x) * T - hD, lx0 = (tile % tiles_x) * T - hD;
-        const float *plane = src + (size_t)j * H * W;
+        const TileJob &fj = batch.job[batch_job(batch, tile)];
+        const int H = fj.H, W = fj.W, lt = tile - fj.tile0;
+        const int ly0 = (lt / fj.tiles_x) * T - hD, lx0 = (lt % fj.tiles_x) * T - hD;
+        const float *plane = fj.src + (size_t)j * H * W;
         const int total = Q * rowlen;
         for (int base = tid; base < total; base += kLoadBatch * blockDim.x) {
             float v[kLoadBatch];
@@ -311,13 +341,11 @@ __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const float *__restri
 // 1-D grid of nt * planes * N blocks, work item = tile * (planes * N) + j*N + ar
 // (consecutive phases of one tile read adjacent spectra and share an XCD).
 template <int Q>
-__global__ __launch_bounds__(512) void k_c2r_fft(const float2 *__restrict__ spec,
+__global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
+                                                  const float2 *__restrict__ spec,
                                                   size_t split_stride, int nsplit, size_t sk,
                                                   size_t stile, size_t sc, int N, int planes,
-                                                  int T, int hD, int tiles_x, int H, int W,
-                                                  int mode, float *__restrict__ dst,
-                                                  const float *__restrict__ aux0,
-                                                  const float *__restrict__ aux1,
+                                                  int T, int hD, int mode,
                                                   const float2 *__restrict__ twg)
 {
     constexpr int QH = Q / 2 + 1;
@@ -330,7 +358,12 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const float2 *__restrict__ spec
     const int item = xcd_item(blockIdx.x, gridDim.x);
     const int tile = item / (planes * N), jar = item % (planes * N);
     const int j = jar / N, ar = jar % N;
-    const int ty = tile / tiles_x, tx = tile % tiles_x;
+    const TileJob &fj = batch.job[batch_job(batch, tile)];
+    const int H = fj.H, W = fj.W, lt = tile - fj.tile0;
+    const int ty = lt / fj.tiles_x, tx = lt % fj.tiles_x;
+    float *__restrict__ dst = fj.dst;
+    const float *__restrict__ aux0 = fj.aux0;
+    const float *__restrict__ aux1 = fj.aux1;
     for (int i = tid; i < Q; i += blockDim.x)
         tw[i] = twg[i];
     const size_t kkbase = (size_t)j * N * N + (size_t)ar * N;
