@@ -115,6 +115,125 @@ def cpu_baseline(psf, x, y, xs, ys, budget_s: float = 8.0) -> dict:
             "kind": "oracle", "sample": sample}
 
 
+def request_images(specs, plans, cfg, dev):
+    """Measured images of the serving requests, made on the device: the bead
+    splats of each request's seed scattered into a volume, projected with the
+    request's plan, scaled to the peak count, Poisson counts from a device
+    generator seeded with the request seed, plus the background.  Returned as
+    pinned host tensors (a request's image arrives from the host)."""
+    import numpy as np
+    import torch
+
+    import lfrl_synth as S
+    out = []
+    for sp in specs:
+        n, nz, h, w = sp["nnum"], sp["nz"], sp["h"], sp["w"]
+        idx, val = S.bead_splats(nz, h, w, cfg["beads"], sp["seed"])
+        uidx, inv = np.unique(idx, return_inverse=True)
+        uval = np.zeros(uidx.size)
+        np.add.at(uval, inv, val)                       # overlaps summed in bead order
+        vol = torch.zeros(nz * h * w, dtype=torch.float32, device=dev)
+        vol[torch.from_numpy(uidx).to(dev)] = torch.from_numpy(uval.astype(np.float32)).to(dev)
+        lam = plans[sp["set"]].forward(vol.view(nz, h, w))
+        lam = torch.clamp_min(lam * (cfg["peak"] / lam.max()), 0.0)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(sp["seed"])
+        y = torch.poisson(lam, generator=gen) + cfg["background"]
+        host = torch.empty((h, w), dtype=torch.float32, pin_memory=True)
+        host.copy_(y)
+        out.append(host)
+    torch.cuda.synchronize()
+    return out
+
+
+def serving_leg(args, dev) -> dict:
+    """Served deconvolution requests for four resident split-FP16 PSF sets:
+    saturation rate from a closed loop (every request queued at t = 0), then
+    open-loop Poisson arrivals at 0.8 and 0.5 of it; latency is arrival to
+    result volume in host memory."""
+    import torch
+
+    import lfrl_synth as S
+    import paper_2208_11422_amd as lf
+    from paper_2208_11422_amd.serve import JobExecutor, Request, Scheduler, latency_stats
+    cfg = S.SERVING
+    t_all = time.perf_counter()
+    plans = []
+    for k, (n, nz, seed) in enumerate(cfg["sets"]):
+        t = time.perf_counter()
+        psf = S._cached(f"psf_serving_{n}_{nz}_{cfg['ksize']}_{seed}",
+                        lambda: S.serving_psf(k), CACHE)
+        t_gen = time.perf_counter() - t
+        psf_d = torch.from_numpy(psf).to(dev)
+        del psf
+        side = cfg["max_side"] // n * n
+        plans.append(lf.Plan(psf_d, side, side, precision=lf.SPLIT_FP16,
+                             max_batch=args.serving_batch))
+        del psf_d
+        torch.cuda.synchronize()
+        info = plans[-1].info
+        log(f"serving: set {k} (N={n}, nz={nz}) PSF {t_gen:.1f} s, plan Q={info['tile_q']} "
+            f"spectra {info['resident_bytes'] / 1e9:.2f} GB, workspace "
+            f"{info['workspace_bytes'] / 1e9:.2f} GB, {time.perf_counter() - t:.1f} s")
+    specs = S.serving_requests(args.serving_requests)
+    t = time.perf_counter()
+    images = request_images(specs, plans, cfg, dev)
+    log(f"serving: {len(specs)} request images in {time.perf_counter() - t:.1f} s")
+    r = cfg["spot_radius"]
+    legs = {sp["rid"]: (sp["w"] / (sp["nnum"] * 2.0 * r), sp["h"] / (sp["nnum"] * 2.0 * r))
+            for sp in specs}
+
+    def opts_for(req):
+        xs, ys = legs[req.rid]
+        return dict(iters=cfg["max_iters"], stop=lf.STOP_METRIC, patience=1, xs=xs, ys=ys)
+
+    check = [sp["rid"] for sp in specs[:3]]
+    budget = int(args.serving_budget_gb * 1e9)
+
+    def run(arrivals, keep=()):
+        reqs = [Request(rid=sp["rid"], plan=sp["set"], h=sp["h"], w=sp["w"], image=img,
+                        arrival=float(a)) for sp, img, a in zip(specs, images, arrivals)]
+        ex = JobExecutor(plans, opts_for, keep=keep)
+        sched = Scheduler(ex, budget, max_active=args.serving_active)
+        t0 = time.perf_counter()
+        sched.run(reqs)
+        span = time.perf_counter() - t0
+        st = latency_stats(reqs, span)
+        st.update(span_s=span, rounds=sched.rounds, peak_active=sched.peak_active,
+                  peak_job_gb=sched.peak_bytes / 1e9,
+                  mean_batch=sum(sched.batch_sizes) / max(len(sched.batch_sizes), 1),
+                  mean_iters=sum(q.iters for q in reqs) / len(reqs),
+                  op_seconds={k: round(v, 4) for k, v in sched.op_seconds.items()})
+        return st, reqs
+
+    closed, reqs = run([0.0] * len(specs), keep=check)
+    mu = closed["frames_per_s"]
+    log(f"serving: closed loop {json.dumps(closed)}")
+    # a served result is the volume the same request gets alone
+    same = True
+    for q in reqs:
+        if q.rid in check:
+            sp = specs[q.rid]
+            xs, ys = legs[q.rid]
+            alone, _ = plans[sp["set"]].deconvolve(images[q.rid].to(dev), cfg["max_iters"],
+                                                   stop=lf.STOP_METRIC, xs=xs, ys=ys)
+            same &= bool(torch.equal(alone.cpu(), q.result))
+    out = {"requests": len(specs), "psf_sets": [list(s[:2]) for s in cfg["sets"]],
+           "ksize": cfg["ksize"], "precision": "split-fp16", "stop": "metric, cap 50",
+           "budget_gb": args.serving_budget_gb, "saturation_frames_per_s": mu,
+           "closed_loop": closed, "alone_vs_mix_equal": same}
+    for frac in (0.8, 0.5):
+        arr = S.poisson_arrivals(len(specs), frac * mu)
+        st, _ = run(arr)
+        log(f"serving: open loop at {frac} x saturation {json.dumps(st)}")
+        out[f"open_loop_{frac}"] = st
+    for p in plans:
+        p.close()
+    torch.cuda.empty_cache()
+    out["leg_seconds"] = time.perf_counter() - t_all
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +243,13 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-split", action="store_true",
                     help="skip the split-FP16 measurement")
+    ap.add_argument("--serving-requests", type=int, default=2000,
+                    help="requests of the serving leg (0 skips it; the full workload is 2000)")
+    ap.add_argument("--serving-batch", type=int, default=4,
+                    help="largest frames one projection launch of a PSF set covers")
+    ap.add_argument("--serving-active", type=int, default=32, help="jobs in flight at most")
+    ap.add_argument("--serving-budget-gb", type=float, default=96.0,
+                    help="device memory admitted jobs may hold")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy (reference kernel of known "
                          "size for hardware byte counters)")
@@ -273,6 +399,13 @@ def main() -> int:
         log(f"bench: split FP16 {ms16:.3f} ms/iter ({1000.0 / ms16:.1f} it/s), "
             f"rel L2 vs FP32 {diff:.2e}")
         plan = plan16
+    if args.serving_requests > 0:
+        plan.close()
+        torch.cuda.empty_cache()
+        out["serving"] = serving_leg(args, dev)
+        out["p50_ms"] = out["serving"]["open_loop_0.8"]["p50_ms"]
+        out["p99_ms"] = out["serving"]["open_loop_0.8"]["p99_ms"]
+        plan = None
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle, bounded sample)")
         # oracle inputs come from the generators, never from the GPU path; the
@@ -280,7 +413,8 @@ def main() -> int:
         x_dense = p["x_true"] + np.float32(1.0)
         y_syn = np.random.default_rng(1).uniform(10.0, 2000.0, size=(h, w)).astype(np.float32)
         out["cpu_baseline"] = cpu_baseline(p["psf_array"], x_dense, y_syn, xs, ys)
-    plan.close()
+    if plan is not None:
+        plan.close()
     print(json.dumps(out), flush=True)
     return 0
 

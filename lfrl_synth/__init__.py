@@ -28,6 +28,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 
 import numpy as np
 
@@ -142,11 +143,12 @@ def disk_psf(nnum: int, nz: int, ksize: int, seed: int, *,
     out = np.empty((nz, nnum, nnum, ksize, ksize), dtype=np.float32)
     cache: dict[float, tuple[np.ndarray, np.ndarray]] = {}
     for j in range(nz):
-        rad = r0 + r_slope * abs(z[j])
-        key = round(rad, 12)
+        key = round(r0 + r_slope * abs(z[j]), 12)
         if key not in cache:
-            cache[key] = _disk_blur_profile(rad, blur, rmax)
-        rgrid, prof = cache[key]
+            cache[key] = _disk_blur_profile(key, blur, rmax)
+
+    def plane(j: int) -> None:
+        rgrid, prof = cache[round(r0 + r_slope * abs(z[j]), 12)]
         cu = c0 + shift_scale * ph[:, None] * z[j] + jit[j, :, :, 0]
         cv = c0 + shift_scale * ph[None, :] * z[j] + jit[j, :, :, 1]
         du = (u[None, None, :] - cu[..., None]) ** 2          # [a][b][u]
@@ -155,6 +157,12 @@ def disk_psf(nnum: int, nz: int, ksize: int, seed: int, *,
             d = np.sqrt(du[a][:, :, None] + dv[a][:, None, :])  # [b][u][v]
             k = np.interp(d, rgrid, prof)
             out[j, a] = _unit_sum_f32(k)
+
+    # planes are independent: numpy releases the GIL in the heavy calls
+    from concurrent.futures import ThreadPoolExecutor
+    workers = max(1, min(16, os.cpu_count() or 1, nz))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(plane, range(nz)))
     return out
 
 
@@ -188,6 +196,37 @@ def bead_volume(nz: int, h: int, w: int, n_beads: int, seed: int, *,
     for i in range(n_beads):
         _splat(vol, (cz[i], cr[i], cs[i]), sigma, amp, trunc)
     return vol if as_float64 else vol.astype(np.float32)
+
+
+def bead_splats(nz: int, h: int, w: int, n_beads: int, seed: int, *,
+                sigma: float = 1.0, amp: float = 1.0,
+                trunc: float = 4.0) -> tuple[np.ndarray, np.ndarray]:
+    """The beads of ``bead_volume`` (same draws, same values) as flat voxel
+    indices and float64 values, in bead order: adding the values at the
+    indices, in order, onto a zero volume gives ``bead_volume(...,
+    as_float64=True)``.  Lets a large sparse volume be built where it is
+    used instead of being shipped whole."""
+    rng = np.random.default_rng(seed)
+    c = np.stack([rng.uniform(0, nz, n_beads), rng.uniform(0, h, n_beads),
+                  rng.uniform(0, w, n_beads)], axis=1)               # [bead][axis]
+    rad = trunc * sigma
+    dims = np.array([nz, h, w])
+    lo = np.maximum(np.floor(c - rad).astype(np.int64), 0)
+    hi = np.minimum(np.ceil(c + rad).astype(np.int64), dims - 1)
+    m = int(2 * math.ceil(rad) + 2)                                  # widest box side
+    ax = lo[:, :, None] + np.arange(m)[None, None, :]               # [bead][axis][m]
+    inside = ax <= hi[:, :, None]
+    dz = (ax[:, 0] - c[:, 0:1]) ** 2
+    dr = (ax[:, 1] - c[:, 1:2]) ** 2
+    ds = (ax[:, 2] - c[:, 2:3]) ** 2
+    d2 = dz[:, :, None, None] + dr[:, None, :, None] + ds[:, None, None, :]
+    g = amp * np.exp(-d2 / (2 * sigma * sigma))
+    g[d2 > rad * rad] = 0.0
+    keep = (inside[:, 0][:, :, None, None] & inside[:, 1][:, None, :, None]
+            & inside[:, 2][:, None, None, :])
+    flat = ((ax[:, 0][:, :, None, None] * h + ax[:, 1][:, None, :, None]) * w
+            + ax[:, 2][:, None, None, :])
+    return flat[keep].astype(np.int64), g[keep]
 
 
 def add_filaments(vol: np.ndarray, n: int, seed: int, *, step: float = 0.25,
@@ -240,6 +279,52 @@ PRESETS = {
                   beads=500, vol_seed=22, filaments=3, peak=2000.0, background=10.0,
                   noise_seed=23, iters=8, spot_radius=2.0),
 }
+
+
+# Serving workload: four resident PSF sets (Nnum, planes, seed), K = 255, built
+# with the defocus-disk generator and depths rescaled so every set has the
+# largest disk and shift of the 31-plane set; requests pick a set uniformly
+# and a square size uniformly among the lenslet counts L with
+# min_side <= Nnum * L <= max_side.
+SERVING = dict(sets=((11, 21, 501), (13, 31, 502), (15, 31, 503), (15, 51, 504)),
+               ksize=255, depth_rescale=15.0, requests=2000, arrival_seed=51,
+               request_seed0=5000, beads=200, peak=1000.0, background=10.0,
+               min_side=363, max_side=900, max_iters=50, spot_radius=2.0)
+
+
+def serving_psf(k: int, ksize: int | None = None) -> np.ndarray:
+    """PSF set k of the serving workload."""
+    n, nz, seed = SERVING["sets"][k]
+    return disk_psf(n, nz, ksize or SERVING["ksize"], seed,
+                    depth_rescale=SERVING["depth_rescale"])
+
+
+def serving_requests(count: int, *, seed0: int | None = None,
+                     sets=None, min_side: int | None = None,
+                     max_side: int | None = None) -> list[dict]:
+    """Seeded request specs: PSF set index, Nnum, planes, lenslets per side,
+    image size and the seed of the request's bead volume and noise."""
+    sets = sets or SERVING["sets"]
+    seed0 = SERVING["request_seed0"] if seed0 is None else seed0
+    lo_side = min_side or SERVING["min_side"]
+    hi_side = max_side or SERVING["max_side"]
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng(seed0 + i)
+        k = int(rng.integers(len(sets)))
+        n, nz = sets[k][0], sets[k][1]
+        lo = -(-lo_side // n)
+        hi = hi_side // n
+        L = int(rng.integers(lo, hi + 1))
+        out.append(dict(rid=i, set=k, nnum=n, nz=nz, lenslets=L, h=n * L, w=n * L,
+                        seed=seed0 + i))
+    return out
+
+
+def poisson_arrivals(count: int, rate: float, seed: int | None = None) -> np.ndarray:
+    """Arrival times (s) of an open-loop Poisson process of `rate` per second."""
+    rng = np.random.default_rng(SERVING["arrival_seed"] if seed is None else seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))
 
 
 def _cached(key: str, make, cache_dir: str | None):

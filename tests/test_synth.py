@@ -61,3 +61,31 @@ def test_measure_counts():
     assert np.all(y >= 10.0)
     assert np.all(np.mod(y - 10.0, 1.0) == 0)      # integer counts on the background
     assert digest(y) == digest(S.measure(clean, 1000.0, 10.0, seed=13))
+
+
+def test_bead_splats_rebuild_the_bead_volume():
+    import numpy as np
+    import lfrl_synth as S
+    for args in [(5, 40, 50, 30, 3), (3, 9, 12, 40, 4)]:
+        v = S.bead_volume(*args, as_float64=True)
+        idx, val = S.bead_splats(*args)
+        z = np.zeros(v.size)
+        np.add.at(z, idx, val)
+        assert np.array_equal(z.reshape(v.shape), v)
+
+
+def test_serving_request_specs():
+    import lfrl_synth as S
+    a = S.serving_requests(200)
+    assert a == S.serving_requests(200)
+    seen = set()
+    for r in a:
+        n, nz = S.SERVING["sets"][r["set"]][:2]
+        assert (r["nnum"], r["nz"]) == (n, nz)
+        assert r["h"] == r["w"] == n * r["lenslets"]
+        assert 363 <= r["h"] <= 900
+        seen.add(r["set"])
+    assert seen == {0, 1, 2, 3}
+    t = S.poisson_arrivals(1000, 50.0)
+    assert (t[1:] > t[:-1]).all()
+    assert abs(t[-1] / 1000 - 1 / 50.0) < 0.2 / 50.0
