@@ -115,34 +115,111 @@ def cpu_baseline(psf, x, y, xs, ys, budget_s: float = 8.0) -> dict:
             "kind": "oracle", "sample": sample}
 
 
-def request_images(specs, plans, cfg, dev):
-    """Measured images of the serving requests, made on the device: the bead
-    splats of each request's seed scattered into a volume, projected with the
-    request's plan, scaled to the peak count, Poisson counts from a device
-    generator seeded with the request seed, plus the background.  Returned as
-    pinned host tensors (a request's image arrives from the host)."""
+def synth_measurement(plan, nz, h, w, seed, beads, peak, background, dev):
+    """Measured image of a bead volume, made on the device: the bead splats of
+    `seed` scattered into a volume, projected with `plan`, scaled to `peak`
+    expected counts, Poisson counts from a device generator seeded with
+    `seed`, plus `background`."""
     import numpy as np
     import torch
 
     import lfrl_synth as S
+    idx, val = S.bead_splats(nz, h, w, beads, seed)
+    uidx, inv = np.unique(idx, return_inverse=True)
+    uval = np.zeros(uidx.size)
+    np.add.at(uval, inv, val)                       # overlaps summed in bead order
+    vol = torch.zeros(nz * h * w, dtype=torch.float32, device=dev)
+    vol[torch.from_numpy(uidx).to(dev)] = torch.from_numpy(uval.astype(np.float32)).to(dev)
+    lam = plan.forward(vol.view(nz, h, w))
+    lam = torch.clamp_min(lam * (peak / lam.max()), 0.0)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    return torch.poisson(lam, generator=gen) + background
+
+
+def request_images(specs, plans, cfg, dev):
+    """Serving request images (see synth_measurement), as pinned host tensors:
+    a request's image arrives from the host."""
+    import torch
     out = []
     for sp in specs:
-        n, nz, h, w = sp["nnum"], sp["nz"], sp["h"], sp["w"]
-        idx, val = S.bead_splats(nz, h, w, cfg["beads"], sp["seed"])
-        uidx, inv = np.unique(idx, return_inverse=True)
-        uval = np.zeros(uidx.size)
-        np.add.at(uval, inv, val)                       # overlaps summed in bead order
-        vol = torch.zeros(nz * h * w, dtype=torch.float32, device=dev)
-        vol[torch.from_numpy(uidx).to(dev)] = torch.from_numpy(uval.astype(np.float32)).to(dev)
-        lam = plans[sp["set"]].forward(vol.view(nz, h, w))
-        lam = torch.clamp_min(lam * (cfg["peak"] / lam.max()), 0.0)
-        gen = torch.Generator(device=dev)
-        gen.manual_seed(sp["seed"])
-        y = torch.poisson(lam, generator=gen) + cfg["background"]
-        host = torch.empty((h, w), dtype=torch.float32, pin_memory=True)
+        y = synth_measurement(plans[sp["set"]], sp["nz"], sp["h"], sp["w"], sp["seed"],
+                              cfg["beads"], cfg["peak"], cfg["background"], dev)
+        host = torch.empty(y.shape, dtype=torch.float32, pin_memory=True)
         host.copy_(y)
         out.append(host)
     torch.cuda.synchronize()
+    return out
+
+
+def batched_leg(args, dev) -> dict:
+    """Independent frames of uneven sizes, each with its own FP32 plan (tile
+    side chosen by the autotuner): the frames one after another through
+    lfrl_deconvolve, then all together as jobs stepped in lock-step (plans run
+    side by side on internal streams).  A^T 1 of each frame is formed before
+    the timed regions, like the plans."""
+    import torch
+
+    import lfrl_synth as S
+    import paper_2208_11422_amd as lf
+    cfg = S.BATCHED
+    t_all = time.perf_counter()
+    specs = S.batched_frames(args.batched_frames)
+    plans, imgs, opts = [], [], []
+    for sp in specs:
+        t = time.perf_counter()
+        psf_d = torch.from_numpy(S.batched_psf(sp)).to(dev)
+        plans.append(lf.Plan(psf_d, sp["h"], sp["w"], autotune=True))
+        del psf_d
+        imgs.append(synth_measurement(plans[-1], sp["nz"], sp["h"], sp["w"], sp["seed"],
+                                      cfg["beads"], cfg["peak"], cfg["background"], dev))
+        xs = sp["w"] / (sp["nnum"] * 2.0 * cfg["spot_radius"])
+        ys = sp["h"] / (sp["nnum"] * 2.0 * cfg["spot_radius"])
+        opts.append(lf.RlOpts(max_iters=cfg["iters"], stop=lf.STOP_TRACK, patience=1, init=0,
+                              xs=xs, ys=ys))
+        info = plans[-1].info
+        log(f"batched: frame {sp['frame']} N={sp['nnum']} {sp['h']}x{sp['w']}x{sp['nz']} "
+            f"K={sp['ksize']} Q={info['tile_q']} (tuned over {info['tune_candidates']}, "
+            f"{info['tune_ms']:.2f} ms) {time.perf_counter() - t:.1f} s")
+    vols_seq = [torch.empty((sp["nz"], sp["h"], sp["w"]), device=dev) for sp in specs]
+    vols_bat = [torch.empty_like(v) for v in vols_seq]
+    for pl, sp, y, o, v in zip(plans, specs, imgs, opts, vols_seq):   # warm-up, A^T 1
+        o1 = lf.RlOpts(max_iters=1, stop=o.stop, patience=1, init=0, xs=o.xs, ys=o.ys)
+        lf.lfrl_deconvolve(pl.handle, sp["h"], sp["w"], y, v, o1, want_metric=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for pl, sp, y, o, v in zip(plans, specs, imgs, opts, vols_seq):
+        lf.lfrl_deconvolve(pl.handle, sp["h"], sp["w"], y, v, o, want_metric=False)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    jobs = [lf.Job(pl, y, cfg["iters"], stop=lf.STOP_TRACK, xs=o.xs, ys=o.ys)
+            for pl, y, o in zip(plans, imgs, opts)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while lf.Job.step(jobs) > 0:
+        pass
+    for j, v in zip(jobs, vols_bat):
+        j.result(out=v)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    same = all(bool(torch.equal(a, b)) for a, b in zip(vols_seq, vols_bat))
+    for j in jobs:
+        j.close()
+    n_it = len(specs) * cfg["iters"]
+    vox = sum(sp["nz"] * sp["h"] * sp["w"] for sp in specs) * cfg["iters"]
+    out = {"frames": len(specs), "iters_per_frame": cfg["iters"], "precision": "fp32",
+           "stop": "metric tracked, best kept",
+           "batched": {"seconds": t_bat, "frames_per_s": len(specs) / t_bat,
+                       "iters_per_s": n_it / t_bat, "voxel_updates_per_s": vox / t_bat},
+           "sequential": {"seconds": t_seq, "frames_per_s": len(specs) / t_seq,
+                          "iters_per_s": n_it / t_seq, "voxel_updates_per_s": vox / t_seq},
+           "speedup": t_seq / t_bat, "batched_equals_sequential": same,
+           "tile_q": [pl.info["tile_q"] for pl in plans]}
+    for pl in plans:
+        pl.close()
+    torch.cuda.empty_cache()
+    out["leg_seconds"] = time.perf_counter() - t_all
+    log(f"batched: {json.dumps(out)}")
     return out
 
 
@@ -243,6 +320,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-split", action="store_true",
                     help="skip the split-FP16 measurement")
+    ap.add_argument("--batched-frames", type=int, default=16,
+                    help="frames of the batched uneven-size leg (0 skips it)")
     ap.add_argument("--serving-requests", type=int, default=2000,
                     help="requests of the serving leg (0 skips it; the full workload is 2000)")
     ap.add_argument("--serving-batch", type=int, default=4,
@@ -399,13 +478,16 @@ def main() -> int:
         log(f"bench: split FP16 {ms16:.3f} ms/iter ({1000.0 / ms16:.1f} it/s), "
             f"rel L2 vs FP32 {diff:.2e}")
         plan = plan16
-    if args.serving_requests > 0:
+    if args.batched_frames > 0 or args.serving_requests > 0:
         plan.close()
+        plan = None
         torch.cuda.empty_cache()
+    if args.batched_frames > 0:
+        out["batched"] = batched_leg(args, dev)
+    if args.serving_requests > 0:
         out["serving"] = serving_leg(args, dev)
         out["p50_ms"] = out["serving"]["open_loop_0.8"]["p50_ms"]
         out["p99_ms"] = out["serving"]["open_loop_0.8"]["p99_ms"]
-        plan = None
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle, bounded sample)")
         # oracle inputs come from the generators, never from the GPU path; the

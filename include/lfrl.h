@@ -60,6 +60,11 @@ typedef enum {
                              projection about 1e-4 instead of 1e-7. */
 } lfrl_precision;
 
+/* Plan flags.  LFRL_PLAN_AUTOTUNE (with tile_q = 0): time the best few tile
+ * sides by the model on the device (one forward and one back projection of
+ * max_batch largest frames each, on zero spectra) and keep the fastest. */
+enum { LFRL_PLAN_AUTOTUNE = 1u << 0 };
+
 /* Plan description.  Geometry of the PSF set and the largest image the plan
  * serves (the memory estimate of Fig. 1 is made for that size). */
 typedef struct {
@@ -70,7 +75,7 @@ typedef struct {
     int32_t max_w;     /* largest image width served, multiple of nnum */
     int32_t precision; /* lfrl_precision */
     int32_t tile_q;    /* DFT tile side in lenslets; 0 = choose from the model */
-    uint32_t flags;    /* reserved, must be 0 */
+    uint32_t flags;    /* 0 or LFRL_PLAN_AUTOTUNE */
     int32_t max_batch; /* frames of max_h x max_w whose tiles one batched
                           projection covers (lfrl_job_step); 0 or 1 = one
                           frame, at most 16.  Workspace grows with it. */
@@ -88,11 +93,15 @@ typedef struct {
     size_t resident_bytes; /* spectra held for the plan's lifetime */
     size_t workspace_bytes;/* workspace: tile spectra for max_tiles tiles plus
                               the frame state of lfrl_deconvolve */
+    int32_t tune_candidates; /* tile sides timed (autotuned plans), else 0 */
+    double tune_ms;        /* measured forward + back projection of max_batch
+                              largest frames at the chosen side, else 0 */
 } lfrl_plan_info_t;
 
 /* Memory estimate before allocation (Fig. 1: the required memory is
  * estimated before anything is placed on the card).  [host], no device work.
- * Either output pointer may be NULL. */
+ * Either output pointer may be NULL.  With LFRL_PLAN_AUTOTUNE the figures are
+ * the largest over the tile sides the tuner may choose. */
 int lfrl_plan_footprint(const lfrl_plan_desc *desc, size_t *resident_bytes,
                         size_t *workspace_bytes);
 

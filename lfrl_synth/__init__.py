@@ -97,7 +97,8 @@ def gaussian_psf(nnum: int, nz: int, ksize: int, seed: int, *,
     jit = rng.uniform(-jitter, jitter, size=(nz, nnum, nnum, 2))
     u = np.arange(ksize, dtype=np.float64)
     out = np.empty((nz, nnum, nnum, ksize, ksize), dtype=np.float32)
-    for j in range(nz):
+
+    def plane(j: int) -> None:
         sig = sigma0 + abs(z[j])
         cu = c0 + shift_scale * ph[:, None] * z[j] + jit[j, :, :, 0]   # [a][b]
         cv = c0 + shift_scale * ph[None, :] * z[j] + jit[j, :, :, 1]
@@ -105,7 +106,21 @@ def gaussian_psf(nnum: int, nz: int, ksize: int, seed: int, *,
         gv = np.exp(-(u[None, None, :] - cv[..., None]) ** 2 / (2 * sig * sig))
         k = gu[..., :, None] * gv[..., None, :]
         out[j] = _unit_sum_f32(k)
+
+    _each_plane(plane, nz)
     return out
+
+
+def _each_plane(fn, nz: int) -> None:
+    """Run fn(j) for every plane on a thread pool (the planes are independent
+    and numpy releases the GIL in the heavy calls)."""
+    if nz <= 1:
+        fn(0)
+        return
+    from concurrent.futures import ThreadPoolExecutor
+    workers = max(1, min(16, os.cpu_count() or 1, nz))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(fn, range(nz)))
 
 
 def _disk_blur_profile(radius: float, blur: float, rmax: float,
@@ -158,11 +173,7 @@ def disk_psf(nnum: int, nz: int, ksize: int, seed: int, *,
             k = np.interp(d, rgrid, prof)
             out[j, a] = _unit_sum_f32(k)
 
-    # planes are independent: numpy releases the GIL in the heavy calls
-    from concurrent.futures import ThreadPoolExecutor
-    workers = max(1, min(16, os.cpu_count() or 1, nz))
-    with ThreadPoolExecutor(max_workers=workers) as ex:
-        list(ex.map(plane, range(nz)))
+    _each_plane(plane, nz)
     return out
 
 
@@ -319,6 +330,34 @@ def serving_requests(count: int, *, seed0: int | None = None,
         out.append(dict(rid=i, set=k, nnum=n, nz=nz, lenslets=L, h=n * L, w=n * L,
                         seed=seed0 + i))
     return out
+
+
+# Batched workload: independent frames, each with its own Nnum, planes, size
+# and Gaussian PSF set (K = min(255, 8 Nnum + 1), shift scale kept inside the
+# support), 200 beads, peak 1000 counts, background 10, 8 iterations.
+BATCHED = dict(frames=16, seed0=300, nnums=(11, 13, 15), nzs=(21, 31, 41), min_lenslets=33,
+               max_side=900, beads=200, peak=1000.0, background=10.0, iters=8,
+               spot_radius=1.0)
+
+
+def batched_frames(count: int | None = None) -> list[dict]:
+    """Seeded specs of the batched workload's frames."""
+    cfg = BATCHED
+    out = []
+    for f in range(cfg["frames"] if count is None else count):
+        seed = cfg["seed0"] + f
+        rng = np.random.default_rng(seed)
+        n = int(rng.choice(cfg["nnums"]))
+        L = int(rng.integers(cfg["min_lenslets"], cfg["max_side"] // n + 1))
+        nz = int(rng.choice(cfg["nzs"]))
+        k = min(255, 8 * n + 1)
+        out.append(dict(frame=f, seed=seed, nnum=n, lenslets=L, h=n * L, w=n * L, nz=nz,
+                        ksize=k))
+    return out
+
+
+def batched_psf(spec: dict) -> np.ndarray:
+    return gaussian_psf(spec["nnum"], spec["nz"], spec["ksize"], spec["seed"], shift_scale=None)
 
 
 def poisson_arrivals(count: int, rate: float, seed: int | None = None) -> np.ndarray:

@@ -52,7 +52,8 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("tile_q", ctypes.c_int32), ("tile_out", ctypes.c_int32),
                 ("taps", ctypes.c_int32), ("nfreq", ctypes.c_int32),
                 ("max_tiles", ctypes.c_int32), ("split_k", ctypes.c_int32),
-                ("resident_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t)]
+                ("resident_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
+                ("tune_candidates", ctypes.c_int32), ("tune_ms", ctypes.c_double)]
 
 
 class RlOpts(ctypes.Structure):
@@ -213,6 +214,7 @@ def lfrl_metric_cutoff(d_ml: float, mag: float, nnum: int, wavelength: float, na
 
 
 JOB_FLUX = 1
+PLAN_AUTOTUNE = 1
 
 
 def _report_buffers(n: int, want_metric: bool, want_flux: bool):
@@ -311,13 +313,14 @@ class Plan:
     """Resident PSF spectra for one PSF set, serving images up to max_h x max_w."""
 
     def __init__(self, psf: torch.Tensor, max_h: int, max_w: int, tile_q: int = 0,
-                 precision: int = FP32, max_batch: int = 1, stream=None):
+                 precision: int = FP32, max_batch: int = 1, autotune: bool = False,
+                 stream=None):
         nz, n, n2, k, k2 = psf.shape
         if n != n2 or k != k2:
             raise LfrlError(-1, "psf must be [nz][N][N][K][K]")
         self.desc = PlanDesc(nnum=n, nz=nz, ksize=k, max_h=max_h, max_w=max_w,
-                             precision=precision, tile_q=tile_q, flags=0,
-                             max_batch=max_batch)
+                             precision=precision, tile_q=tile_q,
+                             flags=PLAN_AUTOTUNE if autotune else 0, max_batch=max_batch)
         self.nnum, self.nz, self.ksize = n, nz, k
         self.device = psf.device
         self.handle = lfrl_plan(self.desc, psf, stream)

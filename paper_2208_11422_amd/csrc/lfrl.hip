@@ -450,7 +450,7 @@ __global__ __launch_bounds__(512) void k_contract_fwd(const float2 *__restrict__
                                                       int KK, int KKs, int nt, int nf, int kchunk)
 {
     const int k = blockIdx.x, s = blockIdx.y, t0 = blockIdx.z * 16;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, kq = lane >> 4;
     const int kb0 = s * kchunk;
     const int kb1 = min(KK, kb0 + kchunk);
@@ -1185,6 +1185,8 @@ struct lfrl_plan_s {
     int *gexp = nullptr;                // per-frequency exponents of the FP16 spectra
     unsigned *xmax = nullptr, *rmax = nullptr;  // per-(frequency, tile) maxima of tile spectra
     int thr_r2c = 256, thr_c2r = 256;
+    double tune_ms = 0.0;     // measured projection pair at the chosen tile (autotuned plans)
+    int tune_candidates = 0;  // tile sides timed
     // profiling
     bool prof = false;
     std::vector<hipEvent_t> ev[2];
@@ -1205,8 +1207,8 @@ static int validate_desc(const lfrl_plan_desc *d)
         return set_error(LFRL_ERR_ARG, "max_h/max_w must be positive multiples of nnum");
     if (d->precision != LFRL_FP32 && d->precision != LFRL_SPLIT_FP16)
         return set_error(LFRL_ERR_UNSUPPORTED, "precision %d not supported", d->precision);
-    if (d->flags != 0)
-        return set_error(LFRL_ERR_ARG, "flags must be 0");
+    if (d->flags & ~(uint32_t)LFRL_PLAN_AUTOTUNE)
+        return set_error(LFRL_ERR_ARG, "unknown plan flags 0x%x", d->flags);
     if (d->tile_q < 0 || d->tile_q > kMaxQ)
         return set_error(LFRL_ERR_ARG, "tile_q must be in [0, %d]", kMaxQ);
     if (d->max_batch < 0 || d->max_batch > kMaxBatchJobs)
@@ -1242,11 +1244,14 @@ static size_t lds_limit()
     return 160 * 1024;
 }
 
-static int pick_q(const lfrl_plan_desc *d, size_t lds_max, int *q_out)
+// Tile sides a plan may use, ranked by the model (best first).  An explicit
+// tile_q is the only candidate.
+static int rank_q(const lfrl_plan_desc *d, size_t lds_max, std::vector<int> *out)
 {
     Geo g;
     geo_init(g, d->nnum, d->nz, d->ksize, 1);
     const int R = g.R;
+    out->clear();
     if (d->tile_q > 0) {
         if (d->tile_q < R)
             return set_error(LFRL_ERR_ARG, "tile_q %d smaller than the polyphase taps %d",
@@ -1259,11 +1264,10 @@ static int pick_q(const lfrl_plan_desc *d, size_t lds_max, int *q_out)
         if (d->precision == LFRL_SPLIT_FP16 && !fft_usable(gq, lds_max))
             return set_error(LFRL_ERR_UNSUPPORTED, "split FP16 needs an FFT tile size (tile_q %d)",
                              d->tile_q);
-        *q_out = d->tile_q;
+        out->push_back(d->tile_q);
         return LFRL_OK;
     }
-    double best = 1e300;
-    int bq = -1;
+    std::vector<std::pair<double, int>> ranked;
     for (int q = std::max(R, 2); q <= kMaxQ; ++q) {
         Geo gq;
         geo_init(gq, d->nnum, d->nz, d->ksize, q);
@@ -1272,15 +1276,33 @@ static int pick_q(const lfrl_plan_desc *d, size_t lds_max, int *q_out)
         if (d->precision == LFRL_SPLIT_FP16 && !fft_usable(gq, lds_max))
             continue;  // the split path takes its row scales from the FFT tile kernels
         const Tiles t = tiles_for(gq, d->max_h, d->max_w);
-        const double tm = model_time(gq, t);
-        if (tm < best * 0.999) {
-            best = tm;
-            bq = q;
-        }
+        ranked.push_back({model_time(gq, t), q});
     }
-    if (bq < 0)
+    if (ranked.empty())
         return set_error(LFRL_ERR_UNSUPPORTED, "no DFT tile fits in %zu bytes of LDS", lds_max);
-    *q_out = bq;
+    // the model's choice: ascending q, a larger tile only when clearly faster
+    size_t best = 0;
+    for (size_t i = 1; i < ranked.size(); ++i)
+        if (ranked[i].first < ranked[best].first * 0.999)
+            best = i;
+    out->push_back(ranked[best].second);
+    ranked.erase(ranked.begin() + best);
+    std::stable_sort(ranked.begin(), ranked.end(),
+                     [](const std::pair<double, int> &x, const std::pair<double, int> &y) {
+                         return x.first < y.first;
+                     });
+    for (auto &r : ranked)
+        out->push_back(r.second);
+    return LFRL_OK;
+}
+
+static int pick_q(const lfrl_plan_desc *d, size_t lds_max, int *q_out)
+{
+    std::vector<int> c;
+    int rc = rank_q(d, lds_max, &c);
+    if (rc)
+        return rc;
+    *q_out = c[0];
     return LFRL_OK;
 }
 
@@ -1429,6 +1451,8 @@ static Sizes sizes_for(const Geo &g, int max_h, int max_w, int max_batch, int sp
 // Check that [ptr, ptr + bytes) lies inside one device allocation, so a host
 // pointer or a short buffer is reported as an argument error instead of
 // faulting the GPU.
+static constexpr size_t kTuneCandidatesFp = 4;  // tile sides an autotuned plan times
+
 static int check_buf(const void *ptr, size_t bytes, const char *name)
 {
     if (!ptr)
@@ -1452,18 +1476,27 @@ extern "C" int lfrl_plan_footprint(const lfrl_plan_desc *desc, size_t *resident_
     int rc = validate_desc(desc);
     if (rc)
         return rc;
-    int q = 0;
-    rc = pick_q(desc, 160 * 1024, &q);
+    std::vector<int> cands;
+    rc = rank_q(desc, 160 * 1024, &cands);
     if (rc)
         return rc;
-    Geo g;
-    geo_init(g, desc->nnum, desc->nz, desc->ksize, q);
-    const Sizes s = sizes_for(g, desc->max_h, desc->max_w, desc->max_batch, pick_split(g),
-                              desc->precision == LFRL_SPLIT_FP16);
+    // an autotuned plan may take any of the timed candidates: report the largest
+    const size_t n = (desc->flags & LFRL_PLAN_AUTOTUNE)
+                         ? std::min<size_t>(cands.size(), kTuneCandidatesFp)
+                         : 1;
+    size_t res = 0, ws = 0;
+    for (size_t i = 0; i < n; ++i) {
+        Geo g;
+        geo_init(g, desc->nnum, desc->nz, desc->ksize, cands[i]);
+        const Sizes s = sizes_for(g, desc->max_h, desc->max_w, desc->max_batch, pick_split(g),
+                                  desc->precision == LFRL_SPLIT_FP16);
+        res = std::max(res, s.resident());
+        ws = std::max(ws, s.workspace());
+    }
     if (resident_bytes)
-        *resident_bytes = s.resident();
+        *resident_bytes = res;
     if (workspace_bytes)
-        *workspace_bytes = s.workspace();
+        *workspace_bytes = ws;
     return LFRL_OK;
 }
 
@@ -1550,27 +1583,15 @@ static void set_lds_attrs(size_t lds)
     (void)hipFuncSetAttribute((const void *)k_c2r, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-extern "C" int lfrl_plan(lfrl_plan_t *out, const lfrl_plan_desc *desc, const float *psf,
-                         void *stream)
+// Allocate a plan for tile side q and build its spectra from `psf`.  With
+// psf == nullptr the plan is for timing only: its spectra are zero, it has no
+// PSF copy and no frame state (lfrl_deconvolve cannot run on it).
+static int plan_build(lfrl_plan_s **out, const lfrl_plan_desc *desc, int q, const float *psf,
+                      hipStream_t st)
 {
-    if (!out)
-        return set_error(LFRL_ERR_ARG, "out is NULL");
     *out = nullptr;
-    int rc = validate_desc(desc);
-    if (rc)
-        return rc;
-    if (!psf)
-        return set_error(LFRL_ERR_ARG, "psf is NULL");
-    hipStream_t st = (hipStream_t)stream;
+    const bool timing = psf == nullptr;
     const size_t lmax = lds_limit();
-    int q = 0;
-    rc = pick_q(desc, lmax, &q);
-    if (rc)
-        return rc;
-    rc = check_buf(psf, (size_t)desc->nz * desc->nnum * desc->nnum * desc->ksize * desc->ksize *
-                            sizeof(float), "psf");
-    if (rc)
-        return rc;
     lfrl_plan_s *p = new lfrl_plan_s();
     {
         hipError_t e0 = hipGetDevice(&p->device);
@@ -1619,14 +1640,18 @@ extern "C" int lfrl_plan(lfrl_plan_t *out, const lfrl_plan_desc *desc, const flo
         p->lds_r2c_bytes = lds_r2c(g);
         p->lds_c2r_bytes = lds_c2r(g);
     }
-    TRY(dalloc(&p->Gf, s.Gf));
-    TRY(dalloc(&p->Gb, s.Gb));
+    if (!(timing && p->split)) {
+        TRY(dalloc(&p->Gf, s.Gf));
+        TRY(dalloc(&p->Gb, s.Gb));
+    }
     TRY(dalloc(&p->tw, s.tw));
     TRY(dalloc(&p->X, s.X));
     TRY(dalloc(&p->Yp, s.Yp));
     TRY(dalloc(&p->Rs, s.Rs));
-    TRY(dalloc(&p->psf, s.psf));
-    TRY(frame_alloc(p->fr, g, p->max_h, p->max_w, false));
+    if (!timing) {
+        TRY(dalloc(&p->psf, s.psf));
+        TRY(frame_alloc(p->fr, g, p->max_h, p->max_w, false));
+    }
     if (p->split) {
         TRY(dalloc(&p->Hf, s.Hf));
         TRY(dalloc(&p->Hb, s.Hb));
@@ -1644,6 +1669,23 @@ extern "C" int lfrl_plan(lfrl_plan_t *out, const lfrl_plan_desc *desc, const flo
     if (p->use_fft)
         set_fft_lds_attrs(g.Q, std::max(p->lds_r2c_bytes, p->lds_c2r_bytes));
     hipError_t e = hipMemcpyAsync(p->tw, tw.data(), g.Q * sizeof(float2), hipMemcpyHostToDevice, st);
+    if (timing) {
+        // zero spectra: the projections' cost does not depend on the values
+        if (e == hipSuccess)
+            e = p->split ? hipMemsetAsync(p->Hf, 0, s.Hf, st) : hipMemsetAsync(p->Gf, 0, s.Gf, st);
+        if (e == hipSuccess)
+            e = p->split ? hipMemsetAsync(p->Hb, 0, s.Hb, st) : hipMemsetAsync(p->Gb, 0, s.Gb, st);
+        if (e == hipSuccess && p->split)
+            e = hipMemsetAsync(p->gexp, 0, s.gexp, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            free_plan(p);
+            return set_error(LFRL_ERR_DEVICE, "plan build failed: %s", hipGetErrorString(e));
+        }
+        *out = p;
+        return LFRL_OK;
+    }
     if (e == hipSuccess)
         e = hipMemcpyAsync(p->psf, psf, s.psf, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess && g.NNp != g.NN)
@@ -1696,6 +1738,43 @@ extern "C" int lfrl_plan(lfrl_plan_t *out, const lfrl_plan_desc *desc, const flo
 
 #undef TRY
 
+static constexpr int kTuneCandidates = (int)kTuneCandidatesFp;
+static int autotune_q(const lfrl_plan_desc *desc, const std::vector<int> &cands, hipStream_t st,
+                      int *q_out, double *ms_out, int *tried);
+
+extern "C" int lfrl_plan(lfrl_plan_t *out, const lfrl_plan_desc *desc, const float *psf,
+                         void *stream)
+{
+    if (!out)
+        return set_error(LFRL_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = validate_desc(desc);
+    if (rc)
+        return rc;
+    if (!psf)
+        return set_error(LFRL_ERR_ARG, "psf is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int> cands;
+    if ((rc = rank_q(desc, lds_limit(), &cands)))
+        return rc;
+    rc = check_buf(psf, (size_t)desc->nz * desc->nnum * desc->nnum * desc->ksize * desc->ksize *
+                            sizeof(float), "psf");
+    if (rc)
+        return rc;
+    int q = cands[0], tried = 0;
+    double tune_ms = 0.0;
+    if ((desc->flags & LFRL_PLAN_AUTOTUNE) && cands.size() > 1 &&
+        (rc = autotune_q(desc, cands, st, &q, &tune_ms, &tried)))
+        return rc;
+    lfrl_plan_s *p = nullptr;
+    if ((rc = plan_build(&p, desc, q, psf, st)))
+        return rc;
+    p->tune_ms = tune_ms;
+    p->tune_candidates = tried;
+    *out = p;
+    return LFRL_OK;
+}
+
 extern "C" int lfrl_plan_destroy(lfrl_plan_t plan)
 {
     free_plan(plan);
@@ -1714,6 +1793,8 @@ extern "C" int lfrl_plan_get_info(lfrl_plan_t p, lfrl_plan_info_t *info)
     info->split_k = p->split_k;
     info->resident_bytes = p->resident;
     info->workspace_bytes = p->workspace;
+    info->tune_candidates = p->tune_candidates;
+    info->tune_ms = p->tune_ms;
     return LFRL_OK;
 }
 
@@ -1958,6 +2039,79 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
                            g.hD, mode, p->tw);
     LAUNCH_CHECK("k_c2r(backward)");
     return LFRL_OK;
+}
+
+// Measured choice of the tile side: for the best few sides by the model, a
+// timing-only plan runs one forward and one back projection of max_batch
+// largest frames (after a warm-up pair); the fastest side wins.
+static int autotune_q(const lfrl_plan_desc *desc, const std::vector<int> &cands, hipStream_t st,
+                      int *q_out, double *ms_out, int *tried)
+{
+    const int nb = std::max(1, (int)desc->max_batch);
+    const size_t hw = (size_t)desc->max_h * desc->max_w, nvox = hw * desc->nz;
+    float *vol = nullptr, *img = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = LFRL_OK;
+    double best = 1e300;
+    int bq = cands[0], n = 0;
+    if ((rc = dalloc(&vol, nvox * sizeof(float))) || (rc = dalloc(&img, hw * sizeof(float))))
+        goto done;
+    if (hipMemsetAsync(vol, 0, nvox * sizeof(float), st) != hipSuccess ||
+        hipMemsetAsync(img, 0, hw * sizeof(float), st) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        rc = set_error(LFRL_ERR_DEVICE, "autotune set-up failed");
+        goto done;
+    }
+    for (size_t i = 0; i < cands.size() && i < (size_t)kTuneCandidates; ++i) {
+        lfrl_plan_s *tp = nullptr;
+        rc = plan_build(&tp, desc, cands[i], nullptr, st);
+        if (rc == LFRL_ERR_NOMEM) {  // this side does not fit: try the next
+            rc = LFRL_OK;
+            continue;
+        }
+        if (rc)
+            goto done;
+        FrameIO fw[kMaxBatchJobs], bw[kMaxBatchJobs];
+        for (int b = 0; b < nb; ++b) {
+            fw[b] = FrameIO{desc->max_h, desc->max_w, vol, img, nullptr, nullptr};
+            bw[b] = FrameIO{desc->max_h, desc->max_w, img, vol, nullptr, nullptr};
+        }
+        float ms = 0.f;
+        for (int rep = 0; rep < 3 && rc == LFRL_OK; ++rep) {
+            if (rep == 1 && hipEventRecord(e0, st) != hipSuccess)
+                rc = set_error(LFRL_ERR_DEVICE, "hipEventRecord failed");
+            if (!rc)
+                rc = run_forward(tp, fw, nb, EPI_STORE, st);
+            if (!rc)
+                rc = run_backward(tp, bw, nb, EPI_STORE, st);
+        }
+        if (!rc && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = set_error(LFRL_ERR_DEVICE, "autotune timing failed");
+        free_plan(tp);
+        if (rc)
+            goto done;
+        ++n;
+        if (ms / 2.0 < best) {
+            best = ms / 2.0;
+            bq = cands[i];
+        }
+    }
+    if (n == 0)
+        rc = set_error(LFRL_ERR_NOMEM, "no tile size fits in device memory");
+done:
+    if (vol)
+        (void)hipFree(vol);
+    if (img)
+        (void)hipFree(img);
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    *q_out = bq;
+    *ms_out = n ? best : 0.0;
+    *tried = n;
+    return rc;
 }
 
 static int launch_fill(float *ptr, size_t n, float v, hipStream_t st)

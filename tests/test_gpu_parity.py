@@ -263,3 +263,31 @@ def test_argument_errors(lf):
         plan.close()
     with pytest.raises(lf.LfrlError):
         lf.Plan(to_dev(random_psf(2, 3, 4, seed=1)), 12, 12)  # even support
+
+
+def test_autotuned_plan(lf):
+    """The tuner times a few tile sides and keeps one; the plan then behaves
+    exactly like a plan built with that side."""
+    import torch
+    n, ly, nz, k = 5, 14, 4, 25
+    psf = S.gaussian_psf(n, nz, k, seed=91, shift_scale=None)
+    h = w = n * ly
+    rng = np.random.default_rng(92)
+    x = rng.uniform(0.0, 1.0, size=(nz, h, w)).astype(np.float32)
+    y = rng.uniform(0.0, 1.0, size=(h, w)).astype(np.float32)
+    tuned = lf.Plan(to_dev(psf), h, w, autotune=True, max_batch=2)
+    try:
+        info = tuned.info
+        print(f"autotune: Q={info['tile_q']} over {info['tune_candidates']} sides, "
+              f"{info['tune_ms']:.3f} ms", flush=True)
+        assert info["tune_candidates"] >= 2 and info["tune_ms"] > 0
+        fixed = lf.Plan(to_dev(psf), h, w, tile_q=info["tile_q"], max_batch=2)
+        try:
+            assert fixed.info["tune_candidates"] == 0
+            assert torch.equal(tuned.forward(to_dev(x)), fixed.forward(to_dev(x)))
+            assert torch.equal(tuned.backward(to_dev(y)), fixed.backward(to_dev(y)))
+        finally:
+            fixed.close()
+        assert rel_l2(tuned.forward(to_dev(x)).cpu().numpy(), oracle.forward(psf, x)) <= TOL
+    finally:
+        tuned.close()
