@@ -50,9 +50,13 @@ def contraction_flops(info: dict, g, nt: int) -> float:
 
 
 def source_digest() -> str:
-    path = os.path.join(ROOT, "paper_2208_11422_amd", "csrc", "lfrl.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """sha256 over the kernel sources (every file under the package's csrc)."""
+    d = os.path.join(ROOT, "paper_2208_11422_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel: str, bytes_alg: float):

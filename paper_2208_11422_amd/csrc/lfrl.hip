@@ -80,7 +80,7 @@ static constexpr float kWeakThreshold = 1e-2f;  // weak voxel: A^T 1 < this * ma
 // geometry
 // ---------------------------------------------------------------------------
 struct Geo {
-    int N, Nz, K, c0, hD, R, Q, QH, T, nf, NN, NNp, KK, KKs;
+    int N, Nz, K, c0, hD, R, Q, QH, T, nf, NN, NNp, KK, KKs, NCp, KKb;
 };
 
 static void geo_init(Geo &g, int N, int Nz, int K, int Q)
@@ -99,6 +99,8 @@ static void geo_init(Geo &g, int N, int Nz, int K, int Q)
     g.NNp = (g.NN + 15) / 16 * 16;  // forward spectra row stride (aligned 16-column blocks)
     g.KK = g.NN * Nz;
     g.KKs = (g.KK + 31) / 32 * 32;  // row stride of the volume tile spectra
+    g.NCp = (g.NN + 7) / 8 * 8;     // adjoint reduction length in fragment pairs
+    g.KKb = (g.KK + 15) / 16 * 16;  // adjoint output columns in 16-column blocks
 }
 
 struct Tiles {
@@ -433,88 +435,204 @@ __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c)
 
 #include "contract_f16.hpp"
 
+// Spectra in fragment order.  One load instruction of a wave then reads one
+// contiguous kilobyte: each lane takes 16 bytes, the two complex values it
+// feeds to two consecutive MFMA steps.  (Row-major spectra with 8-byte loads
+// touch four separate 128-byte pieces per instruction and stream at about
+// 70% of the rate of contiguous 16-byte loads.)
+//   forward  Ff[k][p][cb][lane] = {G(8p+2q, 16cb+col), G(8p+2q+1, 16cb+col)},
+//            G(kk, c) = Gf[k][kk][c], p < KKs/8, cb < NNp/16;
+//   adjoint  fragment (p, kb) of frequency k = {H(8p+2q, 16kb+col), H(8p+2q+1, 16kb+col)},
+//            H(c, kk) = Gb[k][c][kk], p < NCp/8, kb < KKb/16, stored range-major
+//            (adj_frag);
+// with q = lane / 16, col = lane % 16 and zeros outside the valid ranges.
+// The reduction index kk (forward) or c (adjoint) of MFMA step 2u + h is
+// 8u + 2q + h for lane group q: the sums are the same, taken in this order.
+__global__ void k_pack_fwd_f32(const float2 *__restrict__ Gf, int KK, int NNp, int KKs,
+                               float4 *__restrict__ Ff, size_t total)
+{
+    const int ncb = NNp / 16, np = KKs / 8;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int lane = (int)(i % 64);
+        const size_t r = i / 64;
+        const int cb = (int)(r % ncb);
+        const size_t r2 = r / ncb;
+        const int p = (int)(r2 % np);
+        const size_t k = r2 / np;
+        const int kk = 8 * p + 2 * (lane >> 4), c = 16 * cb + (lane & 15);
+        const float2 *gk = Gf + k * (size_t)KK * NNp;
+        const float2 a = kk < KK ? gk[(size_t)kk * NNp + c] : make_float2(0.f, 0.f);
+        const float2 b = kk + 1 < KK ? gk[(size_t)(kk + 1) * NNp + c] : make_float2(0.f, 0.f);
+        Ff[i] = make_float4(a.x, a.y, b.x, b.y);
+    }
+}
+
+// Adjoint fragments, range-major so that the fragments one block of the
+// adjoint contraction reads (RB column blocks of every pair) are contiguous:
+// range rb = kb / RB starts at fragment rb * RB * np; inside it fragment
+// (p, j = kb % RB) sits at p * w + j, w = min(RB, nkb - rb * RB).
+__device__ __forceinline__ size_t adj_frag(int p, int kb, int np, int nkb, int RB)
+{
+    const int rb = kb / RB, j = kb - rb * RB;
+    const int w = min(RB, nkb - rb * RB);
+    return (size_t)rb * RB * np + (size_t)p * w + j;
+}
+
+__global__ void k_pack_adj_f32(const float2 *__restrict__ Gb, int NN, int KK, int NCp, int KKb,
+                               int RB, float4 *__restrict__ Fb, size_t total)
+{
+    const int nkb = KKb / 16, np = NCp / 8;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int lane = (int)(i % 64);
+        const size_t r = i / 64;
+        const int kb = (int)(r % nkb);
+        const size_t r2 = r / nkb;
+        const int p = (int)(r2 % np);
+        const size_t k = r2 / np;
+        const int c = 8 * p + 2 * (lane >> 4), kk = 16 * kb + (lane & 15);
+        const float2 *gk = Gb + k * (size_t)NN * KK;
+        const bool okk = kk < KK;
+        const float2 a = okk && c < NN ? gk[(size_t)c * KK + kk] : make_float2(0.f, 0.f);
+        const float2 b = okk && c + 1 < NN ? gk[(size_t)(c + 1) * KK + kk] : make_float2(0.f, 0.f);
+        Fb[(k * np * nkb + adj_frag(p, kb, np, nkb, RB)) * 64 + lane] = make_float4(a.x, a.y, b.x, b.y);
+    }
+}
+
+__device__ __forceinline__ float mask_f(float v, bool keep)
+{
+    return __uint_as_float(__float_as_uint(v) & (keep ? 0xffffffffu : 0u));
+}
+
 // Forward contraction for one frequency k and one reduction chunk s, computed
 // transposed so that tiles are the MFMA rows:
 //   Yp[s][k][t][c] = sum_{kk in chunk} X[k][t][kk] * Gf[k][kk][c]
-// A = X (16 tiles x 4 kk, loaded straight from HBM), B = Gf (4 kk x 16 c per
-// block of c, CB blocks per wave).  Gf rows are padded to NNp (a multiple of
-// 16, zero filled) so each 16-column block is one aligned 128-byte line that
-// no other wave touches.  Register groups of U steps are double-buffered: the
-// loads of group g+1 are in flight while group g runs on the matrix cores.
-// Every load is unconditional (clamped index; kk past the chunk end is zeroed
-// in X by a multiply); outputs for t >= nt or c >= NN are simply not stored.
+// A = X: every wave needs the same 16 x 8U fragment per register group, so
+// the block loads it once, coalesced (16-byte loads along the tile rows), and
+// keeps it in LDS in fragment order (double-buffered, one barrier per group).
+// The block must have at least 64 * U threads (U waves): one value each.
+// B = Ff fragments, CB blocks of 16 columns per wave, loaded straight into
+// registers and double-buffered.  X past KK (padding that may hold stale
+// data) is cleared by a bit mask when it is written to LDS.  Outputs for
+// t >= nt or c >= NN are not stored.
 template <int CB, int U>
-__global__ __launch_bounds__(512) void k_contract_fwd(const float2 *__restrict__ Gf,
+__global__ __launch_bounds__(512) void k_contract_fwd(const float4 *__restrict__ Ff,
                                                       const float2 *__restrict__ X,
                                                       float2 *__restrict__ Yp, int NN, int NNp,
                                                       int KK, int KKs, int nt, int nf, int kchunk)
 {
+    __shared__ float4 la[2][U][64];
     const int k = blockIdx.x, s = blockIdx.y, t0 = blockIdx.z * 16;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = lane & 15, kq = lane >> 4;
-    const int kb0 = s * kchunk;
-    const int kb1 = min(KK, kb0 + kchunk);
-    const int nsteps = (kb1 - kb0 + 3) / 4;
-    const int ngroups = (nsteps + U - 1) / U;
-    const int t = t0 + col;
-    const float2 *xrow = X + ((size_t)k * nt + min(t, nt - 1)) * KKs;
-    const float2 *gk = Gf + (size_t)k * KK * NNp;
-    int cidx[CB];
+    const int ncb = NNp / 16;
+    const int p0 = s * (kchunk / 8);
+    const int p1 = min((KK + 7) / 8, p0 + kchunk / 8);
+    const int npairs = p1 - p0;
+    const int ngroups = (npairs + U - 1) / U;
+    if (npairs <= 0)
+        return;
+    // staging: thread i handles float4 j = i' % 4U (kk pair 2j) of tile row
+    // i' / 4U, i' = i % 64U; threads with equal i' load and store the same
+    // value to the same slot (an unconditional store keeps the compiler from
+    // sinking the prefetch load into a branch next to its use)
+    const int si = tid % (64 * U);
+    const int st_t = si / (4 * U), st_j = si % (4 * U);
+    const float4 *st_row =
+        reinterpret_cast<const float4 *>(X + ((size_t)k * nt + min(t0 + st_t, nt - 1)) * KKs);
+    const float4 *fk = Ff + (size_t)k * (KKs / 8) * ncb * 64;
+    int cbi[CB];
 #pragma unroll
     for (int b = 0; b < CB; ++b)
-        cidx[b] = min(16 * (wave * CB + b) + col, NNp - 1);
+        cbi[b] = min(wave * CB + b, ncb - 1);
     f32x4 accr[CB], acci[CB];
 #pragma unroll
     for (int b = 0; b < CB; ++b) {
         accr[b] = f32x4{0.f, 0.f, 0.f, 0.f};
         acci[b] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    float2 xa0[U], xa1[U], gb0[U][CB], gb1[U][CB];
-    auto load_group = [&](int grp, float2(&xa)[U], float2(&gb)[U][CB]) {
+    auto a_load = [&](int grp) -> float4 {
+        const int pg = min(p0 + grp * U + st_j / 4, p1 - 1);
+        return st_row[4 * pg + st_j % 4];
+    };
+    auto a_store = [&](int grp, int buf, const float4 &v) {
+        const int pg = p0 + grp * U + st_j / 4;
+        const int kk = 8 * pg + 2 * (st_j % 4);
+        const bool ok0 = pg < p1 && kk < KK, ok1 = pg < p1 && kk + 1 < KK;
+        la[buf][st_j / 4][16 * (st_j % 4) + st_t] =
+            make_float4(mask_f(v.x, ok0), mask_f(v.y, ok0), mask_f(v.z, ok1), mask_f(v.w, ok1));
+    };
+    auto b_load = [&](int grp, float4(&gb)[U][CB]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int kk = kb0 + 4 * (grp * U + u) + kq;
-            const float m = kk < kb1 ? 1.f : 0.f;
-            const int kkc = min(kk, kb1 - 1);
-            const float2 xv = xrow[kkc];
-            xa[u] = make_float2(xv.x * m, xv.y * m);
+            const int p = min(p0 + grp * U + u, p1 - 1);
 #pragma unroll
             for (int b = 0; b < CB; ++b)
-                gb[u][b] = gk[(size_t)kkc * NNp + cidx[b]];
+                gb[u][b] = fk[((size_t)p * ncb + cbi[b]) * 64 + lane];
         }
     };
-    auto compute_group = [&](const float2(&xa)[U], const float2(&gb)[U][CB]) {
+    auto compute_group = [&](int buf, const float4(&gb)[U][CB]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const float2 a = xa[u];
+            const float4 a = la[buf][u][lane];
+            // product-major order: consecutive MFMAs update different
+            // accumulators (2 * CB independent chains)
 #pragma unroll
             for (int b = 0; b < CB; ++b) {
-                const float2 g = gb[u][b];
-                accr[b] = mfma4(a.x, g.x, accr[b]);
-                accr[b] = mfma4(-a.y, g.y, accr[b]);
-                acci[b] = mfma4(a.x, g.y, acci[b]);
-                acci[b] = mfma4(a.y, g.x, acci[b]);
+                accr[b] = mfma4(a.x, gb[u][b].x, accr[b]);
+                acci[b] = mfma4(a.x, gb[u][b].y, acci[b]);
+            }
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                accr[b] = mfma4(-a.y, gb[u][b].y, accr[b]);
+                acci[b] = mfma4(a.y, gb[u][b].x, acci[b]);
+            }
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                accr[b] = mfma4(a.z, gb[u][b].z, accr[b]);
+                acci[b] = mfma4(a.z, gb[u][b].w, acci[b]);
+            }
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                accr[b] = mfma4(-a.w, gb[u][b].w, accr[b]);
+                acci[b] = mfma4(a.w, gb[u][b].z, acci[b]);
             }
         }
     };
-    if (ngroups > 0)
-        load_group(0, xa0, gb0);
+    // Straight-line loop body: every group's loads are issued (clamped, so a
+    // surplus group re-reads valid data) and every group is computed (surplus
+    // pairs meet zeros in LDS).  A conditional prefetch would join paths with
+    // different numbers of loads in flight, and the waits at the join would
+    // then cover the prefetch too.  The scheduling barriers keep each
+    // prefetch ahead of the products it is meant to overlap.
+    float4 gb0[U][CB], gb1[U][CB];
+    float4 av = a_load(0);
+    b_load(0, gb0);
+    a_store(0, 0, av);
+    __syncthreads();
     for (int grp = 0; grp < ngroups; grp += 2) {
-        if (grp + 1 < ngroups)
-            load_group(grp + 1, xa1, gb1);
-        compute_group(xa0, gb0);
-        if (grp + 1 < ngroups) {
-            if (grp + 2 < ngroups)
-                load_group(grp + 2, xa0, gb0);
-            compute_group(xa1, gb1);
-        }
+        av = a_load(grp + 1);
+        b_load(grp + 1, gb1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute_group(0, gb0);
+        __builtin_amdgcn_sched_barrier(0);
+        a_store(grp + 1, 1, av);
+        __syncthreads();
+        av = a_load(grp + 2);
+        b_load(grp + 2, gb0);
+        __builtin_amdgcn_sched_barrier(0);
+        compute_group(1, gb1);
+        __builtin_amdgcn_sched_barrier(0);
+        a_store(grp + 2, 0, av);
+        __syncthreads();
     }
     // D[t][c]: lane holds tiles t0 + 4 * kq + i, column c of each block
     float2 *yk = Yp + ((size_t)s * nf + k) * nt * NN;
 #pragma unroll
     for (int b = 0; b < CB; ++b) {
         const int c = 16 * (wave * CB + b) + col;
-        if (c >= NN)
+        if (c >= NN || wave * CB + b >= ncb)
             continue;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -525,97 +643,135 @@ __global__ __launch_bounds__(512) void k_contract_fwd(const float2 *__restrict__
     }
 }
 
-// Adjoint contraction for one frequency k and a range of kk, computed
+// Row stride (float2) of the staged image spectra rs[c][t] of the adjoint:
+// 16 tiles plus one pad, so the coalesced staging writes spread over banks.
+static constexpr int kRsStride = 17;
+
+// Adjoint contraction for one frequency k and `ranges` ranges of kk, computed
 // transposed so that tiles are the MFMA rows:
 //   B[k][t][kk] = sum_c R[k][t][c] * conj(Gb[k][c][kk])
-// A = R (16 tiles x 4 c, staged once per block in LDS as rs[c][t]),
-// B = conj(Gb) (4 c x 16 kk per block of kk, CB blocks per wave), with the same
-// double-buffered (groups of U steps), unconditional loads as the forward
-// contraction.
+// A = R (16 tiles x NCp), staged once per block in LDS as rs[c][t] with
+// coalesced loads along c and reused for every range; B = conj(H) from the Fb
+// fragments (CB blocks of 16 kk per wave), with the same double-buffered,
+// straight-line groups of U fragment pairs as the forward contraction.
 template <int CB, int U>
-__global__ __launch_bounds__(256) void k_contract_adj(const float2 *__restrict__ Gb,
+__global__ __launch_bounds__(256) void k_contract_adj(const float4 *__restrict__ Fb,
                                                       const float2 *__restrict__ Rs,
                                                       float2 *__restrict__ B, int NN, int KK,
-                                                      int nt)
+                                                      int NCp, int nt, int ranges)
 {
-    extern __shared__ float2 rs[];  // [NN rounded up to 4 * U][16], zero padded
+    extern __shared__ float2 rs[];  // [even number of groups of 8 * U rows][kRsStride]
     const int k = blockIdx.x, t0 = blockIdx.z * 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const int col = lane & 15, kq = lane >> 4;
-    const int NCp = (NN + 4 * U - 1) / (4 * U) * (4 * U);
-    for (int idx = threadIdx.x; idx < NCp * 16; idx += blockDim.x) {
-        const int c = idx / 16, tt = idx % 16;
-        float2 v = make_float2(0.f, 0.f);
-        if (c < NN && t0 + tt < nt)
-            v = Rs[((size_t)k * nt + t0 + tt) * NN + c];
-        rs[idx] = v;
+    const int nkb = (KK + 15) / 16;
+    const int npairs = NCp / 8;
+    const int ngroups = ((npairs + U - 1) / U + 1) / 2 * 2;  // even: see the loop
+    const int ncl = ngroups * U * 8;
+    // coalesced staging along c, in batches of loads issued before their
+    // stores (clamped addresses; out-of-range values cleared by a bit mask)
+    const int total = ncl * 16;
+    for (int base = threadIdx.x; base < total; base += 8 * blockDim.x) {
+        float2 v[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int idx = min(base + b * (int)blockDim.x, total - 1);
+            const int tt = idx / ncl, c = idx % ncl;
+            const bool ok = c < NN && t0 + tt < nt;
+            const float2 x = Rs[((size_t)k * nt + min(t0 + tt, nt - 1)) * NN + min(c, NN - 1)];
+            v[b] = make_float2(mask_f(x.x, ok), mask_f(x.y, ok));
+        }
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int idx = base + b * (int)blockDim.x;
+            if (idx < total)
+                rs[(idx % ncl) * kRsStride + idx / ncl] = v[b];
+        }
     }
     __syncthreads();
-    const float2 *gk = Gb + (size_t)k * NN * KK;
-    int kidx[CB];
-    bool k_ok[CB];
-#pragma unroll
-    for (int b = 0; b < CB; ++b) {
-        const int kk = 16 * ((blockIdx.y * nwaves + wave) * CB + b) + col;
-        k_ok[b] = kk < KK;
-        kidx[b] = k_ok[b] ? kk : KK - 1;
-    }
-    f32x4 accr[CB], acci[CB];
-#pragma unroll
-    for (int b = 0; b < CB; ++b) {
-        accr[b] = f32x4{0.f, 0.f, 0.f, 0.f};
-        acci[b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
-    const int ngroups = NCp / (4 * U);
-    float2 gb0[U][CB], gb1[U][CB];
-    // rows c >= NN read a valid row (clamped) that meets a zero in rs; columns
-    // kk >= KK only feed outputs that are not stored
-    auto load_group = [&](int grp, float2(&gb)[U][CB]) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int cc = min(4 * (grp * U + u) + kq, NN - 1);
-#pragma unroll
-            for (int b = 0; b < CB; ++b)
-                gb[u][b] = gk[(size_t)cc * KK + kidx[b]];
-        }
-    };
-    auto compute_group = [&](int grp, const float2(&gb)[U][CB]) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const float2 am = rs[(4 * (grp * U + u) + kq) * 16 + col];
-#pragma unroll
-            for (int b = 0; b < CB; ++b) {
-                const float2 g = gb[u][b];
-                accr[b] = mfma4(am.x, g.x, accr[b]);
-                accr[b] = mfma4(am.y, g.y, accr[b]);
-                acci[b] = mfma4(am.y, g.x, acci[b]);
-                acci[b] = mfma4(-am.x, g.y, acci[b]);
-            }
-        }
-    };
-    if (ngroups > 0)
-        load_group(0, gb0);
-    for (int grp = 0; grp < ngroups; grp += 2) {
-        if (grp + 1 < ngroups)
-            load_group(grp + 1, gb1);
-        compute_group(grp, gb0);
-        if (grp + 1 < ngroups) {
-            if (grp + 2 < ngroups)
-                load_group(grp + 2, gb0);
-            compute_group(grp + 1, gb1);
-        }
-    }
-    // D[t][kk]: lane holds tiles t0 + 4 * kq + i, column kk of each block
+    const float4 *fk = Fb + (size_t)k * npairs * nkb * 64;
     float2 *bk = B + (size_t)k * nt * KK;
+    const int RB = nwaves * CB;  // column blocks per range (the packing's RB)
+    for (int r = 0; r < ranges; ++r) {
+        const int kb0 = ((blockIdx.y * ranges + r) * nwaves + wave) * CB;
+        if (kb0 >= nkb)
+            break;
+        int kbi[CB];
+        bool k_ok[CB];
 #pragma unroll
-    for (int b = 0; b < CB; ++b) {
-        if (!k_ok[b])
-            continue;
+        for (int b = 0; b < CB; ++b) {
+            k_ok[b] = kb0 + b < nkb;
+            kbi[b] = k_ok[b] ? kb0 + b : nkb - 1;
+        }
+        f32x4 accr[CB], acci[CB];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int tt = t0 + 4 * kq + i;
-            if (tt < nt)
-                bk[(size_t)tt * KK + kidx[b]] = make_float2(accr[b][i], acci[b][i]);
+        for (int b = 0; b < CB; ++b) {
+            accr[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+            acci[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+        float4 gb0[U][CB], gb1[U][CB];
+        // pairs past the last read a valid fragment (clamped) that meets zeros in rs
+        auto load_group = [&](int grp, float4(&gb)[U][CB]) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int p = min(grp * U + u, npairs - 1);
+#pragma unroll
+                for (int b = 0; b < CB; ++b)
+                    gb[u][b] = fk[adj_frag(p, kbi[b], npairs, nkb, RB) * 64 + lane];
+            }
+        };
+        auto compute_group = [&](int grp, const float4(&gb)[U][CB]) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = 8 * (grp * U + u) + 2 * kq;
+                const float2 a0 = rs[c * kRsStride + col], a1 = rs[(c + 1) * kRsStride + col];
+                // product-major order: consecutive MFMAs update different
+                // accumulators (2 * CB independent chains)
+#pragma unroll
+                for (int b = 0; b < CB; ++b) {
+                    accr[b] = mfma4(a0.x, gb[u][b].x, accr[b]);
+                    acci[b] = mfma4(a0.y, gb[u][b].x, acci[b]);
+                }
+#pragma unroll
+                for (int b = 0; b < CB; ++b) {
+                    accr[b] = mfma4(a0.y, gb[u][b].y, accr[b]);
+                    acci[b] = mfma4(-a0.x, gb[u][b].y, acci[b]);
+                }
+#pragma unroll
+                for (int b = 0; b < CB; ++b) {
+                    accr[b] = mfma4(a1.x, gb[u][b].z, accr[b]);
+                    acci[b] = mfma4(a1.y, gb[u][b].z, acci[b]);
+                }
+#pragma unroll
+                for (int b = 0; b < CB; ++b) {
+                    accr[b] = mfma4(a1.y, gb[u][b].w, accr[b]);
+                    acci[b] = mfma4(-a1.x, gb[u][b].w, acci[b]);
+                }
+            }
+        };
+        load_group(0, gb0);
+        for (int grp = 0; grp < ngroups; grp += 2) {
+            load_group(grp + 1, gb1);
+            __builtin_amdgcn_sched_barrier(0);
+            compute_group(grp, gb0);
+            __builtin_amdgcn_sched_barrier(0);
+            load_group(grp + 2, gb0);
+            __builtin_amdgcn_sched_barrier(0);
+            compute_group(grp + 1, gb1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // D[t][kk]: lane holds tiles t0 + 4 * kq + i, column kk of each block
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            const int kk = 16 * kbi[b] + col;
+            if (!k_ok[b] || kk >= KK)
+                continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int tt = t0 + 4 * kq + i;
+                if (tt < nt)
+                    bk[(size_t)tt * KK + kk] = make_float2(accr[b][i], acci[b][i]);
+            }
         }
     }
 }
@@ -1171,7 +1327,8 @@ struct lfrl_plan_s {
     int max_tiles = 0;    // tiles one batched launch covers
     int split_k = 1;
     size_t resident = 0, workspace = 0;
-    float2 *Gf = nullptr, *Gb = nullptr, *tw = nullptr;
+    float2 *Gf = nullptr, *Gb = nullptr, *tw = nullptr;  // natural spectra (plan build only)
+    float4 *Ff = nullptr, *Fb = nullptr;                 // FP32 spectra in fragment order
     float2 *X = nullptr, *Yp = nullptr, *Rs = nullptr;
     float *psf = nullptr;  // resident copy of the PSF set (weak-voxel sums)
     Frame fr;              // frame state of lfrl_deconvolve (sized for max_h x max_w)
@@ -1318,30 +1475,37 @@ static int pick_split(const Geo &g)
 // NNp / 16 column blocks over at most 8 waves; the adjoint uses 4 waves.
 static constexpr int kAdjWaves = 4;
 
-static bool fwd_cb_ok(int cb) { return cb == 1 || cb == 2 || cb == 3 || cb == 4 || cb == 5 || cb == 8; }
-static bool adj_cb_ok(int cb) { return cb == 1 || cb == 2 || cb == 4 || cb == 8; }
-static bool u_ok(int u) { return u == 2 || u == 4 || u == 8; }
+// (U counts fragment pairs: two MFMA steps each)
+static bool fwd_cb_ok(int cb) { return cb >= 2 && cb <= 5; }
+static bool adj_cb_ok(int cb) { return cb == 2 || cb == 4; }
+static bool u_ok(int u) { return u == 1 || u == 2 || u == 4; }
 
 static void default_shapes(const Geo &g, int *fcb, int *fu, int *acb, int *au)
 {
+    // measured at Nnum 15 (15 column blocks): 4 blocks per wave, 4 waves
     const int ncb = g.NNp / 16;
-    int cb = std::min(5, (ncb + 4) / 5);
-    while (!fwd_cb_ok(cb) || (ncb + cb - 1) / cb > 8)
+    int cb = std::max(2, std::min(5, (ncb + 3) / 4));
+    while (cb < 5 && (ncb + cb - 1) / cb > 8)
         ++cb;
     *fcb = cb;
-    *fu = 4;
+    *fu = 1;
     *acb = 4;
-    *au = 4;
+    *au = 1;
     // tuning override: LFRL_CONTRACT_SHAPE="fwd_cb,fwd_u,adj_cb,adj_u"
     const char *env = getenv("LFRL_CONTRACT_SHAPE");
     int a = 0, b = 0, c = 0, d = 0;
     if (env && sscanf(env, "%d,%d,%d,%d", &a, &b, &c, &d) == 4 && fwd_cb_ok(a) &&
-        (ncb + a - 1) / a <= 8 && u_ok(b) && !(a == 8 && b == 8) && adj_cb_ok(c) && u_ok(d)) {
+        (ncb + a - 1) / a <= 8 && u_ok(b) && !(a >= 4 && b == 4) && adj_cb_ok(c) && u_ok(d)) {
         *fcb = a;
         *fu = b;
         *acb = c;
         *au = d;
     }
+    // the forward stages its 64 * U A values per group with one per thread:
+    // a block (one wave per CB column blocks) needs at least U waves
+    const int fwaves = (ncb + *fcb - 1) / *fcb;
+    while (*fu > fwaves)
+        *fu /= 2;
 }
 
 static unsigned weak_cap_for(size_t nvox)
@@ -1418,10 +1582,11 @@ static void frame_bind(Frame &f, const Geo &g, int h, int w, void *block, const 
 }
 
 struct Sizes {
-    size_t Gf, Gb, tw, psf, X, Yp, Rs, frame;
+    size_t Gf, Gb, tw, psf, X, Yp, Rs, frame;  // Gf, Gb: natural layouts, plan build only
+    size_t Ff = 0, Fb = 0;                      // FP32 fragment-ordered spectra
     size_t Hf = 0, Hb = 0, gexp = 0, rowmax = 0;  // split FP16 only
     bool split = false;
-    size_t resident() const { return (split ? Hf + Hb + gexp : Gf + Gb) + tw + psf; }
+    size_t resident() const { return (split ? Hf + Hb + gexp : Ff + Fb) + tw + psf; }
     size_t workspace() const { return X + Yp + Rs + 2 * rowmax + frame; }
 };
 
@@ -1431,6 +1596,8 @@ static Sizes sizes_for(const Geo &g, int max_h, int max_w, int max_batch, int sp
     Sizes s;
     s.Gf = (size_t)g.nf * g.NNp * g.KK * sizeof(float2);
     s.Gb = (size_t)g.nf * g.NN * g.KK * sizeof(float2);
+    s.Ff = (size_t)g.nf * g.KKs * g.NNp * sizeof(float2);
+    s.Fb = (size_t)g.nf * g.NCp * g.KKb * sizeof(float2);
     s.tw = (size_t)g.Q * sizeof(float2);
     s.X = (size_t)g.nf * nt * g.KKs * sizeof(float2);
     s.Yp = (size_t)split * g.nf * nt * g.NN * sizeof(float2);
@@ -1521,7 +1688,7 @@ static void free_plan(lfrl_plan_s *p)
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
-    void *bufs[] = {p->Gf, p->Gb, p->tw, p->X, p->Yp, p->Rs, p->psf,
+    void *bufs[] = {p->Gf, p->Gb, p->Ff, p->Fb, p->tw, p->X, p->Yp, p->Rs, p->psf,
                     p->Hf, p->Hb, p->gexp, p->xmax, p->rmax};
     for (void *b : bufs)
         if (b)
@@ -1640,9 +1807,13 @@ static int plan_build(lfrl_plan_s **out, const lfrl_plan_desc *desc, int q, cons
         p->lds_r2c_bytes = lds_r2c(g);
         p->lds_c2r_bytes = lds_c2r(g);
     }
-    if (!(timing && p->split)) {
+    if (!timing) {
         TRY(dalloc(&p->Gf, s.Gf));
         TRY(dalloc(&p->Gb, s.Gb));
+    }
+    if (!p->split) {
+        TRY(dalloc(&p->Ff, s.Ff));
+        TRY(dalloc(&p->Fb, s.Fb));
     }
     TRY(dalloc(&p->tw, s.tw));
     TRY(dalloc(&p->X, s.X));
@@ -1672,9 +1843,9 @@ static int plan_build(lfrl_plan_s **out, const lfrl_plan_desc *desc, int q, cons
     if (timing) {
         // zero spectra: the projections' cost does not depend on the values
         if (e == hipSuccess)
-            e = p->split ? hipMemsetAsync(p->Hf, 0, s.Hf, st) : hipMemsetAsync(p->Gf, 0, s.Gf, st);
+            e = p->split ? hipMemsetAsync(p->Hf, 0, s.Hf, st) : hipMemsetAsync(p->Ff, 0, s.Ff, st);
         if (e == hipSuccess)
-            e = p->split ? hipMemsetAsync(p->Hb, 0, s.Hb, st) : hipMemsetAsync(p->Gb, 0, s.Gb, st);
+            e = p->split ? hipMemsetAsync(p->Hb, 0, s.Hb, st) : hipMemsetAsync(p->Fb, 0, s.Fb, st);
         if (e == hipSuccess && p->split)
             e = hipMemsetAsync(p->gexp, 0, s.gexp, st);
         if (e == hipSuccess)
@@ -1707,8 +1878,7 @@ static int plan_build(lfrl_plan_s **out, const lfrl_plan_desc *desc, int q, cons
         e = hipGetLastError();
     }
     if (e == hipSuccess && p->split) {
-        // FP16 fragments with per-frequency power-of-two scales, then drop the
-        // FP32 spectra
+        // FP16 fragments with per-frequency power-of-two scales
         hipLaunchKernelGGL(k_spec_exp, dim3(g.nf), dim3(256), 0, st, (const float2 *)p->Gf,
                            (size_t)g.KK * g.NNp, p->gexp);
         const size_t nhf = s.Hf / sizeof(half2c), nhb = s.Hb / sizeof(half2c);
@@ -1718,13 +1888,22 @@ static int plan_build(lfrl_plan_s **out, const lfrl_plan_desc *desc, int q, cons
                            g.NN, g.KK, g.NNp / 16, (g.KK + 15) / 16, (const int *)p->gexp, p->Hb,
                            nhb);
         e = hipGetLastError();
-        if (e == hipSuccess)
-            e = hipStreamSynchronize(st);
-        if (e == hipSuccess) {
-            (void)hipFree(p->Gf);
-            (void)hipFree(p->Gb);
-            p->Gf = p->Gb = nullptr;
-        }
+    } else if (e == hipSuccess) {
+        // FP32 fragments
+        hipLaunchKernelGGL(k_pack_fwd_f32, dim3(8192), dim3(256), 0, st, (const float2 *)p->Gf,
+                           g.KK, g.NNp, g.KKs, p->Ff, s.Ff / sizeof(float4));
+        hipLaunchKernelGGL(k_pack_adj_f32, dim3(8192), dim3(256), 0, st, (const float2 *)p->Gb,
+                           g.NN, g.KK, g.NCp, g.KKb, p->adj_cb * kAdjWaves, p->Fb,
+                           s.Fb / sizeof(float4));
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e == hipSuccess) {
+        // the natural-layout spectra were only the packers' input
+        (void)hipFree(p->Gf);
+        (void)hipFree(p->Gb);
+        p->Gf = p->Gb = nullptr;
     }
     if (e == hipSuccess)
         e = hipStreamSynchronize(st);  // the tw staging vector goes out of scope
@@ -1842,18 +2021,20 @@ static int prof_event(lfrl_plan_s *p, int which, hipStream_t st)
 
 #define LFRL_FWD_CASE(CBV, UV)                                                                   \
     if (p->fwd_cb == CBV && p->fwd_u == UV) {                                                    \
-        hipLaunchKernelGGL((k_contract_fwd<CBV, UV>), grid, block, 0, st, p->Gf, p->X, p->Yp,    \
-                           g.NN, g.NNp, g.KK, g.KKs, nt, g.nf, kchunk);                          \
+        hipLaunchKernelGGL((k_contract_fwd<CBV, UV>), grid, block, 0, st, (const float4 *)p->Ff, \
+                           (const float2 *)p->X, p->Yp, g.NN, g.NNp, g.KK, g.KKs, nt, g.nf,     \
+                           kchunk);                                                              \
         launched = true;                                                                         \
     }
-#define LFRL_FWD_CASES(CBV) LFRL_FWD_CASE(CBV, 2) LFRL_FWD_CASE(CBV, 4) LFRL_FWD_CASE(CBV, 8)
+#define LFRL_FWD_CASES(CBV) LFRL_FWD_CASE(CBV, 1) LFRL_FWD_CASE(CBV, 2) LFRL_FWD_CASE(CBV, 4)
 #define LFRL_ADJ_CASE(CBV, UV)                                                                   \
     if (p->adj_cb == CBV && p->adj_u == UV) {                                                    \
-        hipLaunchKernelGGL((k_contract_adj<CBV, UV>), grid, dim3(64 * kAdjWaves), lds, st, p->Gb, \
-                           p->Rs, p->X, g.NN, g.KK, nt);                                         \
+        hipLaunchKernelGGL((k_contract_adj<CBV, UV>), grid, dim3(64 * kAdjWaves), lds, st,       \
+                           (const float4 *)p->Fb, (const float2 *)p->Rs, p->X, g.NN, g.KK,      \
+                           g.NCp, nt, ranges);                                                   \
         launched = true;                                                                         \
     }
-#define LFRL_ADJ_CASES(CBV) LFRL_ADJ_CASE(CBV, 2) LFRL_ADJ_CASE(CBV, 4) LFRL_ADJ_CASE(CBV, 8)
+#define LFRL_ADJ_CASES(CBV) LFRL_ADJ_CASE(CBV, 1) LFRL_ADJ_CASE(CBV, 2) LFRL_ADJ_CASE(CBV, 4)
 
 static int contraction_split(const lfrl_plan_s *p, int *kchunk)
 {
@@ -1946,8 +2127,8 @@ static int run_forward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipSt
         LFRL_HFWD_CASE(3, 1)
 #undef LFRL_HFWD_CASE
     } else {
-    LFRL_FWD_CASES(1) LFRL_FWD_CASES(2) LFRL_FWD_CASES(3) LFRL_FWD_CASES(4) LFRL_FWD_CASES(5)
-    LFRL_FWD_CASE(8, 2) LFRL_FWD_CASE(8, 4)
+    LFRL_FWD_CASES(2) LFRL_FWD_CASES(3) LFRL_FWD_CASE(4, 1) LFRL_FWD_CASE(4, 2)
+    LFRL_FWD_CASE(5, 1) LFRL_FWD_CASE(5, 2)
     }
     if (!launched)
         return set_error(LFRL_ERR_UNSUPPORTED, "no forward contraction for shape %d/%d",
@@ -1995,11 +2176,22 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
                            g.Q, g.QH, g.T, g.hD, nt, g.NN, p->Rs, p->tw);
     LAUNCH_CHECK("k_vol_r2c(image)");
     const int acb = p->split ? p->hadj_cb : p->adj_cb;
-    const int kk_per_block = 16 * acb * kAdjWaves;
-    const dim3 grid(g.nf, (g.KK + kk_per_block - 1) / kk_per_block, (nt + 15) / 16);
-    const int ustep = 4 * p->adj_u;
+    const int kk_per_range = 16 * acb * kAdjWaves;
+    const int nrange = (g.KK + kk_per_range - 1) / kk_per_range;
+    // FP32: each block stages R once and covers `ranges` kk ranges, as many as
+    // keep about 2048 blocks in the launch
+    int ranges = 1;
+    if (!p->split) {
+        const long long blocks1 = (long long)g.nf * nrange * ((nt + 15) / 16);
+        ranges = (int)std::max(1LL, std::min(4LL, blocks1 / 2048));
+    }
+    const dim3 grid(g.nf, (nrange + ranges - 1) / ranges, (nt + 15) / 16);
+    // FP32: rows of R staged in LDS, an even number of register groups of
+    // 8 * adj_u reduction indices (as the kernel assumes), row stride kRsStride
+    const int ustep = 8 * p->adj_u;
+    const int agroups = ((g.NCp + ustep - 1) / ustep + 1) / 2 * 2;
     const size_t lds = p->split ? (size_t)(g.NNp / 16) * 64 * 16 * sizeof(_Float16)
-                                : (size_t)(g.NN + ustep - 1) / ustep * ustep * 16 * sizeof(float2);
+                                : (size_t)agroups * ustep * kRsStride * sizeof(float2);
     if (p->prof) {
         int rc = prof_event(p, 1, st);
         if (rc)
@@ -2017,7 +2209,7 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
         LFRL_HADJ_CASE(2, 2) LFRL_HADJ_CASE(2, 4) LFRL_HADJ_CASE(4, 2) LFRL_HADJ_CASE(4, 4)
 #undef LFRL_HADJ_CASE
     } else {
-    LFRL_ADJ_CASES(1) LFRL_ADJ_CASES(2) LFRL_ADJ_CASES(4) LFRL_ADJ_CASES(8)
+    LFRL_ADJ_CASES(2) LFRL_ADJ_CASES(4)
     }
     if (!launched)
         return set_error(LFRL_ERR_UNSUPPORTED, "no adjoint contraction for shape %d/%d",
