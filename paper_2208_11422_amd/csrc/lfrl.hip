@@ -1587,6 +1587,8 @@ struct Sizes {
     size_t Hf = 0, Hb = 0, gexp = 0, rowmax = 0;  // split FP16 only
     bool split = false;
     size_t resident() const { return (split ? Hf + Hb + gexp : Ff + Fb) + tw + psf; }
+    // the inverse tile DFT addresses tile spectra with 32-bit offsets
+    bool indexable() const { return X / sizeof(float2) < (1ull << 32) && Yp / sizeof(float2) < (1ull << 32); }
     size_t workspace() const { return X + Yp + Rs + 2 * rowmax + frame; }
 };
 
@@ -1657,6 +1659,9 @@ extern "C" int lfrl_plan_footprint(const lfrl_plan_desc *desc, size_t *resident_
         geo_init(g, desc->nnum, desc->nz, desc->ksize, cands[i]);
         const Sizes s = sizes_for(g, desc->max_h, desc->max_w, desc->max_batch, pick_split(g),
                                   desc->precision == LFRL_SPLIT_FP16);
+        if (!s.indexable())
+            return set_error(LFRL_ERR_UNSUPPORTED, "tile workspace above 2^32 complex values "
+                                                   "(lower max_batch or the image size)");
         res = std::max(res, s.resident());
         ws = std::max(ws, s.workspace());
     }
@@ -1776,6 +1781,11 @@ static int plan_build(lfrl_plan_s **out, const lfrl_plan_desc *desc, int q, cons
     p->split_k = pick_split(g);
     p->split = desc->precision == LFRL_SPLIT_FP16;
     const Sizes s = sizes_for(g, p->max_h, p->max_w, desc->max_batch, p->split_k, p->split);
+    if (!s.indexable()) {
+        delete p;
+        return set_error(LFRL_ERR_UNSUPPORTED, "tile workspace above 2^32 complex values "
+                                               "(lower max_batch or the image size)");
+    }
     p->resident = s.resident();
     p->workspace = s.workspace();
     p->use_fft = fft_usable(g, lmax);

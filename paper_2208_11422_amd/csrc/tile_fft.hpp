@@ -132,12 +132,15 @@ __device__ __forceinline__ void fft(float2 (&v)[Q], const float2 *__restrict__ t
 
 enum { SRC_PLANES = 0, SRC_PSF = 1 };
 
-// Loads in these kernels are issued in batches of kLoadBatch per thread before
-// any of them is consumed, so a thread keeps that many requests in flight
+// Loads in these kernels are issued in batches (the constants below) per thread
+// before any of them is consumed, so a thread keeps that many requests in flight
 // instead of waiting out the memory latency once per element.  Addresses are
 // clamped to valid elements and unwanted values cleared with a bit mask (not a
 // select, which the compiler would turn into a branch around the load).
-static constexpr int kLoadBatch = 8;
+// (deeper batches were measured slower: fewer blocks fit per CU)
+static constexpr int kGatherBatch = 8;   // forward tile gather (floats per thread)
+static constexpr int kSpecBatch = 8;     // inverse: spectrum staging (complex per thread)
+static constexpr int kEpiBatch = 8;      // inverse: epilogue pixels per thread
 
 // Frames whose tiles one launch covers.  Tiles of all frames are numbered
 // consecutively (frame f owns tiles [tile0, tile0 + its tile count)); the
@@ -231,10 +234,10 @@ __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const TileBatch batch
         const int ly0 = (lt / fj.tiles_x) * T - hD, lx0 = (lt % fj.tiles_x) * T - hD;
         const float *plane = fj.src + (size_t)j * H * W;
         const int total = Q * rowlen;
-        for (int base = tid; base < total; base += kLoadBatch * blockDim.x) {
-            float v[kLoadBatch];
+        for (int base = tid; base < total; base += kGatherBatch * blockDim.x) {
+            float v[kGatherBatch];
 #pragma unroll
-            for (int b = 0; b < kLoadBatch; ++b) {
+            for (int b = 0; b < kGatherBatch; ++b) {
                 const int idx = min(base + b * (int)blockDim.x, total - 1);
                 const int i = idx / rowlen, col = idx % rowlen;
                 const int pr = N * (ly0 + i) + ar;
@@ -244,7 +247,7 @@ __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const TileBatch batch
                 v[b] = keep_if(x, ok);
             }
 #pragma unroll
-            for (int b = 0; b < kLoadBatch; ++b) {
+            for (int b = 0; b < kGatherBatch; ++b) {
                 const int idx = base + b * (int)blockDim.x;
                 if (idx < total)
                     buf[idx] = v[b];
@@ -368,30 +371,32 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
         tw[i] = twg[i];
     const size_t kkbase = (size_t)j * N * N + (size_t)ar * N;
     const int total = Q * QH * N;
-    for (int base = tid; base < total; base += kLoadBatch * blockDim.x) {
-        float2 acc[kLoadBatch];
-        size_t off[kLoadBatch];
+    // spectrum offsets fit in 32 bits (the workspace holds fewer than 2^32
+    // complex values), which keeps the deeper batches in registers
+    for (int base = tid; base < total; base += kSpecBatch * blockDim.x) {
+        float2 acc[kSpecBatch];
+        unsigned off[kSpecBatch];
 #pragma unroll
-        for (int b = 0; b < kLoadBatch; ++b) {
+        for (int b = 0; b < kSpecBatch; ++b) {
             const int idx = min(base + b * (int)blockDim.x, total - 1);
             const int p = idx % N;
             const size_t k = idx / N;
-            off[b] = k * sk + tile * stile + (kkbase + p) * sc;
+            off[b] = (unsigned)(k * sk + tile * stile + (kkbase + p) * sc);
             acc[b] = spec[off[b]];
         }
         for (int s = 1; s < nsplit; ++s) {
-            float2 part[kLoadBatch];
+            float2 part[kSpecBatch];
 #pragma unroll
-            for (int b = 0; b < kLoadBatch; ++b)
+            for (int b = 0; b < kSpecBatch; ++b)
                 part[b] = spec[off[b] + s * split_stride];
 #pragma unroll
-            for (int b = 0; b < kLoadBatch; ++b) {
+            for (int b = 0; b < kSpecBatch; ++b) {
                 acc[b].x += part[b].x;
                 acc[b].y += part[b].y;
             }
         }
 #pragma unroll
-        for (int b = 0; b < kLoadBatch; ++b) {
+        for (int b = 0; b < kSpecBatch; ++b) {
             const int idx = base + b * (int)blockDim.x;
             if (idx < total)
                 X[idx] = acc[b];
@@ -455,12 +460,12 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
     const int Ly = H / N, Lx = W / N;
     const int rowpix = T * N;
     const int ototal = T * rowpix;
-    for (int base = tid; base < ototal; base += kLoadBatch * blockDim.x) {
-        size_t o[kLoadBatch];
-        bool ok[kLoadBatch];
-        float a0[kLoadBatch], a1[kLoadBatch];
+    for (int base = tid; base < ototal; base += kEpiBatch * blockDim.x) {
+        size_t o[kEpiBatch];
+        bool ok[kEpiBatch];
+        float a0[kEpiBatch], a1[kEpiBatch];
 #pragma unroll
-        for (int b = 0; b < kLoadBatch; ++b) {
+        for (int b = 0; b < kEpiBatch; ++b) {
             const int idx = min(base + b * (int)blockDim.x, ototal - 1);
             const int ti = idx / rowpix, rem = idx % rowpix;
             const int Lr = ty * T + ti, Lc = tx * T + rem / N;
@@ -472,7 +477,7 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
             a1[b] = (mode == 2) ? aux1[o[b]] : 0.f;
         }
 #pragma unroll
-        for (int b = 0; b < kLoadBatch; ++b) {
+        for (int b = 0; b < kEpiBatch; ++b) {
             if (!ok[b])
                 continue;
             const float val = obuf[base + b * (int)blockDim.x];
