@@ -156,6 +156,58 @@ def request_images(specs, plans, cfg, dev):
     return out
 
 
+def small_leg(args, dev) -> dict:
+    """The small workload (Nnum 5, 55 x 55, 5 planes, K = 25), which is bound
+    by launch latency rather than bandwidth: calls of lfrl_deconvolve with its
+    5 iterations, with the run replayed from a captured graph and with direct
+    launches; then the split-FP16 path's drift from the FP32 path over 30
+    iterations (relative L2 per iterate)."""
+    import numpy as np
+    import torch
+
+    import lfrl_synth as S
+    import paper_2208_11422_amd as lf
+    p = S.preset("small")
+    g = p["geometry"]
+    psf_d = torch.from_numpy(p["psf_array"]).to(dev)
+    plan = lf.Plan(psf_d, g.h, g.w)
+    clean = plan.forward(torch.from_numpy(p["x_true"]).to(dev)).cpu().numpy()
+    y = torch.from_numpy(S.measure(clean, p["peak"], p["background"], p["noise_seed"])).to(dev)
+    xs = ys = g.w / (g.nnum * 2.0 * p["spot_radius"])
+    vol = torch.empty((g.nz, g.h, g.w), dtype=torch.float32, device=dev)
+    opts = lf.RlOpts(max_iters=p["iters"], stop=lf.STOP_TRACK, patience=1, init=0, xs=xs, ys=ys)
+    out = {"workload": "Nnum 5, 11x11 lenslets (55x55), 5 planes, K=25, 5 iterations per call",
+           "iters_per_call": p["iters"]}
+    for mode in ("graph", "direct"):
+        os.environ["LFRL_GRAPH"] = "1" if mode == "graph" else "0"
+        for _ in range(5):
+            lf.lfrl_deconvolve(plan.handle, g.h, g.w, y, vol, opts, want_metric=False)
+        torch.cuda.synchronize()
+        calls = args.small_calls
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            lf.lfrl_deconvolve(plan.handle, g.h, g.w, y, vol, opts, want_metric=False)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / calls
+        out[mode] = {"ms_per_call": ms, "iters_per_s": p["iters"] * 1e3 / ms}
+    os.environ.pop("LFRL_GRAPH", None)
+    out["graph_speedup"] = out["direct"]["ms_per_call"] / out["graph"]["ms_per_call"]
+    # precision: split FP16 against FP32, per iterate
+    plan16 = lf.Plan(psf_d, g.h, g.w, precision=lf.SPLIT_FP16)
+    errs = []
+    for k in range(1, 31):
+        a, _ = plan.deconvolve(y, k, stop=lf.STOP_NONE)
+        b, _ = plan16.deconvolve(y, k, stop=lf.STOP_NONE)
+        errs.append(float(torch.linalg.vector_norm(b - a) / torch.linalg.vector_norm(a)))
+    out["split_fp16_drift"] = {"max_rel_l2_vs_fp32": max(errs), "at_iter": 1 + int(np.argmax(errs)),
+                               "rel_l2_by_iter": errs}
+    plan.close()
+    plan16.close()
+    log(f"small: {json.dumps({k: v for k, v in out.items() if k != 'split_fp16_drift'})}, "
+        f"split drift max {max(errs):.2e}")
+    return out
+
+
 def batched_leg(args, dev) -> dict:
     """Independent frames of uneven sizes, each with its own FP32 plan (tile
     side chosen by the autotuner): the frames one after another through
@@ -324,6 +376,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-split", action="store_true",
                     help="skip the split-FP16 measurement")
+    ap.add_argument("--small-calls", type=int, default=200,
+                    help="timed calls of the small-workload leg (0 skips it)")
     ap.add_argument("--batched-frames", type=int, default=16,
                     help="frames of the batched uneven-size leg (0 skips it)")
     ap.add_argument("--serving-requests", type=int, default=2000,
@@ -482,10 +536,12 @@ def main() -> int:
         log(f"bench: split FP16 {ms16:.3f} ms/iter ({1000.0 / ms16:.1f} it/s), "
             f"rel L2 vs FP32 {diff:.2e}")
         plan = plan16
-    if args.batched_frames > 0 or args.serving_requests > 0:
+    if args.small_calls > 0 or args.batched_frames > 0 or args.serving_requests > 0:
         plan.close()
         plan = None
         torch.cuda.empty_cache()
+    if args.small_calls > 0:
+        out["small"] = small_leg(args, dev)
     if args.batched_frames > 0:
         out["batched"] = batched_leg(args, dev)
     if args.serving_requests > 0:

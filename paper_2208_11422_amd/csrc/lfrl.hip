@@ -1343,6 +1343,23 @@ struct lfrl_plan_s {
     unsigned *xmax = nullptr, *rmax = nullptr;  // per-(frequency, tile) maxima of tile spectra
     int thr_r2c = 256, thr_c2r = 256;
     double tune_ms = 0.0;     // measured projection pair at the chosen tile (autotuned plans)
+    // lfrl_deconvolve runs replayed from a captured graph (fixed-length stop modes)
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    struct GraphKey {
+        int h, w, max_iters, stop, patience, init, flux;
+        double xs, ys;
+        const float *img;
+        const float *vol;
+        bool operator==(const GraphKey &o) const
+        {
+            return h == o.h && w == o.w && max_iters == o.max_iters && stop == o.stop &&
+                   patience == o.patience && init == o.init && flux == o.flux && xs == o.xs &&
+                   ys == o.ys && img == o.img && vol == o.vol;
+        }
+    } graph_key{};
+    int graph_hits = 0;
     int tune_candidates = 0;  // tile sides timed
     // profiling
     bool prof = false;
@@ -1699,6 +1716,12 @@ static void free_plan(lfrl_plan_s *p)
         if (b)
             (void)hipFree(b);
     free_frame(p->fr);
+    if (p->graph_exec)
+        (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph)
+        (void)hipGraphDestroy(p->graph);
+    if (p->cap_stream)
+        (void)hipStreamDestroy(p->cap_stream);
     for (auto &v : p->ev)
         for (hipEvent_t e : v)
             (void)hipEventDestroy(e);
@@ -2688,6 +2711,54 @@ extern "C" int lfrl_deconvolve(lfrl_plan_t p, int32_t h, int32_t w, const float 
     f.y = img;
     f.opts = *opts;
     f.want_flux = report && report->flux_trace;
+    // Fixed-length runs (no host decision between iterations) are captured
+    // once into a graph and replayed: one launch instead of a dozen per
+    // iteration, which is what small frames are bound by.
+    const char *genv = getenv("LFRL_GRAPH");
+    const bool use_graph = opts->stop != LFRL_STOP_METRIC && !p->prof && !(genv && genv[0] == '0');
+    if (use_graph) {
+        const lfrl_plan_s::GraphKey key{h, w, opts->max_iters, opts->stop, opts->patience,
+                                         opts->init, f.want_flux ? 1 : 0, opts->xs, opts->ys,
+                                         img, vol};
+        if (!(p->graph_exec && p->graph_key == key)) {
+            if (p->graph_exec)
+                (void)hipGraphExecDestroy(p->graph_exec);
+            if (p->graph)
+                (void)hipGraphDestroy(p->graph);
+            p->graph_exec = nullptr;
+            p->graph = nullptr;
+            if (!p->cap_stream)
+                HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+            // the graph builds its own DCT tables (a later call with other legs
+            // may reuse the table buffers between replays)
+            f.tab_h = f.tab_nv = f.tab_w = f.tab_nu = -1;
+            HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+            Frame *one[1] = {&f};
+            rc = frame_start(f, p->g.Nz, opts->init == 1 ? vol : nullptr, p->cap_stream);
+            while (rc == LFRL_OK && f.iters < opts->max_iters)
+                rc = step_frames(p, one, 1, p->cap_stream);
+            hipGraph_t gr = nullptr;
+            const hipError_t ec = hipStreamEndCapture(p->cap_stream, &gr);
+            if (rc) {
+                if (gr)
+                    (void)hipGraphDestroy(gr);
+                return rc;
+            }
+            if (ec != hipSuccess)
+                return set_error(LFRL_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+            p->graph = gr;
+            HIP_TRY(hipGraphInstantiate(&p->graph_exec, gr, nullptr, nullptr, 0));
+            p->graph_key = key;
+        } else {
+            ++p->graph_hits;
+        }
+        HIP_TRY(hipGraphLaunch(p->graph_exec, st));
+        f.tab_h = f.tab_nv = f.tab_w = f.tab_nu = -1;  // the replay rewrote the tables
+        f.iters = opts->max_iters;
+        f.done = true;
+        f.stopped = false;
+        return frame_result(f, p->g.Nz, vol, report, st);
+    }
     if ((rc = frame_start(f, p->g.Nz, opts->init == 1 ? vol : nullptr, st)))
         return rc;
     Frame *one[1] = {&f};

@@ -291,3 +291,41 @@ def test_autotuned_plan(lf):
         assert rel_l2(tuned.forward(to_dev(x)).cpu().numpy(), oracle.forward(psf, x)) <= TOL
     finally:
         tuned.close()
+
+
+def test_graph_replays_match_direct_launches(lf, monkeypatch):
+    """Fixed-length runs replay a captured graph; every replay, with other
+    work and synchronisations in between, equals the run with graphs off."""
+    import torch
+    p, psf, y, xs, ys = small_problem()
+    g = p["geometry"]
+    plan = lf.Plan(to_dev(psf), g.h, g.w)
+    try:
+        yd = to_dev(y)
+        monkeypatch.setenv("LFRL_GRAPH", "0")
+        want, rep_w = plan.deconvolve(yd, 7, stop=lf.STOP_TRACK, xs=xs, ys=ys, want_flux=True)
+        want = want.clone()
+        monkeypatch.setenv("LFRL_GRAPH", "1")
+        out = torch.empty_like(want)
+        for rep in range(4):
+            plan.forward(want)                      # eager work between replays
+            torch.cuda.synchronize()
+            got, rep_g = plan.deconvolve(yd, 7, stop=lf.STOP_TRACK, xs=xs, ys=ys, out=out,
+                                         want_flux=True)
+            torch.cuda.synchronize()
+            assert torch.equal(got, want), rep
+            assert rep_g["metric_trace"] == rep_w["metric_trace"]
+            assert rep_g["flux_trace"] == rep_w["flux_trace"]
+            assert rep_g["best_iter"] == rep_w["best_iter"]
+        # other legs between replays must not leak into the graph's tables
+        monkeypatch.setenv("LFRL_GRAPH", "0")
+        plan.deconvolve(yd, 3, stop=lf.STOP_METRIC, xs=xs * 0.5, ys=ys * 0.7)
+        monkeypatch.setenv("LFRL_GRAPH", "1")
+        got, rep_g = plan.deconvolve(yd, 7, stop=lf.STOP_TRACK, xs=xs, ys=ys, out=out,
+                                     want_flux=True)
+        torch.cuda.synchronize()
+        assert torch.equal(got, want)
+        assert rep_g["metric_trace"] == rep_w["metric_trace"]
+        assert rel_l2(got.cpu().numpy(), oracle.deconvolve(psf, y, 7, xs, ys, stop=False)[0]) <= TOL
+    finally:
+        plan.close()
