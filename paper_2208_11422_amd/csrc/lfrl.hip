@@ -1333,6 +1333,18 @@ struct lfrl_plan_s {
     float *psf = nullptr;  // resident copy of the PSF set (weak-voxel sums)
     Frame fr;              // frame state of lfrl_deconvolve (sized for max_h x max_w)
     int sens_h = -1, sens_w = -1;
+    // A^T 1 and weak-voxel lists of recent image sizes, copied into new jobs
+    struct SensEntry {
+        int h = 0, w = 0;
+        float *sens = nullptr;
+        unsigned *weak = nullptr;
+        unsigned nweak = 0;
+        size_t bytes = 0;
+        unsigned long long stamp = 0;
+    };
+    std::vector<SensEntry> sens_cache;
+    size_t sens_cache_bytes = 0, sens_cache_limit = 0;
+    unsigned long long sens_clock = 0;
     size_t lds_r2c_bytes = 0, lds_c2r_bytes = 0;
     bool use_fft = false;  // tile DFTs by the register FFT kernels
     int fwd_cb = 3, fwd_u = 4, adj_cb = 4, adj_u = 4;  // contraction launch shapes
@@ -1716,6 +1728,10 @@ static void free_plan(lfrl_plan_s *p)
         if (b)
             (void)hipFree(b);
     free_frame(p->fr);
+    for (auto &e : p->sens_cache) {
+        (void)hipFree(e.sens);
+        (void)hipFree(e.weak);
+    }
     if (p->graph_exec)
         (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph)
@@ -1742,6 +1758,103 @@ static int dalloc(T **ptr, size_t bytes)
 }
 
 // Allocate and bind a Frame's device block and pinned host words.
+// Device blocks of jobs come from a per-device pool: a released job's block
+// and pinned words are kept and handed to a later job of the same size class,
+// so the serving loop does not call hipMalloc / hipFree (which synchronises
+// the device) per request.  Sizes are rounded up to classes about 6% apart;
+// lfrl_job_footprint reports the rounded size.
+static size_t job_size_class(size_t bytes)
+{
+    size_t c = 1 << 20;
+    while (c < bytes && c * 2 > c)
+        c *= 2;
+    if (c <= (1 << 20))
+        return c;
+    const size_t step = c / 32;  // 16 classes per octave
+    return (bytes + step - 1) / step * step;
+}
+
+struct JobSlot {
+    void *block = nullptr;
+    size_t bytes = 0;
+    StopState *state_host = nullptr;
+    unsigned *counters_host = nullptr;
+    hipEvent_t used = nullptr;  // recorded after the last work queued on the job
+};
+static std::mutex g_slot_mu;
+static std::vector<std::vector<JobSlot>> g_slots;  // [device] free slots
+
+static void slot_release_all(int dev)
+{
+    std::vector<JobSlot> v;
+    {
+        std::lock_guard<std::mutex> lk(g_slot_mu);
+        if ((int)g_slots.size() > dev)
+            v.swap(g_slots[dev]);
+    }
+    for (JobSlot &s : v) {
+        (void)hipFree(s.block);
+        (void)hipHostFree(s.state_host);
+        (void)hipHostFree(s.counters_host);
+        (void)hipEventDestroy(s.used);
+    }
+}
+
+// A slot of exactly `bytes` (a size class) from the pool, else a new one.
+static int slot_get(int dev, size_t bytes, JobSlot *out)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_slot_mu);
+        if ((int)g_slots.size() > dev) {
+            auto &v = g_slots[dev];
+            for (size_t i = 0; i < v.size(); ++i)
+                if (v[i].bytes == bytes) {
+                    *out = v[i];
+                    v[i] = v.back();
+                    v.pop_back();
+                    return LFRL_OK;
+                }
+        }
+    }
+    JobSlot s;
+    s.bytes = bytes;
+    hipError_t e = hipMalloc(&s.block, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        slot_release_all(dev);  // cached blocks of other classes may be in the way
+        e = hipMalloc(&s.block, bytes);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(LFRL_ERR_NOMEM, "hipMalloc(%zu) for a job failed: %s", bytes,
+                         hipGetErrorString(e));
+    }
+    e = hipHostMalloc((void **)&s.state_host, sizeof(StopState), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&s.counters_host, 2 * sizeof(unsigned), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&s.used, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(s.block);
+        if (s.state_host)
+            (void)hipHostFree(s.state_host);
+        if (s.counters_host)
+            (void)hipHostFree(s.counters_host);
+        return set_error(LFRL_ERR_NOMEM, "hipHostMalloc failed: %s", hipGetErrorString(e));
+    }
+    *out = s;
+    return LFRL_OK;
+}
+
+static void slot_put(int dev, const JobSlot &s)
+{
+    std::lock_guard<std::mutex> lk(g_slot_mu);
+    if ((int)g_slots.size() <= dev)
+        g_slots.resize(dev + 1);
+    g_slots[dev].push_back(s);
+}
+
 static int frame_alloc(Frame &f, const Geo &g, int h, int w, bool own_y)
 {
     size_t off[FB_COUNT];
@@ -1813,6 +1926,11 @@ static int plan_build(lfrl_plan_s **out, const lfrl_plan_desc *desc, int q, cons
     p->workspace = s.workspace();
     p->use_fft = fft_usable(g, lmax);
     default_shapes(g, &p->fwd_cb, &p->fwd_u, &p->adj_cb, &p->adj_u);
+    {
+        const char *env = getenv("LFRL_SENS_CACHE_MB");
+        const long mb = env ? atol(env) : 2048;
+        p->sens_cache_limit = (size_t)std::max(0L, mb) << 20;
+    }
     {
         // split FP16 shapes; tuning override LFRL_CONTRACT_SHAPE_F16="fcb,fu,acb,au"
         const int ncb = g.NNp / 16;
@@ -2779,7 +2897,15 @@ struct lfrl_job_s {
     lfrl_plan_s *plan = nullptr;  // must outlive the job
     int device = 0;
     Frame f;
+    hipEvent_t used = nullptr;    // the slot's event: recorded after each use
 };
+
+// Mark the job's work queued so far on `st` (release waits for it).
+static int job_mark(lfrl_job_s *j, hipStream_t st)
+{
+    HIP_TRY(hipEventRecord(j->used, st));
+    return LFRL_OK;
+}
 
 extern "C" int lfrl_job_footprint(lfrl_plan_t p, int32_t h, int32_t w, size_t *bytes)
 {
@@ -2789,17 +2915,95 @@ extern "C" int lfrl_job_footprint(lfrl_plan_t p, int32_t h, int32_t w, size_t *b
     if (rc)
         return rc;
     size_t off[FB_COUNT];
-    *bytes = frame_layout(p->g, h, w, true, off);
+    *bytes = job_size_class(frame_layout(p->g, h, w, true, off));
     return LFRL_OK;
 }
 
+// Return a job's block and pinned words to the pool.  Work queued on the
+// job must have completed (as for lfrl_job_destroy).
 static void free_job(lfrl_job_s *j)
 {
     if (!j)
         return;
-    DevGuard dg(j->device);
-    free_frame(j->f);
+    if (j->f.block) {
+        DevGuard dg(j->device);
+        (void)hipEventSynchronize(j->used);  // queued work on the block has finished
+        JobSlot s;
+        s.block = j->f.block;
+        s.bytes = j->f.block_bytes;
+        s.state_host = j->f.state_host;
+        s.counters_host = j->f.counters_host;
+        s.used = j->used;
+        slot_put(j->device, s);
+    }
     delete j;
+}
+
+// A^T 1 of a job: copied from the plan's cache when its image size was seen
+// recently, else formed (frame_sensitivity) and cached (least recently used
+// sizes are dropped beyond the cache limit).  Either way the job's image is
+// checked (LFRL_ERR_NUMERIC) and the stream synchronised.
+static int job_sensitivity(lfrl_plan_s *p, Frame &f, hipStream_t st)
+{
+    const size_t hw = (size_t)f.h * f.w, nvox = (size_t)p->g.Nz * hw;
+    for (auto &e : p->sens_cache) {
+        if (e.h != f.h || e.w != f.w)
+            continue;
+        e.stamp = ++p->sens_clock;
+        HIP_TRY(hipMemcpyAsync(f.sens, e.sens, nvox * sizeof(float), hipMemcpyDeviceToDevice, st));
+        if (e.nweak)
+            HIP_TRY(hipMemcpyAsync(f.weak, e.weak, e.nweak * sizeof(unsigned),
+                                   hipMemcpyDeviceToDevice, st));
+        f.nweak = e.nweak;
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, f.counters + 1);
+        LAUNCH_CHECK("k_zero_u32");
+        hipLaunchKernelGGL(k_check_image, dim3(256), dim3(256), 0, st, f.y, hw, f.counters + 1);
+        LAUNCH_CHECK("k_check_image");
+        HIP_TRY(hipMemcpyAsync(f.counters_host, f.counters, 2 * sizeof(unsigned),
+                               hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (f.counters_host[1])
+            return set_error(LFRL_ERR_NUMERIC, "image has negative or non-finite values");
+        return LFRL_OK;
+    }
+    int rc = frame_sensitivity(p, f, true, st);
+    if (rc)
+        return rc;
+    const size_t bytes = nvox * sizeof(float) + (size_t)f.nweak * sizeof(unsigned);
+    if (bytes > p->sens_cache_limit)
+        return LFRL_OK;
+    while (p->sens_cache_bytes + bytes > p->sens_cache_limit && !p->sens_cache.empty()) {
+        size_t old = 0;
+        for (size_t i = 1; i < p->sens_cache.size(); ++i)
+            if (p->sens_cache[i].stamp < p->sens_cache[old].stamp)
+                old = i;
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(p->sens_cache[old].sens);
+        (void)hipFree(p->sens_cache[old].weak);
+        p->sens_cache_bytes -= p->sens_cache[old].bytes;
+        p->sens_cache[old] = p->sens_cache.back();
+        p->sens_cache.pop_back();
+    }
+    lfrl_plan_s::SensEntry e;
+    e.h = f.h;
+    e.w = f.w;
+    e.nweak = f.nweak;
+    e.bytes = bytes;
+    if (hipMalloc((void **)&e.sens, nvox * sizeof(float)) != hipSuccess ||
+        hipMalloc((void **)&e.weak, std::max<size_t>(1, f.nweak) * sizeof(unsigned)) != hipSuccess) {
+        (void)hipGetLastError();  // no room to cache: the job itself is fine
+        if (e.sens)
+            (void)hipFree(e.sens);
+        return LFRL_OK;
+    }
+    HIP_TRY(hipMemcpyAsync(e.sens, f.sens, nvox * sizeof(float), hipMemcpyDeviceToDevice, st));
+    if (f.nweak)
+        HIP_TRY(hipMemcpyAsync(e.weak, f.weak, f.nweak * sizeof(unsigned), hipMemcpyDeviceToDevice,
+                               st));
+    e.stamp = ++p->sens_clock;
+    p->sens_cache.push_back(e);
+    p->sens_cache_bytes += bytes;
+    return LFRL_OK;
 }
 
 extern "C" int lfrl_job_create(lfrl_job_t *out, lfrl_plan_t p, int32_t h, int32_t w,
@@ -2831,9 +3035,20 @@ extern "C" int lfrl_job_create(lfrl_job_t *out, lfrl_plan_t p, int32_t h, int32_
     j->plan = p;
     j->device = p->device;
     Frame &f = j->f;
-    if ((rc = frame_alloc(f, p->g, h, w, true))) {
-        delete j;
-        return rc;
+    {
+        size_t off[FB_COUNT];
+        const size_t need = frame_layout(p->g, h, w, true, off);
+        JobSlot s;
+        if ((rc = slot_get(p->device, job_size_class(need), &s))) {
+            delete j;
+            return rc;
+        }
+        f.block = s.block;
+        f.block_bytes = s.bytes;
+        f.state_host = s.state_host;
+        f.counters_host = s.counters_host;
+        j->used = s.used;
+        frame_bind(f, p->g, h, w, f.block, off, true);
     }
     f.opts = *opts;
     f.want_flux = (flags & LFRL_JOB_FLUX) != 0;
@@ -2843,8 +3058,9 @@ extern "C" int lfrl_job_create(lfrl_job_t *out, lfrl_plan_t p, int32_t h, int32_
         return set_error(LFRL_ERR_DEVICE, "image copy failed: %s", hipGetErrorString(e));
     }
     f.y = f.y_own;
-    if ((rc = frame_sensitivity(p, f, true, st)) ||
-        (rc = frame_start(f, p->g.Nz, opts->init == 1 ? vol0 : nullptr, st))) {
+    if ((rc = job_sensitivity(p, f, st)) ||
+        (rc = frame_start(f, p->g.Nz, opts->init == 1 ? vol0 : nullptr, st)) ||
+        (rc = job_mark(j, st))) {
         const std::string msg = lfrl_last_error();
         (void)hipStreamSynchronize(st);
         free_job(j);
@@ -2966,6 +3182,11 @@ extern "C" int lfrl_job_step(const lfrl_job_t *jobs, int32_t njobs, int32_t *act
         }
         if (rc)
             return rc;
+        // record each stepped job's use on the caller stream, which the worker
+        // streams have joined
+        for (int i = 0; i < njobs; ++i)
+            if ((rc = job_mark(jobs[i], st)))
+                return rc;
         if (any_metric)
             HIP_TRY(hipStreamSynchronize(st));
         for (auto &gr : groups)
@@ -3000,7 +3221,9 @@ extern "C" int lfrl_job_result(lfrl_job_t j, float *vol, lfrl_rl_report *report,
     int rc;
     if (vol && (rc = check_buf(vol, (size_t)j->plan->g.Nz * j->f.h * j->f.w * sizeof(float), "vol")))
         return rc;
-    return frame_result(j->f, j->plan->g.Nz, vol, report, (hipStream_t)stream);
+    if ((rc = frame_result(j->f, j->plan->g.Nz, vol, report, (hipStream_t)stream)))
+        return rc;
+    return job_mark(j, (hipStream_t)stream);
 }
 
 extern "C" int lfrl_job_destroy(lfrl_job_t j)

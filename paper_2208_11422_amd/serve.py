@@ -73,8 +73,18 @@ class Executor:
         """One iteration for every handle; returns the done flag of each."""
         raise NotImplementedError
 
-    def result(self, handle: Any, req: Request) -> None:
-        """Copy the job's result to the host into req (result, iters, best_iter)."""
+    def result_begin(self, handle: Any, req: Request) -> Any:
+        """Start handing the job's result to the host (fills req.iters and
+        req.best_iter); returns a token.  The job may be destroyed as soon as
+        this returns."""
+        raise NotImplementedError
+
+    def result_ready(self, token: Any) -> bool:
+        """Whether the result volume behind `token` has reached the host."""
+        raise NotImplementedError
+
+    def result_finish(self, token: Any, req: Request) -> None:
+        """Complete a ready result (req.result for kept requests)."""
         raise NotImplementedError
 
     def destroy(self, handle: Any) -> None:
@@ -96,7 +106,8 @@ class Scheduler:
         self.peak_active = 0
         self.rounds = 0
         self.batch_sizes: List[int] = []
-        self.op_seconds = {"create": 0.0, "step": 0.0, "result": 0.0, "destroy": 0.0}
+        self.op_seconds = {"create": 0.0, "step": 0.0, "result": 0.0, "destroy": 0.0,
+                           "drain": 0.0}
 
     def _timed(self, op: str, fn, *a):
         t = self.clock()
@@ -108,15 +119,30 @@ class Scheduler:
     def run(self, requests: Sequence[Request]) -> List[Request]:
         pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
         queue: collections.deque = collections.deque()
-        active: list = []   # [req, handle, bytes]
+        active: list = []    # [req, handle, bytes]
+        draining: list = []  # [req, token]: result on its way to the host
         used = 0
         nomem_wait = False  # an allocation failed: admit nothing until a job finishes
         t0 = self.clock()
         now = lambda: self.clock() - t0  # noqa: E731
-        while pending or queue or active:
+
+        def drain():
+            still = []
+            for req, tok in draining:
+                if self.ex.result_ready(tok):
+                    self.ex.result_finish(tok, req)
+                    req.finished = now()
+                    req.status = "done"
+                else:
+                    still.append([req, tok])
+            draining[:] = still
+
+        while pending or queue or active or draining:
             t = now()
             while pending and pending[0].arrival <= t:
                 queue.append(pending.popleft())
+            if draining:
+                self._timed("drain", drain)
             # admission, in arrival order (no overtaking: a large request at
             # the head waits for memory rather than starving)
             while queue and not nomem_wait and len(active) < self.max_active:
@@ -148,10 +174,9 @@ class Scheduler:
             if not active:
                 if queue and not nomem_wait:
                     continue       # head was rejected or failed: look at the next
-                if pending:
-                    wait = pending[0].arrival - now()
-                    if wait > 0:
-                        self.sleep(min(wait, 0.001))
+                if draining or pending:
+                    wait = pending[0].arrival - now() if pending else 0.0
+                    self.sleep(min(max(wait, 0.0), 0.001) if pending else 0.0001)
                 continue
             done = self._timed("step", self.ex.step, [a[1] for a in active])
             self.rounds += 1
@@ -161,12 +186,11 @@ class Scheduler:
                 if not d:
                     still.append([req, handle, fp])
                     continue
-                self._timed("result", self.ex.result, handle, req)
-                req.finished = now()
-                req.status = "done"
+                tok = self._timed("result", self.ex.result_begin, handle, req)
                 self._timed("destroy", self.ex.destroy, handle)
                 used -= fp
                 nomem_wait = False
+                draining.append([req, tok])
             active = still
         return list(requests)
 
@@ -196,9 +220,9 @@ class JobExecutor(Executor):
 
     ``plans`` are ``paper_2208_11422_amd.Plan`` objects; request images are
     host float32 tensors (pinned for an asynchronous copy).  Each result volume
-    is copied to host memory through one reusable pinned staging buffer; the
-    results of requests listed in ``keep`` are kept (as host tensors) in
-    ``req.result``."""
+    is copied to a device buffer, then to a pooled pinned host buffer on a copy
+    stream; the results of requests listed in ``keep`` are kept (as host
+    tensors) in ``req.result``."""
 
     def __init__(self, plans, opts_for: Callable[[Request], dict], stream=None, keep=()):
         import torch
@@ -210,7 +234,8 @@ class JobExecutor(Executor):
         self.stream = stream
         self.device = plans[0].device
         self.keep = set(keep)
-        self.staging = None
+        self.pinned = {}                            # numel -> free pinned buffers
+        self.copy_stream = torch.cuda.Stream()      # device-to-host result copies
 
     def footprint(self, req: Request) -> int:
         return self.lf.lfrl_job_footprint(self.plans[req.plan].handle, req.h, req.w)
@@ -227,16 +252,28 @@ class JobExecutor(Executor):
         self.lf.Job.step(handles, self.stream)
         return [h.poll()[0] for h in handles]
 
-    def result(self, handle, req: Request) -> None:
-        vol, rep = handle.result(stream=self.stream)
-        n = vol.numel()
-        if self.staging is None or self.staging.numel() < n:
-            self.staging = self.torch.empty(n, dtype=self.torch.float32, pin_memory=True)
-        host = self.staging[:n].view(vol.shape)
-        host.copy_(vol)   # synchronous: the volume is on the host when this returns
-        req.result = host.clone() if req.rid in self.keep else None
+    def result_begin(self, handle, req: Request):
+        vol, rep = handle.result(stream=self.stream)   # device copy; synchronises
         req.iters = rep["iters_run"]
         req.best_iter = rep["best_iter"]
+        n = vol.numel()
+        free = self.pinned.setdefault(n, [])
+        host = free.pop() if free else self.torch.empty(n, dtype=self.torch.float32,
+                                                          pin_memory=True)
+        with self.torch.cuda.stream(self.copy_stream):
+            host.copy_(vol.view(-1), non_blocking=True)
+            ev = self.torch.cuda.Event()
+            ev.record(self.copy_stream)
+        return (vol, host, ev)
+
+    def result_ready(self, token) -> bool:
+        return token[2].query()
+
+    def result_finish(self, token, req: Request) -> None:
+        vol, host, ev = token
+        if req.rid in self.keep:
+            req.result = host.view(vol.shape).clone()
+        self.pinned.setdefault(host.numel(), []).append(host)
 
     def destroy(self, handle) -> None:
         handle.close()

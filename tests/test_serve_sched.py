@@ -21,8 +21,10 @@ class FakeExecutor(Executor):
     """Job state = remaining iterations; one step costs step_s of clock time
     plus per_job_s per job in the batch."""
 
-    def __init__(self, clock, iters_of, step_s=1e-3, per_job_s=2e-4, nomem_once=()):
+    def __init__(self, clock, iters_of, step_s=1e-3, per_job_s=2e-4, nomem_once=(),
+                 copy_s=0.0):
         self.clock = clock
+        self.copy_s = copy_s
         self.iters_of = iters_of
         self.step_s = step_s
         self.per_job_s = per_job_s
@@ -56,10 +58,16 @@ class FakeExecutor(Executor):
             out.append(self.live[h][0] <= 0)
         return out
 
-    def result(self, handle, req):
+    def result_begin(self, handle, req):
         req.iters = self.iters_of(req)
         req.best_iter = max(1, req.iters - 1)
-        req.result = ("volume", req.rid)
+        return ("volume", req.rid, self.clock.t + self.copy_s)
+
+    def result_ready(self, token):
+        return self.clock.t >= token[2]
+
+    def result_finish(self, token, req):
+        req.result = token[:2]
 
     def destroy(self, handle):
         self.live_bytes -= self.footprint(self.live[handle][1])
@@ -139,6 +147,22 @@ def test_open_loop_waits_for_arrivals():
     for r in reqs:
         assert r.admitted >= r.arrival
         assert r.latency == pytest.approx(1e-4, abs=2e-3)
+
+
+def test_results_in_flight_to_the_host():
+    """A request finishes when its volume reaches the host; its job's memory
+    is released when the copy starts, so admission does not wait for it."""
+    clk = FakeClock()
+    ex = FakeExecutor(clk, iters_of=lambda r: 2, copy_s=0.01)
+    reqs = make(4)
+    sched = Scheduler(ex, budget_bytes=200, clock=clk, sleep=clk.sleep)
+    sched.run(reqs)
+    assert all(r.status == "done" and r.result == ("volume", r.rid) for r in reqs)
+    for r in reqs:
+        assert r.finished - r.admitted >= 0.01
+    # two at a time fit the budget; the second pair is admitted before the first
+    # pair's volumes have landed
+    assert reqs[2].admitted < reqs[0].finished
 
 
 def test_latency_percentiles():
