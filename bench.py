@@ -192,19 +192,22 @@ def small_leg(args, dev) -> dict:
         out[mode] = {"ms_per_call": ms, "iters_per_s": p["iters"] * 1e3 / ms}
     os.environ.pop("LFRL_GRAPH", None)
     out["graph_speedup"] = out["direct"]["ms_per_call"] / out["graph"]["ms_per_call"]
-    # precision: split FP16 against FP32, per iterate
-    plan16 = lf.Plan(psf_d, g.h, g.w, precision=lf.SPLIT_FP16)
-    errs = []
-    for k in range(1, 31):
-        a, _ = plan.deconvolve(y, k, stop=lf.STOP_NONE)
-        b, _ = plan16.deconvolve(y, k, stop=lf.STOP_NONE)
-        errs.append(float(torch.linalg.vector_norm(b - a) / torch.linalg.vector_norm(a)))
-    out["split_fp16_drift"] = {"max_rel_l2_vs_fp32": max(errs), "at_iter": 1 + int(np.argmax(errs)),
-                               "rel_l2_by_iter": errs}
+    # precision: split FP16 and split BF16 against FP32, per iterate
+    drift = {}
+    for name, prec in (("split_fp16_drift", lf.SPLIT_FP16), ("split_bf16_drift", lf.SPLIT_BF16)):
+        planx = lf.Plan(psf_d, g.h, g.w, precision=prec)
+        errs = []
+        for k in range(1, 31):
+            a, _ = plan.deconvolve(y, k, stop=lf.STOP_NONE)
+            b, _ = planx.deconvolve(y, k, stop=lf.STOP_NONE)
+            errs.append(float(torch.linalg.vector_norm(b - a) / torch.linalg.vector_norm(a)))
+        planx.close()
+        out[name] = {"max_rel_l2_vs_fp32": max(errs), "at_iter": 1 + int(np.argmax(errs)),
+                     "rel_l2_by_iter": errs}
+        drift[name] = max(errs)
     plan.close()
-    plan16.close()
-    log(f"small: {json.dumps({k: v for k, v in out.items() if k != 'split_fp16_drift'})}, "
-        f"split drift max {max(errs):.2e}")
+    log(f"small: {json.dumps({k: v for k, v in out.items() if not k.endswith('_drift')})}, "
+        f"drift max {drift}")
     return out
 
 
@@ -535,7 +538,28 @@ def main() -> int:
         }
         log(f"bench: split FP16 {ms16:.3f} ms/iter ({1000.0 / ms16:.1f} it/s), "
             f"rel L2 vs FP32 {diff:.2e}")
-        plan = plan16
+        # the same with BF16 spectra and BF16 matrix cores
+        plan16.close()
+        torch.cuda.empty_cache()
+        psf_d = torch.from_numpy(p["psf_array"]).to(dev)
+        planb = lf.Plan(psf_d, h, w, tile_q=args.tile_q, precision=lf.SPLIT_BF16)
+        del psf_d
+        optsb = lf.RlOpts(max_iters=args.warmup if args.warmup > 0 else 1, stop=lf.STOP_TRACK,
+                          patience=1, init=0, xs=xs, ys=ys)
+        lf.lfrl_deconvolve(planb.handle, h, w, y_d, vol, optsb)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        optsb.max_iters = args.steps
+        lf.lfrl_deconvolve(planb.handle, h, w, y_d, vol, optsb)
+        torch.cuda.synchronize()
+        msb = (time.perf_counter() - t0) * 1000.0 / args.steps
+        diffb = float(torch.linalg.vector_norm(vol - vol32) / torch.linalg.vector_norm(vol32))
+        out["split_bf16"] = {"value": 1000.0 / msb, "unit": "iters/s", "ms_per_step": msb,
+                             "dtype": "bf16 spectra, hi/lo bf16 tile spectra, f32 accumulate",
+                             "rel_l2_vs_fp32_after_steps": diffb}
+        log(f"bench: split BF16 {msb:.3f} ms/iter ({1000.0 / msb:.1f} it/s), "
+            f"rel L2 vs FP32 {diffb:.2e}")
+        plan = planb
     if args.small_calls > 0 or args.batched_frames > 0 or args.serving_requests > 0:
         plan.close()
         plan = None

@@ -52,12 +52,15 @@ typedef enum {
 
 typedef enum {
     LFRL_FP32 = 0,        /* spectra, tile DFTs and contractions in float32 */
-    LFRL_SPLIT_FP16 = 1   /* PSF spectra stored in FP16 (per-frequency power-of-two
+    LFRL_SPLIT_FP16 = 1,  /* PSF spectra stored in FP16 (per-frequency power-of-two
                              scale; half the bytes streamed per projection); tile
                              spectra split into hi + lo FP16 parts, products on
                              FP16 matrix cores with FP32 accumulation; tile DFTs,
                              ratio and update in float32.  Relative error of a
-                             projection about 1e-4 instead of 1e-7. */
+                             projection about 1e-5 to 1e-4 instead of 1e-7. */
+    LFRL_SPLIT_BF16 = 2   /* as LFRL_SPLIT_FP16 with BF16 storage and BF16 matrix
+                             cores: 8 significant bits per spectrum value (FP16:
+                             11), so errors about 8 times larger. */
 } lfrl_precision;
 
 /* Plan flags.  LFRL_PLAN_AUTOTUNE (with tile_q = 0): time the best few tile

@@ -28,7 +28,7 @@ __all__ = [
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liblfrl.so")
 
-FP32, SPLIT_FP16 = 0, 1
+FP32, SPLIT_FP16, SPLIT_BF16 = 0, 1, 2
 STOP_NONE, STOP_METRIC, STOP_TRACK = 0, 1, 2
 
 _STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_NOMEM", -3: "ERR_DEVICE",

@@ -1,41 +1,77 @@
-// contract_f16.hpp - spectral contractions with FP16 spectra on matrix cores.
+// contract_split.hpp - spectral contractions with 16-bit spectra on matrix cores.
 //
-// Precision mode "split FP16": the per-frequency PSF spectra are stored once in
-// FP16 (each frequency scaled by a power of two so its largest component lies
-// in [2^14, 2^15)), which halves the bytes streamed per projection.  The tile
-// spectra stay FP32 in HBM and are split on the fly into hi + lo FP16 parts
-// (hi = fp16(v), lo = fp16(v - hi)) after a power-of-two scale per (frequency,
-// tile) row, so they keep about 22 significant bits; each real product is the
-// sum of two FP16 matrix products (hi and lo) accumulated in FP32.  The spectra
-// are laid out in MFMA fragment order so that every lane loads one contiguous
-// 16- or 32-byte piece.
+// Split precision modes (FP16 or BF16 storage): the per-frequency PSF spectra
+// are stored once in the 16-bit type (each frequency scaled by a power of two
+// so its largest component lies in [2^14, 2^15)), which halves the bytes
+// streamed per projection.  The tile spectra stay FP32 in HBM and are split on
+// the fly into hi + lo parts (hi = round(v), lo = round(v - hi)) after a
+// power-of-two scale per (frequency, tile) row; each real product is the sum
+// of two 16-bit matrix products (hi and lo) accumulated in FP32.  FP16 keeps
+// 11 significant bits per spectrum value and about 22 per tile value; BF16
+// keeps 8 and about 16.  The spectra are laid out in MFMA fragment order so
+// that every lane loads one contiguous 16- or 32-byte piece.
 //
-// Fragment layouts (wave64), checked against a CPU product on gfx950:
-//   v_mfma_f32_16x16x32_f16: A[i][k] in lane i + 16 (k / 8), element k % 8;
-//                            B[k][j] in lane j + 16 (k / 8), element k % 8.
-//   v_mfma_f32_16x16x16_f16: A[i][k] in lane i + 16 (k / 4), element k % 4;
-//                            B[k][j] in lane j + 16 (k / 4), element k % 4.
+// Fragment layouts (wave64), checked against a CPU product on gfx950 for
+// both types:
+//   16x16x32: A[i][k] in lane i + 16 (k / 8), element k % 8;
+//             B[k][j] in lane j + 16 (k / 8), element k % 8.
+//   16x16x16: A[i][k] in lane i + 16 (k / 4), element k % 4;
+//             B[k][j] in lane j + 16 (k / 4), element k % 4.
 //   Both: D[i][j] in lane j + 16 (i / 4), element i % 4.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4v __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
 
-struct alignas(4) half2c {
-    _Float16 re, im;
+// one complex spectrum value in a 16-bit type
+template <typename S>
+struct alignas(4) cplx16 {
+    S re, im;
 };
 
-__device__ __forceinline__ f32x4v mfma_h32(f16x8 a, f16x8 b, f32x4v c)
-{
-    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
-}
+struct PrecF16 {
+    typedef _Float16 S;
+    typedef _Float16 v8 __attribute__((ext_vector_type(8)));
+    typedef _Float16 v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ S from(float v) { return (S)v; }
+    static __device__ __forceinline__ float to(S s) { return (float)s; }
+    static __device__ __forceinline__ f32x4v m32(v8 a, v8 b, f32x4v c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ f32x4v m16(v4 a, v4 b, f32x4v c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+    }
+};
 
-__device__ __forceinline__ f32x4v mfma_h16(f16x4 a, f16x4 b, f32x4v c)
+struct PrecBF16 {
+    typedef __bf16 S;
+    typedef __bf16 v8 __attribute__((ext_vector_type(8)));
+    typedef __bf16 v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ S from(float v) { return (S)v; }
+    static __device__ __forceinline__ float to(S s) { return (float)s; }
+    static __device__ __forceinline__ f32x4v m32(v8 a, v8 b, f32x4v c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ f32x4v m16(v4 a, v4 b, f32x4v c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, a),
+                                                         __builtin_bit_cast(s16x4, b), c, 0, 0,
+                                                         0);
+    }
+};
+
+// sign flip of every element (exact for both types)
+template <typename V, typename U>
+__device__ __forceinline__ V neg16(V v)
 {
-    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+    return __builtin_bit_cast(V, __builtin_bit_cast(U, v) ^ (unsigned short)0x8000);
 }
 
 // Exponent e with max * 2^e in [2^14, 2^15) (0 for max == 0 or not finite).
@@ -70,8 +106,10 @@ __global__ void k_spec_exp(const float2 *__restrict__ Gf, size_t per_k, int *__r
 
 // Forward fragments: Hf[k][kb][cb][lane][e], kk = 32 kb + 8 (lane / 16) + e,
 // c = 16 cb + lane % 16, value Gf[k][kk][c] 2^gexp[k] (0 past KK).
-__global__ void k_pack_fwd_f16(const float2 *__restrict__ Gf, int KK, int NNp, int nkb,
-                               const int *__restrict__ gexp, half2c *__restrict__ Hf, size_t total)
+template <class P>
+__global__ void k_pack_fwd_split(const float2 *__restrict__ Gf, int KK, int NNp, int nkb,
+                                 const int *__restrict__ gexp,
+                                 cplx16<typename P::S> *__restrict__ Hf, size_t total)
 {
     const int ncb = NNp / 16;
     for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
@@ -88,17 +126,19 @@ __global__ void k_pack_fwd_f16(const float2 *__restrict__ Gf, int KK, int NNp, i
         if (kk < KK)
             v = Gf[(k * KK + kk) * NNp + c];
         const int ex = gexp[k];
-        half2c h;
-        h.re = (_Float16)ldexpf(v.x, ex);
-        h.im = (_Float16)ldexpf(v.y, ex);
+        cplx16<typename P::S> h;
+        h.re = P::from(ldexpf(v.x, ex));
+        h.im = P::from(ldexpf(v.y, ex));
         Hf[idx] = h;
     }
 }
 
 // Adjoint fragments: Hb[k][cc][kb][lane][e], c = 16 cc + 4 (lane / 16) + e,
 // kk = 16 kb + lane % 16, value Gb[k][c][kk] 2^gexp[k] (0 past NN or KK).
-__global__ void k_pack_adj_f16(const float2 *__restrict__ Gb, int NN, int KK, int ncc, int nkb,
-                               const int *__restrict__ gexp, half2c *__restrict__ Hb, size_t total)
+template <class P>
+__global__ void k_pack_adj_split(const float2 *__restrict__ Gb, int NN, int KK, int ncc, int nkb,
+                                 const int *__restrict__ gexp,
+                                 cplx16<typename P::S> *__restrict__ Hb, size_t total)
 {
     for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
          idx += (size_t)gridDim.x * blockDim.x) {
@@ -114,31 +154,35 @@ __global__ void k_pack_adj_f16(const float2 *__restrict__ Gb, int NN, int KK, in
         if (c < NN && kk < KK)
             v = Gb[(k * NN + c) * KK + kk];
         const int ex = gexp[k];
-        half2c h;
-        h.re = (_Float16)ldexpf(v.x, ex);
-        h.im = (_Float16)ldexpf(v.y, ex);
+        cplx16<typename P::S> h;
+        h.re = P::from(ldexpf(v.x, ex));
+        h.im = P::from(ldexpf(v.y, ex));
         Hb[idx] = h;
     }
 }
 
 // hi/lo split of a scaled value
-__device__ __forceinline__ void split_f16(float v, _Float16 &hi, _Float16 &lo)
+template <class P>
+__device__ __forceinline__ void split_lohi(float v, typename P::S &hi, typename P::S &lo)
 {
-    hi = (_Float16)v;
-    lo = (_Float16)(v - (float)hi);
+    hi = P::from(v);
+    lo = P::from(v - P::to(hi));
 }
 
-// Forward contraction, split FP16 (see the FP32 k_contract_fwd for the roles):
+// Forward contraction, split precision (see the FP32 k_contract_fwd for the
+// roles):
 //   Yp[s][k][t][c] = sum_{kk in chunk} X[k][t][kk] Gf[k][kk][c]
 // A = X rows (16 tiles x 32 kk, row stride KKs, scaled by 2^xexp and split),
-// B = Hf fragments (32 kk x 16 c), CB blocks of c per wave, U prefetched steps.
-// kchunk is a multiple of 32.
-template <int CB, int U>
-__global__ __launch_bounds__(512) void k_contract_fwd_f16(
-    const half2c *__restrict__ Hf, const float2 *__restrict__ X, const unsigned *__restrict__ xmax,
-    const int *__restrict__ gexp, float2 *__restrict__ Yp, int NN, int NNp, int KK, int KKs,
-    int nkb, int nt, int nf, int kchunk)
+// B = Hf fragments (32 kk x 16 c), CB blocks of c per wave, U prefetched
+// steps, double-buffered (clamped loads).  kchunk is a multiple of 32.
+template <class P, int CB, int U>
+__global__ __launch_bounds__(512) void k_contract_fwd_split(
+    const cplx16<typename P::S> *__restrict__ Hf, const float2 *__restrict__ X,
+    const unsigned *__restrict__ xmax, const int *__restrict__ gexp, float2 *__restrict__ Yp,
+    int NN, int NNp, int KK, int KKs, int nkb, int nt, int nf, int kchunk)
 {
+    typedef typename P::S S;
+    typedef typename P::v8 V8;
     const int k = blockIdx.x, s = blockIdx.y, t0 = blockIdx.z * 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, kg = lane >> 4;
@@ -187,42 +231,45 @@ __global__ __launch_bounds__(512) void k_contract_fwd_f16(
         for (int u = 0; u < U; ++u) {
             const int step = grp * U + u;
             const int kk = kb0 + 32 * step + 8 * kg;
-            f16x8 arh, arl, aih, ail;
+            V8 arh, arl, aih, ail;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const float4 q = xa[u][e / 2];
                 const bool ok = step < nsteps && kk + e < kb1;
                 const float re = ok ? ldexpf((e & 1) ? q.z : q.x, ex) : 0.f;
                 const float im = ok ? ldexpf((e & 1) ? q.w : q.y, ex) : 0.f;
-                _Float16 h, l;
-                split_f16(re, h, l);
+                S h, l;
+                split_lohi<P>(re, h, l);
                 arh[e] = h;
                 arl[e] = l;
-                split_f16(im, h, l);
+                split_lohi<P>(im, h, l);
                 aih[e] = h;
                 ail[e] = l;
             }
-            const f16x8 naih = -aih, nail = -ail;
+            const V8 naih = neg16<V8, u16x8>(aih), nail = neg16<V8, u16x8>(ail);
 #pragma unroll
             for (int b = 0; b < CB; ++b) {
-                const half2c *hp = reinterpret_cast<const half2c *>(&gb[u][b][0]);
-                f16x8 gr, gi;
+                const cplx16<S> *hp = reinterpret_cast<const cplx16<S> *>(&gb[u][b][0]);
+                V8 gr, gi;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     gr[e] = hp[e].re;
                     gi[e] = hp[e].im;
                 }
-                accr[b] = mfma_h32(arh, gr, accr[b]);
-                accr[b] = mfma_h32(arl, gr, accr[b]);
-                accr[b] = mfma_h32(naih, gi, accr[b]);
-                accr[b] = mfma_h32(nail, gi, accr[b]);
-                acci[b] = mfma_h32(arh, gi, acci[b]);
-                acci[b] = mfma_h32(arl, gi, acci[b]);
-                acci[b] = mfma_h32(aih, gr, acci[b]);
-                acci[b] = mfma_h32(ail, gr, acci[b]);
+                accr[b] = P::m32(arh, gr, accr[b]);
+                accr[b] = P::m32(arl, gr, accr[b]);
+                accr[b] = P::m32(naih, gi, accr[b]);
+                accr[b] = P::m32(nail, gi, accr[b]);
+                acci[b] = P::m32(arh, gi, acci[b]);
+                acci[b] = P::m32(arl, gi, acci[b]);
+                acci[b] = P::m32(aih, gr, acci[b]);
+                acci[b] = P::m32(ail, gr, acci[b]);
             }
         }
     };
+    // (measured: for this kernel, whose products wait on VALU conversions of
+    // the tile spectra, the plain double-buffered loop beats the straight-line
+    // form with scheduling barriers used by the other contractions)
     if (ngroups > 0)
         load_group(0, xa0, gb0);
     for (int grp = 0; grp < ngroups; grp += 2) {
@@ -253,24 +300,36 @@ __global__ __launch_bounds__(512) void k_contract_fwd_f16(
     }
 }
 
-// Adjoint contraction, split FP16:
+// Rows (16-c chunks) of image tile spectra the split adjoint stages in LDS:
+// an even number of register groups of U chunks, zero past NN.
+__host__ __device__ __forceinline__ int split_adj_chunks(int ncc, int U)
+{
+    return ((ncc + U - 1) / U + 1) / 2 * 2 * U;
+}
+
+// Adjoint contraction, split precision:
 //   B[k][t][kk] = sum_c R[k][t][c] conj(Gb[k][c][kk])
 // A = R rows (16 tiles x 16 c per step, scaled by 2^rexp and split hi/lo once
-// per block into LDS), B = Hb fragments (16 c x 16 kk), CB blocks of kk per
-// wave, U prefetched steps.
-template <int CB, int U>
-__global__ __launch_bounds__(256) void k_contract_adj_f16(
-    const half2c *__restrict__ Hb, const float2 *__restrict__ Rs, const unsigned *__restrict__ rmax,
-    const int *__restrict__ gexp, float2 *__restrict__ B, int NN, int NNp, int KK, int nkb,
-    int nt)
+// per block into LDS, zero past NN), B = Hb fragments (16 c x 16 kk), CB
+// blocks of kk per wave, U prefetched steps in a straight-line
+// double-buffered loop (surplus chunks meet zeros in LDS).
+template <class P, int CB, int U>
+__global__ __launch_bounds__(256) void k_contract_adj_split(
+    const cplx16<typename P::S> *__restrict__ Hb, const float2 *__restrict__ Rs,
+    const unsigned *__restrict__ rmax, const int *__restrict__ gexp, float2 *__restrict__ B,
+    int NN, int NNp, int KK, int nkb, int nt)
 {
+    typedef typename P::S S;
+    typedef typename P::v4 V4;
     // LDS: per 16-c chunk and lane, 4 c values x {re hi, re lo, im hi, im lo}
-    extern __shared__ _Float16 ra[];
+    extern __shared__ unsigned short ra_bits[];
+    S *ra = reinterpret_cast<S *>(ra_bits);
     const int k = blockIdx.x, t0 = blockIdx.z * 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const int col = lane & 15, kg = lane >> 4;
     const int ncc = NNp / 16;
-    for (int idx = threadIdx.x; idx < ncc * 64 * 4; idx += blockDim.x) {
+    const int ncl = split_adj_chunks(ncc, U);
+    for (int idx = threadIdx.x; idx < ncl * 64 * 4; idx += blockDim.x) {
         const int e = idx % 4, l = (idx / 4) % 64, cc = idx / 256;
         const int c = 16 * cc + 4 * (l / 16) + e;
         const int tt = t0 + l % 16;
@@ -280,12 +339,12 @@ __global__ __launch_bounds__(256) void k_contract_adj_f16(
             v = Rs[((size_t)k * nt + tt) * NN + c];
             ex = f16_scale_exp(__uint_as_float(rmax[(size_t)k * nt + tt]));
         }
-        _Float16 h, lo;
-        _Float16 *dst = ra + ((size_t)(cc * 64 + l) * 4 + e) * 4;
-        split_f16(ldexpf(v.x, ex), h, lo);
+        S h, lo;
+        S *dst = ra + ((size_t)(cc * 64 + l) * 4 + e) * 4;
+        split_lohi<P>(ldexpf(v.x, ex), h, lo);
         dst[0] = h;
         dst[1] = lo;
-        split_f16(ldexpf(v.y, ex), h, lo);
+        split_lohi<P>(ldexpf(v.y, ex), h, lo);
         dst[2] = h;
         dst[3] = lo;
     }
@@ -305,7 +364,7 @@ __global__ __launch_bounds__(256) void k_contract_adj_f16(
         acci[b] = f32x4v{0.f, 0.f, 0.f, 0.f};
     }
     const size_t fbase = (size_t)k * ncc * nkb;
-    const int ngroups = (ncc + U - 1) / U;
+    const int ngroups = ncl / U;
     uint4 gb0[U][CB], gb1[U][CB];
     auto load_group = [&](int grp, uint4(&gb)[U][CB]) {
 #pragma unroll
@@ -321,10 +380,8 @@ __global__ __launch_bounds__(256) void k_contract_adj_f16(
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int cc = grp * U + u;
-            if (cc >= ncc)
-                break;
-            const _Float16 *src = ra + (size_t)(cc * 64 + lane) * 16;
-            f16x4 rrh, rrl, rih, ril;
+            const S *src = ra + (size_t)(cc * 64 + lane) * 16;
+            V4 rrh, rrl, rih, ril;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 rrh[e] = src[4 * e + 0];
@@ -332,39 +389,50 @@ __global__ __launch_bounds__(256) void k_contract_adj_f16(
                 rih[e] = src[4 * e + 2];
                 ril[e] = src[4 * e + 3];
             }
-            const f16x4 nrrh = -rrh, nrrl = -rrl;
+            const V4 nrrh = neg16<V4, u16x4>(rrh), nrrl = neg16<V4, u16x4>(rrl);
+            V4 gr[CB], gi[CB];
 #pragma unroll
             for (int b = 0; b < CB; ++b) {
-                const half2c *hp = reinterpret_cast<const half2c *>(&gb[u][b]);
-                f16x4 gr, gi;
+                const cplx16<S> *hp = reinterpret_cast<const cplx16<S> *>(&gb[u][b]);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    gr[e] = hp[e].re;
-                    gi[e] = hp[e].im;
+                    gr[b][e] = hp[e].re;
+                    gi[b][e] = hp[e].im;
                 }
-                // conj(G) R = (Gr Rr + Gi Ri) + i (Gr Ri - Gi Rr)
-                accr[b] = mfma_h16(rrh, gr, accr[b]);
-                accr[b] = mfma_h16(rrl, gr, accr[b]);
-                accr[b] = mfma_h16(rih, gi, accr[b]);
-                accr[b] = mfma_h16(ril, gi, accr[b]);
-                acci[b] = mfma_h16(rih, gr, acci[b]);
-                acci[b] = mfma_h16(ril, gr, acci[b]);
-                acci[b] = mfma_h16(nrrh, gi, acci[b]);
-                acci[b] = mfma_h16(nrrl, gi, acci[b]);
+            }
+            // conj(G) R = (Gr Rr + Gi Ri) + i (Gr Ri - Gi Rr), product-major
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                accr[b] = P::m16(rrh, gr[b], accr[b]);
+                acci[b] = P::m16(rih, gr[b], acci[b]);
+            }
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                accr[b] = P::m16(rrl, gr[b], accr[b]);
+                acci[b] = P::m16(ril, gr[b], acci[b]);
+            }
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                accr[b] = P::m16(rih, gi[b], accr[b]);
+                acci[b] = P::m16(nrrh, gi[b], acci[b]);
+            }
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                accr[b] = P::m16(ril, gi[b], accr[b]);
+                acci[b] = P::m16(nrrl, gi[b], acci[b]);
             }
         }
     };
-    if (ngroups > 0)
-        load_group(0, gb0);
+    load_group(0, gb0);
     for (int grp = 0; grp < ngroups; grp += 2) {
-        if (grp + 1 < ngroups)
-            load_group(grp + 1, gb1);
+        load_group(grp + 1, gb1);
+        __builtin_amdgcn_sched_barrier(0);
         compute_group(grp, gb0);
-        if (grp + 1 < ngroups) {
-            if (grp + 2 < ngroups)
-                load_group(grp + 2, gb0);
-            compute_group(grp + 1, gb1);
-        }
+        __builtin_amdgcn_sched_barrier(0);
+        load_group(grp + 2, gb0);
+        __builtin_amdgcn_sched_barrier(0);
+        compute_group(grp + 1, gb1);
+        __builtin_amdgcn_sched_barrier(0);
     }
     float2 *bk = B + (size_t)k * nt * KK;
     const int gx = gexp[k];

@@ -433,7 +433,7 @@ __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-#include "contract_f16.hpp"
+#include "contract_split.hpp"
 
 // Spectra in fragment order.  One load instruction of a wave then reads one
 // contiguous kilobyte: each lane takes 16 bytes, the two complex values it
@@ -1348,9 +1348,10 @@ struct lfrl_plan_s {
     size_t lds_r2c_bytes = 0, lds_c2r_bytes = 0;
     bool use_fft = false;  // tile DFTs by the register FFT kernels
     int fwd_cb = 3, fwd_u = 4, adj_cb = 4, adj_u = 4;  // contraction launch shapes
-    bool split = false;                 // split FP16 spectra (LFRL_SPLIT_FP16)
+    bool split = false;                 // split precision: 16-bit spectra (FP16 or BF16)
+    bool bf16 = false;                  // ... in BF16 (LFRL_SPLIT_BF16)
     int hfwd_cb = 3, hfwd_u = 1, hadj_cb = 4, hadj_u = 2;  // their contraction shapes
-    half2c *Hf = nullptr, *Hb = nullptr;  // FP16 spectra in fragment order
+    cplx16<_Float16> *Hf = nullptr, *Hb = nullptr;  // 16-bit spectra in fragment order
     int *gexp = nullptr;                // per-frequency exponents of the FP16 spectra
     unsigned *xmax = nullptr, *rmax = nullptr;  // per-(frequency, tile) maxima of tile spectra
     int thr_r2c = 256, thr_c2r = 256;
@@ -1391,7 +1392,8 @@ static int validate_desc(const lfrl_plan_desc *d)
         return set_error(LFRL_ERR_UNSUPPORTED, "nnum^2 must be <= %d", kMaxNN);
     if (d->max_h < d->nnum || d->max_w < d->nnum || d->max_h % d->nnum || d->max_w % d->nnum)
         return set_error(LFRL_ERR_ARG, "max_h/max_w must be positive multiples of nnum");
-    if (d->precision != LFRL_FP32 && d->precision != LFRL_SPLIT_FP16)
+    if (d->precision != LFRL_FP32 && d->precision != LFRL_SPLIT_FP16 &&
+        d->precision != LFRL_SPLIT_BF16)
         return set_error(LFRL_ERR_UNSUPPORTED, "precision %d not supported", d->precision);
     if (d->flags & ~(uint32_t)LFRL_PLAN_AUTOTUNE)
         return set_error(LFRL_ERR_ARG, "unknown plan flags 0x%x", d->flags);
@@ -1447,7 +1449,7 @@ static int rank_q(const lfrl_plan_desc *d, size_t lds_max, std::vector<int> *out
         if (lds_r2c(gq) > lds_max || lds_c2r(gq) > lds_max)
             return set_error(LFRL_ERR_UNSUPPORTED, "tile_q %d needs more LDS than available",
                              d->tile_q);
-        if (d->precision == LFRL_SPLIT_FP16 && !fft_usable(gq, lds_max))
+        if (d->precision != LFRL_FP32 && !fft_usable(gq, lds_max))
             return set_error(LFRL_ERR_UNSUPPORTED, "split FP16 needs an FFT tile size (tile_q %d)",
                              d->tile_q);
         out->push_back(d->tile_q);
@@ -1459,7 +1461,7 @@ static int rank_q(const lfrl_plan_desc *d, size_t lds_max, std::vector<int> *out
         geo_init(gq, d->nnum, d->nz, d->ksize, q);
         if (lds_r2c(gq) > lds_max || lds_c2r(gq) > lds_max)
             continue;
-        if (d->precision == LFRL_SPLIT_FP16 && !fft_usable(gq, lds_max))
+        if (d->precision != LFRL_FP32 && !fft_usable(gq, lds_max))
             continue;  // the split path takes its row scales from the FFT tile kernels
         const Tiles t = tiles_for(gq, d->max_h, d->max_w);
         ranked.push_back({model_time(gq, t), q});
@@ -1638,8 +1640,8 @@ static Sizes sizes_for(const Geo &g, int max_h, int max_w, int max_batch, int sp
     s.frame = frame_layout(g, max_h, max_w, false, off);
     if (f16) {
         s.split = true;
-        s.Hf = (size_t)g.nf * g.KKs * g.NNp * sizeof(half2c);
-        s.Hb = (size_t)g.nf * g.NNp * ((g.KK + 15) / 16 * 16) * sizeof(half2c);
+        s.Hf = (size_t)g.nf * g.KKs * g.NNp * sizeof(cplx16<_Float16>);
+        s.Hb = (size_t)g.nf * g.NNp * ((g.KK + 15) / 16 * 16) * sizeof(cplx16<_Float16>);
         s.gexp = (size_t)g.nf * sizeof(int);
         s.rowmax = (size_t)g.nf * nt * sizeof(unsigned);
     }
@@ -1687,7 +1689,7 @@ extern "C" int lfrl_plan_footprint(const lfrl_plan_desc *desc, size_t *resident_
         Geo g;
         geo_init(g, desc->nnum, desc->nz, desc->ksize, cands[i]);
         const Sizes s = sizes_for(g, desc->max_h, desc->max_w, desc->max_batch, pick_split(g),
-                                  desc->precision == LFRL_SPLIT_FP16);
+                                  desc->precision != LFRL_FP32);
         if (!s.indexable())
             return set_error(LFRL_ERR_UNSUPPORTED, "tile workspace above 2^32 complex values "
                                                    "(lower max_batch or the image size)");
@@ -1915,7 +1917,8 @@ static int plan_build(lfrl_plan_s **out, const lfrl_plan_desc *desc, int q, cons
     p->frame_tiles = tiles_for(g, desc->max_h, desc->max_w).nt;
     p->max_tiles = p->frame_tiles * std::max(1, (int)desc->max_batch);
     p->split_k = pick_split(g);
-    p->split = desc->precision == LFRL_SPLIT_FP16;
+    p->split = desc->precision != LFRL_FP32;
+    p->bf16 = desc->precision == LFRL_SPLIT_BF16;
     const Sizes s = sizes_for(g, p->max_h, p->max_w, desc->max_batch, p->split_k, p->split);
     if (!s.indexable()) {
         delete p;
@@ -2029,15 +2032,25 @@ static int plan_build(lfrl_plan_s **out, const lfrl_plan_desc *desc, int q, cons
         e = hipGetLastError();
     }
     if (e == hipSuccess && p->split) {
-        // FP16 fragments with per-frequency power-of-two scales
+        // 16-bit fragments with per-frequency power-of-two scales
         hipLaunchKernelGGL(k_spec_exp, dim3(g.nf), dim3(256), 0, st, (const float2 *)p->Gf,
                            (size_t)g.KK * g.NNp, p->gexp);
-        const size_t nhf = s.Hf / sizeof(half2c), nhb = s.Hb / sizeof(half2c);
-        hipLaunchKernelGGL(k_pack_fwd_f16, dim3(8192), dim3(256), 0, st, (const float2 *)p->Gf,
-                           g.KK, g.NNp, g.KKs / 32, (const int *)p->gexp, p->Hf, nhf);
-        hipLaunchKernelGGL(k_pack_adj_f16, dim3(8192), dim3(256), 0, st, (const float2 *)p->Gb,
-                           g.NN, g.KK, g.NNp / 16, (g.KK + 15) / 16, (const int *)p->gexp, p->Hb,
-                           nhb);
+        const size_t nhf = s.Hf / sizeof(cplx16<_Float16>), nhb = s.Hb / sizeof(cplx16<_Float16>);
+        if (p->bf16) {
+            hipLaunchKernelGGL(k_pack_fwd_split<PrecBF16>, dim3(8192), dim3(256), 0, st,
+                               (const float2 *)p->Gf, g.KK, g.NNp, g.KKs / 32,
+                               (const int *)p->gexp, (cplx16<__bf16> *)p->Hf, nhf);
+            hipLaunchKernelGGL(k_pack_adj_split<PrecBF16>, dim3(8192), dim3(256), 0, st,
+                               (const float2 *)p->Gb, g.NN, g.KK, g.NNp / 16, (g.KK + 15) / 16,
+                               (const int *)p->gexp, (cplx16<__bf16> *)p->Hb, nhb);
+        } else {
+            hipLaunchKernelGGL(k_pack_fwd_split<PrecF16>, dim3(8192), dim3(256), 0, st,
+                               (const float2 *)p->Gf, g.KK, g.NNp, g.KKs / 32,
+                               (const int *)p->gexp, p->Hf, nhf);
+            hipLaunchKernelGGL(k_pack_adj_split<PrecF16>, dim3(8192), dim3(256), 0, st,
+                               (const float2 *)p->Gb, g.NN, g.KK, g.NNp / 16, (g.KK + 15) / 16,
+                               (const int *)p->gexp, p->Hb, nhb);
+        }
         e = hipGetLastError();
     } else if (e == hipSuccess) {
         // FP32 fragments
@@ -2266,17 +2279,23 @@ static int run_forward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipSt
     }
     bool launched = false;
     if (p->split) {
+#define LFRL_HFWD_LAUNCH(PT, CBV, UV)                                                            \
+    hipLaunchKernelGGL((k_contract_fwd_split<PT, CBV, UV>), grid, block, 0, st,                  \
+                       (const cplx16<PT::S> *)p->Hf, (const float2 *)p->X,                       \
+                       (const unsigned *)p->xmax, (const int *)p->gexp, p->Yp, g.NN, g.NNp,     \
+                       g.KK, g.KKs, g.KKs / 32, nt, g.nf, kchunk)
 #define LFRL_HFWD_CASE(CBV, UV)                                                                  \
     if (p->hfwd_cb == CBV && p->hfwd_u == UV) {                                                  \
-        hipLaunchKernelGGL((k_contract_fwd_f16<CBV, UV>), grid, block, 0, st,                    \
-                           (const half2c *)p->Hf, (const float2 *)p->X, (const unsigned *)p->xmax,\
-                           (const int *)p->gexp, p->Yp, g.NN, g.NNp, g.KK, g.KKs, g.KKs / 32,    \
-                           nt, g.nf, kchunk);                                                    \
+        if (p->bf16)                                                                             \
+            LFRL_HFWD_LAUNCH(PrecBF16, CBV, UV);                                                 \
+        else                                                                                     \
+            LFRL_HFWD_LAUNCH(PrecF16, CBV, UV);                                                  \
         launched = true;                                                                         \
     }
         LFRL_HFWD_CASE(1, 1) LFRL_HFWD_CASE(1, 2) LFRL_HFWD_CASE(2, 1) LFRL_HFWD_CASE(2, 2)
         LFRL_HFWD_CASE(3, 1)
 #undef LFRL_HFWD_CASE
+#undef LFRL_HFWD_LAUNCH
     } else {
     LFRL_FWD_CASES(2) LFRL_FWD_CASES(3) LFRL_FWD_CASE(4, 1) LFRL_FWD_CASE(4, 2)
     LFRL_FWD_CASE(5, 1) LFRL_FWD_CASE(5, 2)
@@ -2341,7 +2360,8 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
     // 8 * adj_u reduction indices (as the kernel assumes), row stride kRsStride
     const int ustep = 8 * p->adj_u;
     const int agroups = ((g.NCp + ustep - 1) / ustep + 1) / 2 * 2;
-    const size_t lds = p->split ? (size_t)(g.NNp / 16) * 64 * 16 * sizeof(_Float16)
+    // split: 16-c chunks of hi/lo R values, 2 KB each (split_adj_chunks)
+    const size_t lds = p->split ? (size_t)split_adj_chunks(g.NNp / 16, p->hadj_u) * 64 * 16 * 2
                                 : (size_t)agroups * ustep * kRsStride * sizeof(float2);
     if (p->prof) {
         int rc = prof_event(p, 1, st);
@@ -2350,15 +2370,22 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
     }
     bool launched = false;
     if (p->split) {
+#define LFRL_HADJ_LAUNCH(PT, CBV, UV)                                                            \
+    hipLaunchKernelGGL((k_contract_adj_split<PT, CBV, UV>), grid, dim3(64 * kAdjWaves), lds, st, \
+                       (const cplx16<PT::S> *)p->Hb, (const float2 *)p->Rs,                      \
+                       (const unsigned *)p->rmax, (const int *)p->gexp, p->X, g.NN, g.NNp,      \
+                       g.KK, (g.KK + 15) / 16, nt)
 #define LFRL_HADJ_CASE(CBV, UV)                                                                  \
     if (p->hadj_cb == CBV && p->hadj_u == UV) {                                                  \
-        hipLaunchKernelGGL((k_contract_adj_f16<CBV, UV>), grid, dim3(64 * kAdjWaves), lds, st,   \
-                           (const half2c *)p->Hb, (const float2 *)p->Rs, (const unsigned *)p->rmax,\
-                           (const int *)p->gexp, p->X, g.NN, g.NNp, g.KK, (g.KK + 15) / 16, nt); \
+        if (p->bf16)                                                                             \
+            LFRL_HADJ_LAUNCH(PrecBF16, CBV, UV);                                                 \
+        else                                                                                     \
+            LFRL_HADJ_LAUNCH(PrecF16, CBV, UV);                                                  \
         launched = true;                                                                         \
     }
         LFRL_HADJ_CASE(2, 2) LFRL_HADJ_CASE(2, 4) LFRL_HADJ_CASE(4, 2) LFRL_HADJ_CASE(4, 4)
 #undef LFRL_HADJ_CASE
+#undef LFRL_HADJ_LAUNCH
     } else {
     LFRL_ADJ_CASES(2) LFRL_ADJ_CASES(4)
     }

@@ -1,9 +1,10 @@
-"""Split-FP16 precision mode against the float64 oracle (needs an MI355X).
+"""Split precision modes against the float64 oracle (needs an MI355X).
 
-FP16 PSF spectra (per-frequency power-of-two scale) and hi/lo-split FP16 tile
-spectra on matrix cores with FP32 accumulation.  Bar: relative L2 error
-<= 1e-3 against the oracle, for single projections and for every iterate of a
-30-iteration deconvolution of the Nnum 5, 55 x 55, 5-plane workload."""
+16-bit PSF spectra (FP16 or BF16, per-frequency power-of-two scale) and
+hi/lo-split 16-bit tile spectra on matrix cores with FP32 accumulation.  Bar:
+relative L2 error <= 1e-3 against the oracle, for single projections and for
+every iterate of a 30-iteration deconvolution of the Nnum 5, 55 x 55,
+5-plane workload."""
 import numpy as np
 import pytest
 
@@ -34,27 +35,32 @@ def rel_l2(got, want):
     return float(np.linalg.norm(got - want) / np.linalg.norm(want))
 
 
+PRECS = [pytest.param(1, id="fp16"), pytest.param(2, id="bf16")]
+
+
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n,ly,lx,nz,k,q", [(5, 11, 11, 5, 25, 0), (5, 11, 11, 5, 25, 10),
                                             (3, 7, 9, 3, 11, 0), (15, 4, 4, 2, 31, 0),
                                             (1, 20, 17, 3, 7, 0)])
-def test_projections_split(lf, n, ly, lx, nz, k, q):
+def test_projections_split(lf, n, ly, lx, nz, k, q, prec):
     psf = S.gaussian_psf(n, nz, k, seed=40 + n, shift_scale=None)
     h, w = n * ly, n * lx
     rng = np.random.default_rng(41)
     x = rng.uniform(0.0, 1.0, size=(nz, h, w)).astype(np.float32)
     y = rng.uniform(0.0, 1.0, size=(h, w)).astype(np.float32)
-    plan = lf.Plan(to_dev(psf), h, w, tile_q=q, precision=lf.SPLIT_FP16)
+    plan = lf.Plan(to_dev(psf), h, w, tile_q=q, precision=prec)
     try:
         ef = rel_l2(plan.forward(to_dev(x)).cpu().numpy(), oracle.forward(psf, x))
         eb = rel_l2(plan.backward(to_dev(y)).cpu().numpy(), oracle.backward(psf, y))
-        print(f"split FP16 N={n} {h}x{w} nz={nz} K={k} Q={plan.info['tile_q']}: "
+        print(f"split {'BF16' if prec == 2 else 'FP16'} N={n} {h}x{w} nz={nz} K={k} Q={plan.info['tile_q']}: "
               f"forward {ef:.2e}, backward {eb:.2e}", flush=True)
         assert ef <= TOL and eb <= TOL
     finally:
         plan.close()
 
 
-def test_rl_30_iterations_split(lf):
+@pytest.mark.parametrize("prec", PRECS)
+def test_rl_30_iterations_split(lf, prec):
     """Per-iteration relative L2 error vs the oracle over 30 iterations."""
     import torch
     p = S.preset("small")
@@ -62,7 +68,7 @@ def test_rl_30_iterations_split(lf):
     psf = p["psf_array"]
     y = S.measure(oracle.forward(psf, p["x_true"]), p["peak"], p["background"], p["noise_seed"])
     ref = oracle.rl(psf, y, 30, keep_all=True)
-    plan = lf.Plan(to_dev(psf), g.h, g.w, precision=lf.SPLIT_FP16)
+    plan = lf.Plan(to_dev(psf), g.h, g.w, precision=prec)
     errs = []
     try:
         for it in (1, 2, 5, 10, 20, 30):
@@ -71,7 +77,8 @@ def test_rl_30_iterations_split(lf):
             errs.append((it, rel_l2(vol.cpu().numpy(), ref[it])))
     finally:
         plan.close()
-    print("split FP16 per-iteration rel L2:", ", ".join(f"{i}:{e:.2e}" for i, e in errs), flush=True)
+    print(f"split {'BF16' if prec == 2 else 'FP16'} per-iteration rel L2:",
+          ", ".join(f"{i}:{e:.2e}" for i, e in errs), flush=True)
     assert max(e for _, e in errs) <= TOL
 
 
