@@ -1068,7 +1068,8 @@ static size_t lds_r2c_fft(const Geo &g)
 
 static size_t lds_c2r_fft(const Geo &g)
 {
-    return (size_t)g.Q * g.QH * g.N * 8 + (size_t)g.T * g.QH * g.N * 8 + (size_t)g.Q * 8;
+    // twiddles, the T valid rows of the column inverse, the output tile
+    return (size_t)g.Q * 8 + (size_t)g.T * g.QH * g.N * 8 + (size_t)g.T * g.T * g.N * 4;
 }
 
 static int round64(int v)
@@ -1618,8 +1619,6 @@ struct Sizes {
     size_t Hf = 0, Hb = 0, gexp = 0, rowmax = 0;  // split FP16 only
     bool split = false;
     size_t resident() const { return (split ? Hf + Hb + gexp : Ff + Fb) + tw + psf; }
-    // the inverse tile DFT addresses tile spectra with 32-bit offsets
-    bool indexable() const { return X / sizeof(float2) < (1ull << 32) && Yp / sizeof(float2) < (1ull << 32); }
     size_t workspace() const { return X + Yp + Rs + 2 * rowmax + frame; }
 };
 
@@ -1690,9 +1689,6 @@ extern "C" int lfrl_plan_footprint(const lfrl_plan_desc *desc, size_t *resident_
         geo_init(g, desc->nnum, desc->nz, desc->ksize, cands[i]);
         const Sizes s = sizes_for(g, desc->max_h, desc->max_w, desc->max_batch, pick_split(g),
                                   desc->precision != LFRL_FP32);
-        if (!s.indexable())
-            return set_error(LFRL_ERR_UNSUPPORTED, "tile workspace above 2^32 complex values "
-                                                   "(lower max_batch or the image size)");
         res = std::max(res, s.resident());
         ws = std::max(ws, s.workspace());
     }
@@ -1920,11 +1916,6 @@ static int plan_build(lfrl_plan_s **out, const lfrl_plan_desc *desc, int q, cons
     p->split = desc->precision != LFRL_FP32;
     p->bf16 = desc->precision == LFRL_SPLIT_BF16;
     const Sizes s = sizes_for(g, p->max_h, p->max_w, desc->max_batch, p->split_k, p->split);
-    if (!s.indexable()) {
-        delete p;
-        return set_error(LFRL_ERR_UNSUPPORTED, "tile workspace above 2^32 complex values "
-                                               "(lower max_batch or the image size)");
-    }
     p->resident = s.resident();
     p->workspace = s.workspace();
     p->use_fft = fft_usable(g, lmax);

@@ -139,7 +139,6 @@ enum { SRC_PLANES = 0, SRC_PSF = 1 };
 // select, which the compiler would turn into a branch around the load).
 // (deeper batches were measured slower: fewer blocks fit per CU)
 static constexpr int kGatherBatch = 8;   // forward tile gather (floats per thread)
-static constexpr int kSpecBatch = 8;     // inverse: spectrum staging (complex per thread)
 static constexpr int kEpiBatch = 8;      // inverse: epilogue pixels per thread
 
 // Frames whose tiles one launch covers.  Tiles of all frames are numbered
@@ -354,9 +353,8 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
     constexpr int QH = Q / 2 + 1;
     extern __shared__ float smem[];
     float2 *tw = reinterpret_cast<float2 *>(smem);
-    float2 *X = tw + Q;
-    float2 *Zs = X + (size_t)Q * QH * N;
-    float *obuf = reinterpret_cast<float *>(X);  // reused once X is consumed
+    float2 *Zs = tw + Q;                                    // [T][QH][N]
+    float *obuf = reinterpret_cast<float *>(Zs + (size_t)T * QH * N);  // [T][T][N]
     const int tid = threadIdx.x;
     const int item = xcd_item(blockIdx.x, gridDim.x);
     const int tile = item / (planes * N), jar = item % (planes * N);
@@ -369,47 +367,36 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
     const float *__restrict__ aux1 = fj.aux1;
     for (int i = tid; i < Q; i += blockDim.x)
         tw[i] = twg[i];
-    const size_t kkbase = (size_t)j * N * N + (size_t)ar * N;
-    const int total = Q * QH * N;
-    // spectrum offsets fit in 32 bits (the workspace holds fewer than 2^32
-    // complex values), which keeps the deeper batches in registers
-    for (int base = tid; base < total; base += kSpecBatch * blockDim.x) {
-        float2 acc[kSpecBatch];
-        unsigned off[kSpecBatch];
-#pragma unroll
-        for (int b = 0; b < kSpecBatch; ++b) {
-            const int idx = min(base + b * (int)blockDim.x, total - 1);
-            const int p = idx % N;
-            const size_t k = idx / N;
-            off[b] = (unsigned)(k * sk + tile * stile + (kkbase + p) * sc);
-            acc[b] = spec[off[b]];
-        }
-        for (int s = 1; s < nsplit; ++s) {
-            float2 part[kSpecBatch];
-#pragma unroll
-            for (int b = 0; b < kSpecBatch; ++b)
-                part[b] = spec[off[b] + s * split_stride];
-#pragma unroll
-            for (int b = 0; b < kSpecBatch; ++b) {
-                acc[b].x += part[b].x;
-                acc[b].y += part[b].y;
-            }
-        }
-#pragma unroll
-        for (int b = 0; b < kSpecBatch; ++b) {
-            const int idx = base + b * (int)blockDim.x;
-            if (idx < total)
-                X[idx] = acc[b];
-        }
-    }
     __syncthreads();
+    const size_t kkbase = (size_t)j * N * N + (size_t)ar * N;
     float2 v[Q];
-    // inverse along tile rows (ku -> i), keeping the T valid rows
+    // inverse along tile rows (ku -> i) for column (kv, p), keeping the T valid
+    // rows: each thread loads its Q spectrum values straight from memory (Q
+    // independent loads in flight, no staging buffer), summing split partials
     if (tid < QH * N) {
         const int kv = tid / N, p = tid % N;
+        const size_t base = tile * stile + (kkbase + p) * sc;
 #pragma unroll
         for (int ku = 0; ku < Q; ++ku)
-            v[ku] = X[((size_t)ku * QH + kv) * N + p];
+            v[ku] = spec[(size_t)(ku * QH + kv) * sk + base];
+        for (int s = 1; s < nsplit; ++s) {
+            // partials in chunks of 8 loads (a second Q-long array would spill)
+#pragma unroll
+            for (int k0 = 0; k0 < Q; k0 += 8) {
+                float2 part[8];
+#pragma unroll
+                for (int d = 0; d < 8; ++d)
+                    if (k0 + d < Q)
+                        part[d] = spec[(size_t)s * split_stride +
+                                       (size_t)((k0 + d) * QH + kv) * sk + base];
+#pragma unroll
+                for (int d = 0; d < 8; ++d)
+                    if (k0 + d < Q) {
+                        v[k0 + d].x += part[d].x;
+                        v[k0 + d].y += part[d].y;
+                    }
+            }
+        }
         tfft::fft<Q, 1>(v, tw);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
