@@ -1060,10 +1060,17 @@ static bool fft_supported(int Q)
     }
 }
 
+// LDS of the forward tile DFT: the PSF mode stages its input tile; the planes
+// mode needs only the half spectrum Z (plus twiddles and row maxima).
 static size_t lds_r2c_fft(const Geo &g)
 {
     const size_t a = (size_t)g.Q * g.Q * g.N * 4, b = (size_t)g.Q * g.QH * g.N * 8;
     return std::max(a, b) + (size_t)g.Q * 8 + (size_t)g.Q * g.QH * 4;  // + row maxima
+}
+
+static size_t lds_r2c_fft_planes(const Geo &g)
+{
+    return (size_t)g.Q * g.QH * g.N * 8 + (size_t)g.Q * 8 + (size_t)g.Q * g.QH * 4;
 }
 
 static size_t lds_c2r_fft(const Geo &g)
@@ -1346,7 +1353,7 @@ struct lfrl_plan_s {
     std::vector<SensEntry> sens_cache;
     size_t sens_cache_bytes = 0, sens_cache_limit = 0;
     unsigned long long sens_clock = 0;
-    size_t lds_r2c_bytes = 0, lds_c2r_bytes = 0;
+    size_t lds_r2c_bytes = 0, lds_c2r_bytes = 0, lds_r2c_vol_bytes = 0;
     bool use_fft = false;  // tile DFTs by the register FFT kernels
     int fwd_cb = 3, fwd_u = 4, adj_cb = 4, adj_u = 4;  // contraction launch shapes
     bool split = false;                 // split precision: 16-bit spectra (FP16 or BF16)
@@ -1945,11 +1952,12 @@ static int plan_build(lfrl_plan_s **out, const lfrl_plan_desc *desc, int q, cons
     }
     if (p->use_fft) {
         p->lds_r2c_bytes = lds_r2c_fft(g);
+        p->lds_r2c_vol_bytes = lds_r2c_fft_planes(g);
         p->lds_c2r_bytes = lds_c2r_fft(g);
         p->thr_r2c = threads_r2c_fft(g);
         p->thr_c2r = threads_c2r_fft(g);
     } else {
-        p->lds_r2c_bytes = lds_r2c(g);
+        p->lds_r2c_bytes = p->lds_r2c_vol_bytes = lds_r2c(g);
         p->lds_c2r_bytes = lds_c2r(g);
     }
     if (!timing) {
@@ -2247,7 +2255,7 @@ static int run_forward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipSt
         LAUNCH_CHECK("k_zero_u32n");
     }
     if (p->use_fft)
-        launch_r2c_fft(g.Q, dim3(nt * g.Nz * g.N), p->thr_r2c, p->lds_r2c_bytes, st, SRC_PLANES,
+        launch_r2c_fft(g.Q, dim3(nt * g.Nz * g.N), p->thr_r2c, p->lds_r2c_vol_bytes, st, SRC_PLANES,
                        batch, nullptr, g.N, g.T, g.hD, nt, g.KKs, g.K, g.c0, g.KK, p->X, p->tw,
                        p->split ? p->xmax : nullptr);
     else
@@ -2329,7 +2337,7 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
         LAUNCH_CHECK("k_zero_u32n");
     }
     if (p->use_fft)
-        launch_r2c_fft(g.Q, dim3(nt * g.N), p->thr_r2c, p->lds_r2c_bytes, st, SRC_PLANES, batch,
+        launch_r2c_fft(g.Q, dim3(nt * g.N), p->thr_r2c, p->lds_r2c_vol_bytes, st, SRC_PLANES, batch,
                        nullptr, g.N, g.T, g.hD, nt, g.NN, g.K, g.c0, g.KK, p->Rs, p->tw,
                        p->split ? p->rmax : nullptr);
     else

@@ -138,7 +138,7 @@ enum { SRC_PLANES = 0, SRC_PSF = 1 };
 // clamped to valid elements and unwanted values cleared with a bit mask (not a
 // select, which the compiler would turn into a branch around the load).
 // (deeper batches were measured slower: fewer blocks fit per CU)
-static constexpr int kGatherBatch = 8;   // forward tile gather (floats per thread)
+// The forward transform loads its rows straight into registers instead.
 static constexpr int kEpiBatch = 8;      // inverse: epilogue pixels per thread
 
 // Frames whose tiles one launch covers.  Tiles of all frames are numbered
@@ -188,7 +188,8 @@ __device__ __forceinline__ int xcd_item(int bid, int n)
 // out[obase + k * kstride + p], k = ku * (Q/2 + 1) + kv.
 //   SRC_PLANES: one overlap-save tile of lenslet rows (plane j, row phase ar)
 //               of a frame's [planes][H][W] array (frames and tiles from
-//               `batch`; `src` unused); 1-D grid of nt * planes * N blocks,
+//               `batch`; `src` unused), each row-pass thread loading its two
+//               rows straight from memory; 1-D grid of nt * planes * N blocks,
 //               work item = (j*N + ar) * nt + tile (tiles of one row phase,
 //               which overlap, land on one XCD).
 //               obase = (tile * KKo + j*N*N + ar*N), kstride = nt * KKo.
@@ -213,8 +214,10 @@ __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const TileBatch batch
     float2 *tw = reinterpret_cast<float2 *>(smem);
     float *buf = smem + 2 * Q;
     float2 *Z = reinterpret_cast<float2 *>(buf);
-    const size_t buf_floats = (size_t)Q * Q * N > (size_t)2 * Q * QH * N ? (size_t)Q * Q * N
-                                                                         : (size_t)2 * Q * QH * N;
+    // SRC_PLANES loads its rows straight from memory: buf holds only Z
+    const size_t zfloats = (size_t)2 * Q * QH * N;
+    const size_t buf_floats = (mode == SRC_PLANES || zfloats > (size_t)Q * Q * N)
+                                  ? zfloats : (size_t)Q * Q * N;
     unsigned *kmax = reinterpret_cast<unsigned *>(buf + buf_floats);  // [Q * QH]
     const int tid = threadIdx.x;
     for (int i = tid; i < Q; i += blockDim.x)
@@ -224,35 +227,21 @@ __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const TileBatch batch
             kmax[i] = 0u;
     const int rowlen = Q * N;
     size_t obase, kstride;
+    const float *plane = nullptr;
+    int H = 0, W = 0, ly0 = 0, lx0 = 0, arow = 0;
     if (mode == SRC_PLANES) {
         const int item = xcd_item(blockIdx.x, gridDim.x);
         const int tile = item % nt, jar = item / nt;
-        const int j = jar / N, ar = jar % N;
+        const int j = jar / N;
+        arow = jar % N;
         const TileJob &fj = batch.job[batch_job(batch, tile)];
-        const int H = fj.H, W = fj.W, lt = tile - fj.tile0;
-        const int ly0 = (lt / fj.tiles_x) * T - hD, lx0 = (lt % fj.tiles_x) * T - hD;
-        const float *plane = fj.src + (size_t)j * H * W;
-        const int total = Q * rowlen;
-        for (int base = tid; base < total; base += kGatherBatch * blockDim.x) {
-            float v[kGatherBatch];
-#pragma unroll
-            for (int b = 0; b < kGatherBatch; ++b) {
-                const int idx = min(base + b * (int)blockDim.x, total - 1);
-                const int i = idx / rowlen, col = idx % rowlen;
-                const int pr = N * (ly0 + i) + ar;
-                const int pc = N * lx0 + col;
-                const bool ok = pr >= 0 && pr < H && pc >= 0 && pc < W;
-                const float x = plane[(size_t)min(max(pr, 0), H - 1) * W + min(max(pc, 0), W - 1)];
-                v[b] = keep_if(x, ok);
-            }
-#pragma unroll
-            for (int b = 0; b < kGatherBatch; ++b) {
-                const int idx = base + b * (int)blockDim.x;
-                if (idx < total)
-                    buf[idx] = v[b];
-            }
-        }
-        obase = (size_t)tile * KKo + (size_t)j * N * N + (size_t)ar * N;
+        H = fj.H;
+        W = fj.W;
+        const int lt = tile - fj.tile0;
+        ly0 = (lt / fj.tiles_x) * T - hD;
+        lx0 = (lt % fj.tiles_x) * T - hD;
+        plane = fj.src + (size_t)j * H * W;
+        obase = (size_t)tile * KKo + (size_t)j * N * N + (size_t)arow * N;
         kstride = (size_t)nt * KKo;
     } else {
         const int cr = blockIdx.x, a = blockIdx.y, j = blockIdx.z;
@@ -286,11 +275,28 @@ __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const TileBatch batch
         s1 = (2 * tid + 1 < nseq) ? 2 * tid + 1 : -1;
         const int i0 = s0 / N, p0 = s0 % N;
         const int i1 = s1 >= 0 ? s1 / N : 0, p1 = s1 >= 0 ? s1 % N : 0;
+        if (mode == SRC_PLANES) {
+            // the two rows straight from the plane: 2Q independent loads,
+            // clamped addresses, values outside the image cleared by a mask
+            const int pr0 = N * (ly0 + i0) + arow, pr1 = N * (ly0 + i1) + arow;
+            const bool r0 = pr0 >= 0 && pr0 < H, r1 = s1 >= 0 && pr1 >= 0 && pr1 < H;
+            const float *row0 = plane + (size_t)min(max(pr0, 0), H - 1) * W;
+            const float *row1 = plane + (size_t)min(max(pr1, 0), H - 1) * W;
 #pragma unroll
-        for (int l = 0; l < Q; ++l) {
-            const float a = buf[(size_t)i0 * rowlen + l * N + p0];
-            const float b = s1 >= 0 ? buf[(size_t)i1 * rowlen + l * N + p1] : 0.f;
-            v[l] = make_float2(a, b);
+            for (int l = 0; l < Q; ++l) {
+                const int pc0 = N * (lx0 + l) + p0, pc1 = N * (lx0 + l) + p1;
+                const float a = row0[min(max(pc0, 0), W - 1)];
+                const float b = row1[min(max(pc1, 0), W - 1)];
+                v[l] = make_float2(keep_if(a, r0 && pc0 >= 0 && pc0 < W),
+                                   keep_if(b, r1 && pc1 >= 0 && pc1 < W));
+            }
+        } else {
+#pragma unroll
+            for (int l = 0; l < Q; ++l) {
+                const float a = buf[(size_t)i0 * rowlen + l * N + p0];
+                const float b = s1 >= 0 ? buf[(size_t)i1 * rowlen + l * N + p1] : 0.f;
+                v[l] = make_float2(a, b);
+            }
         }
     }
     __syncthreads();  // every row is in registers: Z may now overwrite buf
