@@ -28,6 +28,13 @@ notes):
 
 * RL update: x <- x * A^T(y / A x) / A^T 1, with y/Ax := 0 where Ax <= 0 and
   x := 0 where A^T 1 <= 0; ones initialisation.
+* Variants (the paper names none of them; they widen the method): a known
+  constant background b in the image model (A x + b), the ISRA update
+  x <- x * A^T y / A^T(A x + b), and the back projection A^T y as x^0.
+* Metric variants: the rectangle that Eq. (12)'s summation limits state, the
+  whole coefficient matrix (the overall entropy of Fig. 2(c)), each with the
+  prefactor 1 / area; the 2-norm over the region only instead of the whole
+  matrix.  A "decreasing trend" (sec. 2.2) may be read from window means.
 * Transposed PSF = exact adjoint of the forward projection.
 * DCT axes: Eq. (1) pairs u with the width and v with the height (X_S is the
   width of the region, Eq. (6)); F is stored as F[v][u] (row frequency first).
@@ -202,9 +209,14 @@ def normalize_psf(psf) -> np.ndarray:
 # --------------------------------------------------------------------------
 # Richardson-Lucy (sec. 1, sec. 2.1)
 # --------------------------------------------------------------------------
-def rl_step(psf, y, x, c):
-    """One Richardson-Lucy iteration; returns (x_new, yhat) where yhat = A x."""
-    yhat = forward(psf, x)
+def rl_step(psf, y, x, c, background: float = 0.0):
+    """One Richardson-Lucy iteration with a known constant background b >= 0 in
+    the image model (b = 0: the plain update):
+
+        m = A x + b,   x_new = x * A^T(y / m) / c,
+
+    y / m := 0 where m <= 0 and x_new := 0 where c <= 0.  Returns (x_new, m)."""
+    yhat = forward(psf, x) + background
     ratio = np.zeros_like(yhat)
     pos = yhat > 0
     ratio[pos] = y[pos] / yhat[pos]
@@ -215,19 +227,57 @@ def rl_step(psf, y, x, c):
     return x_new, yhat
 
 
-def rl(psf, y, iters: int, x0=None, keep_all: bool = False):
-    """Run ``iters`` Richardson-Lucy iterations from ``x0`` (ones by default).
+def isra_step(psf, y, x, d, background: float = 0.0):
+    """One ISRA iteration (the least-squares counterpart of the update, used
+    under the Richardson-Lucy name in light-field work):
+
+        m = A x + b,   x_new = x * d / A^T m,   d = A^T y,
+
+    x_new := 0 where A^T m <= 0.  Returns (x_new, m)."""
+    yhat = forward(psf, x) + background
+    den = backward(psf, yhat)
+    x_new = np.zeros_like(x)
+    ok = den > 0
+    x_new[ok] = x[ok] * d[ok] / den[ok]
+    return x_new, yhat
+
+
+def initial_volume(psf, y, init: str = "ones", x0=None) -> np.ndarray:
+    """x^0: 'ones', 'given' (a copy of x0) or 'backprojection' (A^T y)."""
+    nz = np.asarray(psf).shape[0]
+    h, w = np.asarray(y).shape
+    if init == "ones":
+        return np.ones((nz, h, w))
+    if init == "given":
+        return np.array(x0, dtype=np.float64)
+    if init == "backprojection":
+        return backward(psf, np.asarray(y, dtype=np.float64))
+    raise ValueError(f"unknown init {init!r}")
+
+
+def rl(psf, y, iters: int, x0=None, keep_all: bool = False, *, update: str = "rl",
+       background: float = 0.0, init: str = None):
+    """Run ``iters`` iterations of the update ('rl' or 'isra') from x^0: ``x0``
+    when given, else ones (or ``init``, see initial_volume).
 
     Returns the final iterate, or the list [x^0, x^1, ..., x^iters] when
     ``keep_all``."""
     y = np.asarray(y, dtype=np.float64)
-    nz = np.asarray(psf).shape[0]
     h, w = y.shape
-    c = sensitivity(psf, h, w)
-    x = np.ones((nz, h, w)) if x0 is None else np.array(x0, dtype=np.float64)
+    if init is None:
+        init = "ones" if x0 is None else "given"
+    x = initial_volume(psf, y, init, x0)
+    if update == "rl":
+        c = sensitivity(psf, h, w)
+        step = lambda x: rl_step(psf, y, x, c, background)[0]  # noqa: E731
+    elif update == "isra":
+        d = backward(psf, y)
+        step = lambda x: isra_step(psf, y, x, d, background)[0]  # noqa: E731
+    else:
+        raise ValueError(f"unknown update {update!r}")
     out = [x]
     for _ in range(iters):
-        x, _ = rl_step(psf, y, x, c)
+        x = step(x)
         out.append(x)
     return out if keep_all else x
 
@@ -274,41 +324,85 @@ def triangle_mask(h: int, w: int, xs: float, ys: float) -> np.ndarray:
     return (u / xs + v / ys) < 1.0
 
 
-def dct_entropy(img, xs: float, ys: float) -> float:
-    """DCT entropy of a 2-D image (Eq. 12): with F the DCT of the image and
-    n = ||F|| (Frobenius, whole matrix), p = |F| / n over S and
-    e = -(2 / (X_S Y_S)) * sum_S p log2 p (0 log 0 = 0).  Returns 0 for an
-    all-zero image."""
+REGIONS = ("triangle", "rectangle", "whole")
+
+
+def region_mask(h: int, w: int, xs: float, ys: float, region: str = "triangle") -> np.ndarray:
+    """Coefficients the entropy sums over: the triangle of Eq. (6), the
+    rectangle u < X_S, v < Y_S that the summation limits of Eq. (12) literally
+    state, or the whole matrix (the overall entropy of Fig. 2(c))."""
+    if region == "triangle":
+        return triangle_mask(h, w, xs, ys)
+    if region == "rectangle":
+        if not (xs > 0 and ys > 0):
+            raise ValueError("rectangle sides must be positive")
+        v = np.arange(h, dtype=np.float64)[:, None]
+        u = np.arange(w, dtype=np.float64)[None, :]
+        return (u < xs) & (v < ys)
+    if region == "whole":
+        return np.ones((h, w), dtype=bool)
+    raise ValueError(f"unknown region {region!r}")
+
+
+def region_area(h: int, w: int, xs: float, ys: float, region: str = "triangle") -> float:
+    """Area G of the region (the entropy's prefactor is 1 / G): X_S Y_S / 2 for
+    the triangle (Eq. 6), X_S Y_S for the rectangle, W H for the whole matrix."""
+    return {"triangle": xs * ys / 2.0, "rectangle": xs * ys, "whole": float(h * w)}[region]
+
+
+def dct_entropy(img, xs: float, ys: float, region: str = "triangle", norm: str = "full") -> float:
+    """DCT entropy of a 2-D image (Eq. 12): with F the DCT of the image and n
+    its 2-norm, p = |F| / n over the region S and
+    e = -(1 / G) * sum_S p log2 p (0 log 0 = 0), G the area of S.
+
+    n is the Frobenius norm of the whole coefficient matrix (norm='full'), or
+    of the coefficients inside S only (norm='region').  The default region is
+    the triangle of Eq. (6) (G = X_S Y_S / 2).  Returns 0 when n = 0."""
     f = dct2(img)
-    n = np.sqrt(np.sum(f * f))
+    h, w = f.shape
+    mask = region_mask(h, w, xs, ys, region)
+    if norm == "full":
+        n = np.sqrt(np.sum(f * f))
+    elif norm == "region":
+        n = np.sqrt(np.sum(f[mask] ** 2))
+    else:
+        raise ValueError(f"unknown norm {norm!r}")
     if n == 0:
         return 0.0
-    p = np.abs(f[triangle_mask(f.shape[0], f.shape[1], xs, ys)]) / n
+    p = np.abs(f[mask]) / n
     p = p[p > 0]
-    return float(-(2.0 / (xs * ys)) * np.sum(p * np.log2(p)))
+    return float(-(1.0 / region_area(h, w, xs, ys, region)) * np.sum(p * np.log2(p)))
 
 
-def metric(vol, xs: float, ys: float) -> float:
+def metric(vol, xs: float, ys: float, region: str = "triangle", norm: str = "full") -> float:
     """Per-iterate quality metric: DCT entropy of the z maximum projection."""
-    return dct_entropy(mip(vol), xs, ys)
+    return dct_entropy(mip(vol), xs, ys, region, norm)
 
 
-def stop_decision(trace, patience: int = 1):
+def stop_decision(trace, patience: int = 1, window: int = 1):
     """Apply the stopping rule to metric values trace[0] = e_1, trace[1] = e_2, ...
 
-    Stops at the first iteration k at which the last ``patience`` steps were all
-    strict decreases (e_i < e_{i-1}); ties are not decreases.  The iterate kept is
-    the one with the largest metric seen so far (ties go to the later iterate).
+    The trend is read from the means of the last ``window`` values,
+    s_k = mean(e_{k-window+1}, ..., e_k), defined from k = window on (window 1:
+    the values themselves).  Stops at the first iteration k at which the last
+    ``patience`` steps of s were all strict decreases (s_i < s_{i-1}); ties are
+    not decreases.  The iterate kept is the one with the largest metric e seen
+    so far (ties go to the later iterate).
 
     Returns (stopped, k_stop, best): ``stopped`` is False if the trace ran out
     first (k_stop is then len(trace)); ``best`` is the 1-based iteration kept."""
     if patience < 1:
         raise ValueError("patience must be >= 1")
+    if window < 1:
+        raise ValueError("window must be >= 1")
     best, best_e, run = 0, -np.inf, 0
+    smooth = []
     for i, e in enumerate(trace):
         k = i + 1
-        if i > 0:
-            run = run + 1 if e < trace[i - 1] else 0
+        if k >= window:
+            smooth.append(float(np.mean(trace[k - window:k])))
+            if len(smooth) > 1:
+                run = run + 1 if smooth[-1] < smooth[-2] else 0
         if e >= best_e:
             best, best_e = k, e
         if run >= patience:
@@ -335,26 +429,39 @@ def synthetic_cutoff(nnum: int, spot_radius: float, h: int, w: int):
 
 
 def deconvolve(psf, y, max_iters: int, xs: float, ys: float, *, stop: bool = True,
-               patience: int = 1, x0=None):
-    """Richardson-Lucy with the metric evaluated on every iterate and the
-    stopping rule applied.  Returns (x_best, best_iter, iters_run, trace)."""
+               patience: int = 1, x0=None, update: str = "rl", background: float = 0.0,
+               init: str = None, region: str = "triangle", norm: str = "full",
+               window: int = 1):
+    """Iterations of ``update`` ('rl' or 'isra', with the constant background
+    ``background``) from x^0 (``init``, see initial_volume), with the metric
+    (``region``, ``norm``) evaluated on every iterate and the stopping rule
+    (``patience``, ``window``) applied.  Returns (x_best, best_iter, iters_run,
+    trace)."""
     y = np.asarray(y, dtype=np.float64)
-    nz = np.asarray(psf).shape[0]
     h, w = y.shape
-    c = sensitivity(psf, h, w)
-    x = np.ones((nz, h, w)) if x0 is None else np.array(x0, dtype=np.float64)
+    if init is None:
+        init = "ones" if x0 is None else "given"
+    x = initial_volume(psf, y, init, x0)
+    if update == "rl":
+        c = sensitivity(psf, h, w)
+        step = lambda x: rl_step(psf, y, x, c, background)[0]  # noqa: E731
+    elif update == "isra":
+        d = backward(psf, y)
+        step = lambda x: isra_step(psf, y, x, d, background)[0]  # noqa: E731
+    else:
+        raise ValueError(f"unknown update {update!r}")
     trace, iterates = [], {}
     best_x = x
     for k in range(1, max_iters + 1):
-        x, _ = rl_step(psf, y, x, c)
-        trace.append(metric(x, xs, ys))
+        x = step(x)
+        trace.append(metric(x, xs, ys, region, norm))
         iterates[k] = x
-        stopped, _, best = stop_decision(trace, patience)
+        stopped, _, best = stop_decision(trace, patience, window)
         best_x = iterates[best]
         for kk in list(iterates):
             if kk != best and kk != k:
                 del iterates[kk]
         if stop and stopped:
             return best_x, best, k, trace
-    _, _, best = stop_decision(trace, patience)
+    _, _, best = stop_decision(trace, patience, window)
     return iterates[best], best, max_iters, trace
