@@ -146,13 +146,42 @@ typedef enum {
                              but always run max_iters iterations */
 } lfrl_stop_mode;
 
+/* Update rules of lfrl_deconvolve. */
+typedef enum {
+    LFRL_UPDATE_RL = 0,  /* Richardson-Lucy: x * A^T(y / (A x + b)) / A^T 1 */
+    LFRL_UPDATE_ISRA = 1 /* ISRA: x * A^T y / A^T(A x + b) (least squares) */
+} lfrl_update;
+
+/* Coefficient regions of the DCT entropy. */
+typedef enum {
+    LFRL_REGION_TRIANGLE = 0,  /* u / xs + v / ys < 1 (Eq. 6), prefactor 2 / (xs ys) */
+    LFRL_REGION_RECTANGLE = 1, /* u < xs and v < ys (Eq. 12's limits), 1 / (xs ys) */
+    LFRL_REGION_WHOLE = 2      /* every coefficient (Fig. 2(c)'s overall value),
+                                  1 / (w h); xs and ys are ignored */
+} lfrl_region;
+
+/* The 2-norm the coefficients are divided by. */
+typedef enum {
+    LFRL_NORM_MATRIX = 0, /* Frobenius norm of the whole coefficient matrix */
+    LFRL_NORM_REGION = 1  /* Frobenius norm of the coefficients in the region */
+} lfrl_norm;
+
 typedef struct {
     int32_t max_iters; /* iteration cap, >= 1 */
     int32_t stop;      /* lfrl_stop_mode */
     int32_t patience;  /* consecutive strict decreases that stop (>= 1) */
-    int32_t init;      /* 0 = start from ones, 1 = start from the caller's vol */
+    int32_t init;      /* 0 = start from ones, 1 = start from the caller's vol,
+                          2 = start from the back projection A^T img */
     double xs, ys;     /* legs of the triangular DCT region, in DCT bins:
                           X_S along the width, Y_S along the height (Eq. 6) */
+    /* Variants (a zero-filled tail gives the method as the paper states it). */
+    int32_t update;    /* lfrl_update */
+    int32_t region;    /* lfrl_region of the metric */
+    int32_t norm;      /* lfrl_norm of the metric */
+    int32_t window;    /* the stop rule compares means of the last `window`
+                          metric values (0 or 1: the values themselves) */
+    double background; /* known constant background b >= 0 of the image model
+                          A x + b */
 } lfrl_rl_opts;
 
 typedef struct {
@@ -169,13 +198,16 @@ typedef struct {
 
 /* Richardson-Lucy deconvolution (sec. 1; all iterations on the GPU and only
  * the result handed back, sec. 2.1):
- *   x^0 = 1 (or vol), c = A^T 1,
- *   x^k = x^{k-1} * A^T( img / A x^{k-1} ) / c,
- * with img / A x := 0 where A x <= 0 and x := 0 where c <= 0.
+ *   x^0 = 1 (or vol, or A^T img), c = A^T 1,
+ *   x^k = x^{k-1} * A^T( img / (A x^{k-1} + b) ) / c,
+ * with img / (A x + b) := 0 where A x + b <= 0 and x := 0 where c <= 0
+ * (b = opts->background, 0 by default).  With opts->update = ISRA instead
+ *   x^k = x^{k-1} * A^T img / A^T(A x^{k-1} + b),  := 0 where A^T(A x + b) <= 0.
  * With a metric stop mode, every iterate is scored by the DCT entropy of its
- * z maximum projection (lfrl_metric) and the stop rule of sec. 2.2 applies:
- * stop once the entropy has strictly decreased `patience` times in a row and
- * return the iterate with the largest entropy seen (ties: the later one).
+ * z maximum projection (lfrl_metric_ex with opts->region and opts->norm) and
+ * the stop rule of sec. 2.2 applies: stop once the entropy (or the mean of its
+ * last opts->window values) has strictly decreased `patience` times in a row
+ * and return the iterate with the largest entropy seen (ties: the later one).
  * img [h][w] -> vol [nz][h][w] (x^{best_iter}, or x^{max_iters} without a
  * metric).  Synchronises `stream` before returning (the host needs the stop
  * decision and the report).  `report` [host] may be NULL. */
@@ -252,6 +284,14 @@ int lfrl_deconvolve_batch(const lfrl_plan_t *plans, int32_t n, const int32_t *h,
  * first use and grows when a larger image needs it. */
 int lfrl_metric(int32_t nz, int32_t h, int32_t w, const float *img, double xs,
                 double ys, double *out, void *stream);
+
+/* lfrl_metric with a choice of region (lfrl_region) and norm (lfrl_norm):
+ *     *out = -(1 / G) * sum_{(u,v) in S} |F/n| log2 |F/n|,
+ * G the area of S (xs ys / 2, xs ys, or w h) and n the Frobenius norm of F
+ * over the whole matrix or over S.  The triangle and the rectangle need legs
+ * of at most 256 bins; the whole region takes any image. */
+int lfrl_metric_ex(int32_t nz, int32_t h, int32_t w, const float *img, double xs, double ys,
+                   int32_t region, int32_t norm, double *out, void *stream);
 
 /* Triangle legs from the optics (Eqs. 7, 9-11), [host]:
  * P_u = d_ml / (mag * nnum), d_psf = 1.22 * lambda * nnum / na,

@@ -20,7 +20,7 @@ import torch
 __all__ = [
     "LfrlError", "PlanDesc", "PlanInfo", "RlOpts", "RlReport",
     "lfrl_plan_footprint", "lfrl_plan", "lfrl_plan_destroy", "lfrl_plan_get_info",
-    "lfrl_forward", "lfrl_backward", "lfrl_deconvolve", "lfrl_metric",
+    "lfrl_forward", "lfrl_backward", "lfrl_deconvolve", "lfrl_metric", "lfrl_metric_ex",
     "lfrl_metric_cutoff", "lfrl_profile_enable", "lfrl_profile_read", "lfrl_last_error",
     "Plan", "library_path", "STOP_NONE", "STOP_METRIC", "STOP_TRACK", "FP32", "SPLIT_FP16",
 ]
@@ -30,6 +30,10 @@ _LIB_PATH = os.path.join(_HERE, "liblfrl.so")
 
 FP32, SPLIT_FP16, SPLIT_BF16 = 0, 1, 2
 STOP_NONE, STOP_METRIC, STOP_TRACK = 0, 1, 2
+UPDATE_RL, UPDATE_ISRA = 0, 1
+INIT_ONES, INIT_GIVEN, INIT_BACKPROJECT = 0, 1, 2
+REGION_TRIANGLE, REGION_RECTANGLE, REGION_WHOLE = 0, 1, 2
+NORM_MATRIX, NORM_REGION = 0, 1
 
 _STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_NOMEM", -3: "ERR_DEVICE",
            -4: "ERR_UNSUPPORTED", -5: "ERR_NUMERIC"}
@@ -59,7 +63,10 @@ class PlanInfo(ctypes.Structure):
 class RlOpts(ctypes.Structure):
     _fields_ = [("max_iters", ctypes.c_int32), ("stop", ctypes.c_int32),
                 ("patience", ctypes.c_int32), ("init", ctypes.c_int32),
-                ("xs", ctypes.c_double), ("ys", ctypes.c_double)]
+                ("xs", ctypes.c_double), ("ys", ctypes.c_double),
+                ("update", ctypes.c_int32), ("region", ctypes.c_int32),
+                ("norm", ctypes.c_int32), ("window", ctypes.c_int32),
+                ("background", ctypes.c_double)]
 
 
 class RlReport(ctypes.Structure):
@@ -96,6 +103,7 @@ def _load():
         "lfrl_deconvolve": [vp, i32, i32, vp, vp, ctypes.POINTER(RlOpts),
                             ctypes.POINTER(RlReport), vp],
         "lfrl_metric": [i32, i32, i32, vp, dbl, dbl, vp, vp],
+        "lfrl_metric_ex": [i32, i32, i32, vp, dbl, dbl, i32, i32, vp, vp],
         "lfrl_metric_cutoff": [dbl, dbl, i32, dbl, dbl, i32, i32,
                                ctypes.POINTER(dbl), ctypes.POINTER(dbl)],
         "lfrl_job_footprint": [vp, i32, i32, sz],
@@ -203,6 +211,14 @@ def lfrl_metric(nz: int, h: int, w: int, img: torch.Tensor, xs: float, ys: float
         raise LfrlError(-1, "out must be a CUDA float64 tensor")
     _check(_load().lfrl_metric(nz, h, w, _dev_f32(img, "img"), float(xs), float(ys),
                                out.data_ptr(), _stream(stream)))
+
+
+def lfrl_metric_ex(nz: int, h: int, w: int, img: torch.Tensor, xs: float, ys: float,
+                   region: int, norm: int, out: torch.Tensor, stream=None) -> None:
+    if not out.is_cuda or out.dtype != torch.float64 or out.numel() < 1:
+        raise LfrlError(-1, "out must be a CUDA float64 tensor")
+    _check(_load().lfrl_metric_ex(nz, h, w, _dev_f32(img, "img"), float(xs), float(ys),
+                                  int(region), int(norm), out.data_ptr(), _stream(stream)))
 
 
 def lfrl_metric_cutoff(d_ml: float, mag: float, nnum: int, wavelength: float, na: float,
@@ -354,17 +370,32 @@ class Plan:
     def deconvolve(self, img: torch.Tensor, iters: int, *, stop: int = STOP_NONE,
                    patience: int = 1, xs: float = 1.0, ys: float = 1.0,
                    init: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
-                   want_flux: bool = False, stream=None):
+                   want_flux: bool = False, stream=None, **variants):
+        """``variants``: update, background, backproject_start, region, norm,
+        window (see rl_opts)."""
         h, w = img.shape
         if out is None:
             out = torch.empty((self.nz, h, w), dtype=torch.float32, device=img.device)
         if init is not None:
             out.copy_(init)
-        opts = RlOpts(max_iters=iters, stop=stop, patience=patience,
-                      init=0 if init is None else 1, xs=xs, ys=ys)
+        opts = rl_opts(iters, stop, patience, xs, ys, init is not None, **variants)
         rep = lfrl_deconvolve(self.handle, h, w, img, out, opts, want_metric=True,
                               want_flux=want_flux, stream=stream)
         return out, rep
+
+
+def rl_opts(iters: int, stop: int = STOP_NONE, patience: int = 1, xs: float = 1.0,
+            ys: float = 1.0, given_start: bool = False, *, update: int = UPDATE_RL,
+            background: float = 0.0, backproject_start: bool = False,
+            region: int = REGION_TRIANGLE, norm: int = NORM_MATRIX, window: int = 1) -> RlOpts:
+    """lfrl_rl_opts from keyword arguments (the defaults are the method as the
+    paper states it)."""
+    if given_start and backproject_start:
+        raise LfrlError(-1, "a given start volume and the back projection start exclude each other")
+    init = INIT_GIVEN if given_start else INIT_BACKPROJECT if backproject_start else INIT_ONES
+    return RlOpts(max_iters=iters, stop=stop, patience=patience, init=init, xs=xs, ys=ys,
+                  update=update, region=region, norm=norm, window=window,
+                  background=background)
 
 
 class Job:
@@ -372,11 +403,11 @@ class Job:
 
     def __init__(self, plan: Plan, img: torch.Tensor, iters: int, *, stop: int = STOP_NONE,
                  patience: int = 1, xs: float = 1.0, ys: float = 1.0,
-                 init: Optional[torch.Tensor] = None, want_flux: bool = False, stream=None):
+                 init: Optional[torch.Tensor] = None, want_flux: bool = False, stream=None,
+                 **variants):
         self.plan = plan
         self.h, self.w = img.shape
-        self.opts = RlOpts(max_iters=iters, stop=stop, patience=patience,
-                           init=0 if init is None else 1, xs=xs, ys=ys)
+        self.opts = rl_opts(iters, stop, patience, xs, ys, init is not None, **variants)
         self.want_flux = want_flux
         self.handle = lfrl_job_create(plan.handle, self.h, self.w, img, self.opts, vol0=init,
                                       flags=JOB_FLUX if want_flux else 0, stream=stream)
@@ -409,12 +440,13 @@ class Job:
             pass
 
 
-def metric(img: torch.Tensor, xs: float, ys: float, stream=None) -> float:
+def metric(img: torch.Tensor, xs: float, ys: float, stream=None, *,
+           region: int = REGION_TRIANGLE, norm: int = NORM_MATRIX) -> float:
     """DCT entropy of a 2-D image, or of the z-MIP of a [nz][h][w] volume."""
     if img.dim() == 2:
         nz, (h, w) = 1, img.shape
     else:
         nz, h, w = img.shape
     out = torch.empty(1, dtype=torch.float64, device=img.device)
-    lfrl_metric(nz, h, w, img, xs, ys, out, stream)
+    lfrl_metric_ex(nz, h, w, img, xs, ys, region, norm, out, stream)
     return float(out.item())

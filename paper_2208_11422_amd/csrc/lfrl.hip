@@ -316,7 +316,6 @@ __global__ void k_vol_r2c(const TileBatch batch, int N, int Q, int QH, int T, in
     }
 }
 
-enum { EPI_STORE = 0, EPI_RATIO = 1, EPI_UPDATE = 2 };
 
 // Inverse tile DFT and scatter of the valid T x T lenslets of one tile for
 // plane j and row phase ar (all N column phases).  The spectrum of column
@@ -328,7 +327,7 @@ enum { EPI_STORE = 0, EPI_RATIO = 1, EPI_UPDATE = 2 };
 //                    (x_new = x_old * A^T rho / A^T 1)
 __global__ void k_c2r(const TileBatch batch, const float2 *__restrict__ spec, size_t split_stride,
                       int nsplit, size_t sk, size_t stile, size_t sc, int N, int Q, int QH, int T,
-                      int hD, int mode, const float2 *__restrict__ twg)
+                      int hD, const float2 *__restrict__ twg)
 {
     extern __shared__ float smem[];
     const int tile = blockIdx.x;
@@ -339,6 +338,8 @@ __global__ void k_c2r(const TileBatch batch, const float2 *__restrict__ spec, si
     float *__restrict__ dst = fj.dst;
     const float *__restrict__ aux0 = fj.aux0;
     const float *__restrict__ aux1 = fj.aux1;
+    const int mode = fj.mode;
+    const float bg = fj.bg;
     float2 *X = reinterpret_cast<float2 *>(smem);
     float2 *Z = X + (size_t)Q * QH * N;
     float2 *tw = Z + (size_t)T * QH * N;
@@ -407,13 +408,17 @@ __global__ void k_c2r(const TileBatch batch, const float2 *__restrict__ spec, si
         const int pr = N * Lr + ar, pc = N * Lc + p;
         const size_t pix = (size_t)pr * W + pc;
         if (mode == EPI_STORE) {
-            dst[(size_t)j * H * W + pix] = v;
+            dst[(size_t)j * H * W + pix] = v + bg;
         } else if (mode == EPI_RATIO) {
-            dst[pix] = v > 0.f ? aux0[pix] / v : 0.f;
-        } else {
+            const float m = v + bg;
+            dst[pix] = m > 0.f ? aux0[pix] / m : 0.f;
+        } else if (mode == EPI_UPDATE) {
             const size_t o = (size_t)j * H * W + pix;
             const float c = aux1[o];
             dst[o] = c > 0.f ? aux0[o] * v / c : 0.f;
+        } else {
+            const size_t o = (size_t)j * H * W + pix;
+            dst[o] = v > 0.f ? aux0[o] * aux1[o] / v : 0.f;
         }
     }
 }
@@ -844,9 +849,10 @@ __global__ void k_dct_rows(const float *__restrict__ mip, int H, int W,
 
 // One wave per candidate coefficient (v, u):
 // F[v][u] = sum_chunk sum_s T1[chunk][v][s] C_W[u][s] for (v, u) inside the
-// triangle u / xs + v / ys < 1; |F| is written, -1 marks coefficients outside.
+// region (LFRL_REGION_*: the triangle u / xs + v / ys < 1, the rectangle
+// u < xs, v < ys, or everything); |F| is written, -1 marks coefficients outside.
 __global__ void k_metric_coeffs(const double *__restrict__ T1, int nchunks, int nv, int nu, int W,
-                                const double *__restrict__ tabW, double xs, double ys,
+                                const double *__restrict__ tabW, double xs, double ys, int region,
                                 double *__restrict__ Fabs)
 {
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -854,7 +860,9 @@ __global__ void k_metric_coeffs(const double *__restrict__ T1, int nchunks, int 
     if (wave >= nv * nu)
         return;
     const int v = wave / nu, u = wave % nu;
-    const bool inside = ((double)u / xs + (double)v / ys) < 1.0;
+    const bool inside = region == LFRL_REGION_TRIANGLE ? ((double)u / xs + (double)v / ys) < 1.0
+                        : region == LFRL_REGION_RECTANGLE ? ((double)u < xs && (double)v < ys)
+                                                          : true;
     if (!inside) {
         if (lane == 0)
             Fabs[wave] = -1.0;
@@ -887,19 +895,30 @@ struct StopState {
     int iter;
 };
 
-// Final entropy (Eq. 12 with the Frobenius norm from Parseval) and stop rule.
-// Single block.  out[0] = e.  When st != nullptr, iteration `k` is recorded:
-// trace[k-1] = e, the best iterate is tracked (ties: later) and the stop flag
-// raised after `patience` consecutive strict decreases.
+// Final entropy (Eq. 12) and stop rule.  Single block.  The norm is the
+// Frobenius norm of the whole matrix (from Parseval's partial sums n2p) or of
+// the coefficients inside the region (norm == LFRL_NORM_REGION), and the
+// prefactor 1 / area.  out[0] = e.  When st != nullptr, iteration `k` is
+// recorded: trace[k-1] = e, the best iterate is tracked (ties: later) and the
+// stop flag raised after `patience` consecutive strict decreases of the mean
+// of the last `window` values (trace must then hold e_1 .. e_k).
 __global__ void k_metric_final(const double *__restrict__ n2p, int n2count,
-                               const double *__restrict__ Fabs, int ncoef, double xs, double ys,
+                               const double *__restrict__ Fabs, int ncoef, int norm, double area,
                                double *__restrict__ out, StopState *st, double *trace, int k,
-                               int patience)
+                               int patience, int window)
 {
     __shared__ double red[256];
     double a = 0.0;
-    for (int i = threadIdx.x; i < n2count; i += blockDim.x)
-        a += n2p[i];
+    if (norm == LFRL_NORM_REGION) {
+        for (int i = threadIdx.x; i < ncoef; i += blockDim.x) {
+            const double f = Fabs[i];
+            if (f > 0.0)
+                a += f * f;
+        }
+    } else {
+        for (int i = threadIdx.x; i < n2count; i += blockDim.x)
+            a += n2p[i];
+    }
     red[threadIdx.x] = a;
     __syncthreads();
     for (int off = blockDim.x / 2; off > 0; off >>= 1) {
@@ -927,14 +946,20 @@ __global__ void k_metric_final(const double *__restrict__ n2p, int n2count,
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const double e = (n > 0.0) ? -(2.0 / (xs * ys)) * red[0] : 0.0;
+        const double e = (n > 0.0) ? -(1.0 / area) * red[0] : 0.0;
         out[0] = e;
         if (st) {
-            if (trace)
-                trace[k - 1] = e;
+            trace[k - 1] = e;
             st->iter = k;
-            if (k > 1)
-                st->run = (e < st->prev_e) ? st->run + 1 : 0;
+            if (k > window) {
+                // means of e_{k-window+1..k} and e_{k-window..k-1}, oldest first
+                double s1 = 0.0, s0 = 0.0;
+                for (int i = k - window; i < k; ++i)
+                    s1 += trace[i];
+                for (int i = k - 1 - window; i < k - 1; ++i)
+                    s0 += trace[i];
+                st->run = (s1 / window < s0 / window) ? st->run + 1 : 0;
+            }
             st->copy_flag = (k == 1 || e >= st->best_e) ? 1 : 0;
             if (st->copy_flag) {
                 st->best_e = e;
@@ -1143,13 +1168,13 @@ static void launch_r2c_fft(int Q, dim3 grid, int block, size_t lds, hipStream_t 
 static void launch_c2r_fft(int Q, dim3 grid, int block, size_t lds, hipStream_t st,
                            const TileBatch &batch, const float2 *spec, size_t split_stride,
                            int nsplit, size_t sk, size_t stile, size_t sc, int N, int planes,
-                           int T, int hD, int mode, const float2 *tw)
+                           int T, int hD, const float2 *tw)
 {
     switch (Q) {
 #define LFRL_CASE(q)                                                                        \
     case q:                                                                                 \
         hipLaunchKernelGGL(k_c2r_fft<q>, grid, dim3(block), lds, st, batch, spec,            \
-                           split_stride, nsplit, sk, stile, sc, N, planes, T, hD, mode, tw);  \
+                           split_stride, nsplit, sk, stile, sc, N, planes, T, hD, tw);        \
         break;
         LFRL_FFT_Q_LIST(LFRL_CASE)
 #undef LFRL_CASE
@@ -1230,17 +1255,19 @@ __global__ void k_zero_u32(unsigned *p)
         *p = 0u;
 }
 
-enum { WEAK_SENS = 0, WEAK_UPDATE = 1 };
+enum { WEAK_SENS = 0, WEAK_UPDATE = 1, WEAK_STORE = 2, WEAK_ISRA = 3 };
 
 // One block per listed voxel (j, r, s): the exact window sum
 //   acc = sum_{taps inside the image} h[j][r mod N][s mod N][u][v] * img[r+u-c0][s+v-c0]
 // in float64 (img == nullptr stands for an all-ones image, i.e. A^T 1).
 //   WEAK_SENS:   sens[vox] = acc
 //   WEAK_UPDATE: dst[vox] = sens[vox] > 0 ? src[vox] * acc / sens[vox] : 0
+//   WEAK_STORE:  dst[vox] = acc
+//   WEAK_ISRA:   dst[vox] = acc > 0 ? src[vox] * aux[vox] / acc : 0
 __global__ void k_weak_exact(const unsigned *__restrict__ list, const float *__restrict__ psf,
                              int N, int K, int H, int W, const float *__restrict__ img,
                              float *__restrict__ sens, const float *__restrict__ src,
-                             float *__restrict__ dst, int mode)
+                             const float *__restrict__ aux, float *__restrict__ dst, int mode)
 {
     __shared__ double red[256];
     const unsigned vox = list[blockIdx.x];
@@ -1269,9 +1296,13 @@ __global__ void k_weak_exact(const unsigned *__restrict__ list, const float *__r
     if (threadIdx.x == 0) {
         if (mode == WEAK_SENS) {
             sens[vox] = (float)red[0];
-        } else {
+        } else if (mode == WEAK_UPDATE) {
             const float c = sens[vox];
             dst[vox] = c > 0.f ? (float)((double)src[vox] * red[0] / (double)c) : 0.f;
+        } else if (mode == WEAK_STORE) {
+            dst[vox] = (float)red[0];
+        } else {
+            dst[vox] = red[0] > 0.0 ? (float)((double)src[vox] * (double)aux[vox] / red[0]) : 0.f;
         }
     }
 }
@@ -1307,6 +1338,7 @@ struct Frame {
     float *V[2] = {nullptr, nullptr};  // x^{k-1} and x^k (ping-pong)
     float *VB = nullptr;               // best iterate under a metric stop mode
     float *sens = nullptr;             // A^T 1 [Nz][h][w]
+    float *D = nullptr;                // A^T y [Nz][h][w] (ISRA numerator)
     unsigned *weak = nullptr;          // weakly observed voxels
     unsigned *counters = nullptr;      // [0] weak count, [1] bad-input flag
     unsigned *counters_host = nullptr; // pinned copy
@@ -1369,15 +1401,17 @@ struct lfrl_plan_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     struct GraphKey {
-        int h, w, max_iters, stop, patience, init, flux;
-        double xs, ys;
+        int h, w, max_iters, stop, patience, init, flux, update, region, norm, window;
+        double xs, ys, background;
         const float *img;
         const float *vol;
         bool operator==(const GraphKey &o) const
         {
             return h == o.h && w == o.w && max_iters == o.max_iters && stop == o.stop &&
-                   patience == o.patience && init == o.init && flux == o.flux && xs == o.xs &&
-                   ys == o.ys && img == o.img && vol == o.vol;
+                   patience == o.patience && init == o.init && flux == o.flux &&
+                   update == o.update && region == o.region && norm == o.norm &&
+                   window == o.window && xs == o.xs && ys == o.ys &&
+                   background == o.background && img == o.img && vol == o.vol;
         }
     } graph_key{};
     int graph_hits = 0;
@@ -1554,29 +1588,31 @@ static unsigned weak_cap_for(size_t nvox)
 
 // Device buffers of one Frame, in the order they are carved from its block.
 enum {
-    FB_Y, FB_RHO, FB_V0, FB_V1, FB_VB, FB_SENS, FB_WEAK, FB_COUNTERS, FB_CMAX, FB_MIP, FB_TABH,
+    FB_Y, FB_RHO, FB_V0, FB_V1, FB_VB, FB_SENS, FB_D, FB_WEAK, FB_COUNTERS, FB_CMAX, FB_MIP, FB_TABH,
     FB_TABW, FB_T1, FB_N2P, FB_FABS, FB_MOUT, FB_TRACE, FB_FLUX, FB_DOTP, FB_STATE, FB_COUNT
 };
 
 // Byte offsets (256-byte aligned) of a Frame's buffers for an h x w image;
 // returns the block size.  own_y: the frame keeps its own copy of the image.
+// The metric buffers hold the whole coefficient matrix (LFRL_REGION_WHOLE).
 static size_t frame_layout(const Geo &g, int h, int w, bool own_y, size_t off[FB_COUNT])
 {
     const size_t hw = (size_t)h * w, nvox = (size_t)g.Nz * hw;
-    const size_t legs_h = std::min(h, kMaxMetricLegs), legs_w = std::min(w, kMaxMetricLegs);
+    const size_t legs_h = std::min(h, kMaxMetricLegs);
     size_t bytes[FB_COUNT];
     bytes[FB_Y] = own_y ? hw * sizeof(float) : 0;
     bytes[FB_RHO] = hw * sizeof(float);
-    bytes[FB_V0] = bytes[FB_V1] = bytes[FB_VB] = bytes[FB_SENS] = nvox * sizeof(float);
+    bytes[FB_V0] = bytes[FB_V1] = bytes[FB_VB] = bytes[FB_SENS] = bytes[FB_D] =
+        nvox * sizeof(float);
     bytes[FB_WEAK] = (size_t)weak_cap_for(nvox) * sizeof(unsigned);
     bytes[FB_COUNTERS] = 2 * sizeof(unsigned);
     bytes[FB_CMAX] = (kDotBlocks + 1) * sizeof(float);
     bytes[FB_MIP] = hw * sizeof(float);
-    bytes[FB_TABH] = legs_h * h * sizeof(double);
-    bytes[FB_TABW] = legs_w * w * sizeof(double);
-    bytes[FB_T1] = (size_t)kMetricChunks * legs_h * w * sizeof(double);
+    bytes[FB_TABH] = (size_t)h * h * sizeof(double);
+    bytes[FB_TABW] = (size_t)w * w * sizeof(double);
+    bytes[FB_T1] = std::max((size_t)kMetricChunks * legs_h * w, hw) * sizeof(double);
     bytes[FB_N2P] = (hw + 255) / 256 * sizeof(double);
-    bytes[FB_FABS] = legs_h * legs_w * sizeof(double);
+    bytes[FB_FABS] = hw * sizeof(double);
     bytes[FB_MOUT] = sizeof(double);
     bytes[FB_TRACE] = bytes[FB_FLUX] = (size_t)kMaxTrace * sizeof(double);
     bytes[FB_DOTP] = (size_t)kDotBlocks * sizeof(double);
@@ -1601,6 +1637,7 @@ static void frame_bind(Frame &f, const Geo &g, int h, int w, void *block, const 
     f.V[1] = (float *)(b + off[FB_V1]);
     f.VB = (float *)(b + off[FB_VB]);
     f.sens = (float *)(b + off[FB_SENS]);
+    f.D = (float *)(b + off[FB_D]);
     f.weak = (unsigned *)(b + off[FB_WEAK]);
     f.counters = (unsigned *)(b + off[FB_COUNTERS]);
     f.cmax = (float *)(b + off[FB_CMAX]);
@@ -2215,10 +2252,12 @@ struct FrameIO {
     const float *src;
     float *dst;
     const float *aux0, *aux1;
+    float bg = 0.f;  // background of EPI_STORE / EPI_RATIO
+    int mode = -1;   // epilogue of this frame (-1: the launch's)
 };
 
 // Concatenate the frames' tiles into one tile index space; returns the total.
-static int make_batch(const Geo &g, const FrameIO *io, int n, TileBatch *b)
+static int make_batch(const Geo &g, const FrameIO *io, int n, int mode, TileBatch *b)
 {
     int nt = 0;
     b->njobs = n;
@@ -2229,6 +2268,8 @@ static int make_batch(const Geo &g, const FrameIO *io, int n, TileBatch *b)
         j.dst = io[i].dst;
         j.aux0 = io[i].aux0;
         j.aux1 = io[i].aux1;
+        j.bg = io[i].bg;
+        j.mode = io[i].mode >= 0 ? io[i].mode : mode;
         j.H = io[i].h;
         j.W = io[i].w;
         j.tiles_x = t.tx;
@@ -2246,7 +2287,7 @@ static int run_forward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipSt
 {
     const Geo &g = p->g;
     TileBatch batch;
-    const int nt = make_batch(g, io, n, &batch);
+    const int nt = make_batch(g, io, n, mode, &batch);
     if (nt > p->max_tiles)
         return set_error(LFRL_ERR_ARG, "batch of %d tiles exceeds the plan capacity %d", nt,
                          p->max_tiles);
@@ -2312,11 +2353,11 @@ static int run_forward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipSt
     const size_t sk = (size_t)g.NN * nt, split_stride = (size_t)g.nf * sk;
     if (p->use_fft)
         launch_c2r_fft(g.Q, dim3(nt * g.N), p->thr_c2r, p->lds_c2r_bytes, st, batch, p->Yp,
-                       split_stride, split2, sk, g.NN, 1, g.N, 1, g.T, g.hD, mode, p->tw);
+                       split_stride, split2, sk, g.NN, 1, g.N, 1, g.T, g.hD, p->tw);
     else
         hipLaunchKernelGGL(k_c2r, dim3(nt, g.N), dim3(256), p->lds_c2r_bytes, st, batch, p->Yp,
                            split_stride, split2, sk, (size_t)g.NN, (size_t)1, g.N, g.Q, g.QH, g.T,
-                           g.hD, mode, p->tw);
+                           g.hD, p->tw);
     LAUNCH_CHECK("k_c2r(forward)");
     return LFRL_OK;
 }
@@ -2328,7 +2369,7 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
 {
     const Geo &g = p->g;
     TileBatch batch;
-    const int nt = make_batch(g, io, n, &batch);
+    const int nt = make_batch(g, io, n, mode, &batch);
     if (nt > p->max_tiles)
         return set_error(LFRL_ERR_ARG, "batch of %d tiles exceeds the plan capacity %d", nt,
                          p->max_tiles);
@@ -2401,11 +2442,11 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
     const size_t sk = (size_t)g.KK * nt;
     if (p->use_fft)
         launch_c2r_fft(g.Q, dim3(nt * g.Nz * g.N), p->thr_c2r, p->lds_c2r_bytes, st, batch, p->X,
-                       (size_t)0, 1, sk, g.KK, 1, g.N, g.Nz, g.T, g.hD, mode, p->tw);
+                       (size_t)0, 1, sk, g.KK, 1, g.N, g.Nz, g.T, g.hD, p->tw);
     else
         hipLaunchKernelGGL(k_c2r, dim3(nt, g.Nz * g.N), dim3(256), p->lds_c2r_bytes, st, batch,
                            p->X, (size_t)0, 1, sk, (size_t)g.KK, (size_t)1, g.N, g.Q, g.QH, g.T,
-                           g.hD, mode, p->tw);
+                           g.hD, p->tw);
     LAUNCH_CHECK("k_c2r(backward)");
     return LFRL_OK;
 }
@@ -2504,13 +2545,22 @@ struct MetricBufs {
     int *tab_h, *tab_nv, *tab_w, *tab_nu;  // cached table shapes (may be null: rebuild)
 };
 
+// Area of a metric region (the entropy's prefactor is its inverse).
+static double region_area(int region, double xs, double ys, int h, int w)
+{
+    return region == LFRL_REGION_TRIANGLE ? 0.5 * xs * ys
+           : region == LFRL_REGION_RECTANGLE ? xs * ys
+                                             : (double)h * (double)w;
+}
+
 // DCT entropy of the z-MIP of vol[nz][h][w] (nz = 1: the image itself) into
 // out[0]; optional stop-state update for iteration k.
-static int run_metric(int nz, int h, int w, const float *vol, double xs, double ys, double *out,
-                      const MetricBufs &mb, StopState *st_dev, double *trace, int k, int patience,
-                      hipStream_t st)
+static int run_metric(int nz, int h, int w, const float *vol, double xs, double ys, int region,
+                      int norm, double *out, const MetricBufs &mb, StopState *st_dev,
+                      double *trace, int k, int patience, int window, hipStream_t st)
 {
-    const int nv = legs_count(ys, h), nu = legs_count(xs, w);
+    const bool whole = region == LFRL_REGION_WHOLE;
+    const int nv = whole ? h : legs_count(ys, h), nu = whole ? w : legs_count(xs, w);
     const bool cached = mb.tab_h && *mb.tab_h == h && *mb.tab_nv >= nv && *mb.tab_w == w &&
                         *mb.tab_nu >= nu;
     if (!cached) {
@@ -2529,7 +2579,8 @@ static int run_metric(int nz, int h, int w, const float *vol, double xs, double 
     const int nblk = (int)((hw + 255) / 256);
     hipLaunchKernelGGL(k_mip, dim3(nblk), dim3(256), 0, st, vol, nz, hw, mb.mip, mb.n2p);
     LAUNCH_CHECK("k_mip");
-    const int chunks = std::min(kMetricChunks, h);
+    // the row transform of the whole matrix fits the buffers as one chunk
+    const int chunks = whole ? 1 : std::min(kMetricChunks, h);
     const int rpc = (h + chunks - 1) / chunks;
     const int nchunks = (h + rpc - 1) / rpc;
     hipLaunchKernelGGL(k_dct_rows, dim3((nv * w + 255) / 256, nchunks), dim3(256), 0, st,
@@ -2538,16 +2589,19 @@ static int run_metric(int nz, int h, int w, const float *vol, double xs, double 
     const int ncoef = nv * nu;
     hipLaunchKernelGGL(k_metric_coeffs, dim3((ncoef + 3) / 4), dim3(256), 0, st,
                        (const double *)mb.T1, nchunks, nv, nu, w, (const double *)mb.tabW, xs, ys,
-                       mb.Fabs);
+                       region, mb.Fabs);
     LAUNCH_CHECK("k_metric_coeffs");
     hipLaunchKernelGGL(k_metric_final, dim3(1), dim3(256), 0, st, (const double *)mb.n2p, nblk,
-                       (const double *)mb.Fabs, ncoef, xs, ys, out, st_dev, trace, k, patience);
+                       (const double *)mb.Fabs, ncoef, norm, region_area(region, xs, ys, h, w),
+                       out, st_dev, trace, k, patience, std::max(1, window));
     LAUNCH_CHECK("k_metric_final");
     return LFRL_OK;
 }
 
-static int check_legs(double xs, double ys)
+static int check_legs(double xs, double ys, int region = LFRL_REGION_TRIANGLE)
 {
+    if (region == LFRL_REGION_WHOLE)
+        return LFRL_OK;
     if (!(xs > 0.0) || !(ys > 0.0) || !std::isfinite(xs) || !std::isfinite(ys))
         return set_error(LFRL_ERR_ARG, "triangle legs xs=%g, ys=%g must be positive", xs, ys);
     if (std::ceil(xs) > kMaxMetricLegs || std::ceil(ys) > kMaxMetricLegs)
@@ -2615,7 +2669,8 @@ static int frame_sensitivity(lfrl_plan_s *p, Frame &f, bool check_input, hipStre
     if (f.nweak) {
         hipLaunchKernelGGL(k_weak_exact, dim3(f.nweak), dim3(256), 0, st, (const unsigned *)f.weak,
                            (const float *)p->psf, p->g.N, p->g.K, h, w, (const float *)nullptr,
-                           f.sens, (const float *)nullptr, (float *)nullptr, (int)WEAK_SENS);
+                           f.sens, (const float *)nullptr, (const float *)nullptr, (float *)nullptr,
+                           (int)WEAK_SENS);
         LAUNCH_CHECK("k_weak_exact(sens)");
     }
     return LFRL_OK;
@@ -2656,22 +2711,57 @@ static int check_opts(const lfrl_rl_opts *opts)
         return set_error(LFRL_ERR_ARG, "max_iters must be in [1, %d]", kMaxTrace);
     if (opts->stop < LFRL_STOP_NONE || opts->stop > LFRL_STOP_TRACK)
         return set_error(LFRL_ERR_ARG, "unknown stop mode %d", opts->stop);
-    if (opts->init != 0 && opts->init != 1)
-        return set_error(LFRL_ERR_ARG, "init must be 0 or 1");
+    if (opts->init < 0 || opts->init > 2)
+        return set_error(LFRL_ERR_ARG, "init must be 0, 1 or 2");
+    if (opts->update != LFRL_UPDATE_RL && opts->update != LFRL_UPDATE_ISRA)
+        return set_error(LFRL_ERR_ARG, "unknown update rule %d", opts->update);
+    if (!(opts->background >= 0.0) || !(opts->background <= 3.4e38))
+        return set_error(LFRL_ERR_ARG, "background must be finite and >= 0");
     if (opts->stop != LFRL_STOP_NONE) {
         if (opts->patience < 1)
             return set_error(LFRL_ERR_ARG, "patience must be >= 1");
-        return check_legs(opts->xs, opts->ys);
+        if (opts->window < 0 || opts->window > kMaxTrace)
+            return set_error(LFRL_ERR_ARG, "window must be in [0, %d]", kMaxTrace);
+        if (opts->region < LFRL_REGION_TRIANGLE || opts->region > LFRL_REGION_WHOLE)
+            return set_error(LFRL_ERR_ARG, "unknown metric region %d", opts->region);
+        if (opts->norm != LFRL_NORM_MATRIX && opts->norm != LFRL_NORM_REGION)
+            return set_error(LFRL_ERR_ARG, "unknown metric norm %d", opts->norm);
+        return check_legs(opts->xs, opts->ys, opts->region);
     }
     return LFRL_OK;
 }
 
-// x^0 (ones, or a copy of vol0), a fresh stop state, and the image sum for the
-// flux trace.
-static int frame_start(Frame &f, int nz, const float *vol0, hipStream_t st)
+// D = A^T y for the ISRA numerator and the back projection start, with the
+// weakly observed voxels' window sums in float64.
+static int frame_backproject_image(lfrl_plan_s *p, Frame &f, hipStream_t st)
 {
-    const size_t nvox = (size_t)nz * f.h * f.w;
-    if (vol0) {
+    const FrameIO io{f.h, f.w, f.y, f.D, nullptr, nullptr};
+    int rc = run_backward(p, &io, 1, EPI_STORE, st);
+    if (rc)
+        return rc;
+    if (f.nweak) {
+        hipLaunchKernelGGL(k_weak_exact, dim3(f.nweak), dim3(256), 0, st, (const unsigned *)f.weak,
+                           (const float *)p->psf, p->g.N, p->g.K, f.h, f.w, f.y, f.sens,
+                           (const float *)nullptr, (const float *)nullptr, f.D, (int)WEAK_STORE);
+        LAUNCH_CHECK("k_weak_exact(store)");
+    }
+    return LFRL_OK;
+}
+
+// x^0 (ones, a copy of vol0, or A^T y), A^T y when the ISRA update needs it, a
+// fresh stop state, and the image sum for the flux trace.  Needs A^T 1 and
+// the weak-voxel list of the frame.
+static int frame_start(lfrl_plan_s *p, Frame &f, const float *vol0, hipStream_t st)
+{
+    const size_t nvox = (size_t)p->g.Nz * f.h * f.w;
+    if (f.opts.update == LFRL_UPDATE_ISRA || f.opts.init == 2) {
+        int rc = frame_backproject_image(p, f, st);
+        if (rc)
+            return rc;
+    }
+    if (f.opts.init == 2) {
+        HIP_TRY(hipMemcpyAsync(f.V[0], f.D, nvox * sizeof(float), hipMemcpyDeviceToDevice, st));
+    } else if (vol0) {
         HIP_TRY(hipMemcpyAsync(f.V[0], vol0, nvox * sizeof(float), hipMemcpyDeviceToDevice, st));
     } else {
         int rc = launch_fill(f.V[0], nvox, 1.0f, st);
@@ -2690,17 +2780,22 @@ static int frame_start(Frame &f, int nz, const float *vol0, hipStream_t st)
     return LFRL_OK;
 }
 
-// One Richardson-Lucy iteration for n frames of plan p, their projections
-// batched: x^k = x^{k-1} * A^T(y / A x^{k-1}) / c, the exact update at the
-// weakly observed voxels, then the metric, best-iterate copy and flux of each
-// frame.  Queued on `st` without synchronising.
+// One iteration for n frames of plan p, their projections batched (each
+// frame with its own update rule and background b):
+//   RL:   rho = y / (A x^{k-1} + b),  x^k = x^{k-1} * A^T rho / c;
+//   ISRA: rho = A x^{k-1} + b,        x^k = x^{k-1} * A^T y / A^T rho;
+// the exact update at the weakly observed voxels, then the metric,
+// best-iterate copy and flux of each frame.  Queued on `st` without
+// synchronising.
 static int step_frames(lfrl_plan_s *p, Frame *const *fr, int n, hipStream_t st)
 {
     FrameIO io[kMaxBatchJobs];
     for (int i = 0; i < n; ++i) {
         Frame &f = *fr[i];
         const int k = f.iters + 1;
-        io[i] = FrameIO{f.h, f.w, f.V[(k - 1) & 1], f.rho, f.y, nullptr};
+        const bool isra = f.opts.update == LFRL_UPDATE_ISRA;
+        io[i] = FrameIO{f.h, f.w, f.V[(k - 1) & 1], f.rho, f.y, nullptr,
+                        (float)f.opts.background, isra ? EPI_STORE : EPI_RATIO};
     }
     int rc = run_forward(p, io, n, EPI_RATIO, st);
     if (rc)
@@ -2708,7 +2803,9 @@ static int step_frames(lfrl_plan_s *p, Frame *const *fr, int n, hipStream_t st)
     for (int i = 0; i < n; ++i) {
         Frame &f = *fr[i];
         const int k = f.iters + 1;
-        io[i] = FrameIO{f.h, f.w, f.rho, f.V[k & 1], f.V[(k - 1) & 1], f.sens};
+        const bool isra = f.opts.update == LFRL_UPDATE_ISRA;
+        io[i] = FrameIO{f.h, f.w, f.rho, f.V[k & 1], f.V[(k - 1) & 1], isra ? f.D : f.sens,
+                        0.f, isra ? EPI_ISRA : EPI_UPDATE};
     }
     rc = run_backward(p, io, n, EPI_UPDATE, st);
     if (rc)
@@ -2720,14 +2817,17 @@ static int step_frames(lfrl_plan_s *p, Frame *const *fr, int n, hipStream_t st)
         float *nxt = f.V[k & 1];
         const size_t nvox = (size_t)p->g.Nz * f.h * f.w;
         if (f.nweak) {
+            const bool isra = f.opts.update == LFRL_UPDATE_ISRA;
             hipLaunchKernelGGL(k_weak_exact, dim3(f.nweak), dim3(256), 0, st,
                                (const unsigned *)f.weak, (const float *)p->psf, p->g.N, p->g.K,
-                               f.h, f.w, (const float *)f.rho, f.sens, cur, nxt, (int)WEAK_UPDATE);
+                               f.h, f.w, (const float *)f.rho, f.sens, cur, (const float *)f.D,
+                               nxt, (int)(isra ? WEAK_ISRA : WEAK_UPDATE));
             LAUNCH_CHECK("k_weak_exact(update)");
         }
         if (f.opts.stop != LFRL_STOP_NONE) {
-            rc = run_metric(p->g.Nz, f.h, f.w, nxt, f.opts.xs, f.opts.ys, f.metric_out,
-                            frame_metric_bufs(f), f.state, f.trace, k, f.opts.patience, st);
+            rc = run_metric(p->g.Nz, f.h, f.w, nxt, f.opts.xs, f.opts.ys, f.opts.region,
+                            f.opts.norm, f.metric_out, frame_metric_bufs(f), f.state, f.trace, k,
+                            f.opts.patience, f.opts.window, st);
             if (rc)
                 return rc;
             hipLaunchKernelGGL(k_cond_copy, dim3(1024), dim3(256), 0, st,
@@ -2861,9 +2961,22 @@ extern "C" int lfrl_deconvolve(lfrl_plan_t p, int32_t h, int32_t w, const float 
     const char *genv = getenv("LFRL_GRAPH");
     const bool use_graph = opts->stop != LFRL_STOP_METRIC && !p->prof && !(genv && genv[0] == '0');
     if (use_graph) {
-        const lfrl_plan_s::GraphKey key{h, w, opts->max_iters, opts->stop, opts->patience,
-                                         opts->init, f.want_flux ? 1 : 0, opts->xs, opts->ys,
-                                         img, vol};
+        const lfrl_plan_s::GraphKey key{h,
+                                         w,
+                                         opts->max_iters,
+                                         opts->stop,
+                                         opts->patience,
+                                         opts->init,
+                                         f.want_flux ? 1 : 0,
+                                         opts->update,
+                                         opts->region,
+                                         opts->norm,
+                                         opts->window,
+                                         opts->xs,
+                                         opts->ys,
+                                         opts->background,
+                                         img,
+                                         vol};
         if (!(p->graph_exec && p->graph_key == key)) {
             if (p->graph_exec)
                 (void)hipGraphExecDestroy(p->graph_exec);
@@ -2878,7 +2991,7 @@ extern "C" int lfrl_deconvolve(lfrl_plan_t p, int32_t h, int32_t w, const float 
             f.tab_h = f.tab_nv = f.tab_w = f.tab_nu = -1;
             HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
             Frame *one[1] = {&f};
-            rc = frame_start(f, p->g.Nz, opts->init == 1 ? vol : nullptr, p->cap_stream);
+            rc = frame_start(p, f, opts->init == 1 ? vol : nullptr, p->cap_stream);
             while (rc == LFRL_OK && f.iters < opts->max_iters)
                 rc = step_frames(p, one, 1, p->cap_stream);
             hipGraph_t gr = nullptr;
@@ -2903,7 +3016,7 @@ extern "C" int lfrl_deconvolve(lfrl_plan_t p, int32_t h, int32_t w, const float 
         f.stopped = false;
         return frame_result(f, p->g.Nz, vol, report, st);
     }
-    if ((rc = frame_start(f, p->g.Nz, opts->init == 1 ? vol : nullptr, st)))
+    if ((rc = frame_start(p, f, opts->init == 1 ? vol : nullptr, st)))
         return rc;
     Frame *one[1] = {&f};
     while (!f.done) {
@@ -3085,7 +3198,7 @@ extern "C" int lfrl_job_create(lfrl_job_t *out, lfrl_plan_t p, int32_t h, int32_
     }
     f.y = f.y_own;
     if ((rc = job_sensitivity(p, f, st)) ||
-        (rc = frame_start(f, p->g.Nz, opts->init == 1 ? vol0 : nullptr, st)) ||
+        (rc = frame_start(p, f, opts->init == 1 ? vol0 : nullptr, st)) ||
         (rc = job_mark(j, st))) {
         const std::string msg = lfrl_last_error();
         (void)hipStreamSynchronize(st);
@@ -3314,11 +3427,22 @@ static void free_metric_scratch(MetricScratch &ms)
 extern "C" int lfrl_metric(int32_t nz, int32_t h, int32_t w, const float *img, double xs,
                            double ys, double *out, void *stream)
 {
+    return lfrl_metric_ex(nz, h, w, img, xs, ys, LFRL_REGION_TRIANGLE, LFRL_NORM_MATRIX, out,
+                          stream);
+}
+
+extern "C" int lfrl_metric_ex(int32_t nz, int32_t h, int32_t w, const float *img, double xs,
+                              double ys, int32_t region, int32_t norm, double *out, void *stream)
+{
     if (!img || !out)
         return set_error(LFRL_ERR_ARG, "NULL argument");
     if (nz < 1 || h < 1 || w < 1)
         return set_error(LFRL_ERR_ARG, "nz, h, w must be >= 1");
-    int rc = check_legs(xs, ys);
+    if (region < LFRL_REGION_TRIANGLE || region > LFRL_REGION_WHOLE)
+        return set_error(LFRL_ERR_ARG, "unknown metric region %d", region);
+    if (norm != LFRL_NORM_MATRIX && norm != LFRL_NORM_REGION)
+        return set_error(LFRL_ERR_ARG, "unknown metric norm %d", norm);
+    int rc = check_legs(xs, ys, region);
     if (rc)
         return rc;
     if ((rc = check_buf(img, (size_t)nz * h * w * sizeof(float), "img")) ||
@@ -3335,13 +3459,16 @@ extern "C" int lfrl_metric(int32_t nz, int32_t h, int32_t w, const float *img, d
             HIP_TRY(hipDeviceSynchronize());
             free_metric_scratch(ms);
         }
+        // room for the whole coefficient matrix of an hc x wc image
         const size_t hc = std::max<size_t>(h, 1024), wc = std::max<size_t>(w, 1024);
         rc = dalloc(&ms.mip, hc * wc * sizeof(float));
-        if (!rc) rc = dalloc(&ms.tabH, (size_t)kMaxMetricLegs * hc * sizeof(double));
-        if (!rc) rc = dalloc(&ms.tabW, (size_t)kMaxMetricLegs * wc * sizeof(double));
-        if (!rc) rc = dalloc(&ms.T1, (size_t)kMetricChunks * kMaxMetricLegs * wc * sizeof(double));
+        if (!rc) rc = dalloc(&ms.tabH, hc * hc * sizeof(double));
+        if (!rc) rc = dalloc(&ms.tabW, wc * wc * sizeof(double));
+        if (!rc)
+            rc = dalloc(&ms.T1, std::max((size_t)kMetricChunks * kMaxMetricLegs * wc, hc * wc) *
+                                    sizeof(double));
         if (!rc) rc = dalloc(&ms.n2p, (hc * wc + 255) / 256 * sizeof(double));
-        if (!rc) rc = dalloc(&ms.Fabs, (size_t)kMaxMetricLegs * kMaxMetricLegs * sizeof(double));
+        if (!rc) rc = dalloc(&ms.Fabs, hc * wc * sizeof(double));
         if (rc) {
             free_metric_scratch(ms);
             return rc;
@@ -3351,7 +3478,8 @@ extern "C" int lfrl_metric(int32_t nz, int32_t h, int32_t w, const float *img, d
     }
     const MetricBufs mb{ms.mip, ms.tabH, ms.tabW, ms.T1, ms.n2p, ms.Fabs,
                         nullptr, nullptr, nullptr, nullptr};
-    return run_metric(nz, h, w, img, xs, ys, out, mb, nullptr, nullptr, 0, 1, (hipStream_t)stream);
+    return run_metric(nz, h, w, img, xs, ys, region, norm, out, mb, nullptr, nullptr, 0, 1, 1,
+                      (hipStream_t)stream);
 }
 
 extern "C" int lfrl_metric_cutoff(double d_ml, double mag, int32_t nnum, double lambda, double na,

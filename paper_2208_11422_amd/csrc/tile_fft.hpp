@@ -147,11 +147,21 @@ static constexpr int kEpiBatch = 8;      // inverse: epilogue pixels per thread
 // spectra stream once for the whole batch.
 static constexpr int kMaxBatchJobs = 16;
 
+// Per-pixel epilogues of the inverse transform (val = the transformed value,
+// b = the frame's background):
+//   EPI_STORE   dst = val + b
+//   EPI_RATIO   dst = aux0 / (val + b), 0 where val + b <= 0   (aux0 = y)
+//   EPI_UPDATE  dst = aux0 * val / aux1, 0 where aux1 <= 0     (x_old, A^T 1)
+//   EPI_ISRA    dst = aux0 * aux1 / val, 0 where val <= 0      (x_old, A^T y)
+enum { EPI_STORE = 0, EPI_RATIO = 1, EPI_UPDATE = 2, EPI_ISRA = 3 };
+
 struct TileJob {
     const float *src;   // forward transform: source planes [planes][H][W]
     float *dst;         // inverse transform: destination (planes or image)
-    const float *aux0;  // inverse transform: y (ratio) or x_old (update)
-    const float *aux1;  // inverse transform: A^T 1 (update)
+    const float *aux0;  // inverse transform: y (ratio) or x_old (updates)
+    const float *aux1;  // inverse transform: A^T 1 (RL update) or A^T y (ISRA)
+    float bg;           // inverse transform: background b
+    int mode;           // inverse transform: epilogue
     int H, W, tiles_x, tile0;
 };
 
@@ -353,8 +363,7 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
                                                   const float2 *__restrict__ spec,
                                                   size_t split_stride, int nsplit, size_t sk,
                                                   size_t stile, size_t sc, int N, int planes,
-                                                  int T, int hD, int mode,
-                                                  const float2 *__restrict__ twg)
+                                                  int T, int hD, const float2 *__restrict__ twg)
 {
     constexpr int QH = Q / 2 + 1;
     extern __shared__ float smem[];
@@ -371,6 +380,8 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
     float *__restrict__ dst = fj.dst;
     const float *__restrict__ aux0 = fj.aux0;
     const float *__restrict__ aux1 = fj.aux1;
+    const int mode = fj.mode;
+    const float bg = fj.bg;
     for (int i = tid; i < Q; i += blockDim.x)
         tw[i] = twg[i];
     __syncthreads();
@@ -465,21 +476,25 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
             ok[b] = base + b * (int)blockDim.x < ototal && Lr < Ly && Lc < Lx;
             const int pr = min(N * Lr + ar, H - 1), pc = min(N * tx * T + rem, W - 1);
             const size_t pix = (size_t)pr * W + pc;
-            o[b] = (mode == 1 ? 0 : (size_t)j * H * W) + pix;
-            a0[b] = (mode != 0) ? aux0[o[b]] : 0.f;
-            a1[b] = (mode == 2) ? aux1[o[b]] : 0.f;
+            o[b] = (mode == EPI_RATIO ? 0 : (size_t)j * H * W) + pix;
+            a0[b] = (mode != EPI_STORE) ? aux0[o[b]] : 0.f;
+            a1[b] = (mode >= EPI_UPDATE) ? aux1[o[b]] : 0.f;
         }
 #pragma unroll
         for (int b = 0; b < kEpiBatch; ++b) {
             if (!ok[b])
                 continue;
             const float val = obuf[base + b * (int)blockDim.x];
-            if (mode == 0)
-                dst[o[b]] = val;
-            else if (mode == 1)
-                dst[o[b]] = val > 0.f ? a0[b] / val : 0.f;
-            else
+            if (mode == EPI_STORE) {
+                dst[o[b]] = val + bg;
+            } else if (mode == EPI_RATIO) {
+                const float m = val + bg;
+                dst[o[b]] = m > 0.f ? a0[b] / m : 0.f;
+            } else if (mode == EPI_UPDATE) {
                 dst[o[b]] = a1[b] > 0.f ? a0[b] * val / a1[b] : 0.f;
+            } else {
+                dst[o[b]] = val > 0.f ? a0[b] * a1[b] / val : 0.f;
+            }
         }
     }
 }

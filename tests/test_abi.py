@@ -87,3 +87,42 @@ def test_null_arguments_rejected_before_device_work(lib):
     assert lf._load().lfrl_plan(ctypes.byref(h), ctypes.byref(d), None, None) == -1
     assert "psf" in lf.lfrl_last_error()
     assert lib.lfrl_plan_destroy(None) == 0
+
+
+@pytest.mark.parametrize("region,norm,xs,msg", [
+    (3, 0, 4.0, "region"),
+    (-1, 0, 4.0, "region"),
+    (0, 2, 4.0, "norm"),
+    (0, 0, 0.0, "legs"),
+    (1, 0, 300.0, "legs"),
+])
+def test_metric_variant_arguments_rejected_before_device_work(region, norm, xs, msg):
+    """Unknown regions and norms, and legs the triangle or rectangle cannot
+    take, are argument errors raised before any device work."""
+    import paper_2208_11422_amd as lf
+    lib = lf._load()
+    fake = ctypes.c_void_p(0x1000)
+    rc = lib.lfrl_metric_ex(1, 16, 16, fake, xs, 4.0, region, norm, fake, None)
+    assert rc in (-1, -4)
+    assert msg in lf.lfrl_last_error()
+
+
+def test_rl_opts_layout_and_defaults():
+    """The option struct keeps the header's field order (a zero-filled tail is
+    the method as the paper states it), and the keyword helper fills it."""
+    import paper_2208_11422_amd as lf
+    names = [f for f, _ in lf.RlOpts._fields_]
+    text = open(HEADER).read()
+    body = text[text.index("typedef struct {\n    int32_t max_iters;"):]
+    body = body[:body.index("} lfrl_rl_opts;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    declared = re.findall(r"\b(?:int32_t|double)\s+([a-z_, ]+);", body)
+    flat = [n.strip() for grp in declared for n in grp.split(",")]
+    assert names == flat
+    o = lf.RlOpts(max_iters=3)
+    assert (o.update, o.region, o.norm, o.window, o.background) == (0, 0, 0, 0, 0.0)
+    o = lf.rl_opts(5, lf.STOP_METRIC, 2, 3.0, 4.0, update=lf.UPDATE_ISRA, background=2.5,
+                   backproject_start=True, region=lf.REGION_WHOLE, norm=lf.NORM_REGION, window=3)
+    assert (o.init, o.update, o.region, o.norm, o.window, o.background) == (2, 1, 2, 1, 3, 2.5)
+    with pytest.raises(lf.LfrlError):
+        lf.rl_opts(5, given_start=True, backproject_start=True)
