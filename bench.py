@@ -370,6 +370,48 @@ def serving_leg(args, dev) -> dict:
     return out
 
 
+def variants_leg(args, lf, plan, y_d, vol, h, w, xs, ys, background, ms_rl) -> dict:
+    """The variants on the headline workload: ISRA with the background term from
+    the back projection start, RL with the background and the window stop on
+    the rectangle with the region norm, and the whole-matrix metric alone."""
+    import torch
+    out = {}
+    steps = max(args.steps, 1)
+    runs = {
+        "isra_background_backproject": dict(update=lf.UPDATE_ISRA, background=background,
+                                            backproject_start=True),
+        "rl_background_rectangle_window3": dict(background=background,
+                                                region=lf.REGION_RECTANGLE,
+                                                norm=lf.NORM_REGION, window=3),
+    }
+    for name, kw in runs.items():
+        opts = lf.rl_opts(max(args.warmup, 1), lf.STOP_TRACK, 1, xs, ys, **kw)
+        lf.lfrl_deconvolve(plan.handle, h, w, y_d, vol, opts)
+        torch.cuda.synchronize()
+        opts.max_iters = steps
+        t0 = time.perf_counter()
+        rep = lf.lfrl_deconvolve(plan.handle, h, w, y_d, vol, opts)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / steps
+        out[name] = {"value": 1000.0 / ms, "unit": "iters/s", "ms_per_step": ms,
+                     "vs_rl": ms_rl / ms, "best_iter": rep["best_iter"]}
+        log(f"bench: variant {name}: {ms:.3f} ms/iter ({1000.0 / ms:.1f} it/s)")
+    out["isra_background_backproject"]["note"] = "includes the one back projection A^T y"
+    res = torch.empty(1, dtype=torch.float64, device=vol.device)
+    for name, region in (("triangle", lf.REGION_TRIANGLE), ("whole", lf.REGION_WHOLE)):
+        nz = vol.shape[0]
+        lf.lfrl_metric_ex(nz, h, w, vol, xs, ys, region, lf.NORM_MATRIX, res)
+        torch.cuda.synchronize()
+        calls = 20
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            lf.lfrl_metric_ex(nz, h, w, vol, xs, ys, region, lf.NORM_MATRIX, res)
+        torch.cuda.synchronize()
+        out[f"metric_{name}_ms"] = (time.perf_counter() - t0) * 1000.0 / calls
+        log(f"bench: metric {name}: {out[f'metric_{name}_ms']:.3f} ms per call")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -390,6 +432,8 @@ def main() -> int:
     ap.add_argument("--serving-active", type=int, default=32, help="jobs in flight at most")
     ap.add_argument("--serving-budget-gb", type=float, default=96.0,
                     help="device memory admitted jobs may hold")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the update / metric variant leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy (reference kernel of known "
                          "size for hardware byte counters)")
@@ -506,8 +550,11 @@ def main() -> int:
         },
         "kernels": kern,
     }
+    vol32 = vol.clone()  # the FP32 result the split legs are compared with
+    if not args.no_variants:
+        out["variants"] = variants_leg(args, lf, plan, y_d, vol, h, w, xs, ys,
+                                       float(p["background"]), ms_per_step)
     if not args.no_split:
-        vol32 = vol.clone()
         plan.close()
         torch.cuda.empty_cache()
         psf_d = torch.from_numpy(p["psf_array"]).to(dev)

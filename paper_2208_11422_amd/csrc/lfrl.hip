@@ -74,6 +74,7 @@ static constexpr int kMaxNN = 256;      // nnum^2 (one thread per output phase)
 static constexpr int kMaxTrace = 4096;  // iterations recorded per deconvolve call
 static constexpr int kMetricChunks = 8;   // row chunks of the DCT row transform
 static constexpr int kMaxMetricLegs = 256;
+static constexpr int kMetricBigCoefs = 16384;  // above: entropy summed over many blocks
 static constexpr float kWeakThreshold = 1e-2f;  // weak voxel: A^T 1 < this * max A^T 1
 
 // ---------------------------------------------------------------------------
@@ -882,6 +883,123 @@ __global__ void k_metric_coeffs(const double *__restrict__ T1, int nchunks, int 
         Fabs[wave] = fabs(acc);
 }
 
+// Whole-matrix DCT passes as tiled float64 matrix products:
+//   C[m][n] = sum_k A[m][k] * B(k, n),  B(k, n) = BT ? B[n * ldb + k] : B[k * ldb + n],
+// A row-major with leading dimension lda.  ABS: C holds |value| (coefficient
+// magnitudes).  32 x 32 outputs per 256-thread block (2 x 2 per thread), k in
+// slices of 32 staged in LDS; edges are zero-filled.
+template <bool BT, bool ABS, typename TB>
+__global__ __launch_bounds__(256) void k_dgemm32(const double *__restrict__ A, int lda,
+                                                 const TB *__restrict__ B, int ldb, int M, int N,
+                                                 int K, double *__restrict__ C, int ldc)
+{
+    __shared__ double As[32][33];  // [k][m]
+    __shared__ double Bs[32][33];  // [k][n]
+    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int idx = tid + 256 * r;
+            const int mm = idx / 32, kk = idx % 32;
+            const int gm = m0 + mm, gk = k0 + kk;
+            As[kk][mm] = (gm < M && gk < K) ? A[(size_t)gm * lda + gk] : 0.0;
+            if (BT) {
+                const int gn = n0 + mm;
+                Bs[kk][mm] = (gn < N && gk < K) ? (double)B[(size_t)gn * ldb + gk] : 0.0;
+            } else {
+                const int gk2 = k0 + idx / 32, gn = n0 + idx % 32;
+                Bs[idx / 32][idx % 32] =
+                    (gn < N && gk2 < K) ? (double)B[(size_t)gk2 * ldb + gn] : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < 32; ++kk) {
+            const double a0 = As[kk][ty], a1 = As[kk][ty + 16];
+            const double b0 = Bs[kk][tx], b1 = Bs[kk][tx + 16];
+            acc[0][0] = fma(a0, b0, acc[0][0]);
+            acc[0][1] = fma(a0, b1, acc[0][1]);
+            acc[1][0] = fma(a1, b0, acc[1][0]);
+            acc[1][1] = fma(a1, b1, acc[1][1]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+            const int m = m0 + ty + 16 * i, n = n0 + tx + 16 * jj;
+            if (m < M && n < N)
+                C[(size_t)m * ldc + n] = ABS ? fabs(acc[i][jj]) : acc[i][jj];
+        }
+}
+
+// Per-block partial sums of |F|^2 over the coefficients inside the region
+// (Fabs >= 0), for the region norm of a large coefficient set.
+__global__ void k_sq_partial(const double *__restrict__ Fabs, int ncoef, double *__restrict__ part)
+{
+    __shared__ double red[256];
+    double a = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ncoef; i += gridDim.x * blockDim.x) {
+        const double f = Fabs[i];
+        if (f > 0.0)
+            a += f * f;
+    }
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = red[0];
+}
+
+// Per-block partial sums of p log2 p, p = |F| / n over the coefficients inside
+// the region.  Every block forms n^2 from the same partial sums (n2src,
+// n2count) in the same order, so all blocks divide by the same n.
+__global__ void k_entropy_partial(const double *__restrict__ n2src, int n2count,
+                                  const double *__restrict__ Fabs, int ncoef,
+                                  double *__restrict__ part)
+{
+    __shared__ double red[256];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n2count; i += blockDim.x)
+        a += n2src[i];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    const double n = sqrt(red[0]);
+    __syncthreads();
+    double e = 0.0;
+    if (n > 0.0) {
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ncoef;
+             i += gridDim.x * blockDim.x) {
+            const double f = Fabs[i];
+            if (f > 0.0) {
+                const double p = f / n;
+                e += p * log2(p);
+            }
+        }
+    }
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = red[0];
+}
+
 // Device-side Richardson-Lucy stop state.
 struct StopState {
     double best_e;
@@ -902,14 +1020,20 @@ struct StopState {
 // recorded: trace[k-1] = e, the best iterate is tracked (ties: later) and the
 // stop flag raised after `patience` consecutive strict decreases of the mean
 // of the last `window` values (trace must then hold e_1 .. e_k).
+//
+// With ent_part != nullptr the entropy sum arrives as nent block partials of
+// k_entropy_partial instead (large coefficient sets) and Fabs is not read.
 __global__ void k_metric_final(const double *__restrict__ n2p, int n2count,
                                const double *__restrict__ Fabs, int ncoef, int norm, double area,
                                double *__restrict__ out, StopState *st, double *trace, int k,
-                               int patience, int window)
+                               int patience, int window, const double *__restrict__ ent_part,
+                               int nent)
 {
     __shared__ double red[256];
     double a = 0.0;
-    if (norm == LFRL_NORM_REGION) {
+    if (ent_part) {
+        a = 0.0;
+    } else if (norm == LFRL_NORM_REGION) {
         for (int i = threadIdx.x; i < ncoef; i += blockDim.x) {
             const double f = Fabs[i];
             if (f > 0.0)
@@ -926,10 +1050,13 @@ __global__ void k_metric_final(const double *__restrict__ n2p, int n2count,
             red[threadIdx.x] += red[threadIdx.x + off];
         __syncthreads();
     }
-    const double n = sqrt(red[0]);
+    const double n = ent_part ? 1.0 : sqrt(red[0]);
     __syncthreads();
     double e_part = 0.0;
-    if (n > 0.0) {
+    if (ent_part) {
+        for (int i = threadIdx.x; i < nent; i += blockDim.x)
+            e_part += ent_part[i];
+    } else if (n > 0.0) {
         for (int i = threadIdx.x; i < ncoef; i += blockDim.x) {
             const double f = Fabs[i];
             if (f > 0.0) {
@@ -946,7 +1073,7 @@ __global__ void k_metric_final(const double *__restrict__ n2p, int n2count,
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const double e = (n > 0.0) ? -(1.0 / area) * red[0] : 0.0;
+        const double e = (n > 0.0 && red[0] != 0.0) ? -(1.0 / area) * red[0] : 0.0;
         out[0] = e;
         if (st) {
             trace[k - 1] = e;
@@ -2579,21 +2706,53 @@ static int run_metric(int nz, int h, int w, const float *vol, double xs, double 
     const int nblk = (int)((hw + 255) / 256);
     hipLaunchKernelGGL(k_mip, dim3(nblk), dim3(256), 0, st, vol, nz, hw, mb.mip, mb.n2p);
     LAUNCH_CHECK("k_mip");
-    // the row transform of the whole matrix fits the buffers as one chunk
-    const int chunks = whole ? 1 : std::min(kMetricChunks, h);
-    const int rpc = (h + chunks - 1) / chunks;
-    const int nchunks = (h + rpc - 1) / rpc;
-    hipLaunchKernelGGL(k_dct_rows, dim3((nv * w + 255) / 256, nchunks), dim3(256), 0, st,
-                       (const float *)mb.mip, h, w, (const double *)mb.tabH, nv, rpc, mb.T1);
-    LAUNCH_CHECK("k_dct_rows");
     const int ncoef = nv * nu;
-    hipLaunchKernelGGL(k_metric_coeffs, dim3((ncoef + 3) / 4), dim3(256), 0, st,
-                       (const double *)mb.T1, nchunks, nv, nu, w, (const double *)mb.tabW, xs, ys,
-                       region, mb.Fabs);
-    LAUNCH_CHECK("k_metric_coeffs");
+    if (whole) {
+        // both passes as dense products: T1 = C_H m, |F| = |T1 C_W^T|
+        hipLaunchKernelGGL((k_dgemm32<false, false, float>), dim3((w + 31) / 32, (h + 31) / 32),
+                           dim3(256), 0, st, (const double *)mb.tabH, h, (const float *)mb.mip, w,
+                           h, w, h, mb.T1, w);
+        LAUNCH_CHECK("k_dgemm32(rows)");
+        hipLaunchKernelGGL((k_dgemm32<true, true, double>), dim3((w + 31) / 32, (h + 31) / 32),
+                           dim3(256), 0, st, (const double *)mb.T1, w, (const double *)mb.tabW, w,
+                           h, w, w, mb.Fabs, w);
+        LAUNCH_CHECK("k_dgemm32(columns)");
+    } else {
+        const int chunks = std::min(kMetricChunks, h);
+        const int rpc = (h + chunks - 1) / chunks;
+        const int nchunks = (h + rpc - 1) / rpc;
+        hipLaunchKernelGGL(k_dct_rows, dim3((nv * w + 255) / 256, nchunks), dim3(256), 0, st,
+                           (const float *)mb.mip, h, w, (const double *)mb.tabH, nv, rpc, mb.T1);
+        LAUNCH_CHECK("k_dct_rows");
+        hipLaunchKernelGGL(k_metric_coeffs, dim3((ncoef + 3) / 4), dim3(256), 0, st,
+                           (const double *)mb.T1, nchunks, nv, nu, w, (const double *)mb.tabW, xs,
+                           ys, region, mb.Fabs);
+        LAUNCH_CHECK("k_metric_coeffs");
+    }
+    // large coefficient sets: the entropy sum over many blocks, its partials in
+    // T1 (free once the coefficients are formed; it holds >= 8 * 16384 doubles)
+    const double *ent = nullptr;
+    int nent = 0;
+    if (ncoef > kMetricBigCoefs) {
+        double *sq = mb.T1, *part = mb.T1 + kDotBlocks;
+        const double *n2src = mb.n2p;
+        int n2count = nblk;
+        if (norm == LFRL_NORM_REGION) {
+            hipLaunchKernelGGL(k_sq_partial, dim3(kDotBlocks), dim3(256), 0, st,
+                               (const double *)mb.Fabs, ncoef, sq);
+            LAUNCH_CHECK("k_sq_partial");
+            n2src = sq;
+            n2count = kDotBlocks;
+        }
+        hipLaunchKernelGGL(k_entropy_partial, dim3(kDotBlocks), dim3(256), 0, st, n2src, n2count,
+                           (const double *)mb.Fabs, ncoef, part);
+        LAUNCH_CHECK("k_entropy_partial");
+        ent = part;
+        nent = kDotBlocks;
+    }
     hipLaunchKernelGGL(k_metric_final, dim3(1), dim3(256), 0, st, (const double *)mb.n2p, nblk,
                        (const double *)mb.Fabs, ncoef, norm, region_area(region, xs, ys, h, w),
-                       out, st_dev, trace, k, patience, std::max(1, window));
+                       out, st_dev, trace, k, patience, std::max(1, window), ent, nent);
     LAUNCH_CHECK("k_metric_final");
     return LFRL_OK;
 }

@@ -145,7 +145,7 @@ def test_isra_split_precision(lf, precision):
 @pytest.mark.parametrize("region", ["triangle", "rectangle", "whole"])
 @pytest.mark.parametrize("norm", ["full", "region"])
 @pytest.mark.parametrize("nz,h,w,xs,ys", [(1, 55, 55, 5.5, 5.5), (3, 40, 64, 7.3, 3.9),
-                                         (1, 600, 600, 10.0, 10.0)])
+                                         (1, 600, 600, 10.0, 10.0), (2, 300, 420, 230.0, 180.0)])
 def test_metric_variants_match_oracle(lf, region, norm, nz, h, w, xs, ys):
     rng = np.random.default_rng(h * w + nz)
     vol = rng.uniform(0.0, 1.0, size=(nz, h, w)).astype(np.float32)
