@@ -1383,6 +1383,7 @@ __global__ void k_zero_u32(unsigned *p)
 }
 
 enum { WEAK_SENS = 0, WEAK_UPDATE = 1, WEAK_STORE = 2, WEAK_ISRA = 3 };
+static constexpr int kWeakThreads = 512;  // threads per weak voxel (a power of two)
 
 // One block per listed voxel (j, r, s): the exact window sum
 //   acc = sum_{taps inside the image} h[j][r mod N][s mod N][u][v] * img[r+u-c0][s+v-c0]
@@ -1396,7 +1397,7 @@ __global__ void k_weak_exact(const unsigned *__restrict__ list, const float *__r
                              float *__restrict__ sens, const float *__restrict__ src,
                              const float *__restrict__ aux, float *__restrict__ dst, int mode)
 {
-    __shared__ double red[256];
+    __shared__ double red[kWeakThreads];
     const unsigned vox = list[blockIdx.x];
     const size_t hw = (size_t)H * W;
     const int j = (int)(vox / hw);
@@ -1408,10 +1409,31 @@ __global__ void k_weak_exact(const unsigned *__restrict__ list, const float *__r
     const float *hk = psf + (((size_t)j * N + r % N) * N + s % N) * (size_t)K * K;
     double acc = 0.0;
     const int total = wu * wv;
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-        const int u = u0 + idx / wv, v = v0 + idx % wv;
-        const double hv = (double)hk[(size_t)u * K + v];
-        acc += img ? hv * (double)img[(size_t)(r + u - c0) * W + (s + v - c0)] : hv;
+    if (total > 0) {
+        // tap idx = uu * wv + vv, advanced by blockDim.x without dividing per
+        // tap; 8 taps' loads are issued before their products (clamped
+        // addresses, taps past the window cleared by a mask)
+        const int dq = blockDim.x / wv, dr = blockDim.x % wv;
+        int uu = threadIdx.x / wv, vv = threadIdx.x % wv;
+        for (int base = threadIdx.x; base < total; base += 8 * blockDim.x) {
+            float hv[8], iv[8];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool ok = base + b * (int)blockDim.x < total;
+                const int u = u0 + min(uu, wu - 1), v = v0 + vv;
+                hv[b] = keep_if(hk[(size_t)u * K + v], ok);
+                iv[b] = keep_if(img ? img[(size_t)(r + u - c0) * W + (s + v - c0)] : 1.0f, ok);
+                uu += dq;
+                vv += dr;
+                if (vv >= wv) {
+                    vv -= wv;
+                    ++uu;
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+                acc = fma((double)hv[b], (double)iv[b], acc);
+        }
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -2826,7 +2848,7 @@ static int frame_sensitivity(lfrl_plan_s *p, Frame &f, bool check_input, hipStre
         return set_error(LFRL_ERR_NUMERIC, "image has negative or non-finite values");
     f.nweak = std::min(found, f.weak_cap);
     if (f.nweak) {
-        hipLaunchKernelGGL(k_weak_exact, dim3(f.nweak), dim3(256), 0, st, (const unsigned *)f.weak,
+        hipLaunchKernelGGL(k_weak_exact, dim3(f.nweak), dim3(kWeakThreads), 0, st, (const unsigned *)f.weak,
                            (const float *)p->psf, p->g.N, p->g.K, h, w, (const float *)nullptr,
                            f.sens, (const float *)nullptr, (const float *)nullptr, (float *)nullptr,
                            (int)WEAK_SENS);
@@ -2899,7 +2921,7 @@ static int frame_backproject_image(lfrl_plan_s *p, Frame &f, hipStream_t st)
     if (rc)
         return rc;
     if (f.nweak) {
-        hipLaunchKernelGGL(k_weak_exact, dim3(f.nweak), dim3(256), 0, st, (const unsigned *)f.weak,
+        hipLaunchKernelGGL(k_weak_exact, dim3(f.nweak), dim3(kWeakThreads), 0, st, (const unsigned *)f.weak,
                            (const float *)p->psf, p->g.N, p->g.K, f.h, f.w, f.y, f.sens,
                            (const float *)nullptr, (const float *)nullptr, f.D, (int)WEAK_STORE);
         LAUNCH_CHECK("k_weak_exact(store)");
@@ -2977,7 +2999,7 @@ static int step_frames(lfrl_plan_s *p, Frame *const *fr, int n, hipStream_t st)
         const size_t nvox = (size_t)p->g.Nz * f.h * f.w;
         if (f.nweak) {
             const bool isra = f.opts.update == LFRL_UPDATE_ISRA;
-            hipLaunchKernelGGL(k_weak_exact, dim3(f.nweak), dim3(256), 0, st,
+            hipLaunchKernelGGL(k_weak_exact, dim3(f.nweak), dim3(kWeakThreads), 0, st,
                                (const unsigned *)f.weak, (const float *)p->psf, p->g.N, p->g.K,
                                f.h, f.w, (const float *)f.rho, f.sens, cur, (const float *)f.D,
                                nxt, (int)(isra ? WEAK_ISRA : WEAK_UPDATE));
