@@ -812,9 +812,17 @@ __global__ void k_mip(const float *__restrict__ vol, int nz, size_t hw, float *_
     const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     double sq = 0.0;
     if (i < hw) {
+        // planes in batches of 8 loads (clamped: a repeated plane leaves the max)
         float m = vol[i];
-        for (int j = 1; j < nz; ++j)
-            m = fmaxf(m, vol[(size_t)j * hw + i]);
+        for (int j0 = 1; j0 < nz; j0 += 8) {
+            float v[8];
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+                v[b] = vol[(size_t)min(j0 + b, nz - 1) * hw + i];
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+                m = fmaxf(m, v[b]);
+        }
         mip[i] = m;
         sq = (double)m * (double)m;
     }
@@ -843,9 +851,38 @@ __global__ void k_dct_rows(const float *__restrict__ mip, int H, int W,
     const int r0 = chunk * rows_per_chunk, r1 = min(H, r0 + rows_per_chunk);
     const double *tv = tabH + (size_t)v * H;
     double acc = 0.0;
-    for (int r = r0; r < r1; ++r)
+    int r = r0;
+    for (; r + 8 <= r1; r += 8) {
+        float m[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+            m[b] = mip[(size_t)(r + b) * W + s];
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+            acc = fma(tv[r + b], (double)m[b], acc);
+    }
+    for (; r < r1; ++r)
         acc = fma(tv[r], (double)mip[(size_t)r * W + s], acc);
     T1[(size_t)chunk * nv * W + idx] = acc;
+}
+
+// Fold the row chunks into the first: T1[0][v][s] = sum_chunk T1[chunk][v][s].
+__global__ void k_dct_fold(double *__restrict__ T1, int nchunks, int n)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n)
+        return;
+    double acc = T1[idx];
+    for (int c0 = 1; c0 < nchunks; c0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+            v[b] = T1[(size_t)min(c0 + b, nchunks - 1) * n + idx];
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+            acc += (c0 + b < nchunks) ? v[b] : 0.0;
+    }
+    T1[idx] = acc;
 }
 
 // One wave per candidate coefficient (v, u):
@@ -2740,15 +2777,24 @@ static int run_metric(int nz, int h, int w, const float *vol, double xs, double 
                            h, w, w, mb.Fabs, w);
         LAUNCH_CHECK("k_dgemm32(columns)");
     } else {
-        const int chunks = std::min(kMetricChunks, h);
+        // chunks of about 16 rows, as many as T1 holds (kMetricChunks blocks of
+        // min(h, kMaxMetricLegs) x w doubles), folded into the first before
+        // the column pass
+        const int cap = kMetricChunks * std::min(h, kMaxMetricLegs) / nv;
+        const int chunks = std::max(1, std::min((h + 15) / 16, cap));
         const int rpc = (h + chunks - 1) / chunks;
         const int nchunks = (h + rpc - 1) / rpc;
         hipLaunchKernelGGL(k_dct_rows, dim3((nv * w + 255) / 256, nchunks), dim3(256), 0, st,
                            (const float *)mb.mip, h, w, (const double *)mb.tabH, nv, rpc, mb.T1);
         LAUNCH_CHECK("k_dct_rows");
+        if (nchunks > 1) {
+            hipLaunchKernelGGL(k_dct_fold, dim3((nv * w + 255) / 256), dim3(256), 0, st, mb.T1,
+                               nchunks, nv * w);
+            LAUNCH_CHECK("k_dct_fold");
+        }
         hipLaunchKernelGGL(k_metric_coeffs, dim3((ncoef + 3) / 4), dim3(256), 0, st,
-                           (const double *)mb.T1, nchunks, nv, nu, w, (const double *)mb.tabW, xs,
-                           ys, region, mb.Fabs);
+                           (const double *)mb.T1, 1, nv, nu, w, (const double *)mb.tabW, xs, ys,
+                           region, mb.Fabs);
         LAUNCH_CHECK("k_metric_coeffs");
     }
     // large coefficient sets: the entropy sum over many blocks, its partials in
