@@ -16,6 +16,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -47,6 +48,30 @@ def contraction_bytes(info: dict, g, nt: int, kernel: str) -> float:
 
 def contraction_flops(info: dict, g, nt: int) -> float:
     return 8.0 * info["nfreq"] * g.nnum ** 2 * (g.nnum ** 2 * g.nz) * nt
+
+
+def iteration_model(info: dict, g, h: int, w: int, nt: int, ms_measured: float,
+                    spectra_bytes_per_coef: float = 8.0) -> dict:
+    """Roofline model of one whole iteration at the plan's tile shape.
+
+    Bytes: both PSF spectra passes, the tile spectra written and read around
+    each contraction, the volume reads of the tile gather (overlap included),
+    the update's volume traffic and the image-sized buffers.  Flops: the two
+    contractions plus the tile DFTs.  The floor is the PSF read once per
+    projection, whatever the shape."""
+    n, nz, k = g.nnum, g.nz, g.ksize
+    q, t, r, nf = info["tile_q"], info["tile_out"], info["taps"], info["nfreq"]
+    s_g = n ** 4 * nz * nf * spectra_bytes_per_coef
+    s_x = n ** 2 * nz * nt * nf * 8.0
+    b = (2 * s_g + 4 * s_x + 4.0 * w * h * nz * (((t + r - 1) / t) ** 2 + 3) + 24.0 * w * h)
+    f = 16.0 * n ** 4 * nz * nf * nt + 2.0 * (n * n * nz + n * n) * nt * 5 * q * q * math.log2(q * q)
+    t_hbm = b / (HBM_PEAK_GBS * 1e9) * 1e3
+    t_alu = f / (FP32_PEAK_TFLOPS * 1e12) * 1e3
+    floor = 2.0 * n * n * nz * k * k * 4 / (HBM_PEAK_GBS * 1e9) * 1e3
+    bound = max(t_hbm, t_alu)
+    return {"bytes_per_iter": b, "flops_per_iter": f, "t_hbm_ms": t_hbm, "t_fp32_ms": t_alu,
+            "t_bound_ms": bound, "frac_of_bound": bound / ms_measured,
+            "floor_ms": floor, "floor_frac": floor / ms_measured}
 
 
 def source_digest() -> str:
@@ -549,6 +574,7 @@ def main() -> int:
             / FP32_PEAK_TFLOPS,
         },
         "kernels": kern,
+        "model": iteration_model(info, g, h, w, nt, ms_per_step),
     }
     vol32 = vol.clone()  # the FP32 result the split legs are compared with
     if not args.no_variants:
@@ -577,6 +603,8 @@ def main() -> int:
         diff = float(torch.linalg.vector_norm(vol - vol32) / torch.linalg.vector_norm(vol32))
         out["split_fp16"] = {
             "value": 1000.0 / ms16, "unit": "iters/s", "ms_per_step": ms16,
+            "model": iteration_model(plan16.info, g, h, w, plan16.info["max_tiles"], ms16,
+                                     spectra_bytes_per_coef=4.0),
             "dtype": "f16 spectra, hi/lo f16 tile spectra, f32 accumulate",
             "rel_l2_vs_fp32_after_steps": diff,
             "speedup_vs_fp32": ms_per_step / ms16,
