@@ -183,7 +183,9 @@ __global__ __launch_bounds__(512) void k_contract_fwd_split(
 {
     typedef typename P::S S;
     typedef typename P::v8 V8;
-    const int k = blockIdx.x, s = blockIdx.y, t0 = blockIdx.z * 16;
+    int k, s, tg;
+    contraction_block(k, s, tg);
+    const int t0 = tg * 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, kg = lane >> 4;
     const int ncb = NNp / 16;
@@ -324,7 +326,9 @@ __global__ __launch_bounds__(256) void k_contract_adj_split(
     // LDS: per 16-c chunk and lane, 4 c values x {re hi, re lo, im hi, im lo}
     extern __shared__ unsigned short ra_bits[];
     S *ra = reinterpret_cast<S *>(ra_bits);
-    const int k = blockIdx.x, t0 = blockIdx.z * 16;
+    int k, by, tg;
+    contraction_block(k, by, tg);
+    const int t0 = tg * 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const int col = lane & 15, kg = lane >> 4;
     const int ncc = NNp / 16;
@@ -353,7 +357,7 @@ __global__ __launch_bounds__(256) void k_contract_adj_split(
     bool k_ok[CB];
 #pragma unroll
     for (int b = 0; b < CB; ++b) {
-        const int kb = (blockIdx.y * nwaves + wave) * CB + b;
+        const int kb = (by * nwaves + wave) * CB + b;
         k_ok[b] = kb < nkb;
         kbk[b] = min(kb, nkb - 1);
     }

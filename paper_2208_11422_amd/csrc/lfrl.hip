@@ -439,6 +439,31 @@ __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Block coordinates of a contraction launch on a (nf, y, tile groups) grid:
+// frequency k, the y index (K chunk or kk ranges) and the tile group.  With
+// several tile groups (batched frames), the groups of one (k, y) are
+// consecutive work items of one XCD: they stream the same PSF fragments at the
+// same time, so HBM delivers each fragment about once and that XCD's L2 the
+// other times, instead of once per group.  A single group keeps the plain
+// order.
+__device__ __forceinline__ void contraction_block(int &k, int &y, int &tg)
+{
+    const int ntg = gridDim.z;
+    if (ntg == 1) {
+        k = blockIdx.x;
+        y = blockIdx.y;
+        tg = 0;
+        return;
+    }
+    const int n = gridDim.x * gridDim.y * ntg;
+    const int lin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const int item = xcd_item(lin, n);
+    tg = item % ntg;
+    const int rest = item / ntg;
+    k = rest % gridDim.x;
+    y = rest / gridDim.x;
+}
+
 #include "contract_split.hpp"
 
 // Spectra in fragment order.  One load instruction of a wave then reads one
@@ -529,7 +554,9 @@ __global__ __launch_bounds__(512) void k_contract_fwd(const float4 *__restrict__
                                                       int KK, int KKs, int nt, int nf, int kchunk)
 {
     __shared__ float4 la[2][U][64];
-    const int k = blockIdx.x, s = blockIdx.y, t0 = blockIdx.z * 16;
+    int k, s, tg;
+    contraction_block(k, s, tg);
+    const int t0 = tg * 16;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = lane & 15, kq = lane >> 4;
     const int ncb = NNp / 16;
@@ -667,7 +694,9 @@ __global__ __launch_bounds__(256) void k_contract_adj(const float4 *__restrict__
                                                       int NCp, int nt, int ranges)
 {
     extern __shared__ float2 rs[];  // [even number of groups of 8 * U rows][kRsStride]
-    const int k = blockIdx.x, t0 = blockIdx.z * 16;
+    int k, by, tg;
+    contraction_block(k, by, tg);
+    const int t0 = tg * 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const int col = lane & 15, kq = lane >> 4;
     const int nkb = (KK + 15) / 16;
@@ -699,7 +728,7 @@ __global__ __launch_bounds__(256) void k_contract_adj(const float4 *__restrict__
     float2 *bk = B + (size_t)k * nt * KK;
     const int RB = nwaves * CB;  // column blocks per range (the packing's RB)
     for (int r = 0; r < ranges; ++r) {
-        const int kb0 = ((blockIdx.y * ranges + r) * nwaves + wave) * CB;
+        const int kb0 = ((by * ranges + r) * nwaves + wave) * CB;
         if (kb0 >= nkb)
             break;
         int kbi[CB];
