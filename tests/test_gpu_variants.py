@@ -260,3 +260,49 @@ def test_variant_argument_errors(lf, problem):
         stop = kw.pop("stop", lf.STOP_NONE)
         with pytest.raises(lf.LfrlError):
             plan.deconvolve(yd, 2, stop=stop, xs=xs, ys=ys, **kw)
+
+
+def test_batch_entry_point_with_per_frame_variants(lf):
+    """lfrl_deconvolve_batch with a different update, background, start and
+    metric per frame (frames of one plan share launches): each frame matches
+    its oracle run."""
+    import torch
+    psf = S.gaussian_psf(3, 3, 13, seed=71, shift_scale=None)
+    plan = lf.Plan(to_dev(psf), 36, 36, max_batch=3)
+    try:
+        specs = [
+            (11, 12, dict(update="rl", background=10.0, init="ones"),
+             lf.rl_opts(5, lf.STOP_NONE, background=10.0)),
+            (12, 10, dict(update="isra", background=4.0, init="backprojection"),
+             lf.rl_opts(5, lf.STOP_NONE, update=lf.UPDATE_ISRA, background=4.0,
+                        backproject_start=True)),
+            (9, 12, dict(update="isra", background=0.0, init="ones"),
+             lf.rl_opts(5, lf.STOP_TRACK, 1, 2.0, 2.5, update=lf.UPDATE_ISRA,
+                        region=lf.REGION_WHOLE, norm=lf.NORM_REGION, window=2)),
+        ]
+        imgs, vols, opts, refs = [], [], [], []
+        for i, (ly, lx, okw, o) in enumerate(specs):
+            h, w = 3 * ly, 3 * lx
+            x = S.bead_volume(3, h, w, 10, 1200 + i)
+            y = S.measure(oracle.forward(psf, x), 500.0, 10.0, 1300 + i)
+            imgs.append(to_dev(y))
+            vols.append(torch.empty((3, h, w), device="cuda:0"))
+            opts.append(o)
+            if o.stop == lf.STOP_NONE:
+                refs.append((oracle.rl(psf, y, 5, **okw), None))
+            else:
+                xb, best, _, trace = oracle.deconvolve(psf, y, 5, 2.0, 2.5, stop=False,
+                                                       region="whole", norm="region",
+                                                       window=2, **okw)
+                refs.append((xb, trace))
+        reps = lf.lfrl_deconvolve_batch([plan.handle] * 3, [3 * s[0] for s in specs],
+                                        [3 * s[1] for s in specs], imgs, vols, opts)
+        torch.cuda.synchronize()
+        for i, (want, trace) in enumerate(refs):
+            err = rel_l2(vols[i].cpu().numpy(), want)
+            print(f"frame {i}: rel L2 {err:.2e}", flush=True)
+            assert err <= TOL
+            if trace is not None:
+                np.testing.assert_allclose(np.array(reps[i]["metric_trace"]), trace, rtol=TOL)
+    finally:
+        plan.close()
