@@ -239,7 +239,8 @@ int lfrl_job_footprint(lfrl_plan_t plan, int32_t h, int32_t w, size_t *bytes);
 /* Create a job for image img [h][w] (copied; the caller may reuse img once
  * the call returns) with the options of lfrl_deconvolve.  vol0 [nz][h][w] is
  * the start volume when opts->init == 1 (copied), else ignored.  Computes A^T 1
- * for the frame and synchronises `stream`.  Returns LFRL_ERR_NUMERIC, and
+ * for the frame (and A^T img for the ISRA update or the back projection start)
+ * and synchronises `stream`.  Returns LFRL_ERR_NUMERIC, and
  * creates nothing, when img holds a negative or non-finite value;
  * LFRL_ERR_NOMEM when the job's memory cannot be allocated. */
 int lfrl_job_create(lfrl_job_t *out, lfrl_plan_t plan, int32_t h, int32_t w,
