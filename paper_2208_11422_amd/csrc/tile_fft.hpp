@@ -34,6 +34,84 @@ __device__ __forceinline__ float2 cmulf(float2 a, float2 b)
     return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
 }
 
+// cos and sin of 2 pi m / R for the odd radices (float constants; the tables
+// are exactly symmetric: cos(m) = cos(R - m), sin(m) = -sin(R - m))
+template <int R>
+__device__ __forceinline__ float root_cos(int m)
+{
+    if constexpr (R == 3) {
+        constexpr float t[3] = {1.0f, -0.5f, -0.5f};
+        return t[m];
+    } else if constexpr (R == 5) {
+        constexpr float t[5] = {1.0f, 0.30901699437494745f, -0.8090169943749475f,
+                                -0.8090169943749475f, 0.30901699437494745f};
+        return t[m];
+    } else {
+        constexpr float t[7] = {1.0f, 0.6234898018587336f, -0.22252093395631440f,
+                                -0.9009688679024191f, -0.9009688679024191f,
+                                -0.22252093395631440f, 0.6234898018587336f};
+        return t[m];
+    }
+}
+
+template <int R>
+__device__ __forceinline__ float root_sin(int m)
+{
+    if constexpr (R == 3) {
+        constexpr float t[3] = {0.0f, 0.8660254037844386f, -0.8660254037844386f};
+        return t[m];
+    } else if constexpr (R == 5) {
+        constexpr float t[5] = {0.0f, 0.9510565162951535f, 0.5877852522924731f,
+                                -0.5877852522924731f, -0.9510565162951535f};
+        return t[m];
+    } else {
+        constexpr float t[7] = {0.0f, 0.7818314824680298f, 0.9749279121818236f,
+                                0.4338837391175582f, -0.4338837391175582f,
+                                -0.9749279121818236f, -0.7818314824680298f};
+        return t[m];
+    }
+}
+
+// Odd R-point DFT (R = 3, 5, 7) from the pairs q, R - q: with a_q = v[q] +
+// v[R-q] and b_q = v[q] - v[R-q],
+//   X[k], X[R-k] = v[0] + sum_q cos(2 pi q k / R) a_q  +- SIGN i sum_q sin(2 pi q k / R) b_q,
+// about a third of the multiplies of the direct sum.
+template <int R, int SIGN>
+__device__ __forceinline__ void dft_odd(float2 (&v)[R])
+{
+    constexpr int H = (R - 1) / 2;
+    float2 a[H], b[H];
+    float2 sum = v[0];
+#pragma unroll
+    for (int q = 1; q <= H; ++q) {
+        a[q - 1] = make_float2(v[q].x + v[R - q].x, v[q].y + v[R - q].y);
+        b[q - 1] = make_float2(v[q].x - v[R - q].x, v[q].y - v[R - q].y);
+        sum.x += a[q - 1].x;
+        sum.y += a[q - 1].y;
+    }
+    float2 o[R];
+    o[0] = sum;
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+        float2 c = v[0], s = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int q = 1; q <= H; ++q) {
+            const float cq = root_cos<R>((q * k) % R), sq = root_sin<R>((q * k) % R);
+            c.x = fmaf(cq, a[q - 1].x, c.x);
+            c.y = fmaf(cq, a[q - 1].y, c.y);
+            s.x = fmaf(sq, b[q - 1].x, s.x);
+            s.y = fmaf(sq, b[q - 1].y, s.y);
+        }
+        // SIGN i s = SIGN (-s.y, s.x)
+        const float isx = SIGN > 0 ? -s.y : s.y, isy = SIGN > 0 ? s.x : -s.x;
+        o[k] = make_float2(c.x + isx, c.y + isy);
+        o[R - k] = make_float2(c.x - isx, c.y - isy);
+    }
+#pragma unroll
+    for (int p = 0; p < R; ++p)
+        v[p] = o[p];
+}
+
 // In-place R-point DFT, natural order: v[p] <- sum_q v[q] exp(SIGN 2 pi i p q / R).
 template <int R, int SIGN, int Q>
 __device__ __forceinline__ void dft_small(float2 (&v)[R], const float2 *__restrict__ tw)
@@ -52,6 +130,8 @@ __device__ __forceinline__ void dft_small(float2 (&v)[R], const float2 *__restri
         v[2] = make_float2(s0.x - s2.x, s0.y - s2.y);
         v[1] = make_float2(s1.x + s3r.x, s1.y + s3r.y);
         v[3] = make_float2(s1.x - s3r.x, s1.y - s3r.y);
+    } else if constexpr (R == 3 || R == 5 || R == 7) {
+        dft_odd<R, SIGN>(v);
     } else {
         float2 o[R];
 #pragma unroll
