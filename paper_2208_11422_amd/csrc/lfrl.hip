@@ -1079,6 +1079,36 @@ struct StopState {
     int iter;
 };
 
+// Record iteration k's metric e in the stop state (one thread): trace[k-1] = e,
+// the best iterate (ties: later) and the stop flag, raised after `patience`
+// consecutive strict decreases of the mean of the last `window` values (the
+// trace holds e_1 .. e_k).
+__device__ void record_metric(double e, StopState *st, double *trace, int k, int patience,
+                              int window)
+{
+    trace[k - 1] = e;
+    st->iter = k;
+    if (k > window) {
+        // means of e_{k-window+1..k} and e_{k-window..k-1}, oldest first
+        double s1 = 0.0, s0 = 0.0;
+        for (int i = k - window; i < k; ++i)
+            s1 += trace[i];
+        for (int i = k - 1 - window; i < k - 1; ++i)
+            s0 += trace[i];
+        st->run = (s1 / window < s0 / window) ? st->run + 1 : 0;
+    }
+    st->copy_flag = (k == 1 || e >= st->best_e) ? 1 : 0;
+    if (st->copy_flag) {
+        st->best_e = e;
+        st->best_k = k;
+    }
+    st->prev_e = e;
+    if (!st->stopped && st->run >= patience) {
+        st->stopped = 1;
+        st->stop_k = k;
+    }
+}
+
 // Final entropy (Eq. 12) and stop rule.  Single block.  The norm is the
 // Frobenius norm of the whole matrix (from Parseval's partial sums n2p) or of
 // the coefficients inside the region (norm == LFRL_NORM_REGION), and the
@@ -1141,30 +1171,109 @@ __global__ void k_metric_final(const double *__restrict__ n2p, int n2count,
     if (threadIdx.x == 0) {
         const double e = (n > 0.0 && red[0] != 0.0) ? -(1.0 / area) * red[0] : 0.0;
         out[0] = e;
-        if (st) {
-            trace[k - 1] = e;
-            st->iter = k;
-            if (k > window) {
-                // means of e_{k-window+1..k} and e_{k-window..k-1}, oldest first
-                double s1 = 0.0, s0 = 0.0;
-                for (int i = k - window; i < k; ++i)
-                    s1 += trace[i];
-                for (int i = k - 1 - window; i < k - 1; ++i)
-                    s0 += trace[i];
-                st->run = (s1 / window < s0 / window) ? st->run + 1 : 0;
-            }
-            st->copy_flag = (k == 1 || e >= st->best_e) ? 1 : 0;
-            if (st->copy_flag) {
-                st->best_e = e;
-                st->best_k = k;
-            }
-            st->prev_e = e;
-            if (!st->stopped && st->run >= patience) {
-                st->stopped = 1;
-                st->stop_k = k;
+        if (st)
+            record_metric(e, st, trace, k, patience, window);
+    }
+}
+
+// The whole metric of a small image in one block (run_metric's limits keep
+// every buffer in LDS): z maximum projection and Parseval sum, the row
+// transform for the nv candidate rows, the nv x nu candidate coefficients of
+// the triangle or rectangle, the norm, the entropy and the stop rule; then,
+// when the iterate is the best so far, its copy into best (nvox floats; best ==
+// nullptr: no copy).  Dynamic LDS: nv * w + nv * nu doubles, then h * w floats.
+__global__ __launch_bounds__(1024) void k_metric_small(
+    const float *__restrict__ vol, int nz, int H, int W, const double *__restrict__ tabH,
+    const double *__restrict__ tabW, int nv, int nu, double xs, double ys, int region, int norm,
+    double area, double *__restrict__ out, StopState *st, double *trace, int k, int patience,
+    int window, float *__restrict__ best, size_t nvox)
+{
+    extern __shared__ double sm[];
+    __shared__ double red[1024];
+    __shared__ int flag;
+    const int hw = H * W;
+    double *T1 = sm;                                    // [nv][W]
+    double *F = T1 + (size_t)nv * W;                    // [nv][nu]
+    float *m = reinterpret_cast<float *>(F + (size_t)nv * nu);  // [H][W]
+    const int tid = threadIdx.x, nth = blockDim.x;
+    auto block_sum = [&](double a) -> double {
+        red[tid] = a;
+        __syncthreads();
+        for (int off = nth / 2; off > 0; off >>= 1) {
+            if (tid < off)
+                red[tid] += red[tid + off];
+            __syncthreads();
+        }
+        const double r = red[0];
+        __syncthreads();
+        return r;
+    };
+    double sq = 0.0;
+    for (int i = tid; i < hw; i += nth) {
+        float v = vol[i];
+        for (int j = 1; j < nz; ++j)
+            v = fmaxf(v, vol[(size_t)j * hw + i]);
+        m[i] = v;
+        sq += (double)v * (double)v;
+    }
+    const double n2 = block_sum(sq);  // its barriers also publish m
+    for (int idx = tid; idx < nv * W; idx += nth) {
+        const int v = idx / W, s = idx % W;
+        const double *tv = tabH + (size_t)v * H;
+        double acc = 0.0;
+        for (int r = 0; r < H; ++r)
+            acc = fma(tv[r], (double)m[r * W + s], acc);
+        T1[idx] = acc;
+    }
+    __syncthreads();
+    for (int c = tid; c < nv * nu; c += nth) {
+        const int v = c / nu, u = c % nu;
+        const bool inside = region == LFRL_REGION_TRIANGLE
+                                ? ((double)u / xs + (double)v / ys) < 1.0
+                                : ((double)u < xs && (double)v < ys);
+        double f = -1.0;
+        if (inside) {
+            const double *tu = tabW + (size_t)u * W;
+            double acc = 0.0;
+            for (int s = 0; s < W; ++s)
+                acc = fma(T1[v * W + s], tu[s], acc);
+            f = fabs(acc);
+        }
+        F[c] = f;
+    }
+    __syncthreads();
+    double nn = n2;
+    if (norm == LFRL_NORM_REGION) {
+        double a = 0.0;
+        for (int c = tid; c < nv * nu; c += nth)
+            if (F[c] > 0.0)
+                a += F[c] * F[c];
+        nn = block_sum(a);
+    }
+    const double n = sqrt(nn);
+    double ep = 0.0;
+    if (n > 0.0)
+        for (int c = tid; c < nv * nu; c += nth) {
+            const double f = F[c];
+            if (f > 0.0) {
+                const double p = f / n;
+                ep += p * log2(p);
             }
         }
+    const double es = block_sum(ep);
+    if (tid == 0) {
+        const double e = (n > 0.0 && es != 0.0) ? -(1.0 / area) * es : 0.0;
+        out[0] = e;
+        flag = 0;
+        if (st) {
+            record_metric(e, st, trace, k, patience, window);
+            flag = st->copy_flag;
+        }
     }
+    __syncthreads();
+    if (best && flag)
+        for (size_t i = tid; i < nvox; i += nth)
+            best[i] = vol[i];
 }
 
 __global__ void k_state_reset(StopState *st)
@@ -2768,12 +2877,26 @@ static double region_area(int region, double xs, double ys, int h, int w)
                                              : (double)h * (double)w;
 }
 
+// Limits of the one-block metric (k_metric_small): image pixels, row-transform
+// values and candidate coefficients held in LDS (44 KB at most), and the
+// volume size up to which that block also copies the best iterate.
+static constexpr int kSmallMetricPixels = 8192;
+static constexpr int kSmallMetricRows = 1024;
+static constexpr int kSmallMetricCoefs = 512;
+static constexpr size_t kSmallCopyVoxels = 65536;
+
 // DCT entropy of the z-MIP of vol[nz][h][w] (nz = 1: the image itself) into
-// out[0]; optional stop-state update for iteration k.
+// out[0]; optional stop-state update for iteration k.  With best != nullptr the
+// iterate vol is to be copied into best when it is the best so far: *copied
+// tells whether the metric did that itself (small frames), else the caller
+// launches k_cond_copy.
 static int run_metric(int nz, int h, int w, const float *vol, double xs, double ys, int region,
                       int norm, double *out, const MetricBufs &mb, StopState *st_dev,
-                      double *trace, int k, int patience, int window, hipStream_t st)
+                      double *trace, int k, int patience, int window, hipStream_t st,
+                      float *best = nullptr, size_t nvox = 0, bool *copied = nullptr)
 {
+    if (copied)
+        *copied = false;
     const bool whole = region == LFRL_REGION_WHOLE;
     const int nv = whole ? h : legs_count(ys, h), nu = whole ? w : legs_count(xs, w);
     const bool cached = mb.tab_h && *mb.tab_h == h && *mb.tab_nv >= nv && *mb.tab_w == w &&
@@ -2791,6 +2914,19 @@ static int run_metric(int nz, int h, int w, const float *vol, double xs, double 
         }
     }
     const size_t hw = (size_t)h * w;
+    if (!whole && hw <= (size_t)kSmallMetricPixels && nv * w <= kSmallMetricRows &&
+        nv * nu <= kSmallMetricCoefs) {
+        const bool copy = best && nvox <= kSmallCopyVoxels;
+        const size_t lds = ((size_t)nv * w + (size_t)nv * nu) * sizeof(double) + hw * sizeof(float);
+        hipLaunchKernelGGL(k_metric_small, dim3(1), dim3(1024), lds, st, vol, nz, h, w,
+                           (const double *)mb.tabH, (const double *)mb.tabW, nv, nu, xs, ys,
+                           region, norm, region_area(region, xs, ys, h, w), out, st_dev, trace, k,
+                           patience, std::max(1, window), copy ? best : nullptr, nvox);
+        LAUNCH_CHECK("k_metric_small");
+        if (copied)
+            *copied = copy;
+        return LFRL_OK;
+    }
     const int nblk = (int)((hw + 255) / 256);
     hipLaunchKernelGGL(k_mip, dim3(nblk), dim3(256), 0, st, vol, nz, hw, mb.mip, mb.n2p);
     LAUNCH_CHECK("k_mip");
@@ -3081,14 +3217,17 @@ static int step_frames(lfrl_plan_s *p, Frame *const *fr, int n, hipStream_t st)
             LAUNCH_CHECK("k_weak_exact(update)");
         }
         if (f.opts.stop != LFRL_STOP_NONE) {
+            bool copied = false;
             rc = run_metric(p->g.Nz, f.h, f.w, nxt, f.opts.xs, f.opts.ys, f.opts.region,
                             f.opts.norm, f.metric_out, frame_metric_bufs(f), f.state, f.trace, k,
-                            f.opts.patience, f.opts.window, st);
+                            f.opts.patience, f.opts.window, st, f.VB, nvox, &copied);
             if (rc)
                 return rc;
-            hipLaunchKernelGGL(k_cond_copy, dim3(1024), dim3(256), 0, st,
-                               (const StopState *)f.state, (const float *)nxt, f.VB, nvox);
-            LAUNCH_CHECK("k_cond_copy");
+            if (!copied) {
+                hipLaunchKernelGGL(k_cond_copy, dim3(1024), dim3(256), 0, st,
+                                   (const StopState *)f.state, (const float *)nxt, f.VB, nvox);
+                LAUNCH_CHECK("k_cond_copy");
+            }
         }
         if (f.want_flux) {
             rc = frame_dot(f, f.sens, nxt, nvox, k, 1, st);
