@@ -465,7 +465,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the z-sharded "
-              "multi-GPU path is a design, not part of this build", file=sys.stderr)
+              "multi-GPU path is designed but not implemented", file=sys.stderr)
         return 2
     if os.environ.get("WORLD_SIZE", "1") != "1":
         print("bench.py is single-process; WORLD_SIZE must be 1", file=sys.stderr)

@@ -46,7 +46,7 @@ typedef enum {
     LFRL_ERR_ARG = -1,          /* bad argument or size */
     LFRL_ERR_NOMEM = -2,        /* device allocation failed */
     LFRL_ERR_DEVICE = -3,       /* HIP runtime / kernel launch error */
-    LFRL_ERR_UNSUPPORTED = -4,  /* valid request this build does not serve */
+    LFRL_ERR_UNSUPPORTED = -4,  /* valid request the library does not serve */
     LFRL_ERR_NUMERIC = -5       /* non-finite value met where one is not allowed */
 } lfrl_status;
 
