@@ -296,7 +296,7 @@ def test_window_means_decrease_iff_values_w_apart_decrease():
 
 
 def test_deconvolve_variants_run_through():
-    """The driver composes the pieces: ISRA with a background from the back
+    """oracle.deconvolve composes the pieces: ISRA with a background from the back
     projection start, scored on the rectangle with the region norm."""
     psf, _, y = small_problem(seed=51)
     x, best, ran, trace = oracle.deconvolve(psf, y, 6, 3.0, 3.0, update="isra", background=2.0,
