@@ -148,3 +148,52 @@ def test_first_iterate_sampled(setup):
     err = rel_l2(vol[jj, rr, ss], want)
     print(f"first iterate sampled rel L2 {err:.2e}", flush=True)
     assert err <= TOL
+
+
+@pytest.mark.parametrize("update", ["rl", "isra"])
+def test_first_iterate_variants_sampled(setup, update):
+    """The first iterate of RL with a background b, and of ISRA with b, at
+    sampled voxels of the full-size frame (the cropped PSF set and window of
+    test_first_iterate_sampled):
+        RL:   x^1 = A^T(y / (A 1 + b)) / A^T 1,
+        ISRA: x^1 = A^T y / A^T(A 1 + b)."""
+    import torch
+    lf, p, plan, dev = setup
+    g = p["geometry"]
+    k = 31
+    bg = 10.0
+    c0, h0 = (g.ksize - 1) // 2, (k - 1) // 2
+    psf = np.ascontiguousarray(p["psf_array"][:, :, :, c0 - h0:c0 + h0 + 1, c0 - h0:c0 + h0 + 1])
+    small = lf.Plan(torch.from_numpy(psf).to(dev), g.h, g.w, tile_q=plan.info["tile_q"])
+    try:
+        y = np.random.default_rng(13).uniform(10.0, 2000.0, size=(g.h, g.w)).astype(np.float32)
+        vol, _ = small.deconvolve(torch.from_numpy(y).to(dev), 1, stop=lf.STOP_NONE,
+                                  update=lf.UPDATE_ISRA if update == "isra" else lf.UPDATE_RL,
+                                  background=bg)
+        vol = vol.cpu().numpy()
+    finally:
+        small.close()
+    r0, r1, s0, s1 = 300, 316, 420, 436
+    pr = np.arange(r0 - h0, r1 + h0)
+    pc = np.arange(s0 - h0, s1 + h0)
+    grid_r, grid_c = np.meshgrid(pr, pc, indexing="ij")
+    ones = np.ones((g.nz, g.h, g.w))
+    model = oracle.forward_at(psf, ones, grid_r.ravel(), grid_c.ravel()).reshape(grid_r.shape) + bg
+    win = (slice(r0 - h0, r1 + h0), slice(s0 - h0, s1 + h0))
+    rng = np.random.default_rng(14)
+    n = 300
+    jj = rng.integers(0, g.nz, n)
+    rr = rng.integers(r0, r1, n)
+    ss = rng.integers(s0, s1, n)
+    img = np.zeros((g.h, g.w))
+    if update == "rl":
+        img[win] = y[win] / model
+        want = (oracle.backward_at(psf, img, jj, rr, ss)
+                / oracle.backward_at(psf, np.ones((g.h, g.w)), jj, rr, ss))
+    else:
+        img[win] = model
+        want = (oracle.backward_at(psf, y.astype(np.float64), jj, rr, ss)
+                / oracle.backward_at(psf, img, jj, rr, ss))
+    err = rel_l2(vol[jj, rr, ss], want)
+    print(f"{update} with background: first iterate sampled rel L2 {err:.2e}", flush=True)
+    assert err <= TOL
