@@ -280,8 +280,10 @@ __device__ __forceinline__ int xcd_item(int bid, int n)
 //               of a frame's [planes][H][W] array (frames and tiles from
 //               `batch`; `src` unused), each row-pass thread loading its two
 //               rows straight from memory; 1-D grid of nt * planes * N blocks,
-//               work item = (j*N + ar) * nt + tile (tiles of one row phase,
-//               which overlap, land on one XCD).
+//               work item = tile * (planes * N) + j*N + ar (the row phases of
+//               one tile write adjacent pieces of every spectrum row and run
+//               together on one XCD, so their partial cache lines merge in L2;
+//               measured faster than keeping overlapping tiles together).
 //               obase = (tile * KKo + j*N*N + ar*N), kstride = nt * KKo.
 //   SRC_PSF:    the polyphase kernels G_{j,a->c}[D] = h[j][a][N*D + c - a + c0]
 //               for output row phase cr and all column phases, placed
@@ -321,7 +323,8 @@ __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const TileBatch batch
     int H = 0, W = 0, ly0 = 0, lx0 = 0, arow = 0;
     if (mode == SRC_PLANES) {
         const int item = xcd_item(blockIdx.x, gridDim.x);
-        const int tile = item % nt, jar = item / nt;
+        const int njar = gridDim.x / nt;
+        const int tile = item / njar, jar = item % njar;
         const int j = jar / N;
         arow = jar % N;
         const TileJob &fj = batch.job[batch_job(batch, tile)];
@@ -425,7 +428,7 @@ __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const TileBatch batch
     }
     if (rowmax) {
         __syncthreads();
-        const int tile = xcd_item(blockIdx.x, gridDim.x) % nt;
+        const int tile = xcd_item(blockIdx.x, gridDim.x) / (gridDim.x / nt);
         for (int i = tid; i < Q * QH; i += blockDim.x)
             if (kmax[i])
                 atomicMax(&rowmax[(size_t)i * nt + tile], kmax[i]);
