@@ -329,7 +329,7 @@ def serving_leg(args, dev) -> dict:
         del psf
         side = cfg["max_side"] // n * n
         plans.append(lf.Plan(psf_d, side, side, precision=lf.SPLIT_FP16,
-                             max_batch=args.serving_batch))
+                             max_batch=args.serving_batch, autotune=args.serving_autotune))
         del psf_d
         torch.cuda.synchronize()
         info = plans[-1].info
@@ -455,6 +455,8 @@ def main() -> int:
     ap.add_argument("--serving-batch", type=int, default=4,
                     help="largest frames one projection launch of a PSF set covers")
     ap.add_argument("--serving-active", type=int, default=32, help="jobs in flight at most")
+    ap.add_argument("--serving-autotune", action="store_true",
+                    help="measured tile side for the serving PSF sets (default: the model's)")
     ap.add_argument("--serving-budget-gb", type=float, default=96.0,
                     help="device memory admitted jobs may hold")
     ap.add_argument("--no-variants", action="store_true",
