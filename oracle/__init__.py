@@ -200,10 +200,12 @@ def sensitivity(psf, h: int, w: int) -> np.ndarray:
 
 def normalize_psf(psf) -> np.ndarray:
     """Scale every (j, a, b) kernel of a float32 PSF set to unit sum, the sums
-    taken in float64, the result rounded back to float32."""
+    taken in float64, the result rounded back to float32.  A kernel whose sum
+    is not positive has no unit-sum scaling and is kept as it is."""
     p = np.asarray(psf, dtype=np.float32).astype(np.float64)
     s = p.sum(axis=(-2, -1), keepdims=True)
-    return (p / s).astype(np.float32)
+    ok = s > 0
+    return np.where(ok, p / np.where(ok, s, 1.0), p).astype(np.float32)
 
 
 # --------------------------------------------------------------------------

@@ -162,3 +162,21 @@ def test_sum_rule_matches_sensitivity():
     x = rng.uniform(size=(nz, h, w))
     c = oracle.sensitivity(psf, h, w)
     assert oracle.forward(psf, x).sum() == pytest.approx(np.sum(c * x), rel=1e-12)
+
+
+def test_psf_normalisation():
+    """Every kernel sums to 1 after normalisation (float32 rounding of each tap
+    bounds the error), a scaled copy normalises to the same taps, and a kernel
+    with no positive weight is kept unchanged."""
+    rng = np.random.default_rng(41)
+    psf = rng.uniform(0.0, 1.0, size=(2, 3, 3, 7, 7)).astype(np.float32)
+    psf *= rng.uniform(0.1, 50.0, size=(2, 3, 3, 1, 1)).astype(np.float32)
+    psf[1, 2, 0] = 0.0
+    out = oracle.normalize_psf(psf)
+    sums = out.astype(np.float64).sum(axis=(-2, -1))
+    live = np.ones((2, 3, 3), dtype=bool)
+    live[1, 2, 0] = False
+    np.testing.assert_allclose(sums[live], 1.0, atol=49 * 2 ** -24)
+    np.testing.assert_array_equal(out[1, 2, 0], 0.0)
+    again = oracle.normalize_psf(out * np.float32(4.0))
+    np.testing.assert_array_equal(again[live], out[live])
