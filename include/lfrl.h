@@ -65,8 +65,12 @@ typedef enum {
 
 /* Plan flags.  LFRL_PLAN_AUTOTUNE (with tile_q = 0): time the best few tile
  * sides by the model on the device (one forward and one back projection of
- * max_batch largest frames each, on zero spectra) and keep the fastest. */
-enum { LFRL_PLAN_AUTOTUNE = 1u << 0 };
+ * max_batch largest frames each, on zero spectra) and keep the fastest.
+ * LFRL_NORMALIZE_PSF: scale every (j, a, b) kernel of the plan's copy of the
+ * PSF set to unit sum (sums in float64, one rounding to float32) before
+ * anything is built from it; a kernel whose sum is not positive is kept as it
+ * is.  The caller's psf array is not modified. */
+enum { LFRL_PLAN_AUTOTUNE = 1u << 0, LFRL_NORMALIZE_PSF = 1u << 1 };
 
 /* Plan description.  Geometry of the PSF set and the largest image the plan
  * serves (the memory estimate of Fig. 1 is made for that size). */
@@ -78,7 +82,7 @@ typedef struct {
     int32_t max_w;     /* largest image width served, multiple of nnum */
     int32_t precision; /* lfrl_precision */
     int32_t tile_q;    /* DFT tile side in lenslets; 0 = choose from the model */
-    uint32_t flags;    /* 0 or LFRL_PLAN_AUTOTUNE */
+    uint32_t flags;    /* LFRL_PLAN_AUTOTUNE | LFRL_NORMALIZE_PSF, or 0 */
     int32_t max_batch; /* frames of max_h x max_w whose tiles one batched
                           projection covers (lfrl_job_step); 0 or 1 = one
                           frame, at most 16.  Workspace grows with it. */

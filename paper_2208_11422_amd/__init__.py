@@ -230,7 +230,7 @@ def lfrl_metric_cutoff(d_ml: float, mag: float, nnum: int, wavelength: float, na
 
 
 JOB_FLUX = 1
-PLAN_AUTOTUNE = 1
+PLAN_AUTOTUNE, NORMALIZE_PSF = 1, 2
 
 
 def _report_buffers(n: int, want_metric: bool, want_flux: bool):
@@ -330,13 +330,14 @@ class Plan:
 
     def __init__(self, psf: torch.Tensor, max_h: int, max_w: int, tile_q: int = 0,
                  precision: int = FP32, max_batch: int = 1, autotune: bool = False,
-                 stream=None):
+                 normalize_psf: bool = False, stream=None):
         nz, n, n2, k, k2 = psf.shape
         if n != n2 or k != k2:
             raise LfrlError(-1, "psf must be [nz][N][N][K][K]")
         self.desc = PlanDesc(nnum=n, nz=nz, ksize=k, max_h=max_h, max_w=max_w,
                              precision=precision, tile_q=tile_q,
-                             flags=PLAN_AUTOTUNE if autotune else 0, max_batch=max_batch)
+                             flags=(PLAN_AUTOTUNE if autotune else 0)
+                             | (NORMALIZE_PSF if normalize_psf else 0), max_batch=max_batch)
         self.nnum, self.nz, self.ksize = n, nz, k
         self.device = psf.device
         self.handle = lfrl_plan(self.desc, psf, stream)

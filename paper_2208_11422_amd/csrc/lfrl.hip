@@ -1650,6 +1650,30 @@ __global__ void k_check_image(const float *__restrict__ a, size_t n, unsigned *_
         atomicOr(flag, 1u);
 }
 
+// Scale each kernel of a PSF set to unit sum: one block per (j, a, b) kernel of
+// n taps, the sum in float64, each tap divided in float64 and rounded once; a
+// kernel whose sum is not positive is left unchanged.
+__global__ void k_normalize_psf(float *__restrict__ psf, size_t n)
+{
+    __shared__ double red[256];
+    float *h = psf + blockIdx.x * n;
+    double a = 0.0;
+    for (size_t i = threadIdx.x; i < n; i += blockDim.x)
+        a += (double)h[i];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    const double s = red[0];
+    if (!(s > 0.0))
+        return;
+    for (size_t i = threadIdx.x; i < n; i += blockDim.x)
+        h[i] = (float)((double)h[i] / s);
+}
+
 // Device state of one frame's Richardson-Lucy run: the measured image, the
 // ratio image, the iterates, A^T 1 with its weakly observed voxels, and the
 // metric / stop state.  The plan holds one for lfrl_deconvolve; every job
@@ -1761,7 +1785,7 @@ static int validate_desc(const lfrl_plan_desc *d)
     if (d->precision != LFRL_FP32 && d->precision != LFRL_SPLIT_FP16 &&
         d->precision != LFRL_SPLIT_BF16)
         return set_error(LFRL_ERR_UNSUPPORTED, "precision %d not supported", d->precision);
-    if (d->flags & ~(uint32_t)LFRL_PLAN_AUTOTUNE)
+    if (d->flags & ~(uint32_t)(LFRL_PLAN_AUTOTUNE | LFRL_NORMALIZE_PSF))
         return set_error(LFRL_ERR_ARG, "unknown plan flags 0x%x", d->flags);
     if (d->tile_q < 0 || d->tile_q > kMaxQ)
         return set_error(LFRL_ERR_ARG, "tile_q must be in [0, %d]", kMaxQ);
@@ -2373,6 +2397,13 @@ static int plan_build(lfrl_plan_s **out, const lfrl_plan_desc *desc, int q, cons
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(p->psf, psf, s.psf, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && (desc->flags & LFRL_NORMALIZE_PSF)) {
+        hipLaunchKernelGGL(k_normalize_psf, dim3(g.Nz * g.NN), dim3(256), 0, st, p->psf,
+                           (size_t)g.K * g.K);
+        e = hipGetLastError();
+    }
+    // everything below is built from the plan's own copy
+    psf = p->psf;
     if (e == hipSuccess && g.NNp != g.NN)
         e = hipMemsetAsync(p->Gf, 0, s.Gf, st);  // zero the row padding
     if (e == hipSuccess) {

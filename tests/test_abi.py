@@ -61,13 +61,17 @@ def test_footprint_and_cutoff_without_gpu():
     r4, w4 = lf.lfrl_plan_footprint(d4)
     r5, w5 = lf.lfrl_plan_footprint(d5)
     assert r5 >= r4 and w5 >= w4
+    # normalising the PSF copy costs no extra memory
+    d6 = lf.PlanDesc(nnum=15, nz=31, ksize=255, max_h=600, max_w=600, precision=0,
+                     tile_q=28, flags=lf.NORMALIZE_PSF)
+    assert lf.lfrl_plan_footprint(d6) == (res, ws)
     xs, ys = lf.lfrl_metric_cutoff(150.0, 40.0, 15, 0.525, 0.95, 450, 600)
     assert xs == pytest.approx(0.25 * 600 / (1.22 * 0.525 * 15 / 0.95), rel=1e-12)
     assert ys == pytest.approx(0.25 * 450 / (1.22 * 0.525 * 15 / 0.95), rel=1e-12)
 
 
 @pytest.mark.parametrize("field,value", [("ksize", 24), ("nnum", 0), ("max_h", 601),
-                                         ("precision", 7), ("flags", 2), ("tile_q", 3),
+                                         ("precision", 7), ("flags", 4), ("tile_q", 3),
                                          ("max_batch", 17), ("max_batch", -1)])
 def test_footprint_rejects_bad_descriptions(field, value):
     import paper_2208_11422_amd as lf

@@ -329,3 +329,32 @@ def test_graph_replays_match_direct_launches(lf, monkeypatch):
         assert rel_l2(got.cpu().numpy(), oracle.deconvolve(psf, y, 7, xs, ys, stop=False)[0]) <= TOL
     finally:
         plan.close()
+
+
+def test_normalized_psf_plan(lf):
+    """A plan built with LFRL_NORMALIZE_PSF from kernels of arbitrary scale (one
+    of them all zero) projects and deconvolves like the oracle on
+    oracle.normalize_psf of the same taps; the caller's PSF array is unchanged."""
+    import torch
+    n, ly, lx, nz, k = 3, 8, 7, 2, 9
+    rng = np.random.default_rng(78)
+    psf = random_psf(nz, n, k, seed=77)
+    psf *= rng.uniform(0.05, 40.0, size=(nz, n, n, 1, 1)).astype(np.float32)
+    psf[1, 0, 2] = 0.0
+    want_psf = oracle.normalize_psf(psf)
+    h, w = n * ly, n * lx
+    x = rng.uniform(0.0, 1.0, size=(nz, h, w)).astype(np.float32)
+    y = rng.uniform(1.0, 5.0, size=(h, w)).astype(np.float32)
+    d_psf = to_dev(psf)
+    plan = lf.Plan(d_psf, h, w, normalize_psf=True)
+    try:
+        fx = plan.forward(to_dev(x))
+        by = plan.backward(to_dev(y))
+        vol, _ = plan.deconvolve(to_dev(y), 3)
+        torch.cuda.synchronize()
+        assert rel_l2(fx.cpu().numpy(), oracle.forward(want_psf, x)) <= TOL
+        assert rel_l2(by.cpu().numpy(), oracle.backward(want_psf, y)) <= TOL
+        assert rel_l2(vol.cpu().numpy(), oracle.rl(want_psf, y, 3)) <= TOL
+        assert torch.equal(d_psf.cpu(), torch.from_numpy(psf))
+    finally:
+        plan.close()
