@@ -34,7 +34,8 @@ notes):
 * Metric variants: the rectangle that Eq. (12)'s summation limits state, the
   whole coefficient matrix (the overall entropy of Fig. 2(c)), each with the
   prefactor 1 / area; the 2-norm over the region only instead of the whole
-  matrix.  A "decreasing trend" (sec. 2.2) may be read from window means.
+  matrix, or its spectral norm.  A "decreasing trend" (sec. 2.2) may be read
+  from window means.
 * Transposed PSF = exact adjoint of the forward projection.
 * DCT axes: Eq. (1) pairs u with the width and v with the height (X_S is the
   width of the region, Eq. (6)); F is stored as F[v][u] (row frequency first).
@@ -357,9 +358,11 @@ def dct_entropy(img, xs: float, ys: float, region: str = "triangle", norm: str =
     its 2-norm, p = |F| / n over the region S and
     e = -(1 / G) * sum_S p log2 p (0 log 0 = 0), G the area of S.
 
-    n is the Frobenius norm of the whole coefficient matrix (norm='full'), or
-    of the coefficients inside S only (norm='region').  The default region is
-    the triangle of Eq. (6) (G = X_S Y_S / 2).  Returns 0 when n = 0."""
+    n is the Frobenius norm of the whole coefficient matrix (norm='full'), of
+    the coefficients inside S only (norm='region'), or the spectral norm (the
+    largest singular value) of the whole coefficient matrix (norm='spectral').
+    The default region is the triangle of Eq. (6) (G = X_S Y_S / 2).  Returns
+    0 when n = 0."""
     f = dct2(img)
     h, w = f.shape
     mask = region_mask(h, w, xs, ys, region)
@@ -367,6 +370,8 @@ def dct_entropy(img, xs: float, ys: float, region: str = "triangle", norm: str =
         n = np.sqrt(np.sum(f * f))
     elif norm == "region":
         n = np.sqrt(np.sum(f[mask] ** 2))
+    elif norm == "spectral":
+        n = float(np.linalg.norm(f, 2))
     else:
         raise ValueError(f"unknown norm {norm!r}")
     if n == 0:

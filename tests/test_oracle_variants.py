@@ -15,9 +15,10 @@ mathematically:
 * without a background both updates are unchanged when x^0 is scaled;
 * the back projection start is A^T y (the dense transpose of A, built from
   deltas, and the 2-D correlation);
-* the rectangle and whole-matrix regions and the region-only norm against
-  closed forms built through scipy's inverse DCT
-  (tests/golden/metric_variants.json);
+* the rectangle and whole-matrix regions, the region-only norm and the
+  spectral norm against closed forms built through scipy's inverse DCT
+  (tests/golden/metric_variants.json), and the spectral norm of a rank-one
+  image against the Frobenius norm;
 * the window-mean stop rule against worked sequences and against the identity
   mean(e_{k-w+1..k}) < mean(e_{k-w..k-1})  <=>  e_k < e_{k-w}.
 """
@@ -239,7 +240,7 @@ def test_region_norm_ignores_energy_outside():
 
 
 @pytest.mark.parametrize("region", ["rectangle", "whole"])
-@pytest.mark.parametrize("norm", ["full", "region"])
+@pytest.mark.parametrize("norm", ["full", "region", "spectral"])
 def test_variants_scale_invariant_and_zero_for_constants(region, norm):
     img = np.random.default_rng(42).uniform(size=(18, 22))
     e = oracle.dct_entropy(img, 4.0, 3.5, region, norm)
@@ -308,3 +309,30 @@ def test_deconvolve_variants_run_through():
     np.testing.assert_allclose(x, xs[best], rtol=1e-15)
     want = [oracle.metric(v, 3.0, 3.0, "rectangle", "region") for v in xs[1:]]
     np.testing.assert_allclose(trace, want, rtol=1e-15)
+
+
+def test_spectral_norm_closed_form():
+    """Two coefficients on the diagonal, 2 and -1: the largest singular value
+    is 2 (tests/golden/metric_variants.json)."""
+    c = golden()["spectral_norm"]
+    f = np.zeros((c["h"], c["w"]))
+    for v, u, val in c["coefficients"]:
+        f[v, u] = val
+    img = idctn(f, type=2, norm="ortho")
+    assert oracle.dct_entropy(img, c["xs"], c["ys"], norm="spectral") == pytest.approx(
+        c["value"], rel=1e-12)
+
+
+def test_spectral_norm_of_rank_one_image_is_frobenius():
+    """For a rank-one image the spectral and Frobenius norms coincide, so both
+    readings give the same entropy; for a generic image the spectral norm is
+    smaller and the entropy differs."""
+    rng = np.random.default_rng(44)
+    a, b = rng.uniform(0.5, 2.0, 20), rng.uniform(0.5, 2.0, 24)
+    img = np.outer(a, b)
+    for region in ("triangle", "rectangle", "whole"):
+        assert oracle.dct_entropy(img, 5.0, 4.0, region, "spectral") == pytest.approx(
+            oracle.dct_entropy(img, 5.0, 4.0, region, "full"), rel=1e-12)
+    img2 = rng.uniform(size=(20, 24))
+    assert oracle.dct_entropy(img2, 5.0, 4.0, norm="spectral") != pytest.approx(
+        oracle.dct_entropy(img2, 5.0, 4.0, norm="full"), rel=1e-3)
