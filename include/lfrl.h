@@ -166,8 +166,11 @@ typedef enum {
 
 /* The 2-norm the coefficients are divided by. */
 typedef enum {
-    LFRL_NORM_MATRIX = 0, /* Frobenius norm of the whole coefficient matrix */
-    LFRL_NORM_REGION = 1  /* Frobenius norm of the coefficients in the region */
+    LFRL_NORM_MATRIX = 0,  /* Frobenius norm of the whole coefficient matrix */
+    LFRL_NORM_REGION = 1,  /* Frobenius norm of the coefficients in the region */
+    LFRL_NORM_SPECTRAL = 2 /* largest singular value of the coefficient matrix
+                              (equal to the image's: the DCT is orthonormal),
+                              by float64 power iteration; h + w <= 6144 */
 } lfrl_norm;
 
 typedef struct {
@@ -293,7 +296,7 @@ int lfrl_metric(int32_t nz, int32_t h, int32_t w, const float *img, double xs,
 /* lfrl_metric with a choice of region (lfrl_region) and norm (lfrl_norm):
  *     *out = -(1 / G) * sum_{(u,v) in S} |F/n| log2 |F/n|,
  * G the area of S (xs ys / 2, xs ys, or w h) and n the Frobenius norm of F
- * over the whole matrix or over S.  The triangle and the rectangle need legs
+ * over the whole matrix or over S, or its spectral norm.  The triangle and the rectangle need legs
  * of at most 256 bins; the whole region takes any image. */
 int lfrl_metric_ex(int32_t nz, int32_t h, int32_t w, const float *img, double xs, double ys,
                    int32_t region, int32_t norm, double *out, void *stream);

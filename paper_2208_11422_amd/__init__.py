@@ -33,7 +33,7 @@ STOP_NONE, STOP_METRIC, STOP_TRACK = 0, 1, 2
 UPDATE_RL, UPDATE_ISRA = 0, 1
 INIT_ONES, INIT_GIVEN, INIT_BACKPROJECT = 0, 1, 2
 REGION_TRIANGLE, REGION_RECTANGLE, REGION_WHOLE = 0, 1, 2
-NORM_MATRIX, NORM_REGION = 0, 1
+NORM_MATRIX, NORM_REGION, NORM_SPECTRAL = 0, 1, 2
 
 _STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_NOMEM", -3: "ERR_DEVICE",
            -4: "ERR_UNSUPPORTED", -5: "ERR_NUMERIC"}

@@ -1002,6 +1002,84 @@ __global__ __launch_bounds__(256) void k_dgemm32(const double *__restrict__ A, i
         }
 }
 
+// Largest singular value squared of the h x w image m (float64 power
+// iteration on m^T m, one block): u = m v one wave per row, v = m^T u one wave
+// per 64 columns, both in a fixed order; v starts from a fixed positive
+// vector.  Stops once the Rayleigh quotient ||m v||^2 / ||v||^2 changes by at
+// most 1e-14 of itself, or after maxit iterations.  Dynamic LDS: (W + H)
+// doubles.  *n2 = the last quotient.
+__global__ __launch_bounds__(1024) void k_spectral_norm(const float *__restrict__ m, int H, int W,
+                                                        int maxit, double *__restrict__ n2)
+{
+    extern __shared__ double sv[];
+    double *v = sv, *u = sv + W;
+    __shared__ double red[1024];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nwave = nth >> 6;
+    auto block_sum = [&](double a) -> double {
+        red[tid] = a;
+        __syncthreads();
+        for (int off = nth / 2; off > 0; off >>= 1) {
+            if (tid < off)
+                red[tid] += red[tid + off];
+            __syncthreads();
+        }
+        const double r = red[0];
+        __syncthreads();
+        return r;
+    };
+    for (int s = tid; s < W; s += nth)
+        v[s] = 1.0 + (double)((unsigned)(s + 1) * 2654435761u % 1024u) / 2048.0;
+    __syncthreads();
+    double lam = 0.0, prev = -1.0;
+    for (int it = 0; it < maxit; ++it) {
+        // u = m v
+        for (int r = wave; r < H; r += nwave) {
+            double acc = 0.0;
+            for (int s = lane; s < W; s += 64)
+                acc = fma((double)m[(size_t)r * W + s], v[s], acc);
+            for (int off = 32; off > 0; off >>= 1)
+                acc += __shfl_down(acc, off, 64);
+            if (lane == 0)
+                u[r] = acc;
+        }
+        __syncthreads();
+        double a = 0.0, b = 0.0;
+        for (int r = tid; r < H; r += nth)
+            a += u[r] * u[r];
+        for (int s = tid; s < W; s += nth)
+            b += v[s] * v[s];
+        const double uu = block_sum(a), vv = block_sum(b);
+        lam = vv > 0.0 ? uu / vv : 0.0;
+        // v = m^T u, then unit length
+        for (int c0 = wave * 64; c0 < W; c0 += nwave * 64) {
+            const int s = c0 + lane;
+            if (s < W) {
+                double acc = 0.0;
+                for (int r = 0; r < H; ++r)
+                    acc = fma((double)m[(size_t)r * W + s], u[r], acc);
+                v[s] = acc;
+            }
+        }
+        __syncthreads();
+        double c = 0.0;
+        for (int s = tid; s < W; s += nth)
+            c += v[s] * v[s];
+        const double nv = block_sum(c);
+        if (!(nv > 0.0))
+            break;  // m v = 0: the image is zero
+        const double scale = 1.0 / sqrt(nv);
+        for (int s = tid; s < W; s += nth)
+            v[s] *= scale;
+        __syncthreads();
+        if (it > 1 && fabs(lam - prev) <= 1e-14 * lam)
+            break;
+        prev = lam;
+    }
+    if (tid == 0)
+        *n2 = lam;
+}
+
 // Per-block partial sums of |F|^2 over the coefficients inside the region
 // (Fabs >= 0), for the region norm of a large coefficient set.
 __global__ void k_sq_partial(const double *__restrict__ Fabs, int ncoef, double *__restrict__ part)
@@ -1110,7 +1188,9 @@ __device__ void record_metric(double e, StopState *st, double *trace, int k, int
 }
 
 // Final entropy (Eq. 12) and stop rule.  Single block.  The norm is the
-// Frobenius norm of the whole matrix (from Parseval's partial sums n2p) or of
+// Frobenius norm of the whole matrix (from Parseval's partial sums n2p), the
+// spectral norm (its square in n2p[n2count], from k_spectral_norm) or the
+// Frobenius norm of
 // the coefficients inside the region (norm == LFRL_NORM_REGION), and the
 // prefactor 1 / area.  out[0] = e.  When st != nullptr, iteration `k` is
 // recorded: trace[k-1] = e, the best iterate is tracked (ties: later) and the
@@ -1129,6 +1209,8 @@ __global__ void k_metric_final(const double *__restrict__ n2p, int n2count,
     double a = 0.0;
     if (ent_part) {
         a = 0.0;
+    } else if (norm == LFRL_NORM_SPECTRAL) {
+        a = threadIdx.x == 0 ? n2p[n2count] : 0.0;  // the power iteration's value
     } else if (norm == LFRL_NORM_REGION) {
         for (int i = threadIdx.x; i < ncoef; i += blockDim.x) {
             const double f = Fabs[i];
@@ -1959,7 +2041,7 @@ static size_t frame_layout(const Geo &g, int h, int w, bool own_y, size_t off[FB
     bytes[FB_TABH] = (size_t)h * h * sizeof(double);
     bytes[FB_TABW] = (size_t)w * w * sizeof(double);
     bytes[FB_T1] = std::max((size_t)kMetricChunks * legs_h * w, hw) * sizeof(double);
-    bytes[FB_N2P] = (hw + 255) / 256 * sizeof(double);
+    bytes[FB_N2P] = ((hw + 255) / 256 + 1) * sizeof(double);  // + the spectral norm
     bytes[FB_FABS] = hw * sizeof(double);
     bytes[FB_MOUT] = sizeof(double);
     bytes[FB_TRACE] = bytes[FB_FLUX] = (size_t)kMaxTrace * sizeof(double);
@@ -2915,6 +2997,18 @@ static constexpr int kSmallMetricPixels = 8192;
 static constexpr int kSmallMetricRows = 1024;
 static constexpr int kSmallMetricCoefs = 512;
 static constexpr size_t kSmallCopyVoxels = 65536;
+// Spectral norm: power iterations at most, and the image size its one block
+// holds (two float64 vectors of h and w in LDS).
+static constexpr int kSpectralMaxIters = 500;
+static constexpr int kSpectralMaxSides = 6144;
+
+// Argument check of a metric norm against the image size.
+static int check_norm_size(int norm, int h, int w)
+{
+    if (norm == LFRL_NORM_SPECTRAL && h + w > kSpectralMaxSides)
+        return set_error(LFRL_ERR_UNSUPPORTED, "spectral norm needs h + w <= %d", kSpectralMaxSides);
+    return LFRL_OK;
+}
 
 // DCT entropy of the z-MIP of vol[nz][h][w] (nz = 1: the image itself) into
 // out[0]; optional stop-state update for iteration k.  With best != nullptr the
@@ -2945,8 +3039,8 @@ static int run_metric(int nz, int h, int w, const float *vol, double xs, double 
         }
     }
     const size_t hw = (size_t)h * w;
-    if (!whole && hw <= (size_t)kSmallMetricPixels && nv * w <= kSmallMetricRows &&
-        nv * nu <= kSmallMetricCoefs) {
+    if (!whole && norm != LFRL_NORM_SPECTRAL && hw <= (size_t)kSmallMetricPixels &&
+        nv * w <= kSmallMetricRows && nv * nu <= kSmallMetricCoefs) {
         const bool copy = best && nvox <= kSmallCopyVoxels;
         const size_t lds = ((size_t)nv * w + (size_t)nv * nu) * sizeof(double) + hw * sizeof(float);
         hipLaunchKernelGGL(k_metric_small, dim3(1), dim3(1024), lds, st, vol, nz, h, w,
@@ -2961,6 +3055,12 @@ static int run_metric(int nz, int h, int w, const float *vol, double xs, double 
     const int nblk = (int)((hw + 255) / 256);
     hipLaunchKernelGGL(k_mip, dim3(nblk), dim3(256), 0, st, vol, nz, hw, mb.mip, mb.n2p);
     LAUNCH_CHECK("k_mip");
+    if (norm == LFRL_NORM_SPECTRAL) {
+        // sigma_1^2 of the projection into the slot after the Parseval partials
+        hipLaunchKernelGGL(k_spectral_norm, dim3(1), dim3(1024), (size_t)(h + w) * sizeof(double),
+                           st, (const float *)mb.mip, h, w, kSpectralMaxIters, mb.n2p + nblk);
+        LAUNCH_CHECK("k_spectral_norm");
+    }
     const int ncoef = nv * nu;
     if (whole) {
         // both passes as dense products: T1 = C_H m, |F| = |T1 C_W^T|
@@ -3001,7 +3101,10 @@ static int run_metric(int nz, int h, int w, const float *vol, double xs, double 
         double *sq = mb.T1, *part = mb.T1 + kDotBlocks;
         const double *n2src = mb.n2p;
         int n2count = nblk;
-        if (norm == LFRL_NORM_REGION) {
+        if (norm == LFRL_NORM_SPECTRAL) {
+            n2src = mb.n2p + nblk;
+            n2count = 1;
+        } else if (norm == LFRL_NORM_REGION) {
             hipLaunchKernelGGL(k_sq_partial, dim3(kDotBlocks), dim3(256), 0, st,
                                (const double *)mb.Fabs, ncoef, sq);
             LAUNCH_CHECK("k_sq_partial");
@@ -3147,7 +3250,7 @@ static int check_opts(const lfrl_rl_opts *opts)
             return set_error(LFRL_ERR_ARG, "window must be in [0, %d]", kMaxTrace);
         if (opts->region < LFRL_REGION_TRIANGLE || opts->region > LFRL_REGION_WHOLE)
             return set_error(LFRL_ERR_ARG, "unknown metric region %d", opts->region);
-        if (opts->norm != LFRL_NORM_MATRIX && opts->norm != LFRL_NORM_REGION)
+        if (opts->norm < LFRL_NORM_MATRIX || opts->norm > LFRL_NORM_SPECTRAL)
             return set_error(LFRL_ERR_ARG, "unknown metric norm %d", opts->norm);
         return check_legs(opts->xs, opts->ys, opts->region);
     }
@@ -3369,6 +3472,8 @@ extern "C" int lfrl_deconvolve(lfrl_plan_t p, int32_t h, int32_t w, const float 
         return rc;
     if ((rc = check_opts(opts)))
         return rc;
+    if (opts->stop != LFRL_STOP_NONE && (rc = check_norm_size(opts->norm, h, w)))
+        return rc;
     DevGuard dg(p->device);
     hipStream_t st = (hipStream_t)stream;
     const size_t nvox = (size_t)p->g.Nz * h * w;
@@ -3584,6 +3689,8 @@ extern "C" int lfrl_job_create(lfrl_job_t *out, lfrl_plan_t p, int32_t h, int32_
     if (rc)
         return rc;
     if ((rc = check_opts(opts)))
+        return rc;
+    if (opts->stop != LFRL_STOP_NONE && (rc = check_norm_size(opts->norm, h, w)))
         return rc;
     if (flags & ~(uint32_t)LFRL_JOB_FLUX)
         return set_error(LFRL_ERR_ARG, "unknown job flags 0x%x", flags);
@@ -3866,10 +3973,10 @@ extern "C" int lfrl_metric_ex(int32_t nz, int32_t h, int32_t w, const float *img
         return set_error(LFRL_ERR_ARG, "nz, h, w must be >= 1");
     if (region < LFRL_REGION_TRIANGLE || region > LFRL_REGION_WHOLE)
         return set_error(LFRL_ERR_ARG, "unknown metric region %d", region);
-    if (norm != LFRL_NORM_MATRIX && norm != LFRL_NORM_REGION)
+    if (norm < LFRL_NORM_MATRIX || norm > LFRL_NORM_SPECTRAL)
         return set_error(LFRL_ERR_ARG, "unknown metric norm %d", norm);
     int rc = check_legs(xs, ys, region);
-    if (rc)
+    if (rc || (rc = check_norm_size(norm, h, w)))
         return rc;
     if ((rc = check_buf(img, (size_t)nz * h * w * sizeof(float), "img")) ||
         (rc = check_buf(out, sizeof(double), "out")))
@@ -3893,7 +4000,7 @@ extern "C" int lfrl_metric_ex(int32_t nz, int32_t h, int32_t w, const float *img
         if (!rc)
             rc = dalloc(&ms.T1, std::max((size_t)kMetricChunks * kMaxMetricLegs * wc, hc * wc) *
                                     sizeof(double));
-        if (!rc) rc = dalloc(&ms.n2p, (hc * wc + 255) / 256 * sizeof(double));
+        if (!rc) rc = dalloc(&ms.n2p, ((hc * wc + 255) / 256 + 1) * sizeof(double));
         if (!rc) rc = dalloc(&ms.Fabs, hc * wc * sizeof(double));
         if (rc) {
             free_metric_scratch(ms);

@@ -96,7 +96,7 @@ def test_null_arguments_rejected_before_device_work(lib):
 @pytest.mark.parametrize("region,norm,xs,msg", [
     (3, 0, 4.0, "region"),
     (-1, 0, 4.0, "region"),
-    (0, 2, 4.0, "norm"),
+    (0, 3, 4.0, "norm"),
     (0, 0, 0.0, "legs"),
     (1, 0, 300.0, "legs"),
 ])

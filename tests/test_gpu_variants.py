@@ -143,7 +143,7 @@ def test_isra_split_precision(lf, precision):
 
 
 @pytest.mark.parametrize("region", ["triangle", "rectangle", "whole"])
-@pytest.mark.parametrize("norm", ["full", "region"])
+@pytest.mark.parametrize("norm", ["full", "region", "spectral"])
 @pytest.mark.parametrize("nz,h,w,xs,ys", [(1, 55, 55, 5.5, 5.5), (3, 40, 64, 7.3, 3.9),
                                          (1, 600, 600, 10.0, 10.0), (2, 300, 420, 230.0, 180.0)])
 def test_metric_variants_match_oracle(lf, region, norm, nz, h, w, xs, ys):
@@ -153,7 +153,7 @@ def test_metric_variants_match_oracle(lf, region, norm, nz, h, w, xs, ys):
     img = vol[0] if nz == 1 else vol
     reg = {"triangle": lf.REGION_TRIANGLE, "rectangle": lf.REGION_RECTANGLE,
            "whole": lf.REGION_WHOLE}[region]
-    nrm = lf.NORM_MATRIX if norm == "full" else lf.NORM_REGION
+    nrm = {"full": lf.NORM_MATRIX, "region": lf.NORM_REGION, "spectral": lf.NORM_SPECTRAL}[norm]
     got = lf.metric(to_dev(img), xs, ys, region=reg, norm=nrm)
     want = oracle.metric(vol, xs, ys, region, norm)
     assert got == pytest.approx(want, rel=1e-9)
@@ -185,6 +185,31 @@ def test_window_stop_and_metric_variants_in_the_loop(lf, problem):
     assert rep2["best_iter"] == best
     ref_best = oracle.rl(psf, y, best, background=b)
     assert rel_l2(vol2.cpu().numpy(), ref_best) <= TOL
+
+
+def test_spectral_norm_in_the_loop(lf, problem):
+    """The spectral-norm reading tracked over the iterations of RL with the
+    background term."""
+    import torch
+    p, psf, y, xs, ys, plan = problem
+    b = float(p["background"])
+    _, best, _, ref_trace = oracle.deconvolve(psf, y, 8, xs, ys, stop=False, background=b,
+                                              norm="spectral")
+    _, rep = plan.deconvolve(to_dev(y), 8, stop=lf.STOP_TRACK, xs=xs, ys=ys, background=b,
+                             norm=lf.NORM_SPECTRAL)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(np.array(rep["metric_trace"]), ref_trace, rtol=TOL)
+    assert rep["best_iter"] == best
+
+
+def test_spectral_norm_size_limit(lf):
+    """The one-block power iteration holds h + w values: larger images are
+    refused before any device work."""
+    import torch
+    out = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    img = torch.zeros((8, 6200), dtype=torch.float32, device="cuda:0")
+    with pytest.raises(lf.LfrlError):
+        lf.lfrl_metric_ex(1, 8, 6200, img, 2.0, 2.0, lf.REGION_TRIANGLE, lf.NORM_SPECTRAL, out)
 
 
 def test_whole_region_in_the_loop(lf, problem):
@@ -254,7 +279,7 @@ def test_variant_argument_errors(lf, problem):
     p, psf, y, xs, ys, plan = problem
     yd = to_dev(y)
     bad = [dict(update=2), dict(background=-1.0), dict(background=float("nan")),
-           dict(stop=lf.STOP_TRACK, region=3), dict(stop=lf.STOP_TRACK, norm=2),
+           dict(stop=lf.STOP_TRACK, region=3), dict(stop=lf.STOP_TRACK, norm=3),
            dict(stop=lf.STOP_TRACK, window=-1)]
     for kw in bad:
         stop = kw.pop("stop", lf.STOP_NONE)
