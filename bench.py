@@ -423,14 +423,16 @@ def variants_leg(args, lf, plan, y_d, vol, h, w, xs, ys, background, ms_rl) -> d
         log(f"bench: variant {name}: {ms:.3f} ms/iter ({1000.0 / ms:.1f} it/s)")
     out["isra_background_backproject"]["note"] = "includes the one back projection A^T y"
     res = torch.empty(1, dtype=torch.float64, device=vol.device)
-    for name, region in (("triangle", lf.REGION_TRIANGLE), ("whole", lf.REGION_WHOLE)):
+    for name, region, norm in (("triangle", lf.REGION_TRIANGLE, lf.NORM_MATRIX),
+                               ("whole", lf.REGION_WHOLE, lf.NORM_MATRIX),
+                               ("triangle_spectral", lf.REGION_TRIANGLE, lf.NORM_SPECTRAL)):
         nz = vol.shape[0]
-        lf.lfrl_metric_ex(nz, h, w, vol, xs, ys, region, lf.NORM_MATRIX, res)
+        lf.lfrl_metric_ex(nz, h, w, vol, xs, ys, region, norm, res)
         torch.cuda.synchronize()
         calls = 20
         t0 = time.perf_counter()
         for _ in range(calls):
-            lf.lfrl_metric_ex(nz, h, w, vol, xs, ys, region, lf.NORM_MATRIX, res)
+            lf.lfrl_metric_ex(nz, h, w, vol, xs, ys, region, norm, res)
         torch.cuda.synchronize()
         out[f"metric_{name}_ms"] = (time.perf_counter() - t0) * 1000.0 / calls
         log(f"bench: metric {name}: {out[f'metric_{name}_ms']:.3f} ms per call")
