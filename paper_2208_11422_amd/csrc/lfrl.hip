@@ -1033,11 +1033,20 @@ __global__ __launch_bounds__(1024) void k_spectral_norm(const float *__restrict_
     __syncthreads();
     double lam = 0.0, prev = -1.0;
     for (int it = 0; it < maxit; ++it) {
-        // u = m v
+        // u = m v (loads in batches of 8, clamped; the masked terms add 0)
         for (int r = wave; r < H; r += nwave) {
+            const float *mr = m + (size_t)r * W;
             double acc = 0.0;
-            for (int s = lane; s < W; s += 64)
-                acc = fma((double)m[(size_t)r * W + s], v[s], acc);
+            for (int s0 = lane; s0 < W; s0 += 8 * 64) {
+                float x[8];
+#pragma unroll
+                for (int b = 0; b < 8; ++b)
+                    x[b] = mr[min(s0 + 64 * b, W - 1)];
+#pragma unroll
+                for (int b = 0; b < 8; ++b)
+                    if (s0 + 64 * b < W)
+                        acc = fma((double)x[b], v[s0 + 64 * b], acc);
+            }
             for (int off = 32; off > 0; off >>= 1)
                 acc += __shfl_down(acc, off, 64);
             if (lane == 0)
@@ -1056,7 +1065,17 @@ __global__ __launch_bounds__(1024) void k_spectral_norm(const float *__restrict_
             const int s = c0 + lane;
             if (s < W) {
                 double acc = 0.0;
-                for (int r = 0; r < H; ++r)
+                int r = 0;
+                for (; r + 8 <= H; r += 8) {
+                    float x[8];
+#pragma unroll
+                    for (int b = 0; b < 8; ++b)
+                        x[b] = m[(size_t)(r + b) * W + s];
+#pragma unroll
+                    for (int b = 0; b < 8; ++b)
+                        acc = fma((double)x[b], u[r + b], acc);
+                }
+                for (; r < H; ++r)
                     acc = fma((double)m[(size_t)r * W + s], u[r], acc);
                 v[s] = acc;
             }
