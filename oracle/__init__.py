@@ -87,9 +87,10 @@ def _load():
             lib.oracle_forward.argtypes = [i, i, i, i, i, fp, dp, dp]
             lib.oracle_backward.argtypes = [i, i, i, i, i, fp, dp, dp]
             lib.oracle_forward_at.argtypes = [i, i, i, i, i, fp, dp, l, ip, ip, dp]
+            lib.oracle_forward_window.argtypes = [i, i, i, i, i, fp, dp, i, i, i, i, dp]
             lib.oracle_backward_at.argtypes = [i, i, i, i, i, fp, dp, l, ip, ip, ip, dp]
-            for f in (lib.oracle_forward, lib.oracle_backward,
-                      lib.oracle_forward_at, lib.oracle_backward_at):
+            for f in (lib.oracle_forward, lib.oracle_backward, lib.oracle_forward_at,
+                      lib.oracle_backward_at, lib.oracle_forward_window):
                 f.restype = ctypes.c_int
             lib.oracle_threads.restype = ctypes.c_int
             _lib = lib
@@ -167,6 +168,27 @@ def forward_at(psf, vol, rows, cols) -> np.ndarray:
                                    _ptr(out, ctypes.c_double))
     if rc != 0:
         raise RuntimeError(f"oracle_forward_at failed ({rc})")
+    return out
+
+
+def forward_window(psf, vol, r0: int, r1: int, s0: int, s1: int) -> np.ndarray:
+    """A x on the pixel window rows [r0, r1) x columns [s0, s1): the same sums
+    as :func:`forward`, evaluated only there (pixels outside the image are 0).
+    Each output row is summed in a fixed order, whatever the thread count."""
+    psf = _f32(psf)
+    nz, n, k = _geom(psf)
+    vol = np.ascontiguousarray(vol, dtype=np.float64)
+    if vol.ndim != 3 or vol.shape[0] != nz:
+        raise ValueError("volume must be [nz][H][W]")
+    h, w = vol.shape[1:]
+    if r1 < r0 or s1 < s0:
+        raise ValueError("empty or inverted window")
+    out = np.empty((r1 - r0, s1 - s0), dtype=np.float64)
+    rc = _load().oracle_forward_window(n, nz, k, h, w, _ptr(psf, ctypes.c_float),
+                                       _ptr(vol, ctypes.c_double), r0, r1, s0, s1,
+                                       _ptr(out, ctypes.c_double))
+    if rc != 0:
+        raise RuntimeError(f"oracle_forward_window failed ({rc})")
     return out
 
 
@@ -283,6 +305,60 @@ def rl(psf, y, iters: int, x0=None, keep_all: bool = False, *, update: str = "rl
         x = step(x)
         out.append(x)
     return out if keep_all else x
+
+
+def rl_window(psf, y, iters: int, r0: int, r1: int, s0: int, s1: int,
+              background: float = 0.0):
+    """Richardson-Lucy iterates x^1 .. x^iters (ones start, the update of
+    :func:`rl_step`) on the voxel window rows [r0, r1) x columns [s0, s1) of
+    every plane, without whole-volume iterations.
+
+    A back-projected voxel reads only pixels within c0 = (K - 1) / 2 of it and
+    a projected pixel only voxels within c0, so x^k on the window needs the
+    ratio of iteration k on the window grown by c0, x^{k-1} on the window
+    grown by 2 c0, and so on: each iterate is computed exactly on the window
+    the next step reads (clipped to the image), with the same sums as
+    :func:`forward` and :func:`backward`.
+
+    Returns (xs, c): xs[m] = x^{m+1} on the window as [nz][r1-r0][s1-s0], and
+    c = A^T 1 there."""
+    psf = _f32(psf)
+    nz, n, k = _geom(psf)
+    y = np.asarray(y, dtype=np.float64)
+    h, w = y.shape
+    c0 = (k - 1) // 2
+
+    def grow(m):
+        return (max(0, r0 - m * c0), min(h, r1 + m * c0), max(0, s0 - m * c0),
+                min(w, s1 + m * c0))
+
+    ones_img = np.ones((h, w))
+    x = np.ones((nz, h, w))
+    out = []
+    c_win = None
+    for it in range(1, iters + 1):
+        pr0, pr1, ps0, ps1 = grow(2 * (iters - it) + 1)   # pixels of this ratio
+        vr0, vr1, vs0, vs1 = grow(2 * (iters - it))       # voxels of this iterate
+        yhat = forward_window(psf, x, pr0, pr1, ps0, ps1) + background
+        rho = np.zeros((h, w))
+        pos = yhat > 0
+        rho[pr0:pr1, ps0:ps1][pos] = y[pr0:pr1, ps0:ps1][pos] / yhat[pos]
+        jj, rr, ss = np.meshgrid(np.arange(nz), np.arange(vr0, vr1), np.arange(vs0, vs1),
+                                 indexing="ij")
+        jj, rr, ss = jj.ravel(), rr.ravel(), ss.ravel()
+        c = backward_at(psf, ones_img, jj, rr, ss)
+        b = backward_at(psf, rho, jj, rr, ss)
+        old = x[jj, rr, ss]
+        ok = c > 0
+        new = np.zeros_like(c)
+        new[ok] = old[ok] * b[ok] / c[ok]
+        x = np.zeros((nz, h, w))
+        x[jj, rr, ss] = new
+        shape = (nz, vr1 - vr0, vs1 - vs0)
+        win = (slice(None), slice(r0 - vr0, r1 - vr0), slice(s0 - vs0, s1 - vs0))
+        out.append(new.reshape(shape)[win].copy())
+        c_win = c.reshape(shape)[win].copy()
+    return out, c_win
 
 
 def poisson_loglik(y, yhat) -> float:

@@ -135,6 +135,61 @@ int oracle_forward_at(int nnum, int nz, int ksize, int h, int w,
     return 0;
 }
 
+/* Forward projection evaluated on the pixel window rows [r0, r1) x columns
+ * [s0, s1) (clipped to the image), out[(pr - r0) * (s1 - s0) + (ps - s0)].  The
+ * same sum as oracle_forward restricted to those outputs, gathered one output
+ * row at a time: for output row pr, every voxel row r whose PSF tap row
+ * u = pr - r + c0 lies in [0, K) adds its taps along that row.  Each output row
+ * is summed by one thread in the order (j, r, s, v), so the values do not
+ * depend on the thread count.  Pixels of the window outside the image are 0. */
+int oracle_forward_window(int nnum, int nz, int ksize, int h, int w,
+                          const float *psf, const double *vol,
+                          int r0, int r1, int s0, int s1, double *out)
+{
+    if (nnum < 1 || nz < 1 || ksize < 1 || (ksize & 1) == 0 || r1 < r0 || s1 < s0)
+        return -1;
+    const int c0 = (ksize - 1) / 2;
+    const int ww = s1 - s0;
+    memset(out, 0, (size_t)(r1 - r0) * (size_t)ww * sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int pr = r0; pr < r1; ++pr) {
+        if (pr < 0 || pr >= h)
+            continue;
+        double *orow = out + (size_t)(pr - r0) * ww;
+        const int pc0 = s0 > 0 ? s0 : 0, pc1 = s1 < w ? s1 : w;
+        if (pc1 <= pc0)
+            continue;
+        for (int j = 0; j < nz; ++j) {
+            for (int u = 0; u < ksize; ++u) {
+                const int r = pr - u + c0;
+                if (r < 0 || r >= h)
+                    continue;
+                const double *xrow = vol + ((size_t)j * h + r) * w;
+                /* voxel columns s whose taps reach [pc0, pc1) */
+                const int sa = pc0 - c0 > 0 ? pc0 - c0 : 0;
+                const int sb = pc1 - 1 + c0 < w - 1 ? pc1 - 1 + c0 : w - 1;
+                for (int s = sa; s <= sb; ++s) {
+                    const double xv = xrow[s];
+                    if (xv == 0.0)
+                        continue;
+                    const float *k = psf + psf_index(nnum, ksize, j, r % nnum, s % nnum) +
+                                     (size_t)u * ksize;
+                    /* taps v with ps = s + v - c0 in [pc0, pc1) */
+                    int va = pc0 - s + c0, vb = pc1 - s + c0;
+                    if (va < 0)
+                        va = 0;
+                    if (vb > ksize)
+                        vb = ksize;
+                    double *o = orow + (s - c0 - s0);
+                    for (int v = va; v < vb; ++v)
+                        o[v] += xv * (double)k[v];
+                }
+            }
+        }
+    }
+    return 0;
+}
+
 /* One back-projected voxel (j, r, s): correlate the image with the PSF of the
  * voxel's own depth and phase, centred on the voxel's pixel. */
 static double backward_voxel(int nnum, int ksize, int h, int w,

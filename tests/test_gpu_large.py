@@ -6,6 +6,8 @@ iterations at this size, so it is compared on sampled outputs it computes one
 by one (forward at random and border pixels, back projection at random and
 border voxels), and whole RL runs are checked through invariants that hold at
 any size (flux, non-negativity, likelihood ascent, determinism)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -197,3 +199,93 @@ def test_first_iterate_variants_sampled(setup, update):
     err = rel_l2(vol[jj, rr, ss], want)
     print(f"{update} with background: first iterate sampled rel L2 {err:.2e}", flush=True)
     assert err <= TOL
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "large_rl_iterates.json")
+
+
+def golden_image(seed, h, w):
+    # the generator the golden script states (make_large_rl_golden.image)
+    return np.random.default_rng(seed).uniform(10.0, 2000.0, size=(h, w)).astype(np.float32)
+
+
+@pytest.fixture(scope="module")
+def iterates(setup):
+    """x^1 and x^2 of the bench plan on the golden file's image (2 runs of
+    lfrl_deconvolve with a fixed iteration count, ones start)."""
+    import json
+
+    import torch
+    lf, p, plan, dev = setup
+    g = p["geometry"]
+    with open(GOLDEN) as f:
+        gold = json.load(f)
+    psf = p["psf_array"].astype(np.float64)
+    want = gold["workload"]["psf_checksum"]
+    got = [float(psf.sum()), float((psf * psf).sum())]
+    assert np.allclose(got, want, rtol=1e-12, atol=0), (got, want)
+    y = golden_image(gold["image"]["seed"], g.h, g.w)
+    y_d = torch.from_numpy(y).to(dev)
+    out = {}
+    for k in (1, 2):
+        vol, rep = plan.deconvolve(y_d, k, stop=lf.STOP_NONE)
+        out[k] = vol.cpu().numpy()
+        print(f"x^{k}: weak voxels {rep['weak_voxels']}", flush=True)
+    return gold, y, out
+
+
+def test_rl_iterates_full_size_vs_golden(iterates):
+    """x^1 and x^2 at full size (255 x 255 PSF, Q as in the bench) against
+    oracle values at the corner window's voxels (five whole planes, first and
+    last included, plus every weakly observed voxel, whose update runs as
+    exact window sums), and x^1 in an interior window.  Bar: relative L2
+    1e-5 per window and iterate; every weakly observed voxel to rtol 1e-5."""
+    gold, _, x = iterates
+    for win in gold["windows"]:
+        v = np.asarray(win["voxels"])
+        c = np.asarray(win["c"])
+        for key, k in (("x1", 1), ("x2", 2)):
+            if key not in win:
+                continue
+            want = np.asarray(win[key])
+            got = x[k][v[:, 0], v[:, 1], v[:, 2]].astype(np.float64)
+            err = rel_l2(got, want)
+            print(f"{win['name']} {key}: {v.shape[0]} voxels, rel L2 {err:.2e}", flush=True)
+            assert err <= TOL
+            if win["name"] == "corner":
+                weak = c < 1e-2 * win["c_max"]
+                assert weak.sum() >= 50, "the corner window must hold weakly observed voxels"
+                wr = np.abs(got[weak] - want[weak]) / np.abs(want[weak])
+                print(f"corner {key}: {int(weak.sum())} weak voxels, max rel err "
+                      f"{wr.max():.2e}", flush=True)
+                np.testing.assert_allclose(got[weak], want[weak], rtol=1e-5, atol=0)
+
+
+def test_rl_first_iterate_other_corner_inline(setup, iterates):
+    """x^1 in the bottom-left corner window (rows [h-16, h), columns [0, 16))
+    of the first and last planes, computed here by the oracle: A 1 on the
+    pixels the window's back projection reads, the ratio, then A^T rho / A^T 1
+    voxel by voxel."""
+    lf, p, plan, dev = setup
+    g = p["geometry"]
+    _, y, x = iterates
+    psf = p["psf_array"]
+    c0 = (g.ksize - 1) // 2
+    r0, r1, s0, s1 = g.h - 16, g.h, 0, 16
+    lo_r, hi_r, lo_s, hi_s = r0 - c0, g.h, 0, s1 + c0
+    a1 = oracle.forward_window(psf, np.ones((g.nz, g.h, g.w)), lo_r, hi_r, lo_s, hi_s)
+    rho = np.zeros((g.h, g.w))
+    pos = a1 > 0
+    rho[lo_r:hi_r, lo_s:hi_s][pos] = y[lo_r:hi_r, lo_s:hi_s][pos] / a1[pos]
+    jj, rr, ss = np.meshgrid([0, g.nz - 1], np.arange(r0, r1), np.arange(s0, s1), indexing="ij")
+    jj, rr, ss = jj.ravel(), rr.ravel(), ss.ravel()
+    c = oracle.backward_at(psf, np.ones((g.h, g.w)), jj, rr, ss)
+    want = oracle.backward_at(psf, rho, jj, rr, ss) / c
+    got = x[1][jj, rr, ss].astype(np.float64)
+    err = rel_l2(got, want)
+    weak = c < 1e-2
+    print(f"bottom-left corner x^1: rel L2 {err:.2e}, {int(weak.sum())} weak voxels", flush=True)
+    assert err <= TOL
+    assert weak.sum() > 0
+    np.testing.assert_allclose(got[weak], want[weak], rtol=1e-5, atol=0)

@@ -122,3 +122,38 @@ def test_serving_set_projections_full_size(lf):
         assert ef <= 1e-3 and eb <= 1e-3
     finally:
         plan.close()
+
+
+def test_batched_frame_iterates_full_size(lf):
+    """x^1 and x^2 of a batched-workload frame (Nnum 15, 720 x 720, 41
+    planes, K = 121) on its autotuned FP32 plan, against the oracle's
+    windowed iterates (oracle.rl_window) in the top-left corner window, where
+    the weakly observed voxels sit, and in an interior window.  Bar: relative
+    L2 1e-5 per window and iterate; every weakly observed voxel to rtol 1e-5."""
+    import torch
+    sp = S.batched_frames()[4]
+    psf = S.batched_psf(sp)
+    h, w, nz = sp["h"], sp["w"], sp["nz"]
+    print(f"batched frame 4: {sp}", flush=True)
+    y = np.random.default_rng(sp["seed"] + 7).uniform(10.0, 1000.0, size=(h, w)).astype(np.float32)
+    plan = lf.Plan(torch.from_numpy(psf).cuda(), h, w, autotune=True)
+    try:
+        print(f"plan Q={plan.info['tile_q']} tuned over {plan.info['tune_candidates']}",
+              flush=True)
+        y_d = torch.from_numpy(y).cuda()
+        got = {k: plan.deconvolve(y_d, k, stop=lf.STOP_NONE)[0].cpu().numpy() for k in (1, 2)}
+    finally:
+        plan.close()
+    for name, (r0, r1, s0, s1), iters in (("corner", (0, 16, 0, 16), 2),
+                                          ("interior", (352, 368, 352, 368), 1)):
+        xs, c = oracle.rl_window(psf, y, iters, r0, r1, s0, s1)
+        weak = c < 1e-2 * c.max()
+        for m in range(iters):
+            g = got[m + 1][:, r0:r1, s0:s1].astype(np.float64)
+            err = rel_l2(g, xs[m])
+            print(f"{name} x^{m + 1}: rel L2 {err:.2e}, {int(weak.sum())} weak voxels", flush=True)
+            assert err <= 1e-5
+            if weak.any():
+                np.testing.assert_allclose(g[weak], xs[m][weak], rtol=1e-5, atol=0)
+        if name == "corner":
+            assert weak.sum() > 0

@@ -180,3 +180,26 @@ def test_psf_normalisation():
     np.testing.assert_array_equal(out[1, 2, 0], 0.0)
     again = oracle.normalize_psf(out * np.float32(4.0))
     np.testing.assert_array_equal(again[live], out[live])
+
+
+@pytest.mark.parametrize("win", [(0, 9, 0, 12), (5, 17, 8, 20), (-4, 3, 25, 40), (10, 30, -2, 6),
+                                 (0, 24, 0, 30), (3, 3, 0, 5)])
+def test_window_form_matches_full_form(win):
+    """The windowed forward projection is the full projection cropped to the
+    window (zero where the window leaves the image), for windows inside, on
+    the border of and partly outside the image, and an empty one; the delta
+    pins above fix the full form."""
+    n, k, nz = 3, 9, 3
+    h, w = 24, 30
+    psf = random_psf(nz, n, k, seed=31)
+    x = np.random.default_rng(32).uniform(0.0, 1.0, size=(nz, h, w))
+    x[1, 5:9, :] = 0.0  # zero voxels are skipped by the scatter form
+    full = oracle.forward(psf, x)
+    r0, r1, s0, s1 = win
+    want = np.zeros((r1 - r0, s1 - s0))
+    rr = np.arange(r0, r1)[:, None]
+    ss = np.arange(s0, s1)[None, :]
+    inside = (rr >= 0) & (rr < h) & (ss >= 0) & (ss < w)
+    want[inside] = full[np.clip(rr, 0, h - 1), np.clip(ss, 0, w - 1)][inside]
+    got = oracle.forward_window(psf, x, r0, r1, s0, s1)
+    np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-13)

@@ -97,3 +97,22 @@ def test_zero_prediction_and_zero_sensitivity_rules():
     x = oracle.rl(psf, y, 2)
     np.testing.assert_array_equal(x[1], 0.0)
     np.testing.assert_allclose(x[0], y, rtol=1e-15)
+
+
+@pytest.mark.parametrize("win", [(0, 6, 0, 6), (9, 15, 3, 12), (14, 18, 20, 24)])
+def test_windowed_iterates_match_whole_volume_iterates(win):
+    """rl_window (iterates evaluated only where the next step reads them)
+    equals the whole-volume iteration cropped to the window, for corner,
+    interior and edge windows over three iterations, with and without a
+    background."""
+    n, k, nz = 3, 7, 2
+    h, w = 18, 24
+    psf = np.random.default_rng(41).uniform(0.0, 1.0, size=(nz, n, n, k, k)).astype(np.float32)
+    y = np.random.default_rng(42).uniform(1.0, 50.0, size=(h, w))
+    r0, r1, s0, s1 = win
+    for bg in (0.0, 3.0):
+        full = oracle.rl(psf, y, 3, keep_all=True, background=bg)
+        xs, c = oracle.rl_window(psf, y, 3, r0, r1, s0, s1, background=bg)
+        np.testing.assert_allclose(c, oracle.sensitivity(psf, h, w)[:, r0:r1, s0:s1], rtol=1e-13)
+        for m in range(3):
+            np.testing.assert_allclose(xs[m], full[m + 1][:, r0:r1, s0:s1], rtol=1e-12)
