@@ -28,6 +28,7 @@ if ROOT not in sys.path:
 METRIC = "LF-RL iters/s at 600²×31 (FP32 vs split-FP16); p50/p99 job latency"
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
+F16_PEAK_TFLOPS = 2500.0   # dense FP16 / BF16 matrix peak
 CACHE = os.environ.get("LFRL_SYNTH_CACHE", "/tmp/lfrl_synth_cache")
 
 
@@ -51,25 +52,39 @@ def contraction_flops(info: dict, g, nt: int) -> float:
 
 
 def iteration_model(info: dict, g, h: int, w: int, nt: int, ms_measured: float,
-                    spectra_bytes_per_coef: float = 8.0) -> dict:
+                    precision: str = "fp32") -> dict:
     """Roofline model of one whole iteration at the plan's tile shape.
 
-    Bytes: both PSF spectra passes, the tile spectra written and read around
-    each contraction, the volume reads of the tile gather (overlap included),
-    the update's volume traffic and the image-sized buffers.  Flops: the two
-    contractions plus the tile DFTs.  The floor is the PSF read once per
+    Bytes: both PSF spectra passes (8 bytes per complex coefficient in float32,
+    4 in the split modes' 16-bit words), the tile spectra written and read
+    around each contraction, the volume reads of the tile gather (overlap
+    included), the update's volume traffic and the image-sized buffers.
+    Compute: the two contractions on their own units (float32 matrix cores at
+    157.3 TFLOP/s; the split modes do two 16-bit products, hi and lo, per real
+    product on the FP16/BF16 matrix cores at 2.5 PFLOP/s) plus the tile DFTs
+    in float32 vector arithmetic.  The floor is the PSF read once per
     projection, whatever the shape."""
     n, nz, k = g.nnum, g.nz, g.ksize
     q, t, r, nf = info["tile_q"], info["tile_out"], info["taps"], info["nfreq"]
-    s_g = n ** 4 * nz * nf * spectra_bytes_per_coef
+    split = precision != "fp32"
+    s_g = n ** 4 * nz * nf * (4.0 if split else 8.0)
     s_x = n ** 2 * nz * nt * nf * 8.0
     b = (2 * s_g + 4 * s_x + 4.0 * w * h * nz * (((t + r - 1) / t) ** 2 + 3) + 24.0 * w * h)
-    f = 16.0 * n ** 4 * nz * nf * nt + 2.0 * (n * n * nz + n * n) * nt * 5 * q * q * math.log2(q * q)
+    f_contract = 16.0 * n ** 4 * nz * nf * nt
+    f_dft = 2.0 * (n * n * nz + n * n) * nt * 5 * q * q * math.log2(q * q)
     t_hbm = b / (HBM_PEAK_GBS * 1e9) * 1e3
-    t_alu = f / (FP32_PEAK_TFLOPS * 1e12) * 1e3
+    if split:
+        t_contract = 2.0 * f_contract / (F16_PEAK_TFLOPS * 1e12) * 1e3
+    else:
+        t_contract = f_contract / (FP32_PEAK_TFLOPS * 1e12) * 1e3
+    t_dft = f_dft / (FP32_PEAK_TFLOPS * 1e12) * 1e3
+    t_compute = t_contract + t_dft
     floor = 2.0 * n * n * nz * k * k * 4 / (HBM_PEAK_GBS * 1e9) * 1e3
-    bound = max(t_hbm, t_alu)
-    return {"bytes_per_iter": b, "flops_per_iter": f, "t_hbm_ms": t_hbm, "t_fp32_ms": t_alu,
+    bound = max(t_hbm, t_compute)
+    return {"precision": precision, "bytes_per_iter": b,
+            "flops_per_iter": f_contract * (2.0 if split else 1.0) + f_dft,
+            "t_hbm_ms": t_hbm, "t_contract_ms": t_contract, "t_dft_ms": t_dft,
+            "t_compute_ms": t_compute, "bound": "hbm" if t_hbm >= t_compute else "compute",
             "t_bound_ms": bound, "frac_of_bound": bound / ms_measured,
             "floor_ms": floor, "floor_frac": floor / ms_measured}
 
@@ -144,6 +159,113 @@ def cpu_baseline(psf, x, y, xs, ys, budget_s: float = 8.0) -> dict:
             "kind": "oracle", "sample": sample}
 
 
+GOLDEN_LARGE = os.path.join(ROOT, "tests", "golden", "large_rl_iterates.json")
+
+
+def large_samples(lf, plan, g, dev) -> dict:
+    """x^1 and x^2 of `plan` (fixed iteration counts, ones start) on the seeded
+    image of the golden file of full-size iterates, at that file's sampled
+    voxels: {window: {"x1": values, "x2": values}}.  The file holds the
+    oracle's values at the same voxels (written by its own script from the
+    oracle alone); the CPU leg compares the two."""
+    import numpy as np
+    import torch
+    with open(GOLDEN_LARGE) as f:
+        gold = json.load(f)
+    seed = gold["image"]["seed"]
+    y = np.random.default_rng(seed).uniform(10.0, 2000.0, size=(g.h, g.w)).astype(np.float32)
+    y_d = torch.from_numpy(y).to(dev)
+    out = {}
+    for k in (1, 2):
+        vol, _ = plan.deconvolve(y_d, k, stop=lf.STOP_NONE)
+        v = vol.cpu().numpy()
+        for win in gold["windows"]:
+            if f"x{k}" in win:
+                idx = np.asarray(win["voxels"])
+                out.setdefault(win["name"], {})[f"x{k}"] = v[idx[:, 0], idx[:, 1], idx[:, 2]]
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def rel_l2(a, b) -> float:
+    import numpy as np
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def accuracy_vs_oracle(samples: dict, dev) -> dict:
+    """Relative L2 error against the float64 oracle, per workload:
+
+    * small (Nnum 5, 55 x 55, 5 planes, K = 25) and its precision variant:
+      every iterate x^1 .. x^30 of FP32, split FP16 and split BF16 (BF16 on to
+      x^50, the serving cap), each the result of a fixed-length run, against
+      the oracle's iterates on the same seeded input (the image projected by
+      the oracle, Poisson noise from the generators);
+    * large (600 x 600 x 31, K = 255): x^1 and x^2 at the golden file's
+      sampled voxels (corner window with weakly observed voxels, interior
+      window), per precision, against the oracle's stored values."""
+    import numpy as np
+    import torch
+
+    import lfrl_synth as S
+    import oracle
+    import paper_2208_11422_amd as lf
+    out = {}
+    p = S.preset("small")
+    g = p["geometry"]
+    psf = p["psf_array"]
+    y = S.measure(oracle.forward(psf, p["x_true"]), p["peak"], p["background"], p["noise_seed"])
+    t = time.perf_counter()
+    ref = oracle.rl(psf, y, 50, keep_all=True)
+    log(f"accuracy: oracle 50 iterates of the small workload in {time.perf_counter() - t:.1f} s")
+    y_d = torch.from_numpy(y).to(dev)
+    psf_d = torch.from_numpy(psf).to(dev)
+    for name, prec, iters in (("fp32", lf.FP32, 30), ("split_fp16", lf.SPLIT_FP16, 30),
+                              ("split_bf16", lf.SPLIT_BF16, 50)):
+        plan = lf.Plan(psf_d, g.h, g.w, precision=prec)
+        errs = []
+        for k in range(1, iters + 1):
+            vol, _ = plan.deconvolve(y_d, k, stop=lf.STOP_NONE)
+            errs.append(rel_l2(vol.cpu().numpy(), ref[k]))
+        plan.close()
+        tol = 1e-5 if prec == lf.FP32 else 1e-3
+        within = next((k for k, e in enumerate(errs, 1) if e > tol), None)
+        out[f"small_{name}"] = {"rel_l2_by_iter": errs, "max": max(errs),
+                                "max_first_5": max(errs[:5]), "tol": tol,
+                                "first_iter_above_tol": within}
+    # large workload, sampled
+    with open(GOLDEN_LARGE) as f:
+        gold = json.load(f)
+    for name, smp in samples.items():
+        res = {}
+        for win in gold["windows"]:
+            for key in ("x1", "x2"):
+                if key in win and key in smp.get(win["name"], {}):
+                    want = np.asarray(win[key])
+                    got = smp[win["name"]][key]
+                    res[f"{win['name']}_{key}_rel_l2"] = rel_l2(got, want)
+                    if win["name"] == "corner":
+                        c = np.asarray(win["c"])
+                        weak = c < 1e-2 * win["c_max"]
+                        res[f"corner_{key}_weak_max_rel"] = float(
+                            np.max(np.abs(got[weak] - want[weak]) / np.abs(want[weak])))
+                        res["corner_weak_voxels"] = int(weak.sum())
+        out[f"large_{name}"] = res
+    log(f"accuracy: {json.dumps({k: {kk: vv for kk, vv in v.items() if kk != 'rel_l2_by_iter'} for k, v in out.items()})}")
+    return out
+
+
 def synth_measurement(plan, nz, h, w, seed, beads, peak, background, dev):
     """Measured image of a bead volume, made on the device: the bead splats of
     `seed` scattered into a volume, projected with `plan`, scaled to `peak`
@@ -185,9 +307,8 @@ def small_leg(args, dev) -> dict:
     """The small workload (Nnum 5, 55 x 55, 5 planes, K = 25), which is bound
     by launch latency rather than bandwidth: calls of lfrl_deconvolve with its
     5 iterations, with the run replayed from a captured graph and with direct
-    launches; then the split-FP16 path's drift from the FP32 path over 30
-    iterations (relative L2 per iterate)."""
-    import numpy as np
+    launches.  (Its accuracy against the oracle, per iterate and precision,
+    is measured in the CPU leg.)"""
     import torch
 
     import lfrl_synth as S
@@ -217,22 +338,8 @@ def small_leg(args, dev) -> dict:
         out[mode] = {"ms_per_call": ms, "iters_per_s": p["iters"] * 1e3 / ms}
     os.environ.pop("LFRL_GRAPH", None)
     out["graph_speedup"] = out["direct"]["ms_per_call"] / out["graph"]["ms_per_call"]
-    # precision: split FP16 and split BF16 against FP32, per iterate
-    drift = {}
-    for name, prec in (("split_fp16_drift", lf.SPLIT_FP16), ("split_bf16_drift", lf.SPLIT_BF16)):
-        planx = lf.Plan(psf_d, g.h, g.w, precision=prec)
-        errs = []
-        for k in range(1, 31):
-            a, _ = plan.deconvolve(y, k, stop=lf.STOP_NONE)
-            b, _ = planx.deconvolve(y, k, stop=lf.STOP_NONE)
-            errs.append(float(torch.linalg.vector_norm(b - a) / torch.linalg.vector_norm(a)))
-        planx.close()
-        out[name] = {"max_rel_l2_vs_fp32": max(errs), "at_iter": 1 + int(np.argmax(errs)),
-                     "rel_l2_by_iter": errs}
-        drift[name] = max(errs)
     plan.close()
-    log(f"small: {json.dumps({k: v for k, v in out.items() if not k.endswith('_drift')})}, "
-        f"drift max {drift}")
+    log(f"small: {json.dumps(out)}")
     return out
 
 
@@ -578,67 +685,55 @@ def main() -> int:
             / FP32_PEAK_TFLOPS,
         },
         "kernels": kern,
-        "model": iteration_model(info, g, h, w, nt, ms_per_step),
+        "model": iteration_model(info, g, h, w, nt, ms_per_step, precision="fp32"),
     }
-    vol32 = vol.clone()  # the FP32 result the split legs are compared with
+    # x^steps of a fixed-length run (no stop rule), which the split paths are
+    # compared with; and x^1, x^2 at the golden file's sampled voxels of its
+    # seeded image, compared with the oracle's values in the CPU leg
+    vol32, _ = plan.deconvolve(y_d, args.steps, stop=lf.STOP_NONE)
+    samples = {"fp32": large_samples(lf, plan, g, dev)}
     if not args.no_variants:
         out["variants"] = variants_leg(args, lf, plan, y_d, vol, h, w, xs, ys,
                                        float(p["background"]), ms_per_step)
     if not args.no_split:
-        plan.close()
-        torch.cuda.empty_cache()
-        psf_d = torch.from_numpy(p["psf_array"]).to(dev)
-        plan16 = lf.Plan(psf_d, h, w, tile_q=args.tile_q, precision=lf.SPLIT_FP16)
-        del psf_d
-        torch.cuda.synchronize()
-        opts16 = lf.RlOpts(max_iters=args.warmup if args.warmup > 0 else 1, stop=lf.STOP_TRACK,
-                           patience=1, init=0, xs=xs, ys=ys)
-        lf.lfrl_deconvolve(plan16.handle, h, w, y_d, vol, opts16)
-        lf.lfrl_profile_enable(plan16.handle, True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        opts16.max_iters = args.steps
-        lf.lfrl_deconvolve(plan16.handle, h, w, y_d, vol, opts16)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        prof16 = {k: lf.lfrl_profile_read(plan16.handle, k)
-                  for k in ("contract_fwd", "contract_adj")}
-        ms16 = (t1 - t0) * 1000.0 / args.steps
-        diff = float(torch.linalg.vector_norm(vol - vol32) / torch.linalg.vector_norm(vol32))
-        out["split_fp16"] = {
-            "value": 1000.0 / ms16, "unit": "iters/s", "ms_per_step": ms16,
-            "model": iteration_model(plan16.info, g, h, w, plan16.info["max_tiles"], ms16,
-                                     spectra_bytes_per_coef=4.0),
-            "dtype": "f16 spectra, hi/lo f16 tile spectra, f32 accumulate",
-            "rel_l2_vs_fp32_after_steps": diff,
-            "speedup_vs_fp32": ms_per_step / ms16,
-            "kernels": {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]}
-                        for k, v in prof16.items()},
-        }
-        log(f"bench: split FP16 {ms16:.3f} ms/iter ({1000.0 / ms16:.1f} it/s), "
-            f"rel L2 vs FP32 {diff:.2e}")
-        # the same with BF16 spectra and BF16 matrix cores
-        plan16.close()
-        torch.cuda.empty_cache()
-        psf_d = torch.from_numpy(p["psf_array"]).to(dev)
-        planb = lf.Plan(psf_d, h, w, tile_q=args.tile_q, precision=lf.SPLIT_BF16)
-        del psf_d
-        optsb = lf.RlOpts(max_iters=args.warmup if args.warmup > 0 else 1, stop=lf.STOP_TRACK,
-                          patience=1, init=0, xs=xs, ys=ys)
-        lf.lfrl_deconvolve(planb.handle, h, w, y_d, vol, optsb)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        optsb.max_iters = args.steps
-        lf.lfrl_deconvolve(planb.handle, h, w, y_d, vol, optsb)
-        torch.cuda.synchronize()
-        msb = (time.perf_counter() - t0) * 1000.0 / args.steps
-        diffb = float(torch.linalg.vector_norm(vol - vol32) / torch.linalg.vector_norm(vol32))
-        out["split_bf16"] = {"value": 1000.0 / msb, "unit": "iters/s", "ms_per_step": msb,
-                             "dtype": "bf16 spectra, hi/lo bf16 tile spectra, f32 accumulate",
-                             "rel_l2_vs_fp32_after_steps": diffb}
-        log(f"bench: split BF16 {msb:.3f} ms/iter ({1000.0 / msb:.1f} it/s), "
-            f"rel L2 vs FP32 {diffb:.2e}")
-        plan = planb
+        for name, prec in (("split_fp16", lf.SPLIT_FP16), ("split_bf16", lf.SPLIT_BF16)):
+            plan.close()
+            torch.cuda.empty_cache()
+            psf_d = torch.from_numpy(p["psf_array"]).to(dev)
+            plan = lf.Plan(psf_d, h, w, tile_q=args.tile_q, precision=prec)
+            del psf_d
+            torch.cuda.synchronize()
+            opts16 = lf.RlOpts(max_iters=args.warmup if args.warmup > 0 else 1,
+                               stop=lf.STOP_TRACK, patience=1, init=0, xs=xs, ys=ys)
+            lf.lfrl_deconvolve(plan.handle, h, w, y_d, vol, opts16)
+            lf.lfrl_profile_enable(plan.handle, True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            opts16.max_iters = args.steps
+            lf.lfrl_deconvolve(plan.handle, h, w, y_d, vol, opts16)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            prof16 = {k: lf.lfrl_profile_read(plan.handle, k)
+                      for k in ("contract_fwd", "contract_adj")}
+            lf.lfrl_profile_enable(plan.handle, False)
+            ms16 = (t1 - t0) * 1000.0 / args.steps
+            x16, _ = plan.deconvolve(y_d, args.steps, stop=lf.STOP_NONE)
+            diff = float(torch.linalg.vector_norm(x16 - vol32) / torch.linalg.vector_norm(vol32))
+            del x16
+            samples[name] = large_samples(lf, plan, g, dev)
+            word = "f16" if prec == lf.SPLIT_FP16 else "bf16"
+            out[name] = {
+                "value": 1000.0 / ms16, "unit": "iters/s", "ms_per_step": ms16,
+                "model": iteration_model(plan.info, g, h, w, plan.info["max_tiles"], ms16,
+                                         precision=name.replace("_", "-")),
+                "dtype": f"{word} spectra, hi/lo {word} tile spectra, f32 accumulate",
+                "rel_l2_vs_fp32": {"iterate": args.steps, "stop": "none", "value": diff},
+                "speedup_vs_fp32": ms_per_step / ms16,
+                "kernels": {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]}
+                            for k, v in prof16.items()},
+            }
+            log(f"bench: {name} {ms16:.3f} ms/iter ({1000.0 / ms16:.1f} it/s), "
+                f"x^{args.steps} rel L2 vs FP32 {diff:.2e}")
     if args.small_calls > 0 or args.batched_frames > 0 or args.serving_requests > 0:
         plan.close()
         plan = None
@@ -652,12 +747,22 @@ def main() -> int:
         out["p50_ms"] = out["serving"]["open_loop_0.8"]["p50_ms"]
         out["p99_ms"] = out["serving"]["open_loop_0.8"]["p99_ms"]
     if not args.no_cpu_baseline:
+        import tempfile
+
+        import oracle
         log("bench: cpu baseline (oracle, bounded sample)")
+        with tempfile.TemporaryDirectory() as tmp:
+            flags = oracle.use_native_build(tmp)
         # oracle inputs come from the generators, never from the GPU path; the
         # oracle's cost does not depend on the values
         x_dense = p["x_true"] + np.float32(1.0)
         y_syn = np.random.default_rng(1).uniform(10.0, 2000.0, size=(h, w)).astype(np.float32)
         out["cpu_baseline"] = cpu_baseline(p["psf_array"], x_dense, y_syn, xs, ys)
+        out["cpu_baseline"].update(cpu_model=cpu_model(), build=f"gcc {flags}",
+                                   method="sampled outputs, time scaled to the whole iteration",
+                                   host_cpus=os.cpu_count())
+        log(f"bench: cpu baseline {json.dumps(out['cpu_baseline'])}")
+        out["accuracy_vs_oracle"] = accuracy_vs_oracle(samples, dev)
     if plan is not None:
         plan.close()
     print(json.dumps(out), flush=True)

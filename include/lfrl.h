@@ -22,8 +22,9 @@
  *     NULL = the null stream) unless stated otherwise.
  *   - The caller owns every buffer it passes.  A plan owns its PSF spectra and
  *     its workspace; after lfrl_plan returns, no call allocates device memory
- *     except lfrl_metric (see there) and the job calls (a job's state is
- *     allocated by lfrl_job_create, sized by lfrl_job_footprint).
+ *     except lfrl_metric / lfrl_metric_ex (see there) and the job calls (a
+ *     job's state is allocated by lfrl_job_create, sized by
+ *     lfrl_job_footprint).
  *   - One call at a time per plan (calls on one plan share its workspace).
  *   - Calls return LFRL_OK or a negative lfrl_status and never throw.  Argument
  *     errors are reported before anything is launched; lfrl_last_error() gives
@@ -217,7 +218,11 @@ typedef struct {
  * and return the iterate with the largest entropy seen (ties: the later one).
  * img [h][w] -> vol [nz][h][w] (x^{best_iter}, or x^{max_iters} without a
  * metric).  Synchronises `stream` before returning (the host needs the stop
- * decision and the report).  `report` [host] may be NULL. */
+ * decision and the report).  `report` [host] may be NULL.  The weakly
+ * observed voxels are listed when A^T 1 is first formed for an image size; if
+ * more than min(nz h w, 2^20) of them remain below even 1e-9 of the largest
+ * A^T 1 (a depth plane with an all-zero PSF, say), the call returns
+ * LFRL_ERR_UNSUPPORTED rather than leave some of them on the inexact path. */
 int lfrl_deconvolve(lfrl_plan_t plan, int32_t h, int32_t w, const float *img,
                     float *vol, const lfrl_rl_opts *opts, lfrl_rl_report *report,
                     void *stream);
@@ -249,7 +254,9 @@ int lfrl_job_footprint(lfrl_plan_t plan, int32_t h, int32_t w, size_t *bytes);
  * for the frame (and A^T img for the ISRA update or the back projection start)
  * and synchronises `stream`.  Returns LFRL_ERR_NUMERIC, and
  * creates nothing, when img holds a negative or non-finite value;
- * LFRL_ERR_NOMEM when the job's memory cannot be allocated. */
+ * LFRL_ERR_NOMEM when the job's memory cannot be allocated;
+ * LFRL_ERR_UNSUPPORTED when the frame has more weakly observed voxels than
+ * their list holds (see lfrl_deconvolve). */
 int lfrl_job_create(lfrl_job_t *out, lfrl_plan_t plan, int32_t h, int32_t w,
                     const float *img, const float *vol0, const lfrl_rl_opts *opts,
                     uint32_t flags, void *stream);
@@ -289,7 +296,9 @@ int lfrl_deconvolve_batch(const lfrl_plan_t *plans, int32_t n, const int32_t *h,
  * with 0 log 0 = 0 (0 for an all-zero image).  Pass nz > 1 to score the z
  * maximum projection of a volume img[nz][h][w] instead.  `out` is a device
  * float64.  Uses a per-device scratch buffer that the library allocates on
- * first use and grows when a larger image needs it. */
+ * first use and grows when a larger image needs it.  Calls on one device share
+ * that buffer: each call's kernels wait (on its stream) for the previous
+ * call's, so calls on different streams are serialised on the device. */
 int lfrl_metric(int32_t nz, int32_t h, int32_t w, const float *img, double xs,
                 double ys, double *out, void *stream);
 

@@ -62,15 +62,51 @@ _lock = threading.Lock()
 _lib = None
 
 
+def _compile(out: str, flags) -> None:
+    tmp = out + ".tmp"
+    # ISO C mode and no contraction: every product and sum rounds on its own
+    cmd = (["gcc"] + list(flags) + ["-ffp-contract=off", "-fopenmp", "-shared", "-fPIC",
+                                    "-std=c11", "-Wall", "-Wextra", "-o", tmp, _SRC])
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+
+
 def build(force: bool = True) -> str:
     """Compile the C part of the oracle (gcc, OpenMP, generic x86-64)."""
     if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
-               "-Wall", "-Wextra", "-o", tmp, _SRC]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
+        _compile(_LIB, ["-O2"])
     return _LIB
+
+
+def use_native_build(directory: str) -> str:
+    """Compile the same C source with -O3 -march=native for the host this runs
+    on, into `directory`, and use it from now on in this process (for timing
+    the oracle on the machine it runs on; the arithmetic is the same, each
+    operation rounded on its own).  Returns the compiler flags."""
+    global _lib
+    path = os.path.join(directory, "liblfrl_oracle_native.so")
+    flags = ["-O3", "-march=native"]
+    _compile(path, flags)
+    with _lock:
+        _lib = _bind(ctypes.CDLL(path))
+    return " ".join(flags + ["-ffp-contract=off", "-fopenmp"])
+
+
+def _bind(lib):
+    i, l = ctypes.c_int, ctypes.c_long
+    fp = ctypes.POINTER(ctypes.c_float)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.oracle_forward.argtypes = [i, i, i, i, i, fp, dp, dp]
+    lib.oracle_backward.argtypes = [i, i, i, i, i, fp, dp, dp]
+    lib.oracle_forward_at.argtypes = [i, i, i, i, i, fp, dp, l, ip, ip, dp]
+    lib.oracle_forward_window.argtypes = [i, i, i, i, i, fp, dp, i, i, i, i, dp]
+    lib.oracle_backward_at.argtypes = [i, i, i, i, i, fp, dp, l, ip, ip, ip, dp]
+    for f in (lib.oracle_forward, lib.oracle_backward, lib.oracle_forward_at,
+              lib.oracle_backward_at, lib.oracle_forward_window):
+        f.restype = ctypes.c_int
+    lib.oracle_threads.restype = ctypes.c_int
+    return lib
 
 
 def _load():
@@ -79,21 +115,7 @@ def _load():
         if _lib is None:
             if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
                 build(force=True)
-            lib = ctypes.CDLL(_LIB)
-            i, l = ctypes.c_int, ctypes.c_long
-            fp = ctypes.POINTER(ctypes.c_float)
-            dp = ctypes.POINTER(ctypes.c_double)
-            ip = ctypes.POINTER(ctypes.c_int)
-            lib.oracle_forward.argtypes = [i, i, i, i, i, fp, dp, dp]
-            lib.oracle_backward.argtypes = [i, i, i, i, i, fp, dp, dp]
-            lib.oracle_forward_at.argtypes = [i, i, i, i, i, fp, dp, l, ip, ip, dp]
-            lib.oracle_forward_window.argtypes = [i, i, i, i, i, fp, dp, i, i, i, i, dp]
-            lib.oracle_backward_at.argtypes = [i, i, i, i, i, fp, dp, l, ip, ip, ip, dp]
-            for f in (lib.oracle_forward, lib.oracle_backward, lib.oracle_forward_at,
-                      lib.oracle_backward_at, lib.oracle_forward_window):
-                f.restype = ctypes.c_int
-            lib.oracle_threads.restype = ctypes.c_int
-            _lib = lib
+            _lib = _bind(ctypes.CDLL(_LIB))
     return _lib
 
 

@@ -2032,7 +2032,15 @@ static void default_shapes(const Geo &g, int *fcb, int *fu, int *acb, int *au)
 
 static unsigned weak_cap_for(size_t nvox)
 {
-    return (unsigned)std::min<size_t>(nvox, (size_t)1 << 20);
+    size_t cap = std::min<size_t>(nvox, (size_t)1 << 20);
+    // LFRL_WEAK_CAP lowers the list length (both its allocation and the
+    // selection limit), so small frames can exercise the overflow refusal
+    if (const char *e = getenv("LFRL_WEAK_CAP")) {
+        const long v = atol(e);
+        if (v > 0)
+            cap = std::min<size_t>(cap, (size_t)v);
+    }
+    return (unsigned)std::max<size_t>(cap, 1);
 }
 
 // Device buffers of one Frame, in the order they are carved from its block.
@@ -3021,6 +3029,18 @@ static constexpr size_t kSmallCopyVoxels = 65536;
 static constexpr int kSpectralMaxIters = 500;
 static constexpr int kSpectralMaxSides = 6144;
 
+// Row chunks of the leg-limited row transform: chunks of about 16 rows, as
+// many as T1 holds (kMetricChunks blocks of min(h, kMaxMetricLegs) x w
+// doubles), folded into the first before the column pass.
+static void metric_row_chunks(int h, int nv, int *rows_per_chunk, int *nchunks)
+{
+    const int cap = kMetricChunks * std::min(h, kMaxMetricLegs) / nv;
+    const int chunks = std::max(1, std::min((h + 15) / 16, cap));
+    const int rpc = (h + chunks - 1) / chunks;
+    *rows_per_chunk = rpc;
+    *nchunks = (h + rpc - 1) / rpc;
+}
+
 // Argument check of a metric norm against the image size.
 static int check_norm_size(int norm, int h, int w)
 {
@@ -3092,13 +3112,8 @@ static int run_metric(int nz, int h, int w, const float *vol, double xs, double 
                            h, w, w, mb.Fabs, w);
         LAUNCH_CHECK("k_dgemm32(columns)");
     } else {
-        // chunks of about 16 rows, as many as T1 holds (kMetricChunks blocks of
-        // min(h, kMaxMetricLegs) x w doubles), folded into the first before
-        // the column pass
-        const int cap = kMetricChunks * std::min(h, kMaxMetricLegs) / nv;
-        const int chunks = std::max(1, std::min((h + 15) / 16, cap));
-        const int rpc = (h + chunks - 1) / chunks;
-        const int nchunks = (h + rpc - 1) / rpc;
+        int rpc = 0, nchunks = 0;
+        metric_row_chunks(h, nv, &rpc, &nchunks);
         hipLaunchKernelGGL(k_dct_rows, dim3((nv * w + 255) / 256, nchunks), dim3(256), 0, st,
                            (const float *)mb.mip, h, w, (const double *)mb.tabH, nv, rpc, mb.T1);
         LAUNCH_CHECK("k_dct_rows");
@@ -3189,9 +3204,10 @@ static int frame_sensitivity(lfrl_plan_s *p, Frame &f, bool check_input, hipStre
         hipLaunchKernelGGL(k_check_image, dim3(256), dim3(256), 0, st, f.y, hw, f.counters + 1);
         LAUNCH_CHECK("k_check_image");
     }
-    float thr = kWeakThreshold;
+    float thr = kWeakThreshold, used = thr;
     unsigned found = 0;
     for (int attempt = 0; attempt < 8; ++attempt) {
+        used = thr;
         if (attempt > 0) {
             hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, f.counters);
             LAUNCH_CHECK("k_zero_u32");
@@ -3210,7 +3226,14 @@ static int frame_sensitivity(lfrl_plan_s *p, Frame &f, bool check_input, hipStre
     }
     if (check_input && f.counters_host[1])
         return set_error(LFRL_ERR_NUMERIC, "image has negative or non-finite values");
-    f.nweak = std::min(found, f.weak_cap);
+    if (found > f.weak_cap)
+        // a partial list would leave some weak voxels on the inexact path, and
+        // which ones would depend on the order of the atomic appends
+        return set_error(LFRL_ERR_UNSUPPORTED,
+                         "%u weakly observed voxels (A^T 1 below %g of its maximum) exceed the "
+                         "list of %u",
+                         found, (double)used, f.weak_cap);
+    f.nweak = found;
     if (f.nweak) {
         hipLaunchKernelGGL(k_weak_exact, dim3(f.nweak), dim3(kWeakThreads), 0, st, (const unsigned *)f.weak,
                            (const float *)p->psf, p->g.N, p->g.K, h, w, (const float *)nullptr,
@@ -3959,10 +3982,15 @@ extern "C" int lfrl_deconvolve_batch(const lfrl_plan_t *plans, int32_t n, const 
 }
 
 // Scratch for the plan-less metric entry point: one growable set per device.
+// `done` marks the end of the last call's kernels on its stream; the next call
+// makes its own stream wait for it, so calls on different streams take turns
+// on the shared buffers instead of racing.
 struct MetricScratch {
     float *mip = nullptr;
     double *tabH = nullptr, *tabW = nullptr, *T1 = nullptr, *n2p = nullptr, *Fabs = nullptr;
     size_t h_cap = 0, w_cap = 0;
+    hipEvent_t done = nullptr;
+    bool recorded = false;
 };
 static std::mutex g_metric_mu;
 static std::vector<MetricScratch> g_metric_scratch;
@@ -3973,7 +4001,9 @@ static void free_metric_scratch(MetricScratch &ms)
     for (void *q : b)
         if (q)
             (void)hipFree(q);
+    const hipEvent_t ev = ms.done;
     ms = MetricScratch();
+    ms.done = ev;
 }
 
 extern "C" int lfrl_metric(int32_t nz, int32_t h, int32_t w, const float *img, double xs,
@@ -3983,8 +4013,9 @@ extern "C" int lfrl_metric(int32_t nz, int32_t h, int32_t w, const float *img, d
                           stream);
 }
 
-extern "C" int lfrl_metric_ex(int32_t nz, int32_t h, int32_t w, const float *img, double xs,
-                              double ys, int32_t region, int32_t norm, double *out, void *stream)
+// Argument checks shared by the plan-less metric entry points.
+static int check_metric_args(int32_t nz, int32_t h, int32_t w, const float *img, double xs,
+                             double ys, int32_t region, int32_t norm, double *out)
 {
     if (!img || !out)
         return set_error(LFRL_ERR_ARG, "NULL argument");
@@ -4000,12 +4031,23 @@ extern "C" int lfrl_metric_ex(int32_t nz, int32_t h, int32_t w, const float *img
     if ((rc = check_buf(img, (size_t)nz * h * w * sizeof(float), "img")) ||
         (rc = check_buf(out, sizeof(double), "out")))
         return rc;
+    return LFRL_OK;
+}
+
+extern "C" int lfrl_metric_ex(int32_t nz, int32_t h, int32_t w, const float *img, double xs,
+                              double ys, int32_t region, int32_t norm, double *out, void *stream)
+{
+    int rc = check_metric_args(nz, h, w, img, xs, ys, region, norm, out);
+    if (rc)
+        return rc;
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_metric_mu);
     if ((int)g_metric_scratch.size() <= dev)
         g_metric_scratch.resize(dev + 1);
     MetricScratch &ms = g_metric_scratch[dev];
+    if (!ms.done)
+        HIP_TRY(hipEventCreateWithFlags(&ms.done, hipEventDisableTiming));
     if (ms.h_cap < (size_t)h || ms.w_cap < (size_t)w) {
         if (ms.mip) {
             HIP_TRY(hipDeviceSynchronize());
@@ -4028,10 +4070,17 @@ extern "C" int lfrl_metric_ex(int32_t nz, int32_t h, int32_t w, const float *img
         ms.h_cap = hc;
         ms.w_cap = wc;
     }
+    const hipStream_t st = (hipStream_t)stream;
+    if (ms.recorded)
+        HIP_TRY(hipStreamWaitEvent(st, ms.done, 0));
     const MetricBufs mb{ms.mip, ms.tabH, ms.tabW, ms.T1, ms.n2p, ms.Fabs,
                         nullptr, nullptr, nullptr, nullptr};
-    return run_metric(nz, h, w, img, xs, ys, region, norm, out, mb, nullptr, nullptr, 0, 1, 1,
-                      (hipStream_t)stream);
+    rc = run_metric(nz, h, w, img, xs, ys, region, norm, out, mb, nullptr, nullptr, 0, 1, 1, st);
+    if (rc)
+        return rc;
+    HIP_TRY(hipEventRecord(ms.done, st));
+    ms.recorded = true;
+    return LFRL_OK;
 }
 
 extern "C" int lfrl_metric_cutoff(double d_ml, double mag, int32_t nnum, double lambda, double na,

@@ -216,6 +216,41 @@ def test_rl_weakly_observed_voxels(lf):
         plan.close()
 
 
+def test_weak_voxel_list_overflow_is_refused(lf, monkeypatch):
+    """A depth plane whose PSF is all zero has A^T 1 = 0 on every voxel, below
+    any threshold.  With the weak-voxel list shortened to 64 entries
+    (LFRL_WEAK_CAP) its 900 voxels cannot all be listed, and the call is
+    refused instead of leaving an arbitrary subset on the inexact path.  With
+    the normal list the same frame matches the oracle, the empty plane at 0."""
+    import torch
+    n, ly, nz, k = 3, 10, 3, 11
+    psf = S.gaussian_psf(n, nz, k, seed=5)
+    psf[1] = 0.0
+    h = w = n * ly
+    y = np.random.default_rng(6).uniform(10.0, 100.0, size=(h, w)).astype(np.float32)
+    monkeypatch.setenv("LFRL_WEAK_CAP", "64")
+    plan = lf.Plan(to_dev(psf), h, w)
+    try:
+        with pytest.raises(lf.LfrlError) as e:
+            plan.deconvolve(to_dev(y), 1, stop=lf.STOP_NONE)
+        assert e.value.code == -4
+        print(f"refused: {e.value}", flush=True)
+    finally:
+        plan.close()
+    monkeypatch.delenv("LFRL_WEAK_CAP")
+    plan = lf.Plan(to_dev(psf), h, w)
+    try:
+        vol, rep = plan.deconvolve(to_dev(y), 2, stop=lf.STOP_NONE)
+        torch.cuda.synchronize()
+        got = vol.cpu().numpy()
+    finally:
+        plan.close()
+    assert rep["weak_voxels"] >= h * w
+    assert not got[1].any()
+    ref = oracle.rl(psf, y, 2, keep_all=True)[2]
+    assert rel_l2(got, ref) <= TOL
+
+
 @pytest.mark.parametrize("nz,h,w,xs,ys", [(1, 55, 55, 5.5, 5.5), (3, 40, 64, 7.3, 3.9),
                                          (1, 600, 600, 10.0, 10.0), (5, 31, 17, 2.0, 30.0)])
 def test_metric_matches_oracle(lf, nz, h, w, xs, ys):
