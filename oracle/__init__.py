@@ -45,6 +45,9 @@ notes):
 * Region S = {(u, v): u / X_S + v / Y_S < 1} (the upper-left triangle of Fig.
   2(c)), with real-valued legs X_S, Y_S.
 * Eq. (8) is inverted relative to Eqs. (9)-(10); Eqs. (9)-(10) are used.
+
+The PSF computed from optical parameters (sec. 2.1, Fig. 1) has its own
+oracle module, ``oracle.optics``.
 """
 from __future__ import annotations
 
