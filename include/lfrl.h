@@ -310,6 +310,22 @@ int lfrl_metric(int32_t nz, int32_t h, int32_t w, const float *img, double xs,
 int lfrl_metric_ex(int32_t nz, int32_t h, int32_t w, const float *img, double xs, double ys,
                    int32_t region, int32_t norm, double *out, void *stream);
 
+/* lfrl_metric_ex without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, kernels and results (bit for bit) as
+ * lfrl_metric_ex, but the scratch is a fixed array in the library's device
+ * memory (about 25 MiB per GPU the library runs on, held until the process
+ * ends) instead of a growable buffer.  Limits: h <= 1024 and w <= 1024, region
+ * LFRL_REGION_TRIANGLE or LFRL_REGION_RECTANGLE (legs of at most 256 bins);
+ * anything larger or LFRL_REGION_WHOLE returns LFRL_ERR_UNSUPPORTED before any
+ * launch.  Every call on one GPU uses that GPU's one array, and its contents
+ * persist between calls (each call rebuilds everything it reads): calls that
+ * overlap on one GPU (on different streams, or from different host threads
+ * without an ordering between them) race on it and may return wrong values, so
+ * the caller must serialise them.  Calls on one stream are ordered and safe. */
+int lfrl_metric_noalloc(int32_t nz, int32_t h, int32_t w, const float *img, double xs,
+                        double ys, int32_t region, int32_t norm, double *out, void *stream);
+
 /* Triangle legs from the optics (Eqs. 7, 9-11), [host]:
  * P_u = d_ml / (mag * nnum), d_psf = 1.22 * lambda * nnum / na,
  * xs = P_u * w / d_psf, ys = P_u * h / d_psf.  Lengths in one unit. */

@@ -21,6 +21,7 @@ __all__ = [
     "LfrlError", "PlanDesc", "PlanInfo", "RlOpts", "RlReport",
     "lfrl_plan_footprint", "lfrl_plan", "lfrl_plan_destroy", "lfrl_plan_get_info",
     "lfrl_forward", "lfrl_backward", "lfrl_deconvolve", "lfrl_metric", "lfrl_metric_ex",
+    "lfrl_metric_noalloc",
     "lfrl_metric_cutoff", "lfrl_profile_enable", "lfrl_profile_read", "lfrl_last_error",
     "Plan", "library_path", "STOP_NONE", "STOP_METRIC", "STOP_TRACK", "FP32", "SPLIT_FP16",
 ]
@@ -104,6 +105,7 @@ def _load():
                             ctypes.POINTER(RlReport), vp],
         "lfrl_metric": [i32, i32, i32, vp, dbl, dbl, vp, vp],
         "lfrl_metric_ex": [i32, i32, i32, vp, dbl, dbl, i32, i32, vp, vp],
+        "lfrl_metric_noalloc": [i32, i32, i32, vp, dbl, dbl, i32, i32, vp, vp],
         "lfrl_metric_cutoff": [dbl, dbl, i32, dbl, dbl, i32, i32,
                                ctypes.POINTER(dbl), ctypes.POINTER(dbl)],
         "lfrl_job_footprint": [vp, i32, i32, sz],
@@ -219,6 +221,14 @@ def lfrl_metric_ex(nz: int, h: int, w: int, img: torch.Tensor, xs: float, ys: fl
         raise LfrlError(-1, "out must be a CUDA float64 tensor")
     _check(_load().lfrl_metric_ex(nz, h, w, _dev_f32(img, "img"), float(xs), float(ys),
                                   int(region), int(norm), out.data_ptr(), _stream(stream)))
+
+
+def lfrl_metric_noalloc(nz: int, h: int, w: int, img: torch.Tensor, xs: float, ys: float,
+                        region: int, norm: int, out: torch.Tensor, stream=None) -> None:
+    if not out.is_cuda or out.dtype != torch.float64 or out.numel() < 1:
+        raise LfrlError(-1, "out must be a CUDA float64 tensor")
+    _check(_load().lfrl_metric_noalloc(nz, h, w, _dev_f32(img, "img"), float(xs), float(ys),
+                                       int(region), int(norm), out.data_ptr(), _stream(stream)))
 
 
 def lfrl_metric_cutoff(d_ml: float, mag: float, nnum: int, wavelength: float, na: float,

@@ -4083,6 +4083,88 @@ extern "C" int lfrl_metric_ex(int32_t nz, int32_t h, int32_t w, const float *img
     return LFRL_OK;
 }
 
+// ---------------------------------------------------------------------------
+// allocation-free metric: the scratch of lfrl_metric_ex for the triangle and
+// rectangle regions in a fixed device array, one copy per GPU, held until the
+// process ends.  Layout (byte offsets, each 256-aligned), for images up to
+// kStaticSide x kStaticSide and legs up to kMaxMetricLegs bins:
+//   mip  [h][w] float                          4 MiB
+//   tabH [nv][h], tabW [nu][w] double          2 + 2 MiB
+//   T1   [nchunks][nv][w] double, nchunks * nv <= kMetricChunks * kMaxMetricLegs
+//        (also the entropy partials of large coefficient sets)  16 MiB
+//   n2p  [(h w + 255) / 256 + 1] double         32 KiB
+//   Fabs [nv][nu] double                        512 KiB
+static constexpr int kStaticSide = 1024;
+static constexpr size_t kStaticMip = 0;
+static constexpr size_t kStaticTabH = kStaticMip + (size_t)kStaticSide * kStaticSide * sizeof(float);
+static constexpr size_t kStaticTabW =
+    kStaticTabH + (size_t)kMaxMetricLegs * kStaticSide * sizeof(double);
+static constexpr size_t kStaticT1 =
+    kStaticTabW + (size_t)kMaxMetricLegs * kStaticSide * sizeof(double);
+static constexpr size_t kStaticN2p =
+    kStaticT1 + (size_t)kMetricChunks * kMaxMetricLegs * kStaticSide * sizeof(double);
+static constexpr size_t kStaticFabs =
+    kStaticN2p + (((size_t)kStaticSide * kStaticSide + 255) / 256 + 1 + 31) / 32 * 32 * sizeof(double);
+static constexpr size_t kStaticBytes =
+    kStaticFabs + (size_t)kMaxMetricLegs * kMaxMetricLegs * sizeof(double);
+static_assert(kStaticTabH % 256 == 0 && kStaticTabW % 256 == 0 && kStaticT1 % 256 == 0 &&
+                  kStaticN2p % 256 == 0 && kStaticFabs % 256 == 0,
+              "static metric scratch offsets must stay 256-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+// Device address of `scratch` on each GPU, looked up once per device with that
+// device current (the host-side name is only a stand-in for the symbol).
+static constexpr int kStaticMaxDevices = 64;
+static std::mutex g_static_mu;
+static unsigned char *g_static_ptr[kStaticMaxDevices] = {};
+
+static int static_scratch(int dev, unsigned char **out)
+{
+    if (dev < 0 || dev >= kStaticMaxDevices)
+        return set_error(LFRL_ERR_UNSUPPORTED, "device %d beyond %d", dev, kStaticMaxDevices);
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p)
+            return set_error(LFRL_ERR_DEVICE, "no device address for the metric scratch");
+        g_static_ptr[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = g_static_ptr[dev];
+    return LFRL_OK;
+}
+
+extern "C" int lfrl_metric_noalloc(int32_t nz, int32_t h, int32_t w, const float *img, double xs,
+                                   double ys, int32_t region, int32_t norm, double *out,
+                                   void *stream)
+{
+    int rc = check_metric_args(nz, h, w, img, xs, ys, region, norm, out);
+    if (rc)
+        return rc;
+    if (region == LFRL_REGION_WHOLE)
+        return set_error(LFRL_ERR_UNSUPPORTED,
+                         "lfrl_metric_noalloc serves the triangle and rectangle regions only");
+    if (h > kStaticSide || w > kStaticSide)
+        return set_error(LFRL_ERR_UNSUPPORTED,
+                         "lfrl_metric_noalloc serves images up to %d x %d (got %d x %d)",
+                         kStaticSide, kStaticSide, h, w);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    unsigned char *base = nullptr;
+    if ((rc = static_scratch(dev, &base)))
+        return rc;
+    const MetricBufs mb{reinterpret_cast<float *>(base + kStaticMip),
+                        reinterpret_cast<double *>(base + kStaticTabH),
+                        reinterpret_cast<double *>(base + kStaticTabW),
+                        reinterpret_cast<double *>(base + kStaticT1),
+                        reinterpret_cast<double *>(base + kStaticN2p),
+                        reinterpret_cast<double *>(base + kStaticFabs),
+                        nullptr, nullptr, nullptr, nullptr};
+    return run_metric(nz, h, w, img, xs, ys, region, norm, out, mb, nullptr, nullptr, 0, 1, 1,
+                      (hipStream_t)stream);
+}
+
 extern "C" int lfrl_metric_cutoff(double d_ml, double mag, int32_t nnum, double lambda, double na,
                                   int32_t h, int32_t w, double *xs, double *ys)
 {
