@@ -546,6 +546,55 @@ def variants_leg(args, lf, plan, y_d, vol, h, w, xs, ys, background, ms_rl) -> d
     return out
 
 
+PSF_OPTICS = dict(wavelength=0.52, na=0.5, n_medium=1.0, mag=20.0, d_ml=150.0, f_ml=3000.0,
+                  nnum=15, ksize=255, osr=3, nquad=1024)
+PSF_DEPTHS = [2.0 * (j - 15) for j in range(31)]
+
+
+def psf_optics_leg(args, lf, dev) -> dict:
+    """The PSF set from optical parameters (a 20x / 0.5 objective, 150 um
+    lenslets of f/20, Nnum 15, 255 x 255 pixels at 3 samples per pixel, 31
+    depths 2 um apart): time per full set on the GPU."""
+    import numpy as np
+    import torch
+    log("bench: psf from optics")
+    out = torch.empty((len(PSF_DEPTHS), 15, 15, 255, 255), dtype=torch.float32, device=dev)
+    o = lf.Optics(nz=len(PSF_DEPTHS), flags=lf.PSF_UNIT_SUM, **PSF_OPTICS)
+    lf.lfrl_psf_compute(o, PSF_DEPTHS, out)   # warm-up (first launches, allocations)
+    times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lf.lfrl_psf_compute(o, PSF_DEPTHS, out)
+        times.append(time.perf_counter() - t0)
+    res = {"optics": dict(PSF_OPTICS), "depths": [PSF_DEPTHS[0], PSF_DEPTHS[-1], len(PSF_DEPTHS)],
+           "kernels": len(PSF_DEPTHS) * 15 * 15, "seconds_per_set": float(np.median(times)),
+           "grid": 768}
+    del out
+    log(f"bench: psf from optics {res['seconds_per_set']:.3f} s per set")
+    return res
+
+
+def psf_optics_cpu(res: dict) -> dict:
+    """The oracle on one depth's Debye field and one kernel's propagation,
+    scaled to the whole set (31 depths, 225 kernels each)."""
+    from oracle import optics as O
+    o = O.Optics(**PSF_OPTICS)
+    t0 = time.perf_counter()
+    nip = O.nip_window(PSF_DEPTHS[0], o)
+    t1 = time.perf_counter()
+    for a, b in ((0, 0), (7, 7)):
+        O.bin_pixels(O.sensor_field(nip, a, b, o), o)
+    t2 = time.perf_counter()
+    per_depth = t1 - t0
+    per_kernel = (t2 - t1) / 2
+    total = len(PSF_DEPTHS) * (per_depth + 225 * per_kernel)
+    return {"seconds_per_set_est": total, "sample": "one depth's Debye field "
+            f"({per_depth:.1f} s) and two kernels' propagation ({per_kernel:.2f} s each), "
+            "scaled to 31 depths x 225 kernels", "speedup_gpu_vs_oracle":
+            total / res["seconds_per_set"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -570,6 +619,8 @@ def main() -> int:
                     help="device memory admitted jobs may hold")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the update / metric variant leg")
+    ap.add_argument("--no-psf-optics", action="store_true",
+                    help="skip the PSF-from-optics leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy (reference kernel of known "
                          "size for hardware byte counters)")
@@ -738,6 +789,9 @@ def main() -> int:
         plan.close()
         plan = None
         torch.cuda.empty_cache()
+    if not args.no_psf_optics:
+        out["psf_optics"] = psf_optics_leg(args, lf, dev)
+        torch.cuda.empty_cache()
     if args.small_calls > 0:
         out["small"] = small_leg(args, dev)
     if args.batched_frames > 0:
@@ -763,6 +817,9 @@ def main() -> int:
                                    host_cpus=os.cpu_count())
         log(f"bench: cpu baseline {json.dumps(out['cpu_baseline'])}")
         out["accuracy_vs_oracle"] = accuracy_vs_oracle(samples, dev)
+        if "psf_optics" in out:
+            out["psf_optics"]["cpu_oracle"] = psf_optics_cpu(out["psf_optics"])
+            log(f"bench: psf oracle {json.dumps(out['psf_optics']['cpu_oracle'])}")
     if plan is not None:
         plan.close()
     print(json.dumps(out), flush=True)

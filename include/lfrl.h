@@ -332,6 +332,58 @@ int lfrl_metric_noalloc(int32_t nz, int32_t h, int32_t w, const float *img, doub
 int lfrl_metric_cutoff(double d_ml, double mag, int32_t nnum, double lambda,
                        double na, int32_t h, int32_t w, double *xs, double *ys);
 
+/* ---- PSF from optical parameters (sec. 2.1, Fig. 1) ----------------------
+ * The PSF set of a light-field microscope computed on the GPU from its optics
+ * (Fig. 1: computing it from the system's parameters is the default source;
+ * sec. 2.1: the time-consuming parts of the PSF computation run on the GPU).
+ * Scalar wave-optics model, all lengths in one unit:
+ *   1. field on the native image plane (at the lenslet array) of a point
+ *      source on the axis at depth z, from the Debye integral of an objective
+ *      obeying the sine condition:
+ *        U(r) = int_0^alpha sqrt(cos t) sin t exp(i k n z (1 - cos t))
+ *                             J0(k n r sin t / mag) dt,
+ *      alpha = asin(na / n_medium), k = 2 pi / wavelength, r the image-plane
+ *      radius; Gauss-Legendre quadrature with nquad nodes (0: 1024);
+ *      constant factors and the phase common to a depth are dropped;
+ *   2. each lenslet's thin-lens phase exp(-i pi |x - c|^2 / (wavelength f_ml))
+ *      about its centre c; lenslet l covers sensor pixels l*nnum ..
+ *      l*nnum + nnum - 1 of each axis (the projections' phase convention);
+ *   3. Fresnel propagation over f_ml with the transfer function
+ *      exp(-i pi wavelength f_ml (fx^2 + fy^2));
+ *   4. intensity |U|^2 summed over the osr x osr field samples of each pixel.
+ * Sampling: pixel pitch d_ml / nnum, field samples osr per pixel per axis; a
+ * window of ksize x ksize pixels (G = ksize * osr samples) centred on the
+ * source pixel, zero-padded to the smallest 2^a 3^b 5^c >= G for the periodic
+ * propagation (the window at offset (Gf - G) / 2).  The source of phase (a, b)
+ * sits at the centre of pixel (a, b) of its lenslet, at depth depths[j].
+ * Out: psf [nz][nnum][nnum][ksize][ksize] float32 (device), the layout
+ * lfrl_plan takes; with LFRL_PSF_UNIT_SUM each (j, a, b) kernel is scaled to
+ * unit sum (float64 sums).  Field DFTs run in float32, the quadrature sums in
+ * float64.  Limits: ksize * osr <= 2048.  Allocates its scratch (the Debye
+ * table and up to 1 GiB of field buffers) and frees it before returning;
+ * synchronises `stream`.  Argument errors: LFRL_ERR_ARG (non-positive or
+ * non-finite optics, na >= n_medium, even ksize or osr, a non-finite depth, a
+ * psf buffer too small); LFRL_ERR_UNSUPPORTED beyond the limits. */
+typedef struct {
+    double wavelength; /* emission wavelength */
+    double na;         /* numerical aperture of the objective */
+    double n_medium;   /* refractive index of the immersion medium, > na */
+    double mag;        /* objective magnification */
+    double d_ml;       /* lenslet pitch (sensor side) */
+    double f_ml;       /* lenslet focal length = lenslet-to-sensor distance */
+    int32_t nnum;      /* sensor pixels per lenslet per axis (1..64) */
+    int32_t nz;        /* depth planes */
+    int32_t ksize;     /* PSF window in pixels, odd */
+    int32_t osr;       /* field samples per pixel per axis, odd */
+    int32_t nquad;     /* quadrature nodes of the Debye integral (0: 1024) */
+    uint32_t flags;    /* LFRL_PSF_UNIT_SUM or 0 */
+} lfrl_optics;
+
+enum { LFRL_PSF_UNIT_SUM = 1u << 0 };
+
+int lfrl_psf_compute(const lfrl_optics *optics, const double *depths /* [host] nz */,
+                     float *psf, void *stream);
+
 /* Kernel timing with HIP events on the caller's stream, for benchmarks.
  * While enabled, every launch of the two spectral contraction kernels is
  * bracketed by events.  lfrl_profile_read synchronises and returns, for

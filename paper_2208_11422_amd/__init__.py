@@ -21,7 +21,7 @@ __all__ = [
     "LfrlError", "PlanDesc", "PlanInfo", "RlOpts", "RlReport",
     "lfrl_plan_footprint", "lfrl_plan", "lfrl_plan_destroy", "lfrl_plan_get_info",
     "lfrl_forward", "lfrl_backward", "lfrl_deconvolve", "lfrl_metric", "lfrl_metric_ex",
-    "lfrl_metric_noalloc",
+    "lfrl_metric_noalloc", "lfrl_psf_compute", "Optics", "psf_from_optics",
     "lfrl_metric_cutoff", "lfrl_profile_enable", "lfrl_profile_read", "lfrl_last_error",
     "Plan", "library_path", "STOP_NONE", "STOP_METRIC", "STOP_TRACK", "FP32", "SPLIT_FP16",
 ]
@@ -68,6 +68,18 @@ class RlOpts(ctypes.Structure):
                 ("update", ctypes.c_int32), ("region", ctypes.c_int32),
                 ("norm", ctypes.c_int32), ("window", ctypes.c_int32),
                 ("background", ctypes.c_double)]
+
+
+class Optics(ctypes.Structure):
+    """Optical parameters of lfrl_psf_compute (lengths in one unit)."""
+    _fields_ = [("wavelength", ctypes.c_double), ("na", ctypes.c_double),
+                ("n_medium", ctypes.c_double), ("mag", ctypes.c_double),
+                ("d_ml", ctypes.c_double), ("f_ml", ctypes.c_double),
+                ("nnum", ctypes.c_int32), ("nz", ctypes.c_int32), ("ksize", ctypes.c_int32),
+                ("osr", ctypes.c_int32), ("nquad", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+PSF_UNIT_SUM = 1
 
 
 class RlReport(ctypes.Structure):
@@ -118,6 +130,7 @@ def _load():
         "lfrl_deconvolve_batch": [ctypes.POINTER(vp), i32, ctypes.POINTER(i32),
                                   ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                   ctypes.POINTER(RlOpts), ctypes.POINTER(RlReport), vp],
+        "lfrl_psf_compute": [ctypes.POINTER(Optics), ctypes.POINTER(dbl), vp, vp],
         "lfrl_profile_enable": [vp, i32],
         "lfrl_profile_read": [vp, ctypes.c_char_p, ctypes.POINTER(dbl),
                               ctypes.POINTER(ctypes.c_int64)],
@@ -229,6 +242,30 @@ def lfrl_metric_noalloc(nz: int, h: int, w: int, img: torch.Tensor, xs: float, y
         raise LfrlError(-1, "out must be a CUDA float64 tensor")
     _check(_load().lfrl_metric_noalloc(nz, h, w, _dev_f32(img, "img"), float(xs), float(ys),
                                        int(region), int(norm), out.data_ptr(), _stream(stream)))
+
+
+def lfrl_psf_compute(optics: Optics, depths, psf: torch.Tensor, stream=None) -> None:
+    """PSF set [nz][nnum][nnum][ksize][ksize] from optical parameters into psf
+    (a CUDA float32 tensor); depths has optics.nz entries."""
+    z = (ctypes.c_double * max(1, len(depths)))(*[float(d) for d in depths])
+    if len(depths) != optics.nz:
+        raise LfrlError(-1, f"{len(depths)} depths for nz = {optics.nz}")
+    _check(_load().lfrl_psf_compute(ctypes.byref(optics), z, _dev_f32(psf, "psf"),
+                                    _stream(stream)))
+
+
+def psf_from_optics(*, wavelength: float, na: float, n_medium: float, mag: float,
+                    d_ml: float, f_ml: float, nnum: int, ksize: int, depths, osr: int = 3,
+                    nquad: int = 0, unit_sum: bool = False, device=None,
+                    stream=None) -> torch.Tensor:
+    """Allocate and compute a PSF set (see lfrl_psf_compute)."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", 0)
+    o = Optics(wavelength=wavelength, na=na, n_medium=n_medium, mag=mag, d_ml=d_ml, f_ml=f_ml,
+               nnum=nnum, nz=len(depths), ksize=ksize, osr=osr, nquad=nquad,
+               flags=PSF_UNIT_SUM if unit_sum else 0)
+    out = torch.empty((len(depths), nnum, nnum, ksize, ksize), dtype=torch.float32, device=dev)
+    lfrl_psf_compute(o, depths, out, stream)
+    return out
 
 
 def lfrl_metric_cutoff(d_ml: float, mag: float, nnum: int, wavelength: float, na: float,

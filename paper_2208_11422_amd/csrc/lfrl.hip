@@ -4214,6 +4214,228 @@ extern "C" int lfrl_profile_read(lfrl_plan_t p, const char *kernel, double *tota
     return LFRL_OK;
 }
 
+// ---------------------------------------------------------------------------
+// PSF from optical parameters (sec. 2.1, Fig. 1)
+#include "psf_optics.hpp"
+
+// Gauss-Legendre nodes and weights on [lo, hi]: Newton's method on P_n (three-
+// term recurrence), started from the usual cosine estimates of its roots.
+static void gauss_legendre(int n, double lo, double hi, std::vector<double> &x,
+                           std::vector<double> &w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    const double mid = 0.5 * (hi + lo), half = 0.5 * (hi - lo);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;   // P_0, P_1
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            // p1 = P_n(z), p0 = P_{n-1}(z)
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16)
+                break;
+        }
+        const double wt = 2.0 / ((1.0 - z * z) * dp * dp);
+        x[i] = mid - half * z;          // ascending order
+        x[n - 1 - i] = mid + half * z;
+        w[i] = w[n - 1 - i] = half * wt;
+    }
+}
+
+static int nice_fft_size(int n)
+{
+    for (int m = std::max(1, n);; ++m) {
+        int q = m;
+        for (int p : {2, 3, 5})
+            while (q % p == 0)
+                q /= p;
+        if (q == 1)
+            return m;
+    }
+}
+
+static bool fft_plan_for(int n, psfopt::FftPlan *plan)
+{
+    plan->n = n;
+    plan->nst = 0;
+    int q = n;
+    for (int r : {4, 2, 3, 5})
+        while (q % r == 0) {
+            if (plan->nst == psfopt::kMaxStages)
+                return false;
+            plan->radix[plan->nst++] = r;
+            q /= r;
+        }
+    return q == 1;
+}
+
+// Device buffers of one PSF computation.
+struct PsfScratch {
+    double2 *e = nullptr, *U = nullptr;
+    double *s = nullptr;
+    float2 *tw = nullptr, *hx = nullptr, *W = nullptr;
+    ~PsfScratch()
+    {
+        void *b[] = {e, U, s, tw, hx, W};
+        for (void *p : b)
+            if (p)
+                (void)hipFree(p);
+    }
+};
+
+static constexpr size_t kPsfWorkBytes = (size_t)1 << 30;  // field batch buffer
+
+static int check_optics(const lfrl_optics *o, const double *depths)
+{
+    if (!o || !depths)
+        return set_error(LFRL_ERR_ARG, "NULL argument");
+    const double v[] = {o->wavelength, o->na, o->n_medium, o->mag, o->d_ml, o->f_ml};
+    for (double x : v)
+        if (!(x > 0.0) || !std::isfinite(x))
+            return set_error(LFRL_ERR_ARG, "optical parameters must be positive and finite");
+    if (!(o->na < o->n_medium))
+        return set_error(LFRL_ERR_ARG, "NA %g must be below the medium index %g", o->na,
+                         o->n_medium);
+    if (o->nnum < 1 || o->nnum > 64 || o->nz < 1 || o->ksize < 1 || o->ksize % 2 == 0 ||
+        o->osr < 1 || o->osr % 2 == 0 || o->nquad < 0 || o->nquad > 65536)
+        return set_error(LFRL_ERR_ARG,
+                         "need 1 <= nnum <= 64, nz >= 1, odd ksize and osr, 0 <= nquad <= 65536");
+    for (int j = 0; j < o->nz; ++j)
+        if (!std::isfinite(depths[j]))
+            return set_error(LFRL_ERR_ARG, "depth %d is not finite", j);
+    return LFRL_OK;
+}
+
+extern "C" int lfrl_psf_compute(const lfrl_optics *o, const double *depths, float *psf,
+                                void *stream)
+{
+    int rc = check_optics(o, depths);
+    if (rc)
+        return rc;
+    using namespace psfopt;
+    const int N = o->nnum, K = o->ksize, osr = o->osr, nz = o->nz;
+    const int nq = o->nquad ? o->nquad : 1024;
+    if ((long long)K * osr > kMaxSide)
+        return set_error(LFRL_ERR_UNSUPPORTED, "ksize * osr = %lld above %d samples",
+                         (long long)K * osr, kMaxSide);
+    Window w;
+    w.K = K;
+    w.osr = osr;
+    w.N = N;
+    w.G = K * osr;
+    w.Gf = nice_fft_size(w.G);
+    if (w.Gf > kMaxSide)
+        return set_error(LFRL_ERR_UNSUPPORTED, "FFT grid %d above %d", w.Gf, kMaxSide);
+    w.off = (w.Gf - w.G) / 2;
+    w.hh = (w.G - 1) / 2;
+    w.pixel = o->d_ml / N;
+    w.lens_k = M_PI / (o->wavelength * o->f_ml);
+    const int n = w.Gf;
+    FftPlan plan;
+    if (!fft_plan_for(n, &plan))
+        return set_error(LFRL_ERR_UNSUPPORTED, "FFT size %d", n);
+    const size_t nfield = (size_t)N * N;
+    if ((rc = check_buf(psf, (size_t)nz * nfield * K * K * sizeof(float), "psf")))
+        return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    const double delta = w.pixel / osr;
+
+    // quadrature coefficients: e[j][q] = w_q sqrt(cos t) sin t exp(i k n z_j (1 - cos t)),
+    // s[q] = k n sin t / M (J0 argument per unit image radius)
+    const double alpha = std::asin(o->na / o->n_medium);
+    const double kn = 2.0 * M_PI / o->wavelength * o->n_medium;
+    std::vector<double> t, wq;
+    gauss_legendre(nq, 0.0, alpha, t, wq);
+    std::vector<double2> e((size_t)nz * nq);
+    std::vector<double> s(nq);
+    for (int q = 0; q < nq; ++q)
+        s[q] = kn * std::sin(t[q]) / o->mag;
+    for (int j = 0; j < nz; ++j)
+        for (int q = 0; q < nq; ++q) {
+            const double amp = wq[q] * std::sqrt(std::cos(t[q])) * std::sin(t[q]);
+            const double ph = kn * depths[j] * (1.0 - std::cos(t[q]));
+            e[(size_t)j * nq + q] = make_double2(amp * std::cos(ph), amp * std::sin(ph));
+        }
+    // DFT roots and the 1-D factor of the transfer function
+    std::vector<float2> tw(n), hx(n);
+    for (int m = 0; m < n; ++m) {
+        const double a = 2.0 * M_PI * m / n;
+        tw[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+        const int kf = 2 * m < n ? m : m - n;
+        const double fk = kf / (n * delta);
+        const double ph = -M_PI * o->wavelength * o->f_ml * fk * fk;
+        hx[m] = make_float2((float)std::cos(ph), (float)std::sin(ph));
+    }
+    const int nrad = (w.hh + 1) * (w.hh + 2) / 2;
+    const size_t field_bytes = (size_t)w.G * n * sizeof(float2);
+    int nb = (int)std::max<size_t>(1, std::min(nfield, kPsfWorkBytes / field_bytes));
+    if (const char *cap = std::getenv("LFRL_PSF_BATCH"))   // test hook: smaller field batches
+        nb = std::max(1, std::min(nb, std::atoi(cap)));
+
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    PsfScratch sc;
+    if ((rc = dalloc(&sc.e, e.size() * sizeof(double2))) ||
+        (rc = dalloc(&sc.s, s.size() * sizeof(double))) ||
+        (rc = dalloc(&sc.U, (size_t)nz * nrad * sizeof(double2))) ||
+        (rc = dalloc(&sc.tw, n * sizeof(float2))) || (rc = dalloc(&sc.hx, n * sizeof(float2))) ||
+        (rc = dalloc(&sc.W, (size_t)nb * field_bytes)))
+        return rc;
+    HIP_TRY(hipMemcpyAsync(sc.e, e.data(), e.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(sc.s, s.data(), s.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(sc.tw, tw.data(), n * sizeof(float2), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(sc.hx, hx.data(), n * sizeof(float2), hipMemcpyHostToDevice, st));
+
+    hipLaunchKernelGGL(k_debye, dim3((nrad + kThreads - 1) / kThreads,
+                                     (nz + kDepthsPerThread - 1) / kDepthsPerThread),
+                       dim3(kThreads), 0, st, (const double2 *)sc.e, (const double *)sc.s, nq, nz,
+                       nrad, delta, sc.U);
+    LAUNCH_CHECK("k_debye");
+
+    const int lines = std::max(1, kLineBudget / n);
+    const int nl_rows = lines, S = lines, nl_bin = std::min(osr, lines);
+    const size_t lds_rows = ((size_t)n + w.G + (size_t)nl_rows * n) * sizeof(float2);
+    const size_t lds_cols = ((size_t)n + (size_t)S * n) * sizeof(float2);
+    const size_t lds_bin = ((size_t)n + (w.G + 1) / 2 + (size_t)nl_bin * n) * sizeof(float2);
+    (void)hipFuncSetAttribute((const void *)k_psf_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds_rows);
+    (void)hipFuncSetAttribute((const void *)k_psf_cols, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds_cols);
+    (void)hipFuncSetAttribute((const void *)k_psf_bin, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds_bin);
+    for (int j = 0; j < nz; ++j) {
+        const double2 *Uj = sc.U + (size_t)j * nrad;
+        float *psf_j = psf + (size_t)j * nfield * K * K;
+        for (int f0 = 0; f0 < (int)nfield; f0 += nb) {
+            const int nf = std::min(nb, (int)nfield - f0);
+            hipLaunchKernelGGL(k_psf_rows, dim3((w.G + nl_rows - 1) / nl_rows, nf), dim3(kThreads),
+                               lds_rows, st, Uj, nrad, w, plan, (const float2 *)sc.tw, nl_rows, f0,
+                               sc.W);
+            LAUNCH_CHECK("k_psf_rows");
+            hipLaunchKernelGGL(k_psf_cols, dim3((n + S - 1) / S, nf), dim3(kThreads), lds_cols, st,
+                               w, plan, (const float2 *)sc.tw, (const float2 *)sc.hx, S, sc.W);
+            LAUNCH_CHECK("k_psf_cols");
+            hipLaunchKernelGGL(k_psf_bin, dim3(K, nf), dim3(kThreads), lds_bin, st, w, plan,
+                               (const float2 *)sc.tw, nl_bin, (const float2 *)sc.W, f0, psf_j);
+            LAUNCH_CHECK("k_psf_bin");
+        }
+    }
+    if (o->flags & LFRL_PSF_UNIT_SUM) {
+        hipLaunchKernelGGL(k_normalize_psf, dim3((unsigned)(nz * nfield)), dim3(256), 0, st, psf,
+                           (size_t)K * K);
+        LAUNCH_CHECK("k_normalize_psf");
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    return LFRL_OK;
+}
+
 extern "C" const char *lfrl_last_error(void)
 {
     return g_last_error.c_str();

@@ -130,3 +130,25 @@ def test_rl_opts_layout_and_defaults():
     assert (o.init, o.update, o.region, o.norm, o.window, o.background) == (2, 1, 2, 1, 3, 2.5)
     with pytest.raises(lf.LfrlError):
         lf.rl_opts(5, given_start=True, backproject_start=True)
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("ksize", 24, -1), ("osr", 2, -1), ("na", 1.1, -1), ("wavelength", 0.0, -1),
+    ("f_ml", float("nan"), -1), ("nnum", 0, -1), ("nquad", -3, -1),
+    ("ksize", 1025, -4),   # ksize * osr above the largest field grid
+])
+def test_psf_optics_arguments_rejected_before_device_work(field, value, code):
+    """Optical parameters are checked on the host before anything touches the
+    device (the psf pointer is never dereferenced here)."""
+    import paper_2208_11422_amd as lf
+    o = lf.Optics(wavelength=0.52, na=0.5, n_medium=1.0, mag=20.0, d_ml=150.0, f_ml=3000.0,
+                  nnum=15, nz=2, ksize=255, osr=3, nquad=0, flags=0)
+    setattr(o, field, value)
+    z = (ctypes.c_double * 2)(-1.0, 1.0)
+    rc = lf._load().lfrl_psf_compute(ctypes.byref(o), z, ctypes.c_void_p(0x1000), None)
+    assert rc == code, lf.lfrl_last_error()
+    bad = (ctypes.c_double * 2)(0.0, float("inf"))
+    o2 = lf.Optics(wavelength=0.52, na=0.5, n_medium=1.0, mag=20.0, d_ml=150.0, f_ml=3000.0,
+                   nnum=15, nz=2, ksize=255, osr=3, nquad=0, flags=0)
+    assert lf._load().lfrl_psf_compute(ctypes.byref(o2), bad, ctypes.c_void_p(0x1000), None) == -1
+    assert "depth" in lf.lfrl_last_error()

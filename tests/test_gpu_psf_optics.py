@@ -1,0 +1,105 @@
+"""The PSF computed on the GPU from optical parameters (lfrl_psf_compute,
+sec. 2.1 and Fig. 1) against the float64 oracle (oracle/optics.py), through
+the C ABI (needs an MI355X).
+
+Bar: relative L2 <= 1e-5 per (depth, phase) kernel (float32 field DFTs
+against float64).  Cases cover odd and even Nnum, one and several samples per
+pixel, FFT grids equal to and larger than the window, several field batches,
+the unit-sum option, and the full-size set (Nnum 15, 255 x 255 taps, 31
+depths) at sampled kernels."""
+import numpy as np
+import pytest
+
+from oracle import optics as O
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def lf():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import os
+
+    import paper_2208_11422_amd as lf
+    assert os.path.exists(lf.library_path()), "liblfrl.so missing: build first"
+    return lf
+
+
+def gpu_psf(lf, o: O.Optics, depths, unit_sum=False):
+    import torch
+    print(f"psf: nnum={o.nnum} K={o.ksize} osr={o.osr} nquad={o.nquad} nz={len(depths)} "
+          f"grid={O.grid_sizes(o)}", flush=True)
+    t = lf.psf_from_optics(wavelength=o.wavelength, na=o.na, n_medium=o.n_medium, mag=o.mag,
+                           d_ml=o.d_ml, f_ml=o.f_ml, nnum=o.nnum, ksize=o.ksize, depths=depths,
+                           osr=o.osr, nquad=o.nquad, unit_sum=unit_sum)
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+def per_kernel_rel(got, want):
+    g = got.reshape(-1, got.shape[-2] * got.shape[-1])
+    w = want.reshape(g.shape)
+    return np.linalg.norm(g - w, axis=1) / np.linalg.norm(w, axis=1)
+
+
+CASES = [
+    # (optics, depths)
+    (dict(wavelength=0.52, na=0.5, n_medium=1.0, mag=20.0, d_ml=50.0, f_ml=1000.0, nnum=5,
+          ksize=25, osr=3, nquad=256), [-4.0, 0.0, 3.0]),
+    (dict(wavelength=0.6, na=1.0, n_medium=1.33, mag=40.0, d_ml=100.0, f_ml=2500.0, nnum=4,
+          ksize=15, osr=1, nquad=64), [-2.0, 5.0]),
+    (dict(wavelength=0.5, na=0.3, n_medium=1.0, mag=10.0, d_ml=30.0, f_ml=600.0, nnum=3,
+          ksize=9, osr=5, nquad=128), [0.0]),
+    (dict(wavelength=0.52, na=0.5, n_medium=1.0, mag=20.0, d_ml=70.0, f_ml=1400.0, nnum=7,
+          ksize=23, osr=3, nquad=200), [-6.0, 1.5]),      # FFT grid 72 > window 69
+    (dict(wavelength=0.52, na=0.8, n_medium=1.33, mag=20.0, d_ml=20.0, f_ml=500.0, nnum=2,
+          ksize=7, osr=1, nquad=96), [3.0]),              # FFT grid 8 > window 7
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_psf_matches_oracle(lf, case):
+    kw, depths = CASES[case]
+    o = O.Optics(**kw)
+    got = gpu_psf(lf, o, depths)
+    want = O.lf_psf(o, depths)
+    rel = per_kernel_rel(got, want)
+    print(f"max rel L2 per kernel {rel.max():.3e}", flush=True)
+    assert rel.max() <= TOL
+
+
+def test_psf_unit_sum_and_batches(lf, monkeypatch):
+    kw, depths = CASES[0]
+    o = O.Optics(**kw)
+    monkeypatch.setenv("LFRL_PSF_BATCH", "4")   # 25 fields per depth in 7 launches
+    got = gpu_psf(lf, o, depths, unit_sum=True)
+    want = O.lf_psf(o, depths, unit_sum=True)
+    assert per_kernel_rel(got, want).max() <= TOL
+    np.testing.assert_allclose(got.sum(axis=(3, 4)), 1.0, rtol=1e-6)
+
+
+def test_psf_full_size_sampled(lf):
+    """Nnum 15, 255 x 255 taps, 3 samples per pixel (765-sample window on a
+    768 grid), 31 depths 2 apart: kernels sampled at both depth ends and in
+    the middle, against the oracle; mirror symmetry on the device output."""
+    o = O.Optics(wavelength=0.52, na=0.5, n_medium=1.0, mag=20.0, d_ml=150.0, f_ml=3000.0,
+                 nnum=15, ksize=255, osr=3, nquad=1024)
+    depths = [2.0 * (j - 15) for j in range(31)]
+    got = gpu_psf(lf, o, depths)
+    assert np.all(np.isfinite(got)) and got.min() >= 0.0
+    fields = [(0, 0, 0), (0, 14, 3), (15, 7, 7), (30, 5, 12)]
+    want = O.lf_psf(o, depths, fields=fields)
+    for j, a, b in fields:
+        rel = np.linalg.norm(got[j, a, b] - want[j, a, b]) / np.linalg.norm(want[j, a, b])
+        print(f"field ({j},{a},{b}) rel L2 {rel:.3e}", flush=True)
+        assert rel <= TOL
+    n = o.nnum
+    for j, a, b in ((3, 2, 9), (27, 11, 0)):
+        p = got[j, a, b]
+        m = got[j, a, n - 1 - b][:, ::-1]
+        assert np.linalg.norm(p - m) <= 1e-5 * np.linalg.norm(p)
+        t = got[j, b, a].T
+        assert np.linalg.norm(p - t) <= 1e-5 * np.linalg.norm(p)
