@@ -39,8 +39,9 @@ def log(msg: str) -> None:
 def contraction_bytes(info: dict, g, nt: int, kernel: str) -> float:
     """Algorithmic HBM bytes of one launch of a spectral contraction kernel:
     the PSF spectra it must stream once plus its tile-spectrum input and
-    output (complex float32, 8 bytes per coefficient)."""
-    nf, nn, kk = info["nfreq"], g.nnum ** 2, g.nnum ** 2 * g.nz
+    output (complex float32, 8 bytes per coefficient), at the unique
+    frequencies of the Hermitian half spectrum (the ones the kernels visit)."""
+    nf, nn, kk = info["nfreq_unique"], g.nnum ** 2, g.nnum ** 2 * g.nz
     spectra = nf * nn * kk * 8.0
     if kernel == "contract_fwd":
         return spectra + nf * nt * kk * 8.0 + info["split_k"] * nf * nt * nn * 8.0
@@ -48,7 +49,7 @@ def contraction_bytes(info: dict, g, nt: int, kernel: str) -> float:
 
 
 def contraction_flops(info: dict, g, nt: int) -> float:
-    return 8.0 * info["nfreq"] * g.nnum ** 2 * (g.nnum ** 2 * g.nz) * nt
+    return 8.0 * info["nfreq_unique"] * g.nnum ** 2 * (g.nnum ** 2 * g.nz) * nt
 
 
 def iteration_model(info: dict, g, h: int, w: int, nt: int, ms_measured: float,
@@ -65,7 +66,7 @@ def iteration_model(info: dict, g, h: int, w: int, nt: int, ms_measured: float,
     in float32 vector arithmetic.  The floor is the PSF read once per
     projection, whatever the shape."""
     n, nz, k = g.nnum, g.nz, g.ksize
-    q, t, r, nf = info["tile_q"], info["tile_out"], info["taps"], info["nfreq"]
+    q, t, r, nf = info["tile_q"], info["tile_out"], info["taps"], info["nfreq_unique"]
     split = precision != "fp32"
     s_g = n ** 4 * nz * nf * (4.0 if split else 8.0)
     s_x = n ** 2 * nz * nt * nf * 8.0

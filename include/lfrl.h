@@ -104,6 +104,9 @@ typedef struct {
     int32_t tune_candidates; /* tile sides timed (autotuned plans), else 0 */
     double tune_ms;        /* measured forward + back projection of max_batch
                               largest frames at the chosen side, else 0 */
+    int32_t nfreq_unique;  /* frequencies the contractions visit: nfreq less the
+                              conjugates of others on the kv = 0 and kv = Q/2
+                              columns of the Hermitian half spectrum */
 } lfrl_plan_info_t;
 
 /* Memory estimate before allocation (Fig. 1: the required memory is
@@ -217,8 +220,12 @@ typedef struct {
  * last opts->window values) has strictly decreased `patience` times in a row
  * and return the iterate with the largest entropy seen (ties: the later one).
  * img [h][w] -> vol [nz][h][w] (x^{best_iter}, or x^{max_iters} without a
- * metric).  Synchronises `stream` before returning (the host needs the stop
- * decision and the report).  `report` [host] may be NULL.  The weakly
+ * metric).  With LFRL_STOP_METRIC the iterations are queued in chunks of 4
+ * ahead of the host's reading of the stop rule (each chunk replayed from a
+ * captured graph); the kernels of iterations after the stop return at once,
+ * so the result is that of a run that reads the rule after every iteration.
+ * Synchronises `stream` before returning (the host needs the stop decision
+ * and the report).  `report` [host] may be NULL.  The weakly
  * observed voxels are listed when A^T 1 is first formed for an image size; if
  * more than min(nz h w, 2^20) of them remain below even 1e-9 of the largest
  * A^T 1 (a depth plane with an all-zero PSF, say), the call returns

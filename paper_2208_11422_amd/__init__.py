@@ -58,7 +58,8 @@ class PlanInfo(ctypes.Structure):
                 ("taps", ctypes.c_int32), ("nfreq", ctypes.c_int32),
                 ("max_tiles", ctypes.c_int32), ("split_k", ctypes.c_int32),
                 ("resident_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
-                ("tune_candidates", ctypes.c_int32), ("tune_ms", ctypes.c_double)]
+                ("tune_candidates", ctypes.c_int32), ("tune_ms", ctypes.c_double),
+                ("nfreq_unique", ctypes.c_int32)]
 
 
 class RlOpts(ctypes.Structure):

@@ -179,12 +179,16 @@ template <class P, int CB, int U>
 __global__ __launch_bounds__(512) void k_contract_fwd_split(
     const cplx16<typename P::S> *__restrict__ Hf, const float2 *__restrict__ X,
     const unsigned *__restrict__ xmax, const int *__restrict__ gexp, float2 *__restrict__ Yp,
-    int NN, int NNp, int KK, int KKs, int nkb, int nt, int nf, int kchunk)
+    int NN, int NNp, int KK, int KKs, int nkb, int nt, int nf, int kchunk,
+    const int *__restrict__ skip, FreqMap fm)
 {
+    if (skip && *skip)
+        return;
     typedef typename P::S S;
     typedef typename P::v8 V8;
     int k, s, tg;
     contraction_block(k, s, tg);
+    k = unique_freq(k, fm);
     const int t0 = tg * 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, kg = lane >> 4;
@@ -319,8 +323,10 @@ template <class P, int CB, int U>
 __global__ __launch_bounds__(256) void k_contract_adj_split(
     const cplx16<typename P::S> *__restrict__ Hb, const float2 *__restrict__ Rs,
     const unsigned *__restrict__ rmax, const int *__restrict__ gexp, float2 *__restrict__ B,
-    int NN, int NNp, int KK, int nkb, int nt)
+    int NN, int NNp, int KK, int KKs, int nkb, int nt, const int *__restrict__ skip, FreqMap fm)
 {
+    if (skip && *skip)
+        return;
     typedef typename P::S S;
     typedef typename P::v4 V4;
     // LDS: per 16-c chunk and lane, 4 c values x {re hi, re lo, im hi, im lo}
@@ -328,6 +334,7 @@ __global__ __launch_bounds__(256) void k_contract_adj_split(
     S *ra = reinterpret_cast<S *>(ra_bits);
     int k, by, tg;
     contraction_block(k, by, tg);
+    k = unique_freq(k, fm);
     const int t0 = tg * 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const int col = lane & 15, kg = lane >> 4;
@@ -438,7 +445,7 @@ __global__ __launch_bounds__(256) void k_contract_adj_split(
         compute_group(grp + 1, gb1);
         __builtin_amdgcn_sched_barrier(0);
     }
-    float2 *bk = B + (size_t)k * nt * KK;
+    float2 *bk = B + (size_t)k * nt * KKs;   // rows of KKs: 128-byte aligned
     const int gx = gexp[k];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -450,7 +457,7 @@ __global__ __launch_bounds__(256) void k_contract_adj_split(
         for (int b = 0; b < CB; ++b) {
             const int kk = 16 * kbk[b] + col;
             if (k_ok[b] && kk < KK)
-                bk[(size_t)tt * KK + kk] = make_float2(ldexpf(accr[b][i], sc), ldexpf(acci[b][i], sc));
+                bk[(size_t)tt * KKs + kk] = make_float2(ldexpf(accr[b][i], sc), ldexpf(acci[b][i], sc));
         }
     }
 }

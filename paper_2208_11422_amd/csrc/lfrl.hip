@@ -36,6 +36,10 @@
 #include "lfrl.h"
 #include "tile_fft.hpp"
 
+#ifndef LFRL_KARA
+#define LFRL_KARA 1
+#endif
+
 // ---------------------------------------------------------------------------
 // errors
 // ---------------------------------------------------------------------------
@@ -271,6 +275,8 @@ __global__ void k_vol_r2c(const TileBatch batch, int N, int Q, int QH, int T, in
     const int tile = blockIdx.x;
     const int j = blockIdx.y / N, ar = blockIdx.y % N;
     const TileJob &fj = batch.job[batch_job(batch, tile)];
+    if (fj.skip && *fj.skip)
+        return;   // block-uniform, before any barrier
     const int H = fj.H, W = fj.W, lt = tile - fj.tile0;
     const int ty = lt / fj.tiles_x, tx = lt % fj.tiles_x;
     const int ly0 = ty * T - hD, lx0 = tx * T - hD;
@@ -334,6 +340,8 @@ __global__ void k_c2r(const TileBatch batch, const float2 *__restrict__ spec, si
     const int tile = blockIdx.x;
     const int j = blockIdx.y / N, ar = blockIdx.y % N;
     const TileJob &fj = batch.job[batch_job(batch, tile)];
+    if (fj.skip && *fj.skip)
+        return;   // block-uniform, before any barrier
     const int H = fj.H, W = fj.W, lt = tile - fj.tile0;
     const int ty = lt / fj.tiles_x, tx = lt % fj.tiles_x;
     float *__restrict__ dst = fj.dst;
@@ -350,7 +358,11 @@ __global__ void k_c2r(const TileBatch batch, const float2 *__restrict__ spec, si
     const int total = Q * QH * N;
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
         const int p = idx % N;
-        const size_t k = idx / N;
+        const int kq = idx / N;
+        const int ku = kq / QH, kv = kq % QH;
+        // redundant frequencies (see FreqMap) from their conjugate partners
+        const bool red = ku > Q / 2 && (kv == 0 || (Q % 2 == 0 && kv == Q / 2));
+        const size_t k = red ? (size_t)(Q - ku) * QH + kv : (size_t)kq;
         const size_t off = k * sk + tile * stile + (kkbase + p) * sc;
         float2 acc = spec[off];
         for (int s = 1; s < nsplit; ++s) {
@@ -358,6 +370,8 @@ __global__ void k_c2r(const TileBatch batch, const float2 *__restrict__ spec, si
             acc.x += v.x;
             acc.y += v.y;
         }
+        if (red)
+            acc.y = -acc.y;
         X[idx] = acc;
     }
     __syncthreads();
@@ -551,11 +565,15 @@ template <int CB, int U>
 __global__ __launch_bounds__(512) void k_contract_fwd(const float4 *__restrict__ Ff,
                                                       const float2 *__restrict__ X,
                                                       float2 *__restrict__ Yp, int NN, int NNp,
-                                                      int KK, int KKs, int nt, int nf, int kchunk)
+                                                      int KK, int KKs, int nt, int nf, int kchunk,
+                                                      const int *__restrict__ skip, FreqMap fm)
 {
+    if (skip && *skip)
+        return;
     __shared__ float4 la[2][U][64];
     int k, s, tg;
     contraction_block(k, s, tg);
+    k = unique_freq(k, fm);
     const int t0 = tg * 16;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = lane & 15, kq = lane >> 4;
@@ -585,6 +603,12 @@ __global__ __launch_bounds__(512) void k_contract_fwd(const float4 *__restrict__
         accr[b] = f32x4{0.f, 0.f, 0.f, 0.f};
         acci[b] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
+#if LFRL_KARA
+    f32x4 accs[CB];
+#pragma unroll
+    for (int b = 0; b < CB; ++b)
+        accs[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#endif
     auto a_load = [&](int grp) -> float4 {
         const int pg = min(p0 + grp * U + st_j / 4, p1 - 1);
         return st_row[4 * pg + st_j % 4];
@@ -606,6 +630,30 @@ __global__ __launch_bounds__(512) void k_contract_fwd(const float4 *__restrict__
         }
     };
     auto compute_group = [&](int buf, const float4(&gb)[U][CB]) {
+#if LFRL_KARA
+        // three real products per complex product: accr = sum ar gr,
+        // acci = sum ai gi, accs = sum (ar + ai)(gr + gi)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const float4 a = la[buf][u][lane];
+            const float s0 = a.x + a.y, s1 = a.z + a.w;
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                const float4 g = gb[u][b];
+                accr[b] = mfma4(a.x, g.x, accr[b]);
+                acci[b] = mfma4(a.y, g.y, acci[b]);
+                accs[b] = mfma4(s0, g.x + g.y, accs[b]);
+            }
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                const float4 g = gb[u][b];
+                accr[b] = mfma4(a.z, g.z, accr[b]);
+                acci[b] = mfma4(a.w, g.w, acci[b]);
+                accs[b] = mfma4(s1, g.z + g.w, accs[b]);
+            }
+        }
+        return;
+#endif
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const float4 a = la[buf][u][lane];
@@ -660,6 +708,16 @@ __global__ __launch_bounds__(512) void k_contract_fwd(const float4 *__restrict__
         a_store(grp + 2, 0, av);
         __syncthreads();
     }
+#if LFRL_KARA
+#pragma unroll
+    for (int b = 0; b < CB; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float pr = accr[b][i], pi = acci[b][i];
+            accr[b][i] = pr - pi;
+            acci[b][i] = accs[b][i] - pr - pi;
+        }
+#endif
     // D[t][c]: lane holds tiles t0 + 4 * kq + i, column c of each block
     float2 *yk = Yp + ((size_t)s * nf + k) * nt * NN;
 #pragma unroll
@@ -691,11 +749,15 @@ template <int CB, int U>
 __global__ __launch_bounds__(256) void k_contract_adj(const float4 *__restrict__ Fb,
                                                       const float2 *__restrict__ Rs,
                                                       float2 *__restrict__ B, int NN, int KK,
-                                                      int NCp, int nt, int ranges)
+                                                      int KKs, int NCp, int nt, int ranges,
+                                                      const int *__restrict__ skip, FreqMap fm)
 {
+    if (skip && *skip)
+        return;
     extern __shared__ float2 rs[];  // [even number of groups of 8 * U rows][kRsStride]
     int k, by, tg;
     contraction_block(k, by, tg);
+    k = unique_freq(k, fm);
     const int t0 = tg * 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const int col = lane & 15, kq = lane >> 4;
@@ -725,7 +787,7 @@ __global__ __launch_bounds__(256) void k_contract_adj(const float4 *__restrict__
     }
     __syncthreads();
     const float4 *fk = Fb + (size_t)k * npairs * nkb * 64;
-    float2 *bk = B + (size_t)k * nt * KK;
+    float2 *bk = B + (size_t)k * nt * KKs;   // rows of KKs: 128-byte aligned
     const int RB = nwaves * CB;  // column blocks per range (the packing's RB)
     for (int r = 0; r < ranges; ++r) {
         const int kb0 = ((by * ranges + r) * nwaves + wave) * CB;
@@ -744,6 +806,12 @@ __global__ __launch_bounds__(256) void k_contract_adj(const float4 *__restrict__
             accr[b] = f32x4{0.f, 0.f, 0.f, 0.f};
             acci[b] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
+#if LFRL_KARA
+        f32x4 accs[CB];
+#pragma unroll
+        for (int b = 0; b < CB; ++b)
+            accs[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#endif
         float4 gb0[U][CB], gb1[U][CB];
         // pairs past the last read a valid fragment (clamped) that meets zeros in rs
         auto load_group = [&](int grp, float4(&gb)[U][CB]) {
@@ -756,6 +824,31 @@ __global__ __launch_bounds__(256) void k_contract_adj(const float4 *__restrict__
             }
         };
         auto compute_group = [&](int grp, const float4(&gb)[U][CB]) {
+#if LFRL_KARA
+            // R conj(G) in three real products: accr = sum rr gr, acci = sum ri gi,
+            // accs = sum (rr + ri)(gr - gi)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = 8 * (grp * U + u) + 2 * kq;
+                const float2 a0 = rs[c * kRsStride + col], a1 = rs[(c + 1) * kRsStride + col];
+                const float s0 = a0.x + a0.y, s1 = a1.x + a1.y;
+#pragma unroll
+                for (int b = 0; b < CB; ++b) {
+                    const float4 g = gb[u][b];
+                    accr[b] = mfma4(a0.x, g.x, accr[b]);
+                    acci[b] = mfma4(a0.y, g.y, acci[b]);
+                    accs[b] = mfma4(s0, g.x - g.y, accs[b]);
+                }
+#pragma unroll
+                for (int b = 0; b < CB; ++b) {
+                    const float4 g = gb[u][b];
+                    accr[b] = mfma4(a1.x, g.z, accr[b]);
+                    acci[b] = mfma4(a1.y, g.w, acci[b]);
+                    accs[b] = mfma4(s1, g.z - g.w, accs[b]);
+                }
+            }
+            return;
+#endif
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int c = 8 * (grp * U + u) + 2 * kq;
@@ -795,6 +888,16 @@ __global__ __launch_bounds__(256) void k_contract_adj(const float4 *__restrict__
             compute_group(grp + 1, gb1);
             __builtin_amdgcn_sched_barrier(0);
         }
+#if LFRL_KARA
+#pragma unroll
+        for (int b = 0; b < CB; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float pr = accr[b][i], pi = acci[b][i];
+                accr[b][i] = pr + pi;
+                acci[b][i] = accs[b][i] - pr + pi;
+            }
+#endif
         // D[t][kk]: lane holds tiles t0 + 4 * kq + i, column kk of each block
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
@@ -805,7 +908,7 @@ __global__ __launch_bounds__(256) void k_contract_adj(const float4 *__restrict__
             for (int i = 0; i < 4; ++i) {
                 const int tt = t0 + 4 * kq + i;
                 if (tt < nt)
-                    bk[(size_t)tt * KK + kk] = make_float2(accr[b][i], acci[b][i]);
+                    bk[(size_t)tt * KKs + kk] = make_float2(accr[b][i], acci[b][i]);
             }
         }
     }
@@ -835,8 +938,10 @@ __global__ void k_dct_table(double *__restrict__ tab, int n, int nfreq)
 // z maximum projection m[r][s] = max_j vol[j][r][s] (sec. 2.2, Fig. 2(a)) with
 // per-block float64 partial sums of m^2 (Parseval: sum m^2 = ||F||_F^2).
 __global__ void k_mip(const float *__restrict__ vol, int nz, size_t hw, float *__restrict__ mip,
-                      double *__restrict__ n2p)
+                      double *__restrict__ n2p, const int *__restrict__ skip)
 {
+    if (skip && *skip)
+        return;
     __shared__ double red[256];
     const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     double sq = 0.0;
@@ -1222,8 +1327,12 @@ __global__ void k_metric_final(const double *__restrict__ n2p, int n2count,
                                const double *__restrict__ Fabs, int ncoef, int norm, double area,
                                double *__restrict__ out, StopState *st, double *trace, int k,
                                int patience, int window, const double *__restrict__ ent_part,
-                               int nent)
+                               int nent, const int *skip)
 {
+    // a frame that stopped before this iteration records nothing (block-uniform;
+    // skip points into *st, which only thread 0 writes, after the barriers)
+    if (skip && *skip)
+        return;
     __shared__ double red[256];
     double a = 0.0;
     if (ent_part) {
@@ -1287,8 +1396,10 @@ __global__ __launch_bounds__(1024) void k_metric_small(
     const float *__restrict__ vol, int nz, int H, int W, const double *__restrict__ tabH,
     const double *__restrict__ tabW, int nv, int nu, double xs, double ys, int region, int norm,
     double area, double *__restrict__ out, StopState *st, double *trace, int k, int patience,
-    int window, float *__restrict__ best, size_t nvox)
+    int window, float *__restrict__ best, size_t nvox, const int *skip)
 {
+    if (skip && *skip)
+        return;
     extern __shared__ double sm[];
     __shared__ double red[1024];
     __shared__ int flag;
@@ -1671,8 +1782,11 @@ static constexpr int kWeakThreads = 512;  // threads per weak voxel (a power of 
 __global__ void k_weak_exact(const unsigned *__restrict__ list, const float *__restrict__ psf,
                              int N, int K, int H, int W, const float *__restrict__ img,
                              float *__restrict__ sens, const float *__restrict__ src,
-                             const float *__restrict__ aux, float *__restrict__ dst, int mode)
+                             const float *__restrict__ aux, float *__restrict__ dst, int mode,
+                             const int *__restrict__ skip)
 {
+    if (skip && *skip)
+        return;
     __shared__ double red[kWeakThreads];
     const unsigned vox = list[blockIdx.x];
     const size_t hw = (size_t)H * W;
@@ -1797,7 +1911,7 @@ struct Frame {
     double *tabH = nullptr, *tabW = nullptr, *T1 = nullptr, *n2p = nullptr, *Fabs = nullptr;
     double *metric_out = nullptr, *trace = nullptr, *flux = nullptr, *dotp = nullptr;
     StopState *state = nullptr;
-    StopState *state_host = nullptr;   // pinned
+    StopState *state_host = nullptr;   // pinned, two slots (early-stop runs alternate them)
     int tab_h = -1, tab_nv = -1, tab_w = -1, tab_nu = -1;
     void *block = nullptr;             // the device allocation (owned by the job or plan)
     size_t block_bytes = 0;
@@ -1864,6 +1978,15 @@ struct lfrl_plan_s {
         }
     } graph_key{};
     int graph_hits = 0;
+    // early-stop runs: graphs of kStopChunk iterations each, by first iteration
+    struct ChunkGraph {
+        int k0;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    std::vector<ChunkGraph> chunk_graphs;
+    GraphKey chunk_key{};
+    hipEvent_t chunk_ev[2] = {nullptr, nullptr};
     int tune_candidates = 0;  // tile sides timed
     // profiling
     bool prof = false;
@@ -1901,9 +2024,10 @@ static bool fft_supported(int Q);
 
 static double model_time(const Geo &g, const Tiles &t)
 {
-    const double spec = (double)g.nf * g.NN * g.KK * 8.0;
+    const double nfu = unique_freqs(g.Q);   // frequencies the contractions visit
+    const double spec = nfu * g.NN * g.KK * 8.0;
     const double inter = (double)g.nf * t.nt * (g.KK + g.NN) * 8.0;
-    const double cflops = 8.0 * g.nf * (double)g.NN * g.KK * t.nt;
+    const double cflops = 8.0 * nfu * (double)g.NN * g.KK * t.nt;
     const double contract = 2.0 * std::max((spec + 2.0 * inter) / 5.0e12, cflops / 90.0e12);
     // tile transforms: both directions, volume side and image side
     const double tiles = (double)(g.KK + g.NN) * t.nt * 2.0;
@@ -2231,6 +2355,14 @@ static void free_plan(lfrl_plan_s *p)
         (void)hipFree(e.sens);
         (void)hipFree(e.weak);
     }
+    for (auto &c : p->chunk_graphs) {
+        (void)hipGraphExecDestroy(c.exec);
+        (void)hipGraphDestroy(c.graph);
+    }
+    p->chunk_graphs.clear();
+    for (hipEvent_t e : p->chunk_ev)
+        if (e)
+            (void)hipEventDestroy(e);
     if (p->graph_exec)
         (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph)
@@ -2328,7 +2460,7 @@ static int slot_get(int dev, size_t bytes, JobSlot *out)
         return set_error(LFRL_ERR_NOMEM, "hipMalloc(%zu) for a job failed: %s", bytes,
                          hipGetErrorString(e));
     }
-    e = hipHostMalloc((void **)&s.state_host, sizeof(StopState), hipHostMallocDefault);
+    e = hipHostMalloc((void **)&s.state_host, 2 * sizeof(StopState), hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&s.counters_host, 2 * sizeof(unsigned), hipHostMallocDefault);
     if (e == hipSuccess)
@@ -2363,7 +2495,7 @@ static int frame_alloc(Frame &f, const Geo &g, int h, int w, bool own_y)
         return rc;
     f.block_bytes = bytes;
     frame_bind(f, g, h, w, f.block, off, own_y);
-    hipError_t e = hipHostMalloc((void **)&f.state_host, sizeof(StopState), hipHostMallocDefault);
+    hipError_t e = hipHostMalloc((void **)&f.state_host, 2 * sizeof(StopState), hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&f.counters_host, 2 * sizeof(unsigned), hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -2413,6 +2545,12 @@ static int plan_build(lfrl_plan_s **out, const lfrl_plan_desc *desc, int q, cons
     p->max_w = desc->max_w;
     p->frame_tiles = tiles_for(g, desc->max_h, desc->max_w).nt;
     p->max_tiles = p->frame_tiles * std::max(1, (int)desc->max_batch);
+    // the inverse tile DFTs address one frequency row of a launch's tile
+    // spectra with 32-bit byte offsets
+    if ((size_t)g.QH * g.KKs * p->max_tiles * sizeof(float2) >= ((size_t)1 << 32)) {
+        free_plan(p);
+        return set_error(LFRL_ERR_UNSUPPORTED, "tile spectra of %d tiles too large", p->max_tiles);
+    }
     p->split_k = pick_split(g);
     p->split = desc->precision != LFRL_FP32;
     p->bf16 = desc->precision == LFRL_SPLIT_BF16;
@@ -2632,6 +2770,7 @@ extern "C" int lfrl_plan_get_info(lfrl_plan_t p, lfrl_plan_info_t *info)
     info->tile_out = p->g.T;
     info->taps = p->g.R;
     info->nfreq = p->g.nf;
+    info->nfreq_unique = unique_freqs(p->g.Q);
     info->max_tiles = p->max_tiles;
     info->split_k = p->split_k;
     info->resident_bytes = p->resident;
@@ -2687,7 +2826,7 @@ static int prof_event(lfrl_plan_s *p, int which, hipStream_t st)
     if (p->fwd_cb == CBV && p->fwd_u == UV) {                                                    \
         hipLaunchKernelGGL((k_contract_fwd<CBV, UV>), grid, block, 0, st, (const float4 *)p->Ff, \
                            (const float2 *)p->X, p->Yp, g.NN, g.NNp, g.KK, g.KKs, nt, g.nf,     \
-                           kchunk);                                                              \
+                           kchunk, skip, freq_map(g.Q));                                         \
         launched = true;                                                                         \
     }
 #define LFRL_FWD_CASES(CBV) LFRL_FWD_CASE(CBV, 1) LFRL_FWD_CASE(CBV, 2) LFRL_FWD_CASE(CBV, 4)
@@ -2695,7 +2834,7 @@ static int prof_event(lfrl_plan_s *p, int which, hipStream_t st)
     if (p->adj_cb == CBV && p->adj_u == UV) {                                                    \
         hipLaunchKernelGGL((k_contract_adj<CBV, UV>), grid, dim3(64 * kAdjWaves), lds, st,       \
                            (const float4 *)p->Fb, (const float2 *)p->Rs, p->X, g.NN, g.KK,      \
-                           g.NCp, nt, ranges);                                                   \
+                           g.KKs, g.NCp, nt, ranges, skip, freq_map(g.Q));                       \
         launched = true;                                                                         \
     }
 #define LFRL_ADJ_CASES(CBV) LFRL_ADJ_CASE(CBV, 1) LFRL_ADJ_CASE(CBV, 2) LFRL_ADJ_CASE(CBV, 4)
@@ -2718,6 +2857,7 @@ struct FrameIO {
     const float *aux0, *aux1;
     float bg = 0.f;  // background of EPI_STORE / EPI_RATIO
     int mode = -1;   // epilogue of this frame (-1: the launch's)
+    const int *skip = nullptr;  // device flag: nonzero = the frame's work is skipped
 };
 
 // Concatenate the frames' tiles into one tile index space; returns the total.
@@ -2734,6 +2874,7 @@ static int make_batch(const Geo &g, const FrameIO *io, int n, int mode, TileBatc
         j.aux1 = io[i].aux1;
         j.bg = io[i].bg;
         j.mode = io[i].mode >= 0 ? io[i].mode : mode;
+        j.skip = io[i].skip;
         j.H = io[i].h;
         j.W = io[i].w;
         j.tiles_x = t.tx;
@@ -2767,6 +2908,8 @@ static int run_forward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipSt
         hipLaunchKernelGGL(k_vol_r2c, dim3(nt, g.Nz * g.N), dim3(256), p->lds_r2c_bytes, st, batch,
                            g.N, g.Q, g.QH, g.T, g.hD, nt, g.KKs, p->X, p->tw);
     LAUNCH_CHECK("k_vol_r2c");
+    // a launch of one frame stops with it; frames of a batch share the launch
+    const int *skip = n == 1 ? io[0].skip : nullptr;
     int kchunk = 0;
     (void)contraction_split(p, &kchunk);
     if (p->split)
@@ -2774,7 +2917,7 @@ static int run_forward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipSt
     const int split2 = (g.KK + kchunk - 1) / kchunk;
     const int fcb = p->split ? p->hfwd_cb : p->fwd_cb;
     const int nwaves = (g.NNp / 16 + fcb - 1) / fcb;
-    const dim3 grid(g.nf, split2, (nt + 15) / 16);
+    const dim3 grid(unique_freqs(g.Q), split2, (nt + 15) / 16);
     const dim3 block(64 * nwaves);
     if (p->prof) {
         int rc = prof_event(p, 0, st);
@@ -2787,7 +2930,7 @@ static int run_forward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipSt
     hipLaunchKernelGGL((k_contract_fwd_split<PT, CBV, UV>), grid, block, 0, st,                  \
                        (const cplx16<PT::S> *)p->Hf, (const float2 *)p->X,                       \
                        (const unsigned *)p->xmax, (const int *)p->gexp, p->Yp, g.NN, g.NNp,     \
-                       g.KK, g.KKs, g.KKs / 32, nt, g.nf, kchunk)
+                       g.KK, g.KKs, g.KKs / 32, nt, g.nf, kchunk, skip, freq_map(g.Q))
 #define LFRL_HFWD_CASE(CBV, UV)                                                                  \
     if (p->hfwd_cb == CBV && p->hfwd_u == UV) {                                                  \
         if (p->bf16)                                                                             \
@@ -2849,6 +2992,7 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
         hipLaunchKernelGGL(k_vol_r2c, dim3(nt, g.N), dim3(256), p->lds_r2c_bytes, st, batch, g.N,
                            g.Q, g.QH, g.T, g.hD, nt, g.NN, p->Rs, p->tw);
     LAUNCH_CHECK("k_vol_r2c(image)");
+    const int *skip = n == 1 ? io[0].skip : nullptr;
     const int acb = p->split ? p->hadj_cb : p->adj_cb;
     const int kk_per_range = 16 * acb * kAdjWaves;
     const int nrange = (g.KK + kk_per_range - 1) / kk_per_range;
@@ -2856,10 +3000,10 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
     // keep about 2048 blocks in the launch
     int ranges = 1;
     if (!p->split) {
-        const long long blocks1 = (long long)g.nf * nrange * ((nt + 15) / 16);
+        const long long blocks1 = (long long)unique_freqs(g.Q) * nrange * ((nt + 15) / 16);
         ranges = (int)std::max(1LL, std::min(4LL, blocks1 / 2048));
     }
-    const dim3 grid(g.nf, (nrange + ranges - 1) / ranges, (nt + 15) / 16);
+    const dim3 grid(unique_freqs(g.Q), (nrange + ranges - 1) / ranges, (nt + 15) / 16);
     // FP32: rows of R staged in LDS, an even number of register groups of
     // 8 * adj_u reduction indices (as the kernel assumes), row stride kRsStride
     const int ustep = 8 * p->adj_u;
@@ -2878,7 +3022,7 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
     hipLaunchKernelGGL((k_contract_adj_split<PT, CBV, UV>), grid, dim3(64 * kAdjWaves), lds, st, \
                        (const cplx16<PT::S> *)p->Hb, (const float2 *)p->Rs,                      \
                        (const unsigned *)p->rmax, (const int *)p->gexp, p->X, g.NN, g.NNp,      \
-                       g.KK, (g.KK + 15) / 16, nt)
+                       g.KK, g.KKs, (g.KK + 15) / 16, nt, skip, freq_map(g.Q))
 #define LFRL_HADJ_CASE(CBV, UV)                                                                  \
     if (p->hadj_cb == CBV && p->hadj_u == UV) {                                                  \
         if (p->bf16)                                                                             \
@@ -2902,14 +3046,14 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
         if (rc)
             return rc;
     }
-    // B[k][t][kk]
-    const size_t sk = (size_t)g.KK * nt;
+    // B[k][t][kk], rows of KKs
+    const size_t sk = (size_t)g.KKs * nt;
     if (p->use_fft)
         launch_c2r_fft(g.Q, dim3(nt * g.Nz * g.N), p->thr_c2r, p->lds_c2r_bytes, st, batch, p->X,
-                       (size_t)0, 1, sk, g.KK, 1, g.N, g.Nz, g.T, g.hD, p->tw);
+                       (size_t)0, 1, sk, g.KKs, 1, g.N, g.Nz, g.T, g.hD, p->tw);
     else
         hipLaunchKernelGGL(k_c2r, dim3(nt, g.Nz * g.N), dim3(256), p->lds_c2r_bytes, st, batch,
-                           p->X, (size_t)0, 1, sk, (size_t)g.KK, (size_t)1, g.N, g.Q, g.QH, g.T,
+                           p->X, (size_t)0, 1, sk, (size_t)g.KKs, (size_t)1, g.N, g.Q, g.QH, g.T,
                            g.hD, p->tw);
     LAUNCH_CHECK("k_c2r(backward)");
     return LFRL_OK;
@@ -3057,7 +3201,8 @@ static int check_norm_size(int norm, int h, int w)
 static int run_metric(int nz, int h, int w, const float *vol, double xs, double ys, int region,
                       int norm, double *out, const MetricBufs &mb, StopState *st_dev,
                       double *trace, int k, int patience, int window, hipStream_t st,
-                      float *best = nullptr, size_t nvox = 0, bool *copied = nullptr)
+                      float *best = nullptr, size_t nvox = 0, bool *copied = nullptr,
+                      const int *skip = nullptr)
 {
     if (copied)
         *copied = false;
@@ -3085,14 +3230,14 @@ static int run_metric(int nz, int h, int w, const float *vol, double xs, double 
         hipLaunchKernelGGL(k_metric_small, dim3(1), dim3(1024), lds, st, vol, nz, h, w,
                            (const double *)mb.tabH, (const double *)mb.tabW, nv, nu, xs, ys,
                            region, norm, region_area(region, xs, ys, h, w), out, st_dev, trace, k,
-                           patience, std::max(1, window), copy ? best : nullptr, nvox);
+                           patience, std::max(1, window), copy ? best : nullptr, nvox, skip);
         LAUNCH_CHECK("k_metric_small");
         if (copied)
             *copied = copy;
         return LFRL_OK;
     }
     const int nblk = (int)((hw + 255) / 256);
-    hipLaunchKernelGGL(k_mip, dim3(nblk), dim3(256), 0, st, vol, nz, hw, mb.mip, mb.n2p);
+    hipLaunchKernelGGL(k_mip, dim3(nblk), dim3(256), 0, st, vol, nz, hw, mb.mip, mb.n2p, skip);
     LAUNCH_CHECK("k_mip");
     if (norm == LFRL_NORM_SPECTRAL) {
         // sigma_1^2 of the projection into the slot after the Parseval partials
@@ -3153,7 +3298,7 @@ static int run_metric(int nz, int h, int w, const float *vol, double xs, double 
     }
     hipLaunchKernelGGL(k_metric_final, dim3(1), dim3(256), 0, st, (const double *)mb.n2p, nblk,
                        (const double *)mb.Fabs, ncoef, norm, region_area(region, xs, ys, h, w),
-                       out, st_dev, trace, k, patience, std::max(1, window), ent, nent);
+                       out, st_dev, trace, k, patience, std::max(1, window), ent, nent, skip);
     LAUNCH_CHECK("k_metric_final");
     return LFRL_OK;
 }
@@ -3238,7 +3383,7 @@ static int frame_sensitivity(lfrl_plan_s *p, Frame &f, bool check_input, hipStre
         hipLaunchKernelGGL(k_weak_exact, dim3(f.nweak), dim3(kWeakThreads), 0, st, (const unsigned *)f.weak,
                            (const float *)p->psf, p->g.N, p->g.K, h, w, (const float *)nullptr,
                            f.sens, (const float *)nullptr, (const float *)nullptr, (float *)nullptr,
-                           (int)WEAK_SENS);
+                           (int)WEAK_SENS, (const int *)nullptr);
         LAUNCH_CHECK("k_weak_exact(sens)");
     }
     return LFRL_OK;
@@ -3310,7 +3455,8 @@ static int frame_backproject_image(lfrl_plan_s *p, Frame &f, hipStream_t st)
     if (f.nweak) {
         hipLaunchKernelGGL(k_weak_exact, dim3(f.nweak), dim3(kWeakThreads), 0, st, (const unsigned *)f.weak,
                            (const float *)p->psf, p->g.N, p->g.K, f.h, f.w, f.y, f.sens,
-                           (const float *)nullptr, (const float *)nullptr, f.D, (int)WEAK_STORE);
+                           (const float *)nullptr, (const float *)nullptr, f.D, (int)WEAK_STORE,
+                           (const int *)nullptr);
         LAUNCH_CHECK("k_weak_exact(store)");
     }
     return LFRL_OK;
@@ -3355,6 +3501,14 @@ static int frame_start(lfrl_plan_s *p, Frame &f, const float *vol0, hipStream_t 
 // the exact update at the weakly observed voxels, then the metric,
 // best-iterate copy and flux of each frame.  Queued on `st` without
 // synchronising.
+// Device flag that turns a frame's later iterations into no-ops once its stop
+// rule has fired (early-stop mode only: several iterations may then be queued
+// before the host reads the decision).  Null otherwise.
+static const int *frame_skip(const Frame &f)
+{
+    return f.opts.stop == LFRL_STOP_METRIC ? &f.state->stopped : nullptr;
+}
+
 static int step_frames(lfrl_plan_s *p, Frame *const *fr, int n, hipStream_t st)
 {
     FrameIO io[kMaxBatchJobs];
@@ -3363,7 +3517,7 @@ static int step_frames(lfrl_plan_s *p, Frame *const *fr, int n, hipStream_t st)
         const int k = f.iters + 1;
         const bool isra = f.opts.update == LFRL_UPDATE_ISRA;
         io[i] = FrameIO{f.h, f.w, f.V[(k - 1) & 1], f.rho, f.y, nullptr,
-                        (float)f.opts.background, isra ? EPI_STORE : EPI_RATIO};
+                        (float)f.opts.background, isra ? EPI_STORE : EPI_RATIO, frame_skip(f)};
     }
     int rc = run_forward(p, io, n, EPI_RATIO, st);
     if (rc)
@@ -3373,7 +3527,7 @@ static int step_frames(lfrl_plan_s *p, Frame *const *fr, int n, hipStream_t st)
         const int k = f.iters + 1;
         const bool isra = f.opts.update == LFRL_UPDATE_ISRA;
         io[i] = FrameIO{f.h, f.w, f.rho, f.V[k & 1], f.V[(k - 1) & 1], isra ? f.D : f.sens,
-                        0.f, isra ? EPI_ISRA : EPI_UPDATE};
+                        0.f, isra ? EPI_ISRA : EPI_UPDATE, frame_skip(f)};
     }
     rc = run_backward(p, io, n, EPI_UPDATE, st);
     if (rc)
@@ -3389,14 +3543,15 @@ static int step_frames(lfrl_plan_s *p, Frame *const *fr, int n, hipStream_t st)
             hipLaunchKernelGGL(k_weak_exact, dim3(f.nweak), dim3(kWeakThreads), 0, st,
                                (const unsigned *)f.weak, (const float *)p->psf, p->g.N, p->g.K,
                                f.h, f.w, (const float *)f.rho, f.sens, cur, (const float *)f.D,
-                               nxt, (int)(isra ? WEAK_ISRA : WEAK_UPDATE));
+                               nxt, (int)(isra ? WEAK_ISRA : WEAK_UPDATE), frame_skip(f));
             LAUNCH_CHECK("k_weak_exact(update)");
         }
         if (f.opts.stop != LFRL_STOP_NONE) {
             bool copied = false;
             rc = run_metric(p->g.Nz, f.h, f.w, nxt, f.opts.xs, f.opts.ys, f.opts.region,
                             f.opts.norm, f.metric_out, frame_metric_bufs(f), f.state, f.trace, k,
-                            f.opts.patience, f.opts.window, st, f.VB, nvox, &copied);
+                            f.opts.patience, f.opts.window, st, f.VB, nvox, &copied,
+                            frame_skip(f));
             if (rc)
                 return rc;
             if (!copied) {
@@ -3504,6 +3659,131 @@ extern "C" int lfrl_backward(lfrl_plan_t p, int32_t h, int32_t w, const float *i
     return run_backward(p, &io, 1, EPI_STORE, (hipStream_t)stream);
 }
 
+// Early-stop runs (sec. 2.2: stop once the entropy decreases) queue their
+// iterations in chunks of kStopChunk; the host reads the stop state of a chunk
+// while the next one is already queued.  Every kernel of a frame's iteration
+// returns at once when the frame's stop flag was raised by an earlier
+// iteration, so iterations queued past the stop change nothing and the result
+// equals a run that looks at the rule after every iteration.  With graphs
+// allowed, each chunk is captured once (keyed like the fixed-length graph,
+// plus its first iteration) and replayed.
+static constexpr int kStopChunk = 4;
+static constexpr size_t kMaxChunkGraphs = 64;   // chunk graphs kept per plan
+
+static int launch_stop_chunk(lfrl_plan_s *p, Frame &f, int k0, float *vol0, bool graphs,
+                             hipStream_t st)
+{
+    const int k1 = std::min(f.opts.max_iters, k0 + kStopChunk);
+    Frame *one[1] = {&f};
+    if (!graphs) {
+        int rc = LFRL_OK;
+        if (k0 == 0)
+            rc = frame_start(p, f, vol0, st);
+        f.iters = k0;
+        while (rc == LFRL_OK && f.iters < k1)
+            rc = step_frames(p, one, 1, st);
+        return rc;
+    }
+    for (auto &c : p->chunk_graphs)
+        if (c.k0 == k0) {
+            ++p->graph_hits;
+            HIP_TRY(hipGraphLaunch(c.exec, st));
+            f.iters = k1;
+            return LFRL_OK;
+        }
+    if (p->chunk_graphs.size() >= kMaxChunkGraphs)   // very long runs: launch the rest directly
+        return launch_stop_chunk(p, f, k0, vol0, false, st);
+    if (!p->cap_stream)
+        HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    // the captured chunk builds its own DCT tables
+    f.tab_h = f.tab_nv = f.tab_w = f.tab_nu = -1;
+    HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = LFRL_OK;
+    if (k0 == 0)
+        rc = frame_start(p, f, vol0, p->cap_stream);
+    f.iters = k0;
+    while (rc == LFRL_OK && f.iters < k1)
+        rc = step_frames(p, one, 1, p->cap_stream);
+    hipGraph_t gr = nullptr;
+    const hipError_t ec = hipStreamEndCapture(p->cap_stream, &gr);
+    if (rc) {
+        if (gr)
+            (void)hipGraphDestroy(gr);
+        return rc;
+    }
+    if (ec != hipSuccess)
+        return set_error(LFRL_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(gr);
+        return set_error(LFRL_ERR_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+    }
+    p->chunk_graphs.push_back({k0, gr, ex});
+    f.tab_h = f.tab_nv = f.tab_w = f.tab_nu = -1;
+    HIP_TRY(hipGraphLaunch(ex, st));
+    return LFRL_OK;
+}
+
+static int deconvolve_early_stop(lfrl_plan_s *p, Frame &f, int h, int w, const float *img,
+                                 float *vol, const lfrl_rl_opts *opts, lfrl_rl_report *report,
+                                 hipStream_t st, bool graphs)
+{
+    if (graphs) {
+        const lfrl_plan_s::GraphKey key{h, w, opts->max_iters, opts->stop, opts->patience,
+                                        opts->init, f.want_flux ? 1 : 0, opts->update,
+                                        opts->region, opts->norm, opts->window, opts->xs,
+                                        opts->ys, opts->background, img, vol};
+        if (!(p->chunk_key == key)) {
+            for (auto &c : p->chunk_graphs) {
+                (void)hipGraphExecDestroy(c.exec);
+                (void)hipGraphDestroy(c.graph);
+            }
+            p->chunk_graphs.clear();
+            p->chunk_key = key;
+        }
+    }
+    for (hipEvent_t &e : p->chunk_ev)
+        if (!e)
+            HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    float *vol0 = opts->init == 1 ? vol : nullptr;
+    int k0 = 0, slot = 0;
+    int rc = launch_stop_chunk(p, f, k0, vol0, graphs, st);
+    if (rc)
+        return rc;
+    HIP_TRY(hipMemcpyAsync(&f.state_host[slot], f.state, sizeof(StopState), hipMemcpyDeviceToHost,
+                           st));
+    HIP_TRY(hipEventRecord(p->chunk_ev[slot], st));
+    for (;;) {
+        const int next = k0 + kStopChunk;
+        const bool more = next < opts->max_iters;
+        if (more) {
+            // queue the next chunk before looking at this one's decision
+            if ((rc = launch_stop_chunk(p, f, next, vol0, graphs, st)))
+                return rc;
+            HIP_TRY(hipMemcpyAsync(&f.state_host[1 - slot], f.state, sizeof(StopState),
+                                   hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipEventRecord(p->chunk_ev[1 - slot], st));
+        }
+        HIP_TRY(hipEventSynchronize(p->chunk_ev[slot]));
+        const StopState &ss = f.state_host[slot];
+        if (ss.stopped) {
+            f.iters = ss.stop_k;
+            f.stopped = true;
+            break;
+        }
+        if (!more) {
+            f.iters = opts->max_iters;
+            f.stopped = false;
+            break;
+        }
+        k0 = next;
+        slot = 1 - slot;
+    }
+    f.done = true;
+    return frame_result(f, p->g.Nz, vol, report, st);
+}
+
 extern "C" int lfrl_deconvolve(lfrl_plan_t p, int32_t h, int32_t w, const float *img, float *vol,
                                const lfrl_rl_opts *opts, lfrl_rl_report *report, void *stream)
 {
@@ -3589,14 +3869,15 @@ extern "C" int lfrl_deconvolve(lfrl_plan_t p, int32_t h, int32_t w, const float 
         f.stopped = false;
         return frame_result(f, p->g.Nz, vol, report, st);
     }
+    if (opts->stop == LFRL_STOP_METRIC)
+        return deconvolve_early_stop(p, f, h, w, img, vol, opts, report, st, !p->prof &&
+                                     !(genv && genv[0] == '0'));
     if ((rc = frame_start(p, f, opts->init == 1 ? vol : nullptr, st)))
         return rc;
     Frame *one[1] = {&f};
     while (!f.done) {
-        if ((rc = step_frames(p, one, 1, st)) || (rc = frame_queue_poll(f, st)))
+        if ((rc = step_frames(p, one, 1, st)))
             return rc;
-        if (f.opts.stop == LFRL_STOP_METRIC)
-            HIP_TRY(hipStreamSynchronize(st));
         frame_update_done(f);
     }
     return frame_result(f, p->g.Nz, vol, report, st);

@@ -38,8 +38,8 @@ namespace psfopt {
 
 static constexpr int kMaxStages = 16;
 static constexpr int kMaxSide = 2048;   // largest FFT grid side
-static constexpr int kThreads = 256;
-static constexpr int kLineBudget = 30 * kThreads;  // complex values a block transforms at once
+static constexpr int kThreads = 512;
+static constexpr int kLineBudget = 15 * kThreads;  // complex values a block transforms at once
 static constexpr int kDepthsPerThread = 8;
 static constexpr int kQuadChunk = 256;
 
@@ -189,9 +189,12 @@ __global__ __launch_bounds__(kThreads) void k_debye(const double2 *__restrict__ 
             }
         }
     }
-    if (rho < nrad)
-        for (int d = 0; d < nd; ++d)
-            U[(size_t)(jz + d) * nrad + rho] = acc[d];
+    if (rho < nrad) {
+#pragma unroll
+        for (int d = 0; d < kDepthsPerThread; ++d)
+            if (d < nd)
+                U[(size_t)(jz + d) * nrad + rho] = acc[d];
+    }
 }
 
 // Field on nl window rows of one source (the depth's Debye field times the

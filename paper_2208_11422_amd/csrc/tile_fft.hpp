@@ -212,6 +212,51 @@ __device__ __forceinline__ void fft(float2 (&v)[Q], const float2 *__restrict__ t
 
 enum { SRC_PLANES = 0, SRC_PSF = 1 };
 
+// Half spectra of real tiles are Hermitian: on the columns kv = 0 and (Q even)
+// kv = Q/2, row ku and row Q - ku hold complex conjugates.  The products of two
+// such spectra keep the symmetry, so the contractions compute only the unique
+// frequencies (rows ku <= Q/2 in full, the other rows without those columns)
+// and the inverse transform reads the rest from their partners, conjugated.
+// For Q = 28 that is 394 of 420 frequencies.
+struct FreqMap {
+    int QH;     // Q / 2 + 1 columns
+    int L;      // full rows: ku <= Q / 2
+    int m;      // columns of the other rows: 1 .. m
+};
+
+__host__ __device__ inline FreqMap freq_map(int Q)
+{
+    FreqMap f;
+    f.QH = Q / 2 + 1;
+    f.L = Q / 2 + 1;
+    f.m = f.QH - ((Q % 2 == 0) ? 2 : 1);
+    return f;
+}
+
+__host__ __device__ inline int unique_freqs(int Q)
+{
+    const FreqMap f = freq_map(Q);
+    return f.L * f.QH + (Q - f.L) * f.m;
+}
+
+// Frequency index k = ku * QH + kv of the u-th unique frequency.
+__device__ __forceinline__ int unique_freq(int u, const FreqMap &f)
+{
+    const int full = f.L * f.QH;
+    if (u < full)
+        return u;
+    const int r = u - full;
+    return (f.L + r / f.m) * f.QH + 1 + r % f.m;
+}
+
+// Whether frequency (ku, kv) is the conjugate of a unique one (its partner
+// is row Q - ku of the same column).
+template <int Q>
+__device__ __forceinline__ bool freq_redundant(int ku, int kv)
+{
+    return ku > Q / 2 && (kv == 0 || (Q % 2 == 0 && kv == Q / 2));
+}
+
 // Loads in these kernels are issued in batches (the constants below) per thread
 // before any of them is consumed, so a thread keeps that many requests in flight
 // instead of waiting out the memory latency once per element.  Addresses are
@@ -219,7 +264,7 @@ enum { SRC_PLANES = 0, SRC_PSF = 1 };
 // select, which the compiler would turn into a branch around the load).
 // (deeper batches were measured slower: fewer blocks fit per CU)
 // The forward transform loads its rows straight into registers instead.
-static constexpr int kEpiBatch = 8;      // inverse: epilogue pixels per thread
+static constexpr int kEpiBatch = 4;      // inverse: epilogue pixels per thread
 
 // Frames whose tiles one launch covers.  Tiles of all frames are numbered
 // consecutively (frame f owns tiles [tile0, tile0 + its tile count)); the
@@ -243,6 +288,7 @@ struct TileJob {
     float bg;           // inverse transform: background b
     int mode;           // inverse transform: epilogue
     int H, W, tiles_x, tile0;
+    const int *skip;    // device flag (may be null): nonzero = skip this frame's tiles
 };
 
 struct TileBatch {
@@ -328,6 +374,8 @@ __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const TileBatch batch
         const int j = jar / N;
         arow = jar % N;
         const TileJob &fj = batch.job[batch_job(batch, tile)];
+        if (fj.skip && *fj.skip)
+            return;   // block-uniform, before any barrier
         H = fj.H;
         W = fj.W;
         const int lt = tile - fj.tile0;
@@ -418,7 +466,8 @@ __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const TileBatch batch
         tfft::fft<Q, -1>(v, tw);
 #pragma unroll
         for (int ku = 0; ku < Q; ++ku)
-            out[obase + (size_t)(ku * QH + kv) * kstride + p] = v[ku];
+            if (mode != SRC_PLANES || !freq_redundant<Q>(ku, kv))
+                out[obase + (size_t)(ku * QH + kv) * kstride + p] = v[ku];
         if (rowmax) {
 #pragma unroll
             for (int ku = 0; ku < Q; ++ku)
@@ -458,6 +507,8 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
     const int tile = item / (planes * N), jar = item % (planes * N);
     const int j = jar / N, ar = jar % N;
     const TileJob &fj = batch.job[batch_job(batch, tile)];
+    if (fj.skip && *fj.skip)
+        return;   // block-uniform, before any barrier
     const int H = fj.H, W = fj.W, lt = tile - fj.tile0;
     const int ty = lt / fj.tiles_x, tx = lt % fj.tiles_x;
     float *__restrict__ dst = fj.dst;
@@ -475,11 +526,17 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
     // independent loads in flight, no staging buffer), summing split partials
     if (tid < QH * N) {
         const int kv = tid / N, p = tid % N;
-        const size_t base = tile * stile + (kkbase + p) * sc;
+        // a uniform base per row ku (scalar registers) plus one 32-bit byte
+        // offset per thread (the launch keeps QH * sk * 8 below 2^32): the
+        // loads need no 64-bit address per element
+        const char *blk = reinterpret_cast<const char *>(spec + tile * stile + kkbase * sc);
+        const unsigned toff = (unsigned)(((size_t)kv * sk + (size_t)p * sc) * sizeof(float2));
+        const size_t kstep = (size_t)QH * sk * sizeof(float2);
 #pragma unroll
         for (int ku = 0; ku < Q; ++ku)
-            v[ku] = spec[(size_t)(ku * QH + kv) * sk + base];
+            v[ku] = *reinterpret_cast<const float2 *>(blk + ku * kstep + toff);
         for (int s = 1; s < nsplit; ++s) {
+            const char *blks = blk + (size_t)s * split_stride * sizeof(float2);
             // partials in chunks of 8 loads (a second Q-long array would spill)
 #pragma unroll
             for (int k0 = 0; k0 < Q; k0 += 8) {
@@ -487,8 +544,7 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
 #pragma unroll
                 for (int d = 0; d < 8; ++d)
                     if (k0 + d < Q)
-                        part[d] = spec[(size_t)s * split_stride +
-                                       (size_t)((k0 + d) * QH + kv) * sk + base];
+                        part[d] = *reinterpret_cast<const float2 *>(blks + (k0 + d) * kstep + toff);
 #pragma unroll
                 for (int d = 0; d < 8; ++d)
                     if (k0 + d < Q) {
@@ -496,6 +552,17 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
                         v[k0 + d].y += part[d].y;
                     }
             }
+        }
+        // the redundant rows of the columns kv = 0 and kv = Q/2 were never
+        // written (see FreqMap): the conjugates of their partner rows, which
+        // this thread holds, replace whatever was read there (a select, so
+        // stale values cannot leak)
+        const bool edge = kv == 0 || (Q % 2 == 0 && kv == Q / 2);
+#pragma unroll
+        for (int ku = Q / 2 + 1; ku < Q; ++ku) {
+            const float2 c = v[Q - ku];
+            v[ku].x = edge ? c.x : v[ku].x;
+            v[ku].y = edge ? -c.y : v[ku].y;
         }
         tfft::fft<Q, 1>(v, tw);
 #pragma unroll
@@ -543,12 +610,17 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
         }
     }
     __syncthreads();
-    // coalesced epilogue over whole pixel rows of the tile
+    // coalesced epilogue over whole pixel rows of the tile; the plane's base
+    // pointers are uniform and pixel offsets are 32-bit (a plane is < 2^30 pixels)
     const int Ly = H / N, Lx = W / N;
     const int rowpix = T * N;
     const int ototal = T * rowpix;
+    const size_t plane_off = (mode == EPI_RATIO) ? 0 : (size_t)j * H * W;
+    const float *__restrict__ a0p = aux0 + plane_off;
+    const float *__restrict__ a1p = aux1 + plane_off;
+    float *__restrict__ dp = dst + plane_off;
     for (int base = tid; base < ototal; base += kEpiBatch * blockDim.x) {
-        size_t o[kEpiBatch];
+        unsigned o[kEpiBatch];
         bool ok[kEpiBatch];
         float a0[kEpiBatch], a1[kEpiBatch];
 #pragma unroll
@@ -558,10 +630,9 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
             const int Lr = ty * T + ti, Lc = tx * T + rem / N;
             ok[b] = base + b * (int)blockDim.x < ototal && Lr < Ly && Lc < Lx;
             const int pr = min(N * Lr + ar, H - 1), pc = min(N * tx * T + rem, W - 1);
-            const size_t pix = (size_t)pr * W + pc;
-            o[b] = (mode == EPI_RATIO ? 0 : (size_t)j * H * W) + pix;
-            a0[b] = (mode != EPI_STORE) ? aux0[o[b]] : 0.f;
-            a1[b] = (mode >= EPI_UPDATE) ? aux1[o[b]] : 0.f;
+            o[b] = (unsigned)pr * (unsigned)W + (unsigned)pc;
+            a0[b] = (mode != EPI_STORE) ? a0p[o[b]] : 0.f;
+            a1[b] = (mode >= EPI_UPDATE) ? a1p[o[b]] : 0.f;
         }
 #pragma unroll
         for (int b = 0; b < kEpiBatch; ++b) {
@@ -569,14 +640,14 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
                 continue;
             const float val = obuf[base + b * (int)blockDim.x];
             if (mode == EPI_STORE) {
-                dst[o[b]] = val + bg;
+                dp[o[b]] = val + bg;
             } else if (mode == EPI_RATIO) {
                 const float m = val + bg;
-                dst[o[b]] = m > 0.f ? a0[b] / m : 0.f;
+                dp[o[b]] = m > 0.f ? a0[b] / m : 0.f;
             } else if (mode == EPI_UPDATE) {
-                dst[o[b]] = a1[b] > 0.f ? a0[b] * val / a1[b] : 0.f;
+                dp[o[b]] = a1[b] > 0.f ? a0[b] * val / a1[b] : 0.f;
             } else {
-                dst[o[b]] = val > 0.f ? a0[b] * a1[b] / val : 0.f;
+                dp[o[b]] = val > 0.f ? a0[b] * a1[b] / val : 0.f;
             }
         }
     }
