@@ -174,7 +174,7 @@ typedef enum {
     LFRL_NORM_REGION = 1,  /* Frobenius norm of the coefficients in the region */
     LFRL_NORM_SPECTRAL = 2 /* largest singular value of the coefficient matrix
                               (equal to the image's: the DCT is orthonormal),
-                              by float64 power iteration; h + w <= 6144 */
+                              by float64 Lanczos iteration; h + w <= 6144 */
 } lfrl_norm;
 
 typedef struct {

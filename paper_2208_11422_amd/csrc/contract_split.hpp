@@ -107,11 +107,10 @@ __global__ void k_spec_exp(const float2 *__restrict__ Gf, size_t per_k, int *__r
 // Forward fragments: Hf[k][kb][cb][lane][e], kk = 32 kb + 8 (lane / 16) + e,
 // c = 16 cb + lane % 16, value Gf[k][kk][c] 2^gexp[k] (0 past KK).
 template <class P>
-__global__ void k_pack_fwd_split(const float2 *__restrict__ Gf, int KK, int NNp, int nkb,
+__global__ void k_pack_fwd_split(const float2 *__restrict__ Gf, int KK, int NNp, int ncb, int nkb,
                                  const int *__restrict__ gexp,
                                  cplx16<typename P::S> *__restrict__ Hf, size_t total)
 {
-    const int ncb = NNp / 16;
     for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
          idx += (size_t)gridDim.x * blockDim.x) {
         const int e = idx % 8;
@@ -180,7 +179,7 @@ __global__ __launch_bounds__(512) void k_contract_fwd_split(
     const cplx16<typename P::S> *__restrict__ Hf, const float2 *__restrict__ X,
     const unsigned *__restrict__ xmax, const int *__restrict__ gexp, float2 *__restrict__ Yp,
     int NN, int NNp, int KK, int KKs, int nkb, int nt, int nf, int kchunk,
-    const int *__restrict__ skip, FreqMap fm)
+    const int *__restrict__ skip, FreqMap fm, const float2 *__restrict__ Gx, int xcol)
 {
     if (skip && *skip)
         return;
@@ -213,6 +212,31 @@ __global__ __launch_bounds__(512) void k_contract_fwd_split(
     }
     float4 xa0[U][4], xa1[U][4];
     uint4 gb0[U][CB][2], gb1[U][CB][2];
+    // the lone output column xcol (if any): X G in float32 on the vector ALU,
+    // from the X values the waves hold anyway; wave w takes the steps
+    // w, w + nw, ... and the partial sums meet in LDS at the end
+    const int nw = blockDim.x >> 6;
+    const float2 *gxk = Gx + (xcol >= 0 ? (size_t)k * KKs : 0);
+    float2 accx = make_float2(0.f, 0.f);
+    auto column_group = [&](int grp, const float4(&xa)[U][4]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int step = grp * U + u;
+            const int kk = kb0 + 32 * step + 8 * kg;
+            if (xcol < 0 || step >= nsteps || step % nw != wave)
+                continue;
+            const float4 *gp = reinterpret_cast<const float4 *>(gxk + kk);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 g = gp[q], x = xa[u][q];
+                const bool ok0 = kk + 2 * q < kb1, ok1 = kk + 2 * q + 1 < kb1;
+                const float xr0 = ok0 ? x.x : 0.f, xi0 = ok0 ? x.y : 0.f;
+                const float xr1 = ok1 ? x.z : 0.f, xi1 = ok1 ? x.w : 0.f;
+                accx.x = fmaf(xr0, g.x, fmaf(-xi0, g.y, fmaf(xr1, g.z, fmaf(-xi1, g.w, accx.x))));
+                accx.y = fmaf(xr0, g.y, fmaf(xi0, g.x, fmaf(xr1, g.w, fmaf(xi1, g.z, accx.y))));
+            }
+        }
+    };
     auto load_group = [&](int grp, float4(&xa)[U][4], uint4(&gb)[U][CB][2]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -282,14 +306,36 @@ __global__ __launch_bounds__(512) void k_contract_fwd_split(
         if (grp + 1 < ngroups)
             load_group(grp + 1, xa1, gb1);
         compute_group(grp, xa0, gb0);
+        column_group(grp, xa0);
         if (grp + 1 < ngroups) {
             if (grp + 2 < ngroups)
                 load_group(grp + 2, xa0, gb0);
             compute_group(grp + 1, xa1, gb1);
+            column_group(grp + 1, xa1);
         }
     }
     // D[t][c] rows t0 + 4 kg + i carry the scale 2^(xexp[row] + gexp[k])
     float2 *yk = Yp + ((size_t)s * nf + k) * nt * NN;
+    // lone column: lane (t = col, kg) holds tile t's partial over its kk
+    // slice of this wave's steps; sum over kg, then over the waves in order
+    if (xcol >= 0) {
+        __shared__ float2 colsum[8][16];
+        accx.x += __shfl_xor(accx.x, 16, 64);
+        accx.y += __shfl_xor(accx.y, 16, 64);
+        accx.x += __shfl_xor(accx.x, 32, 64);
+        accx.y += __shfl_xor(accx.y, 32, 64);
+        if (kg == 0)
+            colsum[wave][col] = accx;
+        __syncthreads();
+        if (wave == 0 && kg == 0 && t0 + col < nt) {
+            float2 a = colsum[0][col];
+            for (int w = 1; w < nw; ++w) {
+                a.x += colsum[w][col].x;
+                a.y += colsum[w][col].y;
+            }
+            yk[(size_t)(t0 + col) * NN + xcol] = a;
+        }
+    }
     const int gx = gexp[k];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -300,17 +346,17 @@ __global__ __launch_bounds__(512) void k_contract_fwd_split(
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
             const int c = 16 * (wave * CB + b) + col;
-            if (c < NN)
+            if (c < NN && wave * CB + b < ncb)
                 yk[(size_t)tt * NN + c] = make_float2(ldexpf(accr[b][i], sc), ldexpf(acci[b][i], sc));
         }
     }
 }
 
 // Rows (16-c chunks) of image tile spectra the split adjoint stages in LDS:
-// an even number of register groups of U chunks, zero past NN.
+// whole register groups of U chunks, zero past the ncc fragment chunks.
 __host__ __device__ __forceinline__ int split_adj_chunks(int ncc, int U)
 {
-    return ((ncc + U - 1) / U + 1) / 2 * 2 * U;
+    return (ncc + U - 1) / U * U;
 }
 
 // Adjoint contraction, split precision:
@@ -318,12 +364,14 @@ __host__ __device__ __forceinline__ int split_adj_chunks(int ncc, int U)
 // A = R rows (16 tiles x 16 c per step, scaled by 2^rexp and split hi/lo once
 // per block into LDS, zero past NN), B = Hb fragments (16 c x 16 kk), CB
 // blocks of kk per wave, U prefetched steps in a straight-line
-// double-buffered loop (surplus chunks meet zeros in LDS).
+// double-buffered loop (an odd last group has no partner; chunks past ncc
+// meet zeros in LDS).
 template <class P, int CB, int U>
 __global__ __launch_bounds__(256) void k_contract_adj_split(
     const cplx16<typename P::S> *__restrict__ Hb, const float2 *__restrict__ Rs,
     const unsigned *__restrict__ rmax, const int *__restrict__ gexp, float2 *__restrict__ B,
-    int NN, int NNp, int KK, int KKs, int nkb, int nt, const int *__restrict__ skip, FreqMap fm)
+    int NN, int NNp, int KK, int KKs, int nkb, int nt, const int *__restrict__ skip, FreqMap fm,
+    const float2 *__restrict__ Hx, int xc, int KKb)
 {
     if (skip && *skip)
         return;
@@ -346,7 +394,7 @@ __global__ __launch_bounds__(256) void k_contract_adj_split(
         const int tt = t0 + l % 16;
         float2 v = make_float2(0.f, 0.f);
         int ex = 0;
-        if (c < NN && tt < nt) {
+        if (c < NN && c < 16 * ncc && tt < nt) {
             v = Rs[((size_t)k * nt + tt) * NN + c];
             ex = f16_scale_exp(__uint_as_float(rmax[(size_t)k * nt + tt]));
         }
@@ -442,7 +490,8 @@ __global__ __launch_bounds__(256) void k_contract_adj_split(
         __builtin_amdgcn_sched_barrier(0);
         load_group(grp + 2, gb0);
         __builtin_amdgcn_sched_barrier(0);
-        compute_group(grp + 1, gb1);
+        if (grp + 1 < ngroups)  // an odd last group has no partner
+            compute_group(grp + 1, gb1);
         __builtin_amdgcn_sched_barrier(0);
     }
     float2 *bk = B + (size_t)k * nt * KKs;   // rows of KKs: 128-byte aligned
@@ -453,11 +502,19 @@ __global__ __launch_bounds__(256) void k_contract_adj_split(
         if (tt >= nt)
             continue;
         const int sc = -(f16_scale_exp(__uint_as_float(rmax[(size_t)k * nt + tt])) + gx);
+        // the lone reduction index xc (if any), in float32: + R[t][xc] conj(H[xc][kk])
+        const float2 r = xc >= 0 ? Rs[((size_t)k * nt + tt) * NN + xc] : make_float2(0.f, 0.f);
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
             const int kk = 16 * kbk[b] + col;
+            float2 o = make_float2(ldexpf(accr[b][i], sc), ldexpf(acci[b][i], sc));
+            if (xc >= 0) {
+                const float2 h = Hx[(size_t)k * KKb + 16 * kbk[b] + col];
+                o.x = fmaf(r.x, h.x, fmaf(r.y, h.y, o.x));
+                o.y = fmaf(r.y, h.x, fmaf(-r.x, h.y, o.y));
+            }
             if (k_ok[b] && kk < KK)
-                bk[(size_t)tt * KKs + kk] = make_float2(ldexpf(accr[b][i], sc), ldexpf(acci[b][i], sc));
+                bk[(size_t)tt * KKs + kk] = o;
         }
     }
 }

@@ -86,6 +86,10 @@ static constexpr float kWeakThreshold = 1e-2f;  // weak voxel: A^T 1 < this * ma
 // ---------------------------------------------------------------------------
 struct Geo {
     int N, Nz, K, c0, hD, R, Q, QH, T, nf, NN, NNp, KK, KKs, NCp, KKb;
+    int NCm;  // adjoint reduction on the matrix cores (a multiple of 8)
+    int xc;   // the lone reduction index past them (summed on the vector ALU), or -1
+    int NNm;  // forward output columns on the matrix cores (a multiple of 16)
+    int xcol; // the lone output column past them (summed on the vector ALU), or -1
 };
 
 static void geo_init(Geo &g, int N, int Nz, int K, int Q)
@@ -105,6 +109,13 @@ static void geo_init(Geo &g, int N, int Nz, int K, int Q)
     g.KK = g.NN * Nz;
     g.KKs = (g.KK + 31) / 32 * 32;  // row stride of the volume tile spectra
     g.NCp = (g.NN + 7) / 8 * 8;     // adjoint reduction length in fragment pairs
+    // a single index past the last full group of 8 (NN = 225 for Nnum 15) is not
+    // worth 7 zero-padded fragment rows: it is added on the vector ALU instead
+    g.NCm = (g.NN % 8 == 1 && g.NN > 8) ? g.NN - 1 : g.NCp;
+    g.xc = g.NCm < g.NN ? g.NN - 1 : -1;
+    // likewise a single forward output column past the last full block of 16
+    g.NNm = (g.NN % 16 == 1 && g.NN > 16) ? g.NN - 1 : g.NNp;
+    g.xcol = g.NNm < g.NN ? g.NN - 1 : -1;
     g.KKb = (g.KK + 15) / 16 * 16;  // adjoint output columns in 16-column blocks
 }
 
@@ -493,10 +504,10 @@ __device__ __forceinline__ void contraction_block(int &k, int &y, int &tg)
 // with q = lane / 16, col = lane % 16 and zeros outside the valid ranges.
 // The reduction index kk (forward) or c (adjoint) of MFMA step 2u + h is
 // 8u + 2q + h for lane group q: the sums are the same, taken in this order.
-__global__ void k_pack_fwd_f32(const float2 *__restrict__ Gf, int KK, int NNp, int KKs,
+__global__ void k_pack_fwd_f32(const float2 *__restrict__ Gf, int KK, int NNp, int ncb, int KKs,
                                float4 *__restrict__ Ff, size_t total)
 {
-    const int ncb = NNp / 16, np = KKs / 8;
+    const int np = KKs / 8;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
          i += (size_t)gridDim.x * blockDim.x) {
         const int lane = (int)(i % 64);
@@ -510,6 +521,19 @@ __global__ void k_pack_fwd_f32(const float2 *__restrict__ Gf, int KK, int NNp, i
         const float2 a = kk < KK ? gk[(size_t)kk * NNp + c] : make_float2(0.f, 0.f);
         const float2 b = kk + 1 < KK ? gk[(size_t)(kk + 1) * NNp + c] : make_float2(0.f, 0.f);
         Ff[i] = make_float4(a.x, a.y, b.x, b.y);
+    }
+}
+
+// Column xcol of the forward spectra, Gx[k][kk] = Gf[k][kk][xcol] (0 past KK):
+// the lone output column the forward contraction sums on the vector ALU.
+__global__ void k_spec_column(const float2 *__restrict__ Gf, int KK, int NNp, int KKs, int xcol,
+                              float2 *__restrict__ Gx, size_t total)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t k = i / KKs;
+        const int kk = (int)(i % KKs);
+        Gx[i] = kk < KK ? Gf[(k * KK + kk) * NNp + xcol] : make_float2(0.f, 0.f);
     }
 }
 
@@ -566,7 +590,8 @@ __global__ __launch_bounds__(512) void k_contract_fwd(const float4 *__restrict__
                                                       const float2 *__restrict__ X,
                                                       float2 *__restrict__ Yp, int NN, int NNp,
                                                       int KK, int KKs, int nt, int nf, int kchunk,
-                                                      const int *__restrict__ skip, FreqMap fm)
+                                                      const int *__restrict__ skip, FreqMap fm,
+                                                      const float4 *__restrict__ Gx4, int xcol)
 {
     if (skip && *skip)
         return;
@@ -593,6 +618,12 @@ __global__ __launch_bounds__(512) void k_contract_fwd(const float4 *__restrict__
     const float4 *st_row =
         reinterpret_cast<const float4 *>(X + ((size_t)k * nt + min(t0 + st_t, nt - 1)) * KKs);
     const float4 *fk = Ff + (size_t)k * (KKs / 8) * ncb * 64;
+    // the lone output column xcol (if any) is summed on the vector ALU by every
+    // wave (one broadcast 16-byte load per lane group and pair, negligible next
+    // to the fragments); the last wave stores it.  Without one, Gx4 points at
+    // valid memory and the sum is discarded, so the loop stays branch-free.
+    const float4 *gxk = Gx4 + (xcol >= 0 ? (size_t)k * (KKs / 8) * 4 : 0);
+    float2 accx = make_float2(0.f, 0.f);
     int cbi[CB];
 #pragma unroll
     for (int b = 0; b < CB; ++b)
@@ -620,13 +651,22 @@ __global__ __launch_bounds__(512) void k_contract_fwd(const float4 *__restrict__
         la[buf][st_j / 4][16 * (st_j % 4) + st_t] =
             make_float4(mask_f(v.x, ok0), mask_f(v.y, ok0), mask_f(v.z, ok1), mask_f(v.w, ok1));
     };
-    auto b_load = [&](int grp, float4(&gb)[U][CB]) {
+    auto b_load = [&](int grp, float4(&gb)[U][CB], float4(&gx)[U]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int p = min(p0 + grp * U + u, p1 - 1);
 #pragma unroll
             for (int b = 0; b < CB; ++b)
                 gb[u][b] = fk[((size_t)p * ncb + cbi[b]) * 64 + lane];
+            gx[u] = gxk[xcol >= 0 ? (size_t)p * 4 + kq : 0];
+        }
+    };
+    auto column_group = [&](int buf, const float4(&gx)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const float4 a = la[buf][u][lane], g = gx[u];
+            accx.x = fmaf(a.x, g.x, fmaf(-a.y, g.y, fmaf(a.z, g.z, fmaf(-a.w, g.w, accx.x))));
+            accx.y = fmaf(a.x, g.y, fmaf(a.y, g.x, fmaf(a.z, g.w, fmaf(a.w, g.z, accx.y))));
         }
     };
     auto compute_group = [&](int buf, const float4(&gb)[U][CB]) {
@@ -687,23 +727,25 @@ __global__ __launch_bounds__(512) void k_contract_fwd(const float4 *__restrict__
     // different numbers of loads in flight, and the waits at the join would
     // then cover the prefetch too.  The scheduling barriers keep each
     // prefetch ahead of the products it is meant to overlap.
-    float4 gb0[U][CB], gb1[U][CB];
+    float4 gb0[U][CB], gb1[U][CB], gx0[U], gx1[U];
     float4 av = a_load(0);
-    b_load(0, gb0);
+    b_load(0, gb0, gx0);
     a_store(0, 0, av);
     __syncthreads();
     for (int grp = 0; grp < ngroups; grp += 2) {
         av = a_load(grp + 1);
-        b_load(grp + 1, gb1);
+        b_load(grp + 1, gb1, gx1);
         __builtin_amdgcn_sched_barrier(0);
         compute_group(0, gb0);
+        column_group(0, gx0);
         __builtin_amdgcn_sched_barrier(0);
         a_store(grp + 1, 1, av);
         __syncthreads();
         av = a_load(grp + 2);
-        b_load(grp + 2, gb0);
+        b_load(grp + 2, gb0, gx0);
         __builtin_amdgcn_sched_barrier(0);
         compute_group(1, gb1);
+        column_group(1, gx1);
         __builtin_amdgcn_sched_barrier(0);
         a_store(grp + 2, 0, av);
         __syncthreads();
@@ -720,6 +762,13 @@ __global__ __launch_bounds__(512) void k_contract_fwd(const float4 *__restrict__
 #endif
     // D[t][c]: lane holds tiles t0 + 4 * kq + i, column c of each block
     float2 *yk = Yp + ((size_t)s * nf + k) * nt * NN;
+    // the lone column: lane (t, kq) holds tile t's partial over lane group kq
+    accx.x += __shfl_xor(accx.x, 16, 64);
+    accx.y += __shfl_xor(accx.y, 16, 64);
+    accx.x += __shfl_xor(accx.x, 32, 64);
+    accx.y += __shfl_xor(accx.y, 32, 64);
+    if (xcol >= 0 && wave == (int)(blockDim.x >> 6) - 1 && kq == 0 && t0 + col < nt)
+        yk[(size_t)(t0 + col) * NN + xcol] = accx;
 #pragma unroll
     for (int b = 0; b < CB; ++b) {
         const int c = 16 * (wave * CB + b) + col;
@@ -750,7 +799,9 @@ __global__ __launch_bounds__(256) void k_contract_adj(const float4 *__restrict__
                                                       const float2 *__restrict__ Rs,
                                                       float2 *__restrict__ B, int NN, int KK,
                                                       int KKs, int NCp, int nt, int ranges,
-                                                      const int *__restrict__ skip, FreqMap fm)
+                                                      const int *__restrict__ skip, FreqMap fm,
+                                                      const float2 *__restrict__ Hx, int xc,
+                                                      int KKb)
 {
     if (skip && *skip)
         return;
@@ -774,7 +825,8 @@ __global__ __launch_bounds__(256) void k_contract_adj(const float4 *__restrict__
         for (int b = 0; b < 8; ++b) {
             const int idx = min(base + b * (int)blockDim.x, total - 1);
             const int tt = idx / ncl, c = idx % ncl;
-            const bool ok = c < NN && t0 + tt < nt;
+            // rows past the fragments' NCp (a lone index xc among them) stay zero
+            const bool ok = c < NN && c < NCp && t0 + tt < nt;
             const float2 x = Rs[((size_t)k * nt + min(t0 + tt, nt - 1)) * NN + min(c, NN - 1)];
             v[b] = make_float2(mask_f(x.x, ok), mask_f(x.y, ok));
         }
@@ -786,6 +838,14 @@ __global__ __launch_bounds__(256) void k_contract_adj(const float4 *__restrict__
         }
     }
     __syncthreads();
+    // the lone reduction index xc (if any) is not in the fragments: its
+    // R values for this lane's four output rows
+    float2 rx[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int tt = min(t0 + 4 * kq + i, nt - 1);
+        rx[i] = xc >= 0 ? Rs[((size_t)k * nt + tt) * NN + xc] : make_float2(0.f, 0.f);
+    }
     const float4 *fk = Fb + (size_t)k * npairs * nkb * 64;
     float2 *bk = B + (size_t)k * nt * KKs;   // rows of KKs: 128-byte aligned
     const int RB = nwaves * CB;  // column blocks per range (the packing's RB)
@@ -898,6 +958,18 @@ __global__ __launch_bounds__(256) void k_contract_adj(const float4 *__restrict__
                 acci[b][i] = accs[b][i] - pr + pi;
             }
 #endif
+        if (xc >= 0) {
+            // + R[t][xc] conj(H[xc][kk]) on the vector ALU
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                const float2 h = Hx[(size_t)k * KKb + 16 * kbi[b] + col];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    accr[b][i] = fmaf(rx[i].x, h.x, fmaf(rx[i].y, h.y, accr[b][i]));
+                    acci[b][i] = fmaf(rx[i].y, h.x, fmaf(-rx[i].x, h.y, acci[b][i]));
+                }
+            }
+        }
         // D[t][kk]: lane holds tiles t0 + 4 * kq + i, column kk of each block
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
@@ -1107,20 +1179,61 @@ __global__ __launch_bounds__(256) void k_dgemm32(const double *__restrict__ A, i
         }
 }
 
-// Largest singular value squared of the h x w image m (float64 power
-// iteration on m^T m, one block): u = m v one wave per row, v = m^T u one wave
-// per 64 columns, both in a fixed order; v starts from a fixed positive
-// vector.  Stops once the Rayleigh quotient ||m v||^2 / ||v||^2 changes by at
-// most 1e-14 of itself, or after maxit iterations.  Dynamic LDS: (W + H)
-// doubles.  *n2 = the last quotient.
+// Largest singular value squared of the h x w image m: the largest
+// eigenvalue of A = B^T B, with B = m when w <= h and B = m^T otherwise (A of
+// side n = min(h, w)), by Lanczos iteration in float64 with full
+// reorthogonalisation, in one block.  Step j: y = B v_j (one wave per output
+// or one lane per output, both in a fixed order), w = B^T y, alpha_j = |y|^2
+// (= v_j . A v_j); w is orthogonalised twice against v_0 .. v_j (classical
+// Gram-Schmidt, one wave per dot product), beta_{j+1} = |w|; the largest
+// eigenvalue theta of the tridiagonal (alpha, beta) comes from bisection on
+// its Sturm sequence.  Stops once theta grows by at most 1e-15 of itself, w
+// vanishes (an invariant subspace: theta is exact), or after maxsteps steps
+// (the basis v_j is kept in `basis`, maxsteps x n doubles).  v_0 is a fixed
+// positive vector.  Dynamic LDS: (h + w) doubles.  *n2 = theta.
+__device__ double tridiag_max_eig(const double *al, const double *be, int k)
+{
+    // Gershgorin bounds, then bisection: count(x) = eigenvalues below x
+    double lo = 0.0, hi = 0.0;
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? fabs(be[i]) : 0.0) + (i + 1 < k ? fabs(be[i + 1]) : 0.0);
+        lo = (i == 0) ? al[i] - r : fmin(lo, al[i] - r);
+        hi = (i == 0) ? al[i] + r : fmax(hi, al[i] + r);
+    }
+    for (int it = 0; it < 200 && hi - lo > 1e-17 * fabs(hi); ++it) {
+        const double x = 0.5 * (lo + hi);
+        int below = 0;
+        double d = 1.0;
+        for (int i = 0; i < k; ++i) {
+            d = al[i] - x - (i > 0 ? be[i] * be[i] / d : 0.0);
+            if (d == 0.0)
+                d = -1e-300;
+            below += d < 0.0;
+        }
+        if (below == k)   // every eigenvalue is below x
+            hi = x;
+        else
+            lo = x;
+    }
+    return hi;
+}
+
+static constexpr int kLanczosMaxSteps = 48;
+
 __global__ __launch_bounds__(1024) void k_spectral_norm(const float *__restrict__ m, int H, int W,
-                                                        int maxit, double *__restrict__ n2)
+                                                        int maxsteps, double *__restrict__ basis,
+                                                        double *__restrict__ n2)
 {
     extern __shared__ double sv[];
-    double *v = sv, *u = sv + W;
     __shared__ double red[1024];
+    __shared__ double al[kLanczosMaxSteps + 1], be[kLanczosMaxSteps + 1], coef[kLanczosMaxSteps];
+    __shared__ double theta_s;
+    __shared__ int stop_s;
     const int tid = threadIdx.x, nth = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwave = nth >> 6;
+    const bool tall = W <= H;             // A = m^T m (side W) or m m^T (side H)
+    const int n = tall ? W : H, mo = tall ? H : W;
+    double *x = sv, *y = sv + n;          // x: v_j (n), y: B v_j (mo)
     auto block_sum = [&](double a) -> double {
         red[tid] = a;
         __syncthreads();
@@ -1133,75 +1246,148 @@ __global__ __launch_bounds__(1024) void k_spectral_norm(const float *__restrict_
         __syncthreads();
         return r;
     };
-    for (int s = tid; s < W; s += nth)
-        v[s] = 1.0 + (double)((unsigned)(s + 1) * 2654435761u % 1024u) / 2048.0;
-    __syncthreads();
-    double lam = 0.0, prev = -1.0;
-    for (int it = 0; it < maxit; ++it) {
-        // u = m v (loads in batches of 8, clamped; the masked terms add 0)
-        for (int r = wave; r < H; r += nwave) {
-            const float *mr = m + (size_t)r * W;
-            double acc = 0.0;
-            for (int s0 = lane; s0 < W; s0 += 8 * 64) {
-                float x[8];
+    // rows pass: out[r] = sum_s m[r][s] in[s], a wave per 4 rows at a time
+    // (16 loads in flight per lane: the pass is bound by memory latency)
+    auto rows_pass = [&](const double *in, double *out) {
+        for (int r0 = 4 * wave; r0 < H; r0 += 4 * nwave) {
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int s0 = lane; s0 < W; s0 += 4 * 64) {
+                float v4[4][4];
 #pragma unroll
-                for (int b = 0; b < 8; ++b)
-                    x[b] = mr[min(s0 + 64 * b, W - 1)];
+                for (int q = 0; q < 4; ++q)
 #pragma unroll
-                for (int b = 0; b < 8; ++b)
-                    if (s0 + 64 * b < W)
-                        acc = fma((double)x[b], v[s0 + 64 * b], acc);
-            }
-            for (int off = 32; off > 0; off >>= 1)
-                acc += __shfl_down(acc, off, 64);
-            if (lane == 0)
-                u[r] = acc;
-        }
-        __syncthreads();
-        double a = 0.0, b = 0.0;
-        for (int r = tid; r < H; r += nth)
-            a += u[r] * u[r];
-        for (int s = tid; s < W; s += nth)
-            b += v[s] * v[s];
-        const double uu = block_sum(a), vv = block_sum(b);
-        lam = vv > 0.0 ? uu / vv : 0.0;
-        // v = m^T u, then unit length
-        for (int c0 = wave * 64; c0 < W; c0 += nwave * 64) {
-            const int s = c0 + lane;
-            if (s < W) {
-                double acc = 0.0;
-                int r = 0;
-                for (; r + 8 <= H; r += 8) {
-                    float x[8];
+                    for (int b = 0; b < 4; ++b)
+                        v4[q][b] = m[(size_t)min(r0 + q, H - 1) * W + min(s0 + 64 * b, W - 1)];
 #pragma unroll
-                    for (int b = 0; b < 8; ++b)
-                        x[b] = m[(size_t)(r + b) * W + s];
+                for (int b = 0; b < 4; ++b) {
+                    const double x = s0 + 64 * b < W ? in[min(s0 + 64 * b, W - 1)] : 0.0;
 #pragma unroll
-                    for (int b = 0; b < 8; ++b)
-                        acc = fma((double)x[b], u[r + b], acc);
+                    for (int q = 0; q < 4; ++q)
+                        acc[q] = fma((double)v4[q][b], x, acc[q]);
                 }
-                for (; r < H; ++r)
-                    acc = fma((double)m[(size_t)r * W + s], u[r], acc);
-                v[s] = acc;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                double a = acc[q];
+                for (int off = 32; off > 0; off >>= 1)
+                    a += __shfl_down(a, off, 64);
+                if (lane == 0 && r0 + q < H)
+                    out[r0 + q] = a;
             }
         }
+    };
+    // columns pass: out[s] = sum_r m[r][s] in[r], one lane per column s < W,
+    // rows in batches of 16 loads (in fixed order)
+    auto cols_pass = [&](const double *in, double *out) {
+        for (int s = tid; s < W; s += nth) {
+            double acc = 0.0;
+            int r = 0;
+            for (; r + 16 <= H; r += 16) {
+                float v16[16];
+#pragma unroll
+                for (int b = 0; b < 16; ++b)
+                    v16[b] = m[(size_t)(r + b) * W + s];
+#pragma unroll
+                for (int b = 0; b < 16; ++b)
+                    acc = fma((double)v16[b], in[r + b], acc);
+            }
+            for (; r < H; ++r)
+                acc = fma((double)m[(size_t)r * W + s], in[r], acc);
+            out[s] = acc;
+        }
+    };
+    // v_0: fixed positive vector, unit length
+    double c = 0.0;
+    for (int i = tid; i < n; i += nth) {
+        const double v = 1.0 + (double)((unsigned)(i + 1) * 2654435761u % 1024u) / 2048.0;
+        x[i] = v;
+        c += v * v;
+    }
+    const double n0 = sqrt(block_sum(c));
+    for (int i = tid; i < n; i += nth) {
+        x[i] /= n0;
+        basis[i] = x[i];
+    }
+    if (tid == 0) {
+        theta_s = 0.0;
+        stop_s = 0;
+        be[0] = 0.0;
+    }
+    __syncthreads();
+    const int steps = max(1, min(maxsteps, kLanczosMaxSteps));
+    for (int j = 0; j < steps; ++j) {
+        // y = B v_j; alpha_j = |y|^2
+        if (tall)
+            rows_pass(x, y);
+        else
+            cols_pass(x, y);
         __syncthreads();
-        double c = 0.0;
-        for (int s = tid; s < W; s += nth)
-            c += v[s] * v[s];
-        const double nv = block_sum(c);
-        if (!(nv > 0.0))
-            break;  // m v = 0: the image is zero
-        const double scale = 1.0 / sqrt(nv);
-        for (int s = tid; s < W; s += nth)
-            v[s] *= scale;
-        __syncthreads();
-        if (it > 1 && fabs(lam - prev) <= 1e-14 * lam)
+        double a = 0.0;
+        for (int i = tid; i < mo; i += nth)
+            a += y[i] * y[i];
+        const double alpha = block_sum(a);
+        if (tid == 0)
+            al[j] = alpha;
+        if (j + 1 == steps) {   // no room for another basis vector
+            if (tid == 0)
+                theta_s = tridiag_max_eig(al, be, j + 1);
+            __syncthreads();
             break;
-        prev = lam;
+        }
+        // w = B^T y, into basis row j + 1
+        double *w = basis + (size_t)(j + 1) * n;
+        if (tall)
+            cols_pass(y, w);
+        else
+            rows_pass(y, w);
+        __syncthreads();
+        // w -= sum_i (w . v_i) v_i over i <= j, twice
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int i = wave; i <= j; i += nwave) {
+                const double *vi = basis + (size_t)i * n;
+                double d = 0.0;
+                for (int e = lane; e < n; e += 64)
+                    d = fma(w[e], vi[e], d);
+                for (int off = 32; off > 0; off >>= 1)
+                    d += __shfl_down(d, off, 64);
+                if (lane == 0)
+                    coef[i] = d;
+            }
+            __syncthreads();
+            for (int e = tid; e < n; e += nth) {
+                double t = w[e];
+                for (int i = 0; i <= j; ++i)
+                    t = fma(-coef[i], basis[(size_t)i * n + e], t);
+                w[e] = t;
+            }
+            __syncthreads();
+        }
+        double b2 = 0.0;
+        for (int e = tid; e < n; e += nth)
+            b2 += w[e] * w[e];
+        const double beta = sqrt(block_sum(b2));
+        if (tid == 0) {
+            const double th = tridiag_max_eig(al, be, j + 1);
+            // converged: the largest Ritz value no longer grows, or w vanished
+            // (the Krylov space is invariant and th is exact)
+            if ((j > 0 && th - theta_s <= 1e-15 * th) || !(beta > 1e-14 * th))
+                stop_s = 1;
+            theta_s = th;
+            be[j + 1] = beta;
+        }
+        __syncthreads();
+        if (stop_s)
+            break;
+        // v_{j+1} = w / beta
+        for (int e = tid; e < n; e += nth) {
+            const double v = w[e] / beta;
+            x[e] = v;
+            w[e] = v;
+        }
+        __syncthreads();
     }
     if (tid == 0)
-        *n2 = lam;
+        *n2 = theta_s;
 }
 
 // Per-block partial sums of |F|^2 over the coefficients inside the region
@@ -1338,7 +1524,7 @@ __global__ void k_metric_final(const double *__restrict__ n2p, int n2count,
     if (ent_part) {
         a = 0.0;
     } else if (norm == LFRL_NORM_SPECTRAL) {
-        a = threadIdx.x == 0 ? n2p[n2count] : 0.0;  // the power iteration's value
+        a = threadIdx.x == 0 ? n2p[n2count] : 0.0;  // the Lanczos value
     } else if (norm == LFRL_NORM_REGION) {
         for (int i = threadIdx.x; i < ncoef; i += blockDim.x) {
             const double f = Fabs[i];
@@ -1932,6 +2118,8 @@ struct lfrl_plan_s {
     size_t resident = 0, workspace = 0;
     float2 *Gf = nullptr, *Gb = nullptr, *tw = nullptr;  // natural spectra (plan build only)
     float4 *Ff = nullptr, *Fb = nullptr;                 // FP32 spectra in fragment order
+    float2 *Hx = nullptr;  // FP32: row xc of the adjoint spectra, [k][KKb] (xc >= 0)
+    float2 *Gx = nullptr;  // FP32: column xcol of the forward spectra, [k][KKs] (xcol >= 0)
     float2 *X = nullptr, *Yp = nullptr, *Rs = nullptr;
     float *psf = nullptr;  // resident copy of the PSF set (weak-voxel sums)
     Frame fr;              // frame state of lfrl_deconvolve (sized for max_h x max_w)
@@ -2128,8 +2316,8 @@ static bool u_ok(int u) { return u == 1 || u == 2 || u == 4; }
 
 static void default_shapes(const Geo &g, int *fcb, int *fu, int *acb, int *au)
 {
-    // measured at Nnum 15 (15 column blocks): 4 blocks per wave, 4 waves
-    const int ncb = g.NNp / 16;
+    // measured at Nnum 15 (14 matrix-core column blocks): 4 blocks per wave, 4 waves
+    const int ncb = g.NNm / 16;
     int cb = std::max(2, std::min(5, (ncb + 3) / 4));
     while (cb < 5 && (ncb + cb - 1) / cb > 8)
         ++cb;
@@ -2241,9 +2429,11 @@ static void frame_bind(Frame &f, const Geo &g, int h, int w, void *block, const 
 struct Sizes {
     size_t Gf, Gb, tw, psf, X, Yp, Rs, frame;  // Gf, Gb: natural layouts, plan build only
     size_t Ff = 0, Fb = 0;                      // FP32 fragment-ordered spectra
+    size_t Hx = 0;                              // FP32: spectra row of the lone adjoint index
+    size_t Gx = 0;                              // FP32: spectra column of the lone output column
     size_t Hf = 0, Hb = 0, gexp = 0, rowmax = 0;  // split FP16 only
     bool split = false;
-    size_t resident() const { return (split ? Hf + Hb + gexp : Ff + Fb) + tw + psf; }
+    size_t resident() const { return (split ? Hf + Hb + gexp : Ff + Fb) + Hx + Gx + tw + psf; }
     size_t workspace() const { return X + Yp + Rs + 2 * rowmax + frame; }
 };
 
@@ -2253,8 +2443,10 @@ static Sizes sizes_for(const Geo &g, int max_h, int max_w, int max_batch, int sp
     Sizes s;
     s.Gf = (size_t)g.nf * g.NNp * g.KK * sizeof(float2);
     s.Gb = (size_t)g.nf * g.NN * g.KK * sizeof(float2);
-    s.Ff = (size_t)g.nf * g.KKs * g.NNp * sizeof(float2);
-    s.Fb = (size_t)g.nf * g.NCp * g.KKb * sizeof(float2);
+    s.Ff = (size_t)g.nf * g.KKs * g.NNm * sizeof(float2);
+    s.Gx = g.xcol >= 0 ? (size_t)g.nf * g.KKs * sizeof(float2) : 0;
+    s.Fb = (size_t)g.nf * g.NCm * g.KKb * sizeof(float2);
+    s.Hx = g.xc >= 0 ? (size_t)g.nf * g.KKb * sizeof(float2) : 0;
     s.tw = (size_t)g.Q * sizeof(float2);
     s.X = (size_t)g.nf * nt * g.KKs * sizeof(float2);
     s.Yp = (size_t)split * g.nf * nt * g.NN * sizeof(float2);
@@ -2264,8 +2456,8 @@ static Sizes sizes_for(const Geo &g, int max_h, int max_w, int max_batch, int sp
     s.frame = frame_layout(g, max_h, max_w, false, off);
     if (f16) {
         s.split = true;
-        s.Hf = (size_t)g.nf * g.KKs * g.NNp * sizeof(cplx16<_Float16>);
-        s.Hb = (size_t)g.nf * g.NNp * ((g.KK + 15) / 16 * 16) * sizeof(cplx16<_Float16>);
+        s.Hf = (size_t)g.nf * g.KKs * g.NNm * sizeof(cplx16<_Float16>);
+        s.Hb = (size_t)g.nf * g.NNm * ((g.KK + 15) / 16 * 16) * sizeof(cplx16<_Float16>);
         s.gexp = (size_t)g.nf * sizeof(int);
         s.rowmax = (size_t)g.nf * nt * sizeof(unsigned);
     }
@@ -2345,7 +2537,7 @@ static void free_plan(lfrl_plan_s *p)
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
-    void *bufs[] = {p->Gf, p->Gb, p->Ff, p->Fb, p->tw, p->X, p->Yp, p->Rs, p->psf,
+    void *bufs[] = {p->Gf, p->Gb, p->Ff, p->Fb, p->Hx, p->Gx, p->tw, p->X, p->Yp, p->Rs, p->psf,
                     p->Hf, p->Hb, p->gexp, p->xmax, p->rmax};
     for (void *b : bufs)
         if (b)
@@ -2566,7 +2758,7 @@ static int plan_build(lfrl_plan_s **out, const lfrl_plan_desc *desc, int q, cons
     }
     {
         // split FP16 shapes; tuning override LFRL_CONTRACT_SHAPE_F16="fcb,fu,acb,au"
-        const int ncb = g.NNp / 16;
+        const int ncb = g.NNm / 16;
         p->hfwd_cb = ncb > 8 ? 2 : 1;
         if ((ncb + p->hfwd_cb - 1) / p->hfwd_cb > 8)
             p->hfwd_cb = 3;
@@ -2600,6 +2792,10 @@ static int plan_build(lfrl_plan_s **out, const lfrl_plan_desc *desc, int q, cons
         TRY(dalloc(&p->Ff, s.Ff));
         TRY(dalloc(&p->Fb, s.Fb));
     }
+    if (s.Hx)
+        TRY(dalloc(&p->Hx, s.Hx));
+    if (s.Gx)
+        TRY(dalloc(&p->Gx, s.Gx));
     TRY(dalloc(&p->tw, s.tw));
     TRY(dalloc(&p->X, s.X));
     TRY(dalloc(&p->Yp, s.Yp));
@@ -2631,6 +2827,10 @@ static int plan_build(lfrl_plan_s **out, const lfrl_plan_desc *desc, int q, cons
             e = p->split ? hipMemsetAsync(p->Hf, 0, s.Hf, st) : hipMemsetAsync(p->Ff, 0, s.Ff, st);
         if (e == hipSuccess)
             e = p->split ? hipMemsetAsync(p->Hb, 0, s.Hb, st) : hipMemsetAsync(p->Fb, 0, s.Fb, st);
+        if (e == hipSuccess && s.Hx)
+            e = hipMemsetAsync(p->Hx, 0, s.Hx, st);
+        if (e == hipSuccess && s.Gx)
+            e = hipMemsetAsync(p->Gx, 0, s.Gx, st);
         if (e == hipSuccess && p->split)
             e = hipMemsetAsync(p->gexp, 0, s.gexp, st);
         if (e == hipSuccess)
@@ -2676,28 +2876,43 @@ static int plan_build(lfrl_plan_s **out, const lfrl_plan_desc *desc, int q, cons
         const size_t nhf = s.Hf / sizeof(cplx16<_Float16>), nhb = s.Hb / sizeof(cplx16<_Float16>);
         if (p->bf16) {
             hipLaunchKernelGGL(k_pack_fwd_split<PrecBF16>, dim3(8192), dim3(256), 0, st,
-                               (const float2 *)p->Gf, g.KK, g.NNp, g.KKs / 32,
+                               (const float2 *)p->Gf, g.KK, g.NNp, g.NNm / 16, g.KKs / 32,
                                (const int *)p->gexp, (cplx16<__bf16> *)p->Hf, nhf);
             hipLaunchKernelGGL(k_pack_adj_split<PrecBF16>, dim3(8192), dim3(256), 0, st,
-                               (const float2 *)p->Gb, g.NN, g.KK, g.NNp / 16, (g.KK + 15) / 16,
+                               (const float2 *)p->Gb, g.NN, g.KK, g.NNm / 16, (g.KK + 15) / 16,
                                (const int *)p->gexp, (cplx16<__bf16> *)p->Hb, nhb);
         } else {
             hipLaunchKernelGGL(k_pack_fwd_split<PrecF16>, dim3(8192), dim3(256), 0, st,
-                               (const float2 *)p->Gf, g.KK, g.NNp, g.KKs / 32,
+                               (const float2 *)p->Gf, g.KK, g.NNp, g.NNm / 16, g.KKs / 32,
                                (const int *)p->gexp, p->Hf, nhf);
             hipLaunchKernelGGL(k_pack_adj_split<PrecF16>, dim3(8192), dim3(256), 0, st,
-                               (const float2 *)p->Gb, g.NN, g.KK, g.NNp / 16, (g.KK + 15) / 16,
+                               (const float2 *)p->Gb, g.NN, g.KK, g.NNm / 16, (g.KK + 15) / 16,
                                (const int *)p->gexp, p->Hb, nhb);
         }
         e = hipGetLastError();
     } else if (e == hipSuccess) {
         // FP32 fragments
         hipLaunchKernelGGL(k_pack_fwd_f32, dim3(8192), dim3(256), 0, st, (const float2 *)p->Gf,
-                           g.KK, g.NNp, g.KKs, p->Ff, s.Ff / sizeof(float4));
+                           g.KK, g.NNp, g.NNm / 16, g.KKs, p->Ff, s.Ff / sizeof(float4));
         hipLaunchKernelGGL(k_pack_adj_f32, dim3(8192), dim3(256), 0, st, (const float2 *)p->Gb,
-                           g.NN, g.KK, g.NCp, g.KKb, p->adj_cb * kAdjWaves, p->Fb,
+                           g.NN, g.KK, g.NCm, g.KKb, p->adj_cb * kAdjWaves, p->Fb,
                            s.Fb / sizeof(float4));
         e = hipGetLastError();
+    }
+    // float32 row / column of the lone indices (both precisions)
+    if (e == hipSuccess && s.Gx) {
+        hipLaunchKernelGGL(k_spec_column, dim3(2048), dim3(256), 0, st, (const float2 *)p->Gf, g.KK,
+                           g.NNp, g.KKs, g.xcol, p->Gx, (size_t)g.nf * g.KKs);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && s.Hx) {
+        // Hx[k][kk] = Gb[k][xc][kk], zero past KK
+        e = hipMemsetAsync(p->Hx, 0, s.Hx, st);
+        if (e == hipSuccess)
+            e = hipMemcpy2DAsync(p->Hx, (size_t)g.KKb * sizeof(float2),
+                                 p->Gb + (size_t)g.xc * g.KK, (size_t)g.NN * g.KK * sizeof(float2),
+                                 (size_t)g.KK * sizeof(float2), (size_t)g.nf,
+                                 hipMemcpyDeviceToDevice, st);
     }
     if (e == hipSuccess)
         e = hipStreamSynchronize(st);
@@ -2825,8 +3040,9 @@ static int prof_event(lfrl_plan_s *p, int which, hipStream_t st)
 #define LFRL_FWD_CASE(CBV, UV)                                                                   \
     if (p->fwd_cb == CBV && p->fwd_u == UV) {                                                    \
         hipLaunchKernelGGL((k_contract_fwd<CBV, UV>), grid, block, 0, st, (const float4 *)p->Ff, \
-                           (const float2 *)p->X, p->Yp, g.NN, g.NNp, g.KK, g.KKs, nt, g.nf,     \
-                           kchunk, skip, freq_map(g.Q));                                         \
+                           (const float2 *)p->X, p->Yp, g.NN, g.NNm, g.KK, g.KKs, nt, g.nf,     \
+                           kchunk, skip, freq_map(g.Q),                                          \
+                           (const float4 *)(p->Gx ? p->Gx : (float2 *)p->Ff), g.xcol);           \
         launched = true;                                                                         \
     }
 #define LFRL_FWD_CASES(CBV) LFRL_FWD_CASE(CBV, 1) LFRL_FWD_CASE(CBV, 2) LFRL_FWD_CASE(CBV, 4)
@@ -2834,7 +3050,8 @@ static int prof_event(lfrl_plan_s *p, int which, hipStream_t st)
     if (p->adj_cb == CBV && p->adj_u == UV) {                                                    \
         hipLaunchKernelGGL((k_contract_adj<CBV, UV>), grid, dim3(64 * kAdjWaves), lds, st,       \
                            (const float4 *)p->Fb, (const float2 *)p->Rs, p->X, g.NN, g.KK,      \
-                           g.KKs, g.NCp, nt, ranges, skip, freq_map(g.Q));                       \
+                           g.KKs, g.NCm, nt, ranges, skip, freq_map(g.Q), (const float2 *)p->Hx, \
+                           g.xc, g.KKb);                                                         \
         launched = true;                                                                         \
     }
 #define LFRL_ADJ_CASES(CBV) LFRL_ADJ_CASE(CBV, 1) LFRL_ADJ_CASE(CBV, 2) LFRL_ADJ_CASE(CBV, 4)
@@ -2916,7 +3133,7 @@ static int run_forward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipSt
         kchunk = (kchunk + 31) / 32 * 32;
     const int split2 = (g.KK + kchunk - 1) / kchunk;
     const int fcb = p->split ? p->hfwd_cb : p->fwd_cb;
-    const int nwaves = (g.NNp / 16 + fcb - 1) / fcb;
+    const int nwaves = (g.NNm / 16 + fcb - 1) / fcb;
     const dim3 grid(unique_freqs(g.Q), split2, (nt + 15) / 16);
     const dim3 block(64 * nwaves);
     if (p->prof) {
@@ -2929,8 +3146,9 @@ static int run_forward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipSt
 #define LFRL_HFWD_LAUNCH(PT, CBV, UV)                                                            \
     hipLaunchKernelGGL((k_contract_fwd_split<PT, CBV, UV>), grid, block, 0, st,                  \
                        (const cplx16<PT::S> *)p->Hf, (const float2 *)p->X,                       \
-                       (const unsigned *)p->xmax, (const int *)p->gexp, p->Yp, g.NN, g.NNp,     \
-                       g.KK, g.KKs, g.KKs / 32, nt, g.nf, kchunk, skip, freq_map(g.Q))
+                       (const unsigned *)p->xmax, (const int *)p->gexp, p->Yp, g.NN, g.NNm,     \
+                       g.KK, g.KKs, g.KKs / 32, nt, g.nf, kchunk, skip, freq_map(g.Q),          \
+                       (const float2 *)(p->Gx ? p->Gx : (float2 *)p->X), g.xcol)
 #define LFRL_HFWD_CASE(CBV, UV)                                                                  \
     if (p->hfwd_cb == CBV && p->hfwd_u == UV) {                                                  \
         if (p->bf16)                                                                             \
@@ -3007,9 +3225,9 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
     // FP32: rows of R staged in LDS, an even number of register groups of
     // 8 * adj_u reduction indices (as the kernel assumes), row stride kRsStride
     const int ustep = 8 * p->adj_u;
-    const int agroups = ((g.NCp + ustep - 1) / ustep + 1) / 2 * 2;
+    const int agroups = ((g.NCm + ustep - 1) / ustep + 1) / 2 * 2;
     // split: 16-c chunks of hi/lo R values, 2 KB each (split_adj_chunks)
-    const size_t lds = p->split ? (size_t)split_adj_chunks(g.NNp / 16, p->hadj_u) * 64 * 16 * 2
+    const size_t lds = p->split ? (size_t)split_adj_chunks(g.NNm / 16, p->hadj_u) * 64 * 16 * 2
                                 : (size_t)agroups * ustep * kRsStride * sizeof(float2);
     if (p->prof) {
         int rc = prof_event(p, 1, st);
@@ -3021,8 +3239,9 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
 #define LFRL_HADJ_LAUNCH(PT, CBV, UV)                                                            \
     hipLaunchKernelGGL((k_contract_adj_split<PT, CBV, UV>), grid, dim3(64 * kAdjWaves), lds, st, \
                        (const cplx16<PT::S> *)p->Hb, (const float2 *)p->Rs,                      \
-                       (const unsigned *)p->rmax, (const int *)p->gexp, p->X, g.NN, g.NNp,      \
-                       g.KK, g.KKs, (g.KK + 15) / 16, nt, skip, freq_map(g.Q))
+                       (const unsigned *)p->rmax, (const int *)p->gexp, p->X, g.NN, g.NNm,      \
+                       g.KK, g.KKs, (g.KK + 15) / 16, nt, skip, freq_map(g.Q),                   \
+                       (const float2 *)p->Hx, g.xcol, g.KKb)
 #define LFRL_HADJ_CASE(CBV, UV)                                                                  \
     if (p->hadj_cb == CBV && p->hadj_u == UV) {                                                  \
         if (p->bf16)                                                                             \
@@ -3168,9 +3387,8 @@ static constexpr int kSmallMetricPixels = 8192;
 static constexpr int kSmallMetricRows = 1024;
 static constexpr int kSmallMetricCoefs = 512;
 static constexpr size_t kSmallCopyVoxels = 65536;
-// Spectral norm: power iterations at most, and the image size its one block
-// holds (two float64 vectors of h and w in LDS).
-static constexpr int kSpectralMaxIters = 500;
+// Spectral norm: the image size its one block holds (two float64 vectors of h
+// and w in LDS).
 static constexpr int kSpectralMaxSides = 6144;
 
 // Row chunks of the leg-limited row transform: chunks of about 16 rows, as
@@ -3241,8 +3459,14 @@ static int run_metric(int nz, int h, int w, const float *vol, double xs, double 
     LAUNCH_CHECK("k_mip");
     if (norm == LFRL_NORM_SPECTRAL) {
         // sigma_1^2 of the projection into the slot after the Parseval partials
+        // the Lanczos basis lives in T1 (free until the row transform): at
+        // least kMetricChunks * min(h, 256) * w doubles in every metric scratch
+        const size_t cap = std::max((size_t)kMetricChunks * std::min(h, kMaxMetricLegs) * w,
+                                    (size_t)h * w);
+        const int nside = std::min(h, w);
+        const int steps = (int)std::min<size_t>(kLanczosMaxSteps, cap / nside);
         hipLaunchKernelGGL(k_spectral_norm, dim3(1), dim3(1024), (size_t)(h + w) * sizeof(double),
-                           st, (const float *)mb.mip, h, w, kSpectralMaxIters, mb.n2p + nblk);
+                           st, (const float *)mb.mip, h, w, steps, mb.T1, mb.n2p + nblk);
         LAUNCH_CHECK("k_spectral_norm");
     }
     const int ncoef = nv * nu;

@@ -40,9 +40,10 @@ def test_footprint_and_cutoff_without_gpu():
     res, ws = lf.lfrl_plan_footprint(d)
     nf = 28 * 15
     kk = 225 * 31
-    # both layouts in MFMA fragment order: forward [kk padded to 6976][c padded to 240],
-    # adjoint [c padded to 232][kk padded to 6976]
-    spec = nf * 6976 * 240 * 8 + nf * 232 * 6976 * 8
+    # both layouts in MFMA fragment order, each over the 224 matrix-core indices of
+    # c (forward [kk padded to 6976][c], adjoint [c][kk padded to 6976]), plus
+    # the column / row of the lone index c = 224 (summed on the vector ALU)
+    spec = nf * 6976 * 224 * 8 + nf * 224 * 6976 * 8 + 2 * nf * 6976 * 8
     psf_copy = 31 * 225 * 255 * 255 * 4     # the PSF kept for exact weak-voxel sums
     assert spec + psf_copy <= res < spec + psf_copy + 4096
     assert ws > nf * 16 * 225 * 31 * 8      # tile spectra of the volume

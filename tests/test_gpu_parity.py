@@ -53,6 +53,9 @@ GEOMS = [
     ("nonsquare-N3", 3, 5, 8, 2, 9, "rand", [0, 6]),
     ("nnum1", 1, 20, 17, 3, 7, "rand", [0, 9]),
     ("N15", 15, 4, 4, 2, 31, "gauss", [0]),
+    # Nnum^2 = 1 mod 16: the last lenslet position is contracted apart
+    ("N7", 7, 5, 6, 3, 21, "rand", [0, 9]),
+    ("N9", 9, 4, 5, 2, 27, "gauss", [0]),
     ("delta-N2", 2, 6, 7, 1, 1, "rand", [0, 3]),
 ]
 

@@ -41,6 +41,7 @@ PRECS = [pytest.param(1, id="fp16"), pytest.param(2, id="bf16")]
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n,ly,lx,nz,k,q", [(5, 11, 11, 5, 25, 0), (5, 11, 11, 5, 25, 10),
                                             (3, 7, 9, 3, 11, 0), (15, 4, 4, 2, 31, 0),
+                                            (7, 5, 6, 3, 21, 0), (9, 4, 5, 2, 27, 0),
                                             (1, 20, 17, 3, 7, 0)])
 def test_projections_split(lf, n, ly, lx, nz, k, q, prec):
     psf = S.gaussian_psf(n, nz, k, seed=40 + n, shift_scale=None)

@@ -202,8 +202,33 @@ def test_spectral_norm_in_the_loop(lf, problem):
     assert rep["best_iter"] == best
 
 
+@pytest.mark.parametrize("case", ["equal_top_pair", "rank_one", "tall", "wide", "zero"])
+def test_spectral_norm_hard_spectra(lf, case):
+    """The Lanczos spectral norm where the iteration is stressed: two equal
+    largest singular values, a rank-one image (the Krylov space closes after
+    one step), tall and wide images (the smaller side is iterated), and zero."""
+    rng = np.random.default_rng(7)
+    if case == "equal_top_pair":
+        img = np.zeros((120, 120))
+        img[10:40, 10:40] = 5.0
+        img[70:100, 70:100] = 5.0                 # block-diagonal: sigma_1 = sigma_2
+        img += 1e-3 * rng.uniform(size=img.shape)
+    elif case == "rank_one":
+        img = np.outer(rng.uniform(1, 2, 90), rng.uniform(1, 2, 70))
+    elif case == "tall":
+        img = rng.uniform(0, 1, (500, 40))
+    elif case == "wide":
+        img = rng.uniform(0, 1, (30, 700))
+    else:
+        img = np.zeros((64, 48))
+    img = img.astype(np.float32)
+    got = lf.metric(to_dev(img), 4.0, 3.0, region=lf.REGION_TRIANGLE, norm=lf.NORM_SPECTRAL)
+    want = oracle.metric(img[None], 4.0, 3.0, "triangle", "spectral")
+    assert got == pytest.approx(want, rel=1e-9, abs=1e-300)
+
+
 def test_spectral_norm_size_limit(lf):
-    """The one-block power iteration holds h + w values: larger images are
+    """The one-block Lanczos iteration holds h + w values: larger images are
     refused before any device work."""
     import torch
     out = torch.empty(1, dtype=torch.float64, device="cuda:0")
