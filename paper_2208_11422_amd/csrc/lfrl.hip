@@ -1010,8 +1010,11 @@ __global__ void k_dct_table(double *__restrict__ tab, int n, int nfreq)
 // z maximum projection m[r][s] = max_j vol[j][r][s] (sec. 2.2, Fig. 2(a)) with
 // per-block float64 partial sums of m^2 (Parseval: sum m^2 = ||F||_F^2).
 __global__ void k_mip(const float *__restrict__ vol, int nz, size_t hw, float *__restrict__ mip,
-                      double *__restrict__ n2p, const int *__restrict__ skip)
+                      double *__restrict__ n2p, const int *__restrict__ skip,
+                      unsigned *__restrict__ sync)
 {
+    if (sync && blockIdx.x == 0 && threadIdx.x < 2)
+        sync[threadIdx.x] = 0u;  // the multi-block spectral norm's exchange state
     if (skip && *skip)
         return;
     __shared__ double red[256];
@@ -1179,72 +1182,113 @@ __global__ __launch_bounds__(256) void k_dgemm32(const double *__restrict__ A, i
         }
 }
 
-// Largest singular value squared of the h x w image m: the largest
-// eigenvalue of A = B^T B, with B = m when w <= h and B = m^T otherwise (A of
-// side n = min(h, w)), by Lanczos iteration in float64 with full
-// reorthogonalisation, in one block.  Step j: y = B v_j (one wave per output
-// or one lane per output, both in a fixed order), w = B^T y, alpha_j = |y|^2
-// (= v_j . A v_j); w is orthogonalised twice against v_0 .. v_j (classical
-// Gram-Schmidt, one wave per dot product), beta_{j+1} = |w|; the largest
-// eigenvalue theta of the tridiagonal (alpha, beta) comes from bisection on
-// its Sturm sequence.  Stops once theta grows by at most 1e-15 of itself, w
-// vanishes (an invariant subspace: theta is exact), or after maxsteps steps
-// (the basis v_j is kept in `basis`, maxsteps x n doubles).  v_0 is a fixed
-// positive vector.  Dynamic LDS: (h + w) doubles.  *n2 = theta.
-__device__ double tridiag_max_eig(const double *al, const double *be, int k)
+// Largest eigenvalue of the symmetric tridiagonal with diagonal al[0..k) and
+// off-diagonal be[1..k), by multisection on one wave: Gershgorin bounds, then
+// rounds in which lane l counts the eigenvalues below lo + (l + 1)(hi - lo)/65
+// and the bracket shrinks to the two points around the largest one (about 9
+// rounds to double precision).  The count is the number of sign changes of the
+// characteristic polynomials of the leading submatrices (a Sturm sequence),
+// formed without divisions on the matrix scaled to unit Gershgorin radius;
+// a zero takes the sign opposite to its predecessor.  Every lane of the
+// calling wave takes part and returns the same value.
+__device__ double wave_max_eig(const double *al, const double *be, int k, int lane)
 {
-    // Gershgorin bounds, then bisection: count(x) = eigenvalues below x
     double lo = 0.0, hi = 0.0;
     for (int i = 0; i < k; ++i) {
         const double r = (i > 0 ? fabs(be[i]) : 0.0) + (i + 1 < k ? fabs(be[i + 1]) : 0.0);
         lo = (i == 0) ? al[i] - r : fmin(lo, al[i] - r);
         hi = (i == 0) ? al[i] + r : fmax(hi, al[i] + r);
     }
-    for (int it = 0; it < 200 && hi - lo > 1e-17 * fabs(hi); ++it) {
-        const double x = 0.5 * (lo + hi);
-        int below = 0;
-        double d = 1.0;
-        for (int i = 0; i < k; ++i) {
-            d = al[i] - x - (i > 0 ? be[i] * be[i] / d : 0.0);
-            if (d == 0.0)
-                d = -1e-300;
-            below += d < 0.0;
+    const double amax = fmax(fabs(lo), fabs(hi));
+    if (!(amax > 0.0))
+        return 0.0;  // the zero matrix
+    const double sc = 1.0 / amax;
+    for (int round = 0; round < 40 && hi - lo > 1e-16 * fabs(hi); ++round) {
+        const double step = (hi - lo) / 65.0;
+        const double x = (lo + step * (double)(lane + 1)) * sc;
+        double p0 = 1.0, p1 = al[0] * sc - x;
+        int s1 = p1 > 0.0 ? 1 : -1;   // sign of p1 (a zero: opposite of p0 > 0)
+        int below = s1 < 0;
+        for (int i = 1; i < k; ++i) {
+            const double b = be[i] * sc;
+            double p2 = fma(al[i] * sc - x, p1, -(b * b) * p0);
+            const int s2 = p2 > 0.0 ? 1 : (p2 < 0.0 ? -1 : -s1);
+            below += s2 != s1;
+            // keep the pair in range (the ratio is what counts)
+            const double mag = fmax(fabs(p2), fabs(p1));
+            if (mag > 1e150) {
+                p2 *= 1e-150;
+                p1 *= 1e-150;
+            } else if (mag < 1e-150) {
+                p2 *= 1e150;
+                p1 *= 1e150;
+            }
+            p0 = p1;
+            p1 = p2;
+            s1 = s2;
         }
-        if (below == k)   // every eigenvalue is below x
-            hi = x;
-        else
-            lo = x;
+        // lanes whose point lies above every eigenvalue (monotone in the lane)
+        const unsigned long long above = __ballot(below == k);
+        const int f = above ? __ffsll((long long)above) - 1 : 64;
+        const double nlo = f > 0 ? lo + step * (double)f : lo;
+        const double nhi = f < 64 ? lo + step * (double)(f + 1) : hi;
+        if (!(nhi - nlo < hi - lo))
+            break;  // the bracket no longer shrinks in double precision
+        lo = nlo;
+        hi = nhi;
     }
     return hi;
 }
 
+// Largest singular value squared of the h x w image m: the largest eigenvalue
+// of A = B^T B, with B = m when w <= h and B = m^T otherwise (A of side
+// n = min(h, w)), by Lanczos iteration in float64, in one block.  Step j:
+// y = B v_j (one wave per 4 rows or one lane per column, in a fixed order),
+// alpha_j = |y|^2 (= v_j . A v_j), w = B^T y - alpha_j v_j - beta_j v_{j-1},
+// then once more orthogonalised against v_j and v_{j-1}; beta_{j+1} = |w|,
+// v_{j+1} = w / beta_{j+1}.  No orthogonalisation against older vectors: the
+// largest Ritz value converges to the largest eigenvalue all the same (a lost
+// orthogonality only adds copies of converged values).  The largest eigenvalue
+// theta of the tridiagonal (alpha, beta) comes from wave_max_eig.  Stops once
+// theta grows by at most 1e-15 of itself, w vanishes (an invariant subspace:
+// theta is exact), or after maxsteps steps.  v_0 is a fixed positive vector.
+// Dynamic LDS: (3 n + max(h, w)) doubles.  *n2 = theta.
 static constexpr int kLanczosMaxSteps = 48;
 
 __global__ __launch_bounds__(1024) void k_spectral_norm(const float *__restrict__ m, int H, int W,
-                                                        int maxsteps, double *__restrict__ basis,
+                                                        int maxsteps, const int *__restrict__ skip,
                                                         double *__restrict__ n2)
 {
+    if (skip && *skip)
+        return;
     extern __shared__ double sv[];
-    __shared__ double red[1024];
-    __shared__ double al[kLanczosMaxSteps + 1], be[kLanczosMaxSteps + 1], coef[kLanczosMaxSteps];
+    __shared__ double red[2][16];
+    __shared__ double al[kLanczosMaxSteps + 1], be[kLanczosMaxSteps + 1];
     __shared__ double theta_s;
     __shared__ int stop_s;
     const int tid = threadIdx.x, nth = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwave = nth >> 6;
     const bool tall = W <= H;             // A = m^T m (side W) or m m^T (side H)
     const int n = tall ? W : H, mo = tall ? H : W;
-    double *x = sv, *y = sv + n;          // x: v_j (n), y: B v_j (mo)
-    auto block_sum = [&](double a) -> double {
-        red[tid] = a;
-        __syncthreads();
-        for (int off = nth / 2; off > 0; off >>= 1) {
-            if (tid < off)
-                red[tid] += red[tid + off];
-            __syncthreads();
+    double *x = sv, *xp = sv + n, *w = sv + 2 * n, *y = sv + 3 * n;  // v_j, v_{j-1}, w, B v_j
+    // two block sums at once: wave sums by shuffles, then the waves in order
+    auto block_sum2 = [&](double a, double c, double &ra, double &rc) {
+        for (int off = 32; off > 0; off >>= 1) {
+            a += __shfl_xor(a, off, 64);
+            c += __shfl_xor(c, off, 64);
         }
-        const double r = red[0];
+        if (lane == 0) {
+            red[0][wave] = a;
+            red[1][wave] = c;
+        }
         __syncthreads();
-        return r;
+        ra = red[0][0];
+        rc = red[1][0];
+        for (int q = 1; q < nwave; ++q) {
+            ra += red[0][q];
+            rc += red[1][q];
+        }
+        __syncthreads();
     };
     // rows pass: out[r] = sum_s m[r][s] in[s], a wave per 4 rows at a time
     // (16 loads in flight per lane: the pass is bound by memory latency)
@@ -1260,10 +1304,10 @@ __global__ __launch_bounds__(1024) void k_spectral_norm(const float *__restrict_
                         v4[q][b] = m[(size_t)min(r0 + q, H - 1) * W + min(s0 + 64 * b, W - 1)];
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
-                    const double x = s0 + 64 * b < W ? in[min(s0 + 64 * b, W - 1)] : 0.0;
+                    const double xv = s0 + 64 * b < W ? in[min(s0 + 64 * b, W - 1)] : 0.0;
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
-                        acc[q] = fma((double)v4[q][b], x, acc[q]);
+                        acc[q] = fma((double)v4[q][b], xv, acc[q]);
                 }
             }
 #pragma unroll
@@ -1296,18 +1340,19 @@ __global__ __launch_bounds__(1024) void k_spectral_norm(const float *__restrict_
             out[s] = acc;
         }
     };
-    // v_0: fixed positive vector, unit length
+    // v_0: fixed positive vector, unit length; v_{-1} = 0
     double c = 0.0;
     for (int i = tid; i < n; i += nth) {
         const double v = 1.0 + (double)((unsigned)(i + 1) * 2654435761u % 1024u) / 2048.0;
         x[i] = v;
+        xp[i] = 0.0;
         c += v * v;
     }
-    const double n0 = sqrt(block_sum(c));
-    for (int i = tid; i < n; i += nth) {
+    double n0, unused;
+    block_sum2(c, 0.0, n0, unused);
+    n0 = sqrt(n0);
+    for (int i = tid; i < n; i += nth)
         x[i] /= n0;
-        basis[i] = x[i];
-    }
     if (tid == 0) {
         theta_s = 0.0;
         stop_s = 0;
@@ -1325,69 +1370,281 @@ __global__ __launch_bounds__(1024) void k_spectral_norm(const float *__restrict_
         double a = 0.0;
         for (int i = tid; i < mo; i += nth)
             a += y[i] * y[i];
-        const double alpha = block_sum(a);
+        double alpha;
+        block_sum2(a, 0.0, alpha, unused);
         if (tid == 0)
             al[j] = alpha;
+        __syncthreads();
         if (j + 1 == steps) {   // no room for another basis vector
-            if (tid == 0)
-                theta_s = tridiag_max_eig(al, be, j + 1);
+            if (wave == 0) {
+                const double th = wave_max_eig(al, be, j + 1, lane);
+                if (lane == 0)
+                    theta_s = th;
+            }
             __syncthreads();
             break;
         }
-        // w = B^T y, into basis row j + 1
-        double *w = basis + (size_t)(j + 1) * n;
+        // w = B^T y - alpha v_j - beta_j v_{j-1}
         if (tall)
             cols_pass(y, w);
         else
             rows_pass(y, w);
         __syncthreads();
-        // w -= sum_i (w . v_i) v_i over i <= j, twice
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int i = wave; i <= j; i += nwave) {
-                const double *vi = basis + (size_t)i * n;
-                double d = 0.0;
-                for (int e = lane; e < n; e += 64)
-                    d = fma(w[e], vi[e], d);
-                for (int off = 32; off > 0; off >>= 1)
-                    d += __shfl_down(d, off, 64);
-                if (lane == 0)
-                    coef[i] = d;
-            }
-            __syncthreads();
-            for (int e = tid; e < n; e += nth) {
-                double t = w[e];
-                for (int i = 0; i <= j; ++i)
-                    t = fma(-coef[i], basis[(size_t)i * n + e], t);
-                w[e] = t;
-            }
-            __syncthreads();
+        const double bj = be[j];
+        double c0 = 0.0, c1 = 0.0;
+        for (int e = tid; e < n; e += nth) {
+            const double t = w[e] - alpha * x[e] - bj * xp[e];
+            w[e] = t;
+            c0 = fma(t, x[e], c0);
+            c1 = fma(t, xp[e], c1);
         }
+        double d0, d1;
+        block_sum2(c0, c1, d0, d1);
         double b2 = 0.0;
-        for (int e = tid; e < n; e += nth)
-            b2 += w[e] * w[e];
-        const double beta = sqrt(block_sum(b2));
-        if (tid == 0) {
-            const double th = tridiag_max_eig(al, be, j + 1);
+        for (int e = tid; e < n; e += nth) {
+            const double t = w[e] - d0 * x[e] - d1 * xp[e];
+            w[e] = t;
+            b2 = fma(t, t, b2);
+        }
+        double bb;
+        block_sum2(b2, 0.0, bb, unused);
+        const double beta = sqrt(bb);
+        if (wave == 0) {
+            const double th = wave_max_eig(al, be, j + 1, lane);
             // converged: the largest Ritz value no longer grows, or w vanished
             // (the Krylov space is invariant and th is exact)
-            if ((j > 0 && th - theta_s <= 1e-15 * th) || !(beta > 1e-14 * th))
-                stop_s = 1;
-            theta_s = th;
-            be[j + 1] = beta;
+            if (lane == 0) {
+                if ((j > 0 && th - theta_s <= 1e-15 * th) || !(beta > 1e-14 * th))
+                    stop_s = 1;
+                theta_s = th;
+                be[j + 1] = beta;
+            }
         }
         __syncthreads();
         if (stop_s)
             break;
-        // v_{j+1} = w / beta
+        // v_{j-1} = v_j, v_{j+1} = w / beta
         for (int e = tid; e < n; e += nth) {
-            const double v = w[e] / beta;
-            x[e] = v;
-            w[e] = v;
+            xp[e] = x[e];
+            x[e] = w[e] / beta;
         }
         __syncthreads();
     }
     if (tid == 0)
         *n2 = theta_s;
+}
+
+// The same Lanczos iteration over many blocks, for images that one block
+// would stream too slowly at each step.  A = m^T m throughout (vectors of
+// length W).  Block b keeps rows [b rpb, (b + 1) rpb) of m in LDS and forms,
+// for its rows, y_r = m_r . v_j, its share sum_r y_r^2 of alpha_j and its
+// partial sum_r y_r m_r of A v_j (each wave over rows wave, wave + 4, ...;
+// the four wave sums in wave order).  One grid-wide exchange per step: every
+// block then adds all partials in block order and carries out the rest of the
+// step (the recurrence, beta, the Ritz value, the stop test) on identical
+// data, so all blocks reach the same decisions.  Needs all blocks resident at
+// once (few blocks, one per CU at most by their LDS); a wait that does not end
+// within a bounded number of polls marks the call failed and its result NaN
+// instead of hanging.
+// ws: [64 doubles: arrival count, failure flag (zeroed by k_mip)]
+//     [2][nb][W + 1] partials, by step parity.
+// Dynamic LDS: 7 W doubles + rpb W floats.
+static constexpr unsigned kSpinLimit = 1u << 20;
+
+template <int KW>
+__global__ __launch_bounds__(256) void k_spectral_norm_mb(const float *__restrict__ m, int H, int W,
+                                                          int rpb, int maxsteps, double *ws,
+                                                          const int *__restrict__ skip,
+                                                          double *__restrict__ n2)
+{
+    if (skip && *skip)
+        return;
+    extern __shared__ double lds[];
+    __shared__ double red2[2][4];
+    __shared__ double al[kLanczosMaxSteps + 1], be[kLanczosMaxSteps + 1];
+    __shared__ double aw_s[4], theta_s, alpha_s;
+    __shared__ int stop_s, fail_s;
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    unsigned *sync = reinterpret_cast<unsigned *>(ws);
+    double *part = ws + 64;
+    double *v = lds, *vp = lds + W, *wv = lds + 2 * W, *red = lds + 3 * W;  // red: [4][W]
+    float *ms = reinterpret_cast<float *>(lds + 7 * W);                     // [rpb][W]
+    const int r0 = b * rpb, nr = max(0, min(H, r0 + rpb) - r0);
+    for (size_t i = tid; i < (size_t)nr * W; i += 256)
+        ms[i] = m[(size_t)r0 * W + i];
+    auto block_sum2 = [&](double a, double c, double &ra, double &rc) {
+        for (int off = 32; off > 0; off >>= 1) {
+            a += __shfl_xor(a, off, 64);
+            c += __shfl_xor(c, off, 64);
+        }
+        if (lane == 0) {
+            red2[0][wave] = a;
+            red2[1][wave] = c;
+        }
+        __syncthreads();
+        ra = ((red2[0][0] + red2[0][1]) + red2[0][2]) + red2[0][3];
+        rc = ((red2[1][0] + red2[1][1]) + red2[1][2]) + red2[1][3];
+        __syncthreads();
+    };
+    // v_0: the fixed positive vector of the one-block kernel, unit length
+    double c = 0.0;
+    for (int i = tid; i < W; i += 256) {
+        const double x = 1.0 + (double)((unsigned)(i + 1) * 2654435761u % 1024u) / 2048.0;
+        v[i] = x;
+        vp[i] = 0.0;
+        c += x * x;
+    }
+    double n0, unused;
+    block_sum2(c, 0.0, n0, unused);
+    n0 = sqrt(n0);
+    for (int i = tid; i < W; i += 256)
+        v[i] /= n0;
+    if (tid == 0) {
+        theta_s = 0.0;
+        stop_s = 0;
+        fail_s = 0;
+        be[0] = 0.0;
+    }
+    __syncthreads();
+    const int steps = max(1, min(maxsteps, kLanczosMaxSteps));
+    for (int j = 0; j < steps; ++j) {
+        // this block's rows: y_r, alpha share, partial A v_j (lane holds columns lane + 64 i)
+        double pw[KW];
+#pragma unroll
+        for (int i = 0; i < KW; ++i)
+            pw[i] = 0.0;
+        double aw = 0.0;
+        for (int r = wave; r < nr; r += 4) {
+            const float *row = ms + (size_t)r * W;
+            double d = 0.0;
+#pragma unroll
+            for (int i = 0; i < KW; ++i) {
+                const int cc = lane + 64 * i;
+                if (cc < W)
+                    d = fma((double)row[cc], v[cc], d);
+            }
+            // butterfly: every lane ends with the same sum
+            for (int off = 32; off > 0; off >>= 1)
+                d += __shfl_xor(d, off, 64);
+            aw = fma(d, d, aw);
+#pragma unroll
+            for (int i = 0; i < KW; ++i) {
+                const int cc = lane + 64 * i;
+                if (cc < W)
+                    pw[i] = fma(d, (double)row[cc], pw[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < KW; ++i) {
+            const int cc = lane + 64 * i;
+            if (cc < W)
+                red[(size_t)wave * W + cc] = pw[i];
+        }
+        if (lane == 0)
+            aw_s[wave] = aw;
+        __syncthreads();
+        double *pb = part + ((size_t)(j & 1) * nb + b) * (W + 1);
+        for (int e = tid; e < W; e += 256)
+            pb[e] = ((red[e] + red[W + e]) + red[2 * W + e]) + red[3 * W + e];
+        if (tid == 0)
+            pb[W] = ((aw_s[0] + aw_s[1]) + aw_s[2]) + aw_s[3];
+        // grid-wide exchange: release this block's partials, count in, wait
+        // for every block.  The other blocks' partials are then read with
+        // device-coherent loads, so no cache invalidation is needed.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (tid == 0) {
+            const unsigned target = (unsigned)nb * (unsigned)(j + 1);
+            __hip_atomic_fetch_add(sync, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            unsigned spins = 0;
+            while (__hip_atomic_load(sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                if (__hip_atomic_load(sync + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                    ++spins == kSpinLimit) {
+                    __hip_atomic_fetch_or(sync + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    fail_s = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __syncthreads();
+        if (fail_s)
+            break;
+        // A v_j and alpha_j: all partials, in block order (loads in batches of 8)
+        const double *pj = part + (size_t)(j & 1) * nb * (W + 1);
+        for (int e = tid; e <= W; e += 256) {
+            double a = 0.0;
+            for (int q0 = 0; q0 < nb; q0 += 8) {
+                double pv[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    pv[q] = __hip_atomic_load(pj + (size_t)min(q0 + q, nb - 1) * (W + 1) + e,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (q0 + q < nb)
+                        a += pv[q];
+            }
+            if (e < W)
+                wv[e] = a;
+            else
+                alpha_s = a;
+        }
+        __syncthreads();
+        const double alpha = alpha_s;
+        if (tid == 0)
+            al[j] = alpha;
+        __syncthreads();
+        if (j + 1 == steps) {  // no room for another basis vector
+            if (wave == 0) {
+                const double th = wave_max_eig(al, be, j + 1, lane);
+                if (lane == 0)
+                    theta_s = th;
+            }
+            __syncthreads();
+            break;
+        }
+        // w = A v_j - alpha v_j - beta_j v_{j-1}, once more against v_j, v_{j-1}
+        const double bj = be[j];
+        double c0 = 0.0, c1 = 0.0;
+        for (int e = tid; e < W; e += 256) {
+            const double t = wv[e] - alpha * v[e] - bj * vp[e];
+            wv[e] = t;
+            c0 = fma(t, v[e], c0);
+            c1 = fma(t, vp[e], c1);
+        }
+        double d0, d1;
+        block_sum2(c0, c1, d0, d1);
+        double b2 = 0.0;
+        for (int e = tid; e < W; e += 256) {
+            const double t = wv[e] - d0 * v[e] - d1 * vp[e];
+            wv[e] = t;
+            b2 = fma(t, t, b2);
+        }
+        double bb;
+        block_sum2(b2, 0.0, bb, unused);
+        const double beta = sqrt(bb);
+        if (wave == 0) {
+            const double th = wave_max_eig(al, be, j + 1, lane);
+            if (lane == 0) {
+                if ((j > 0 && th - theta_s <= 1e-15 * th) || !(beta > 1e-14 * th))
+                    stop_s = 1;
+                theta_s = th;
+                be[j + 1] = beta;
+            }
+        }
+        __syncthreads();
+        if (stop_s)
+            break;
+        for (int e = tid; e < W; e += 256) {
+            vp[e] = v[e];
+            v[e] = wv[e] / beta;
+        }
+        __syncthreads();
+    }
+    if (b == 0 && tid == 0)
+        *n2 = fail_s ? __builtin_nan("") : theta_s;
 }
 
 // Per-block partial sums of |F|^2 over the coefficients inside the region
@@ -3383,6 +3640,41 @@ static double region_area(int region, double xs, double ys, int h, int w)
 // Limits of the one-block metric (k_metric_small): image pixels, row-transform
 // values and candidate coefficients held in LDS (44 KB at most), and the
 // volume size up to which that block also copies the best iterate.
+// Launch shape of the multi-block spectral norm for an h x w image (nb = 0:
+// the one-block kernel instead).  Rows of the image are spread over at most
+// kSpecMaxBlocks blocks of 256 threads, each holding its rows in LDS next to
+// 7 w doubles of vectors; the exchange needs 64 + 2 nb (w + 1) doubles of T1.
+static constexpr int kSpecMaxBlocks = 32;
+static constexpr size_t kSpecLds = 120 * 1024;
+static constexpr size_t kSpecMinPixels = 16384;
+struct SpectralLaunch {
+    int nb, rpb, kw, steps;
+    size_t lds;
+};
+static SpectralLaunch spectral_launch(int h, int w, size_t t1cap)
+{
+    SpectralLaunch sp{};
+    if ((size_t)h * w < kSpecMinPixels || w > 64 * 32)
+        return sp;
+    const size_t vec = (size_t)7 * w * sizeof(double);
+    if (vec + (size_t)w * sizeof(float) > kSpecLds)
+        return sp;
+    const int rmax = (int)((kSpecLds - vec) / ((size_t)w * sizeof(float)));
+    const int nb = (h + rmax - 1) / rmax;
+    if (nb > kSpecMaxBlocks)
+        return sp;
+    const int rpb = (h + nb - 1) / nb;
+    if (t1cap < 64 + 2 * (size_t)nb * (w + 1))
+        return sp;
+    const size_t steps = kLanczosMaxSteps;
+    sp.nb = nb;
+    sp.rpb = rpb;
+    sp.kw = w <= 256 ? 4 : w <= 512 ? 8 : w <= 1024 ? 16 : 32;
+    sp.steps = (int)steps;
+    sp.lds = vec + (size_t)rpb * w * sizeof(float);
+    return sp;
+}
+
 static constexpr int kSmallMetricPixels = 8192;
 static constexpr int kSmallMetricRows = 1024;
 static constexpr int kSmallMetricCoefs = 512;
@@ -3455,19 +3747,43 @@ static int run_metric(int nz, int h, int w, const float *vol, double xs, double 
         return LFRL_OK;
     }
     const int nblk = (int)((hw + 255) / 256);
-    hipLaunchKernelGGL(k_mip, dim3(nblk), dim3(256), 0, st, vol, nz, hw, mb.mip, mb.n2p, skip);
+    // spectral norm: sigma_1^2 of the projection into the slot after the
+    // Parseval partials.  Its work space is T1 (free until the row
+    // transform): at least kMetricChunks * min(h, 256) * w doubles in every
+    // metric scratch.
+    const size_t t1cap = std::max((size_t)kMetricChunks * std::min(h, kMaxMetricLegs) * w,
+                                  (size_t)h * w);
+    SpectralLaunch sp{};
+    if (norm == LFRL_NORM_SPECTRAL)
+        sp = spectral_launch(h, w, t1cap);
+    hipLaunchKernelGGL(k_mip, dim3(nblk), dim3(256), 0, st, vol, nz, hw, mb.mip, mb.n2p, skip,
+                       sp.nb > 0 ? reinterpret_cast<unsigned *>(mb.T1) : nullptr);
     LAUNCH_CHECK("k_mip");
     if (norm == LFRL_NORM_SPECTRAL) {
-        // sigma_1^2 of the projection into the slot after the Parseval partials
-        // the Lanczos basis lives in T1 (free until the row transform): at
-        // least kMetricChunks * min(h, 256) * w doubles in every metric scratch
-        const size_t cap = std::max((size_t)kMetricChunks * std::min(h, kMaxMetricLegs) * w,
-                                    (size_t)h * w);
-        const int nside = std::min(h, w);
-        const int steps = (int)std::min<size_t>(kLanczosMaxSteps, cap / nside);
-        hipLaunchKernelGGL(k_spectral_norm, dim3(1), dim3(1024), (size_t)(h + w) * sizeof(double),
-                           st, (const float *)mb.mip, h, w, steps, mb.T1, mb.n2p + nblk);
-        LAUNCH_CHECK("k_spectral_norm");
+        if (sp.nb > 0) {
+#define LFRL_SPEC_MB(KWV)                                                                       \
+    if (sp.kw == KWV) {                                                                         \
+        static const hipError_t attr = hipFuncSetAttribute(                                     \
+            (const void *)k_spectral_norm_mb<KWV>, hipFuncAttributeMaxDynamicSharedMemorySize,  \
+            (int)kSpecLds);                                                                     \
+        (void)attr;                                                                             \
+        hipLaunchKernelGGL(k_spectral_norm_mb<KWV>, dim3(sp.nb), dim3(256), sp.lds, st,         \
+                           (const float *)mb.mip, h, w, sp.rpb, sp.steps, mb.T1, skip,           \
+                           mb.n2p + nblk);                                                       \
+    }
+            LFRL_SPEC_MB(4) LFRL_SPEC_MB(8) LFRL_SPEC_MB(16) LFRL_SPEC_MB(32)
+#undef LFRL_SPEC_MB
+            LAUNCH_CHECK("k_spectral_norm_mb");
+        } else {
+            const size_t lds = (size_t)(3 * std::min(h, w) + std::max(h, w)) * sizeof(double);
+            static const hipError_t attr = hipFuncSetAttribute(
+                (const void *)k_spectral_norm, hipFuncAttributeMaxDynamicSharedMemorySize,
+                (int)(2 * kSpectralMaxSides * sizeof(double)));
+            (void)attr;
+            hipLaunchKernelGGL(k_spectral_norm, dim3(1), dim3(1024), lds, st,
+                               (const float *)mb.mip, h, w, kLanczosMaxSteps, skip, mb.n2p + nblk);
+            LAUNCH_CHECK("k_spectral_norm");
+        }
     }
     const int ncoef = nv * nu;
     if (whole) {

@@ -202,25 +202,31 @@ def test_spectral_norm_in_the_loop(lf, problem):
     assert rep["best_iter"] == best
 
 
+@pytest.mark.parametrize("size", ["small", "large"])
 @pytest.mark.parametrize("case", ["equal_top_pair", "rank_one", "tall", "wide", "zero"])
-def test_spectral_norm_hard_spectra(lf, case):
+def test_spectral_norm_hard_spectra(lf, case, size):
     """The Lanczos spectral norm where the iteration is stressed: two equal
     largest singular values, a rank-one image (the Krylov space closes after
-    one step), tall and wide images (the smaller side is iterated), and zero."""
+    one step), tall and wide images, and zero.  Small images run the one-block
+    kernel, large ones (16384 pixels and up) the multi-block one."""
     rng = np.random.default_rng(7)
+    big = size == "large"
     if case == "equal_top_pair":
-        img = np.zeros((120, 120))
-        img[10:40, 10:40] = 5.0
-        img[70:100, 70:100] = 5.0                 # block-diagonal: sigma_1 = sigma_2
+        n = 240 if big else 120
+        img = np.zeros((n, n))
+        a, b = n // 12, n // 3
+        img[a:b, a:b] = 5.0
+        img[n - b:n - a, n - b:n - a] = 5.0       # block-diagonal: sigma_1 = sigma_2
         img += 1e-3 * rng.uniform(size=img.shape)
     elif case == "rank_one":
-        img = np.outer(rng.uniform(1, 2, 90), rng.uniform(1, 2, 70))
+        img = np.outer(rng.uniform(1, 2, 300 if big else 90), rng.uniform(1, 2, 250 if big else 70))
     elif case == "tall":
-        img = rng.uniform(0, 1, (500, 40))
+        img = rng.uniform(0, 1, (500, 40) if big else (200, 30))
     elif case == "wide":
-        img = rng.uniform(0, 1, (30, 700))
+        img = rng.uniform(0, 1, (30, 700) if big else (20, 300))
     else:
-        img = np.zeros((64, 48))
+        img = np.zeros((200, 160) if big else (64, 48))
+    assert (img.size >= 16384) == big
     img = img.astype(np.float32)
     got = lf.metric(to_dev(img), 4.0, 3.0, region=lf.REGION_TRIANGLE, norm=lf.NORM_SPECTRAL)
     want = oracle.metric(img[None], 4.0, 3.0, "triangle", "spectral")
