@@ -1011,10 +1011,13 @@ __global__ void k_dct_table(double *__restrict__ tab, int n, int nfreq)
 // per-block float64 partial sums of m^2 (Parseval: sum m^2 = ||F||_F^2).
 __global__ void k_mip(const float *__restrict__ vol, int nz, size_t hw, float *__restrict__ mip,
                       double *__restrict__ n2p, const int *__restrict__ skip,
-                      unsigned *__restrict__ sync)
+                      unsigned long long *__restrict__ zero, size_t nzero)
 {
-    if (sync && blockIdx.x == 0 && threadIdx.x < 2)
-        sync[threadIdx.x] = 0u;  // the multi-block spectral norm's exchange state
+    // the multi-block spectral norm's exchange words (zero: no valid tag),
+    // written through to device-coherent memory like the words themselves
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nzero;
+         i += (size_t)gridDim.x * blockDim.x)
+        __hip_atomic_store(zero + i, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (skip && *skip)
         return;
     __shared__ double red[256];
@@ -1182,56 +1185,85 @@ __global__ __launch_bounds__(256) void k_dgemm32(const double *__restrict__ A, i
         }
 }
 
+// Lane l's value of v, for every lane (l uniform).
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Largest eigenvalue of the symmetric tridiagonal with diagonal al[0..k) and
 // off-diagonal be[1..k), by multisection on one wave: Gershgorin bounds, then
 // rounds in which lane l counts the eigenvalues below lo + (l + 1)(hi - lo)/65
 // and the bracket shrinks to the two points around the largest one (about 9
-// rounds to double precision).  The count is the number of sign changes of the
+// rounds to a width of two units in the last place).  The count is the number of sign changes of the
 // characteristic polynomials of the leading submatrices (a Sturm sequence),
 // formed without divisions on the matrix scaled to unit Gershgorin radius;
-// a zero takes the sign opposite to its predecessor.  Every lane of the
-// calling wave takes part and returns the same value.
+// a zero takes the sign opposite to its predecessor.  Row i of the matrix
+// sits in lane i (k <= 64) and enters each Sturm step as scalar operands.
+// Every lane of the calling wave takes part and returns the same value.
 __device__ double wave_max_eig(const double *al, const double *be, int k, int lane)
 {
-    double lo = 0.0, hi = 0.0;
-    for (int i = 0; i < k; ++i) {
-        const double r = (i > 0 ? fabs(be[i]) : 0.0) + (i + 1 < k ? fabs(be[i + 1]) : 0.0);
-        lo = (i == 0) ? al[i] - r : fmin(lo, al[i] - r);
-        hi = (i == 0) ? al[i] + r : fmax(hi, al[i] + r);
+    // lane i < k holds row i: its Gershgorin interval, then its scaled entries
+    double glo = 1e308, ghi = -1e308;
+    double ai = 0.0, bi = 0.0;
+    if (lane < k) {
+        ai = al[lane];
+        bi = lane > 0 ? be[lane] : 0.0;
+        const double r = fabs(bi) + (lane + 1 < k ? fabs(be[lane + 1]) : 0.0);
+        glo = ai - r;
+        ghi = ai + r;
     }
+    for (int off = 32; off > 0; off >>= 1) {
+        glo = fmin(glo, __shfl_xor(glo, off, 64));
+        ghi = fmax(ghi, __shfl_xor(ghi, off, 64));
+    }
+    double lo = glo, hi = ghi;
     const double amax = fmax(fabs(lo), fabs(hi));
     if (!(amax > 0.0))
         return 0.0;  // the zero matrix
     const double sc = 1.0 / amax;
-    for (int round = 0; round < 40 && hi - lo > 1e-16 * fabs(hi); ++round) {
-        const double step = (hi - lo) / 65.0;
+    const double as = ai * sc, b2s = (bi * sc) * (bi * sc);
+    const double a0 = readlane_f64(as, 0);
+    for (int round = 0; round < 40 && hi - lo > 4e-16 * fabs(hi); ++round) {
+        const double step = (hi - lo) * (1.0 / 65.0);
         const double x = (lo + step * (double)(lane + 1)) * sc;
-        double p0 = 1.0, p1 = al[0] * sc - x;
-        int s1 = p1 > 0.0 ? 1 : -1;   // sign of p1 (a zero: opposite of p0 > 0)
-        int below = s1 < 0;
-        for (int i = 1; i < k; ++i) {
-            const double b = be[i] * sc;
-            double p2 = fma(al[i] * sc - x, p1, -(b * b) * p0);
-            const int s2 = p2 > 0.0 ? 1 : (p2 < 0.0 ? -1 : -s1);
-            below += s2 != s1;
-            // keep the pair in range (the ratio is what counts)
-            const double mag = fmax(fabs(p2), fabs(p1));
-            if (mag > 1e150) {
-                p2 *= 1e-150;
-                p1 *= 1e-150;
-            } else if (mag < 1e-150) {
-                p2 *= 1e150;
-                p1 *= 1e150;
-            }
+        double p0 = 1.0, p1 = a0 - x;
+        // n1: p1 negative (a zero takes the opposite sign of its predecessor,
+        // here p0 > 0); selects, no branches
+        int n1 = p1 <= 0.0;
+        int below = n1;
+        // row i's entries come from lane i (uniform: scalar operands)
+        auto sturm_step = [&](int i) {
+            const double a = readlane_f64(as, i), b2 = readlane_f64(b2s, i);
+            const double p2 = fma(a - x, p1, -b2 * p0);
+            const int n2 = p2 == 0.0 ? 1 - n1 : (int)(p2 < 0.0);
+            below += n2 ^ n1;
             p0 = p1;
             p1 = p2;
-            s1 = s2;
+            n1 = n2;
+        };
+        int i = 1;
+        for (; i + 4 <= k; i += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                sturm_step(i + u);
+            // keep the pair in range (the ratio is what counts); on the scaled
+            // matrix a step grows them at most threefold
+            const double mag = fmax(fabs(p0), fabs(p1));
+            const double f = mag > 1e150 ? 1e-150 : (mag < 1e-150 ? 1e150 : 1.0);
+            p0 *= f;
+            p1 *= f;
         }
+        for (; i < k; ++i)
+            sturm_step(i);
         // lanes whose point lies above every eigenvalue (monotone in the lane)
         const unsigned long long above = __ballot(below == k);
-        const int f = above ? __ffsll((long long)above) - 1 : 64;
-        const double nlo = f > 0 ? lo + step * (double)f : lo;
-        const double nhi = f < 64 ? lo + step * (double)(f + 1) : hi;
+        const int fl = above ? __ffsll((long long)above) - 1 : 64;
+        const double nlo = fl > 0 ? lo + step * (double)fl : lo;
+        const double nhi = fl < 64 ? lo + step * (double)(fl + 1) : hi;
         if (!(nhi - nlo < hi - lo))
             break;  // the bracket no longer shrinks in double precision
         lo = nlo;
@@ -1254,6 +1286,7 @@ __device__ double wave_max_eig(const double *al, const double *be, int k, int la
 // theta is exact), or after maxsteps steps.  v_0 is a fixed positive vector.
 // Dynamic LDS: (3 n + max(h, w)) doubles.  *n2 = theta.
 static constexpr int kLanczosMaxSteps = 48;
+static_assert(kLanczosMaxSteps < 64, "wave_max_eig holds one tridiagonal row per lane");
 
 __global__ __launch_bounds__(1024) void k_spectral_norm(const float *__restrict__ m, int H, int W,
                                                         int maxsteps, const int *__restrict__ skip,
@@ -1437,68 +1470,104 @@ __global__ __launch_bounds__(1024) void k_spectral_norm(const float *__restrict_
 // The same Lanczos iteration over many blocks, for images that one block
 // would stream too slowly at each step.  A = m^T m throughout (vectors of
 // length W).  Block b keeps rows [b rpb, (b + 1) rpb) of m in LDS and forms,
-// for its rows, y_r = m_r . v_j, its share sum_r y_r^2 of alpha_j and its
-// partial sum_r y_r m_r of A v_j (each wave over rows wave, wave + 4, ...;
-// the four wave sums in wave order).  One grid-wide exchange per step: every
-// block then adds all partials in block order and carries out the rest of the
-// step (the recurrence, beta, the Ritz value, the stop test) on identical
-// data, so all blocks reach the same decisions.  Needs all blocks resident at
-// once (few blocks, one per CU at most by their LDS); a wait that does not end
-// within a bounded number of polls marks the call failed and its result NaN
-// instead of hanging.
-// ws: [64 doubles: arrival count, failure flag (zeroed by k_mip)]
-//     [2][nb][W + 1] partials, by step parity.
-// Dynamic LDS: 7 W doubles + rpb W floats.
-static constexpr unsigned kSpinLimit = 1u << 20;
+// for its rows, y_r = m_r . v_j (thread (r, s) sums the columns s, s + nseg,
+// ... of row r, then the nseg pieces are added in order), its share
+// sum_r y_r^2 of alpha_j and its partial sum_r y_r m_r of A v_j (a thread per
+// column, rows in order): no cross-lane reductions.  One grid-wide exchange
+// per step: every block then adds all partials in block order and carries out
+// the rest of the step (the recurrence, beta, the Ritz value, the stop test)
+// on identical data, so all blocks reach the same decisions.
+//
+// The exchange carries its own validity: each partial (a double) travels as
+// two 64-bit words, each holding 32 bits of the value and the tag j + 1 of the
+// step, written and read with device-coherent 64-bit accesses (single-copy
+// atomic), so a reader polls each word until it carries the expected tag and
+// no fence or counter is needed.  The words are zeroed by k_mip before every
+// call (a zero tag never matches) and alternate between two buffers by step
+// parity (a block writes step j + 2 only after reading every block's step
+// j + 1, which they wrote after reading step j).  All blocks must be resident
+// at once (few blocks, one per CU at most by their LDS); a wait that does not
+// end within a bounded number of polls raises a failure flag that every
+// block's waits also watch, and the result is then NaN instead of a hang.
+// ws (64-bit words): [0] failure flag, [64 ...] the partials
+//     [2][nb][W + 1][2] (zeroed by k_mip: spectral_mb_words(nb, W) words).
+// Dynamic LDS: (3 W + spectral_mb_pieces(rpb, W) + rpb) doubles + rpb W floats.
+static constexpr unsigned kSpinLimit = 1u << 18;
 
-template <int KW>
-__global__ __launch_bounds__(256) void k_spectral_norm_mb(const float *__restrict__ m, int H, int W,
-                                                          int rpb, int maxsteps, double *ws,
-                                                          const int *__restrict__ skip,
-                                                          double *__restrict__ n2)
+__host__ __device__ __forceinline__ int spectral_mb_segs(int rpb, int W)
+{
+    return max(1, min(W, 1024 / max(rpb, 1)));
+}
+__host__ __device__ __forceinline__ int spectral_mb_pieces(int rpb, int W)
+{
+    return rpb * spectral_mb_segs(rpb, W);
+}
+__host__ __device__ __forceinline__ size_t spectral_mb_words(int nb, int W)
+{
+    return 64 + (size_t)4 * nb * (W + 1);
+}
+
+__global__ __launch_bounds__(1024) void k_spectral_norm_mb(const float *__restrict__ m, int H, int W,
+                                                           int rpb, int maxsteps,
+                                                           unsigned long long *ws,
+                                                           const int *__restrict__ skip,
+                                                           double *__restrict__ n2)
 {
     if (skip && *skip)
         return;
     extern __shared__ double lds[];
-    __shared__ double red2[2][4];
+    __shared__ double red3[3][16];
+    __shared__ double ashare_s;
     __shared__ double al[kLanczosMaxSteps + 1], be[kLanczosMaxSteps + 1];
-    __shared__ double aw_s[4], theta_s, alpha_s;
+    __shared__ double theta_s, alpha_s;
     __shared__ int stop_s, fail_s;
     const int nb = gridDim.x, b = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    unsigned *sync = reinterpret_cast<unsigned *>(ws);
-    double *part = ws + 64;
-    double *v = lds, *vp = lds + W, *wv = lds + 2 * W, *red = lds + 3 * W;  // red: [4][W]
-    float *ms = reinterpret_cast<float *>(lds + 7 * W);                     // [rpb][W]
+    unsigned long long *fail_g = ws;
+    unsigned long long *part = ws + 64;
+    const int nseg = spectral_mb_segs(rpb, W);
+    double *v = lds, *vp = lds + W, *wv = lds + 2 * W;
+    double *py = lds + 3 * W;                        // [rpb][nseg] pieces of y
+    double *yr = py + (size_t)rpb * nseg;            // [rpb]
+    float *ms = reinterpret_cast<float *>(yr + rpb);  // [rpb][W]
     const int r0 = b * rpb, nr = max(0, min(H, r0 + rpb) - r0);
-    for (size_t i = tid; i < (size_t)nr * W; i += 256)
+    for (size_t i = tid; i < (size_t)nr * W; i += 1024)
         ms[i] = m[(size_t)r0 * W + i];
-    auto block_sum2 = [&](double a, double c, double &ra, double &rc) {
+    // three block sums at once: wave sums by shuffles, then the waves in order
+    auto block_sum3 = [&](double a, double c, double e, double &ra, double &rc, double &re) {
         for (int off = 32; off > 0; off >>= 1) {
             a += __shfl_xor(a, off, 64);
             c += __shfl_xor(c, off, 64);
+            e += __shfl_xor(e, off, 64);
         }
         if (lane == 0) {
-            red2[0][wave] = a;
-            red2[1][wave] = c;
+            red3[0][wave] = a;
+            red3[1][wave] = c;
+            red3[2][wave] = e;
         }
         __syncthreads();
-        ra = ((red2[0][0] + red2[0][1]) + red2[0][2]) + red2[0][3];
-        rc = ((red2[1][0] + red2[1][1]) + red2[1][2]) + red2[1][3];
+        ra = red3[0][0];
+        rc = red3[1][0];
+        re = red3[2][0];
+        for (int q = 1; q < 16; ++q) {
+            ra += red3[0][q];
+            rc += red3[1][q];
+            re += red3[2][q];
+        }
         __syncthreads();
     };
     // v_0: the fixed positive vector of the one-block kernel, unit length
     double c = 0.0;
-    for (int i = tid; i < W; i += 256) {
+    for (int i = tid; i < W; i += 1024) {
         const double x = 1.0 + (double)((unsigned)(i + 1) * 2654435761u % 1024u) / 2048.0;
         v[i] = x;
         vp[i] = 0.0;
         c += x * x;
     }
-    double n0, unused;
-    block_sum2(c, 0.0, n0, unused);
+    double n0, unused, unused2;
+    block_sum3(c, 0.0, 0.0, n0, unused, unused2);
     n0 = sqrt(n0);
-    for (int i = tid; i < W; i += 256)
+    for (int i = tid; i < W; i += 1024)
         v[i] /= n0;
     if (tid == 0) {
         theta_s = 0.0;
@@ -1509,89 +1578,151 @@ __global__ __launch_bounds__(256) void k_spectral_norm_mb(const float *__restric
     __syncthreads();
     const int steps = max(1, min(maxsteps, kLanczosMaxSteps));
     for (int j = 0; j < steps; ++j) {
-        // this block's rows: y_r, alpha share, partial A v_j (lane holds columns lane + 64 i)
-        double pw[KW];
-#pragma unroll
-        for (int i = 0; i < KW; ++i)
-            pw[i] = 0.0;
-        double aw = 0.0;
-        for (int r = wave; r < nr; r += 4) {
+        const unsigned long long tag = (unsigned long long)(j + 1) << 32;
+        // y_r in pieces: thread (r, s) over the columns s, s + nseg, ...
+        // (four running sums, four loads in flight, added in order)
+        for (int it = tid; it < nr * nseg; it += 1024) {
+            const int r = it / nseg, sg = it % nseg;
             const float *row = ms + (size_t)r * W;
-            double d = 0.0;
+            double d[4] = {0.0, 0.0, 0.0, 0.0};
+            int cc = sg;
+            for (; cc + 3 * nseg < W; cc += 4 * nseg) {
+                float mv[4];
+                double vv[4];
 #pragma unroll
-            for (int i = 0; i < KW; ++i) {
-                const int cc = lane + 64 * i;
-                if (cc < W)
-                    d = fma((double)row[cc], v[cc], d);
+                for (int q = 0; q < 4; ++q) {
+                    mv[q] = row[cc + q * nseg];
+                    vv[q] = v[cc + q * nseg];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    d[q] = fma((double)mv[q], vv[q], d[q]);
             }
-            // butterfly: every lane ends with the same sum
-            for (int off = 32; off > 0; off >>= 1)
-                d += __shfl_xor(d, off, 64);
-            aw = fma(d, d, aw);
-#pragma unroll
-            for (int i = 0; i < KW; ++i) {
-                const int cc = lane + 64 * i;
-                if (cc < W)
-                    pw[i] = fma(d, (double)row[cc], pw[i]);
-            }
+            for (int q = 0; cc < W; cc += nseg, ++q)
+                d[q] = fma((double)row[cc], v[cc], d[q]);
+            py[it] = (d[0] + d[1]) + (d[2] + d[3]);
         }
-#pragma unroll
-        for (int i = 0; i < KW; ++i) {
-            const int cc = lane + 64 * i;
-            if (cc < W)
-                red[(size_t)wave * W + cc] = pw[i];
-        }
-        if (lane == 0)
-            aw_s[wave] = aw;
         __syncthreads();
-        double *pb = part + ((size_t)(j & 1) * nb + b) * (W + 1);
-        for (int e = tid; e < W; e += 256)
-            pb[e] = ((red[e] + red[W + e]) + red[2 * W + e]) + red[3 * W + e];
-        if (tid == 0)
-            pb[W] = ((aw_s[0] + aw_s[1]) + aw_s[2]) + aw_s[3];
-        // grid-wide exchange: release this block's partials, count in, wait
-        // for every block.  The other blocks' partials are then read with
-        // device-coherent loads, so no cache invalidation is needed.
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        for (int r = tid; r < nr; r += 1024) {
+            const double *pr = py + (size_t)r * nseg;
+            double y = 0.0;
+            int sg = 0;
+            for (; sg + 8 <= nseg; sg += 8) {
+                double t[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    t[q] = pr[sg + q];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    y += t[q];
+            }
+            for (; sg < nseg; ++sg)
+                y += pr[sg];
+            yr[r] = y;
+        }
+        __syncthreads();
+        // alpha's share sum_r y_r^2 by the last wave (rows lane, lane + 64, ...,
+        // then a butterfly), the other waves go on with their columns
+        if (wave == 15) {
+            double a2 = 0.0;
+            for (int r = lane; r < nr; r += 64)
+                a2 = fma(yr[r], yr[r], a2);
+            for (int off = 32; off > 0; off >>= 1)
+                a2 += __shfl_xor(a2, off, 64);
+            if (lane == 0)
+                ashare_s = a2;
+        }
+        // partial A v_j = sum_r y_r m_r: a thread per column, rows in order
+        // (four running sums over r mod 4, eight rows in flight); sent with
+        // alpha's share as tagged words
+        unsigned long long *pb = part + ((size_t)(j & 1) * nb + b) * (W + 1) * 2;
+        // (the share's words go last, from the thread of column W, after a
+        // barrier that publishes it)
+        for (int cc = tid; cc < W; cc += 1024) {
+            double val;
+            {
+                double d[4] = {0.0, 0.0, 0.0, 0.0};
+                int r = 0;
+                for (; r + 8 <= nr; r += 8) {
+                    float mv[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        mv[q] = ms[(size_t)(r + q) * W + cc];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        d[q & 3] = fma(yr[r + q], (double)mv[q], d[q & 3]);
+                }
+                for (; r < nr; ++r)
+                    d[r & 3] = fma(yr[r], (double)ms[(size_t)r * W + cc], d[r & 3]);
+                val = (d[0] + d[1]) + (d[2] + d[3]);
+            }
+            const unsigned long long bits = (unsigned long long)__double_as_longlong(val);
+            __hip_atomic_store(pb + 2 * cc, tag | (bits & 0xffffffffull), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(pb + 2 * cc + 1, tag | (bits >> 32), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
         __syncthreads();
         if (tid == 0) {
-            const unsigned target = (unsigned)nb * (unsigned)(j + 1);
-            __hip_atomic_fetch_add(sync, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            unsigned spins = 0;
-            while (__hip_atomic_load(sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                if (__hip_atomic_load(sync + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
-                    ++spins == kSpinLimit) {
-                    __hip_atomic_fetch_or(sync + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    fail_s = 1;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
+            const unsigned long long bits = (unsigned long long)__double_as_longlong(ashare_s);
+            __hip_atomic_store(pb + 2 * W, tag | (bits & 0xffffffffull), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(pb + 2 * W + 1, tag | (bits >> 32), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         }
-        __syncthreads();
-        if (fail_s)
-            break;
-        // A v_j and alpha_j: all partials, in block order (loads in batches of 8)
-        const double *pj = part + (size_t)(j & 1) * nb * (W + 1);
-        for (int e = tid; e <= W; e += 256) {
+        // A v_j and alpha_j: every block's words for this thread's column, in
+        // block order (batches of 16 blocks, 32 loads in flight; a word with an
+        // older tag is read again until it carries this step's)
+        const unsigned long long *pj = part + (size_t)(j & 1) * nb * (W + 1) * 2;
+        unsigned spins = 0;
+        bool failed = false;
+        for (int e = tid; e <= W; e += 1024) {
             double a = 0.0;
-            for (int q0 = 0; q0 < nb; q0 += 8) {
-                double pv[8];
+            for (int q0 = 0; q0 < nb; q0 += 16) {
+                unsigned long long wd[16][2];
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    pv[q] = __hip_atomic_load(pj + (size_t)min(q0 + q, nb - 1) * (W + 1) + e,
-                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int q = 0; q < 16; ++q)
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (q0 + q < nb)
-                        a += pv[q];
+                    for (int h = 0; h < 2; ++h)
+                        wd[q][h] = __hip_atomic_load(
+                            pj + ((size_t)min(q0 + q, nb - 1) * (W + 1) + e) * 2 + h,
+                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    if (q0 + q >= nb)
+                        continue;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        while ((wd[q][h] & 0xffffffff00000000ull) != tag && !failed) {
+                            if (++spins >= kSpinLimit ||
+                                ((spins & 255) == 0 &&
+                                 __hip_atomic_load(fail_g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                                __hip_atomic_store(fail_g, 1ull, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                                failed = true;
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                            wd[q][h] = __hip_atomic_load(
+                                pj + ((size_t)(q0 + q) * (W + 1) + e) * 2 + h, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    }
+                    const unsigned long long bits =
+                        (wd[q][0] & 0xffffffffull) | ((wd[q][1] & 0xffffffffull) << 32);
+                    a += __longlong_as_double((long long)bits);
+                }
             }
             if (e < W)
                 wv[e] = a;
             else
                 alpha_s = a;
         }
+        if (failed)
+            fail_s = 1;
         __syncthreads();
+        if (fail_s)
+            break;
         const double alpha = alpha_s;
         if (tid == 0)
             al[j] = alpha;
@@ -1605,25 +1736,31 @@ __global__ __launch_bounds__(256) void k_spectral_norm_mb(const float *__restric
             __syncthreads();
             break;
         }
-        // w = A v_j - alpha v_j - beta_j v_{j-1}, once more against v_j, v_{j-1}
+        // t = A v_j - alpha v_j - beta_j v_{j-1}, then w = t - (t.v_j) v_j -
+        // (t.v_{j-1}) v_{j-1}; |w|^2 = |t|^2 - (t.v_j)^2 - (t.v_{j-1})^2 for
+        // orthonormal v_j, v_{j-1} (one block sum for all three); where that
+        // difference is small against |t|^2 it is summed directly instead
         const double bj = be[j];
-        double c0 = 0.0, c1 = 0.0;
-        for (int e = tid; e < W; e += 256) {
+        double c0 = 0.0, c1 = 0.0, tt = 0.0;
+        for (int e = tid; e < W; e += 1024) {
             const double t = wv[e] - alpha * v[e] - bj * vp[e];
             wv[e] = t;
             c0 = fma(t, v[e], c0);
             c1 = fma(t, vp[e], c1);
+            tt = fma(t, t, tt);
         }
-        double d0, d1;
-        block_sum2(c0, c1, d0, d1);
+        double d0, d1, t2;
+        block_sum3(c0, c1, tt, d0, d1, t2);
+        double bb = t2 - d0 * d0 - d1 * d1;
+        const bool direct = !(bb > 1e-6 * t2);
         double b2 = 0.0;
-        for (int e = tid; e < W; e += 256) {
+        for (int e = tid; e < W; e += 1024) {
             const double t = wv[e] - d0 * v[e] - d1 * vp[e];
             wv[e] = t;
             b2 = fma(t, t, b2);
         }
-        double bb;
-        block_sum2(b2, 0.0, bb, unused);
+        if (direct)  // block-uniform
+            block_sum3(b2, 0.0, 0.0, bb, unused, unused2);
         const double beta = sqrt(bb);
         if (wave == 0) {
             const double th = wave_max_eig(al, be, j + 1, lane);
@@ -1637,7 +1774,7 @@ __global__ __launch_bounds__(256) void k_spectral_norm_mb(const float *__restric
         __syncthreads();
         if (stop_s)
             break;
-        for (int e = tid; e < W; e += 256) {
+        for (int e = tid; e < W; e += 1024) {
             vp[e] = v[e];
             v[e] = wv[e] / beta;
         }
@@ -3642,36 +3779,39 @@ static double region_area(int region, double xs, double ys, int h, int w)
 // volume size up to which that block also copies the best iterate.
 // Launch shape of the multi-block spectral norm for an h x w image (nb = 0:
 // the one-block kernel instead).  Rows of the image are spread over at most
-// kSpecMaxBlocks blocks of 256 threads, each holding its rows in LDS next to
-// 7 w doubles of vectors; the exchange needs 64 + 2 nb (w + 1) doubles of T1.
+// kSpecMaxBlocks blocks of 1024 threads, each holding its rows in LDS next to
+// 3 w doubles of vectors and its row sums; the exchange needs
+// spectral_mb_words(nb, w) 64-bit words of T1.
 static constexpr int kSpecMaxBlocks = 32;
 static constexpr size_t kSpecLds = 120 * 1024;
 static constexpr size_t kSpecMinPixels = 16384;
 struct SpectralLaunch {
-    int nb, rpb, kw, steps;
+    int nb, rpb, steps;
     size_t lds;
 };
 static SpectralLaunch spectral_launch(int h, int w, size_t t1cap)
 {
     SpectralLaunch sp{};
-    if ((size_t)h * w < kSpecMinPixels || w > 64 * 32)
+    if ((size_t)h * w < kSpecMinPixels)
         return sp;
-    const size_t vec = (size_t)7 * w * sizeof(double);
-    if (vec + (size_t)w * sizeof(float) > kSpecLds)
+    // per row: w floats in LDS, its y value and at most 1024 / rpb + 1 pieces
+    const size_t vec = (size_t)3 * w * sizeof(double) + 1024 * sizeof(double);
+    const size_t per_row = (size_t)w * sizeof(float) + 2 * sizeof(double);
+    if (vec + per_row > kSpecLds)
         return sp;
-    const int rmax = (int)((kSpecLds - vec) / ((size_t)w * sizeof(float)));
+    const int rmax = (int)((kSpecLds - vec) / per_row);
     const int nb = (h + rmax - 1) / rmax;
     if (nb > kSpecMaxBlocks)
         return sp;
     const int rpb = (h + nb - 1) / nb;
-    if (t1cap < 64 + 2 * (size_t)nb * (w + 1))
+    if (t1cap < spectral_mb_words(nb, w))
         return sp;
     const size_t steps = kLanczosMaxSteps;
     sp.nb = nb;
     sp.rpb = rpb;
-    sp.kw = w <= 256 ? 4 : w <= 512 ? 8 : w <= 1024 ? 16 : 32;
     sp.steps = (int)steps;
-    sp.lds = vec + (size_t)rpb * w * sizeof(float);
+    sp.lds = ((size_t)3 * w + spectral_mb_pieces(rpb, w) + rpb) * sizeof(double) +
+             (size_t)rpb * w * sizeof(float);
     return sp;
 }
 
@@ -3757,22 +3897,19 @@ static int run_metric(int nz, int h, int w, const float *vol, double xs, double 
     if (norm == LFRL_NORM_SPECTRAL)
         sp = spectral_launch(h, w, t1cap);
     hipLaunchKernelGGL(k_mip, dim3(nblk), dim3(256), 0, st, vol, nz, hw, mb.mip, mb.n2p, skip,
-                       sp.nb > 0 ? reinterpret_cast<unsigned *>(mb.T1) : nullptr);
+                       reinterpret_cast<unsigned long long *>(mb.T1),
+                       sp.nb > 0 ? spectral_mb_words(sp.nb, w) : (size_t)0);
     LAUNCH_CHECK("k_mip");
     if (norm == LFRL_NORM_SPECTRAL) {
         if (sp.nb > 0) {
-#define LFRL_SPEC_MB(KWV)                                                                       \
-    if (sp.kw == KWV) {                                                                         \
-        static const hipError_t attr = hipFuncSetAttribute(                                     \
-            (const void *)k_spectral_norm_mb<KWV>, hipFuncAttributeMaxDynamicSharedMemorySize,  \
-            (int)kSpecLds);                                                                     \
-        (void)attr;                                                                             \
-        hipLaunchKernelGGL(k_spectral_norm_mb<KWV>, dim3(sp.nb), dim3(256), sp.lds, st,         \
-                           (const float *)mb.mip, h, w, sp.rpb, sp.steps, mb.T1, skip,           \
-                           mb.n2p + nblk);                                                       \
-    }
-            LFRL_SPEC_MB(4) LFRL_SPEC_MB(8) LFRL_SPEC_MB(16) LFRL_SPEC_MB(32)
-#undef LFRL_SPEC_MB
+            static const hipError_t attr =
+                hipFuncSetAttribute((const void *)k_spectral_norm_mb,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSpecLds);
+            (void)attr;
+            hipLaunchKernelGGL(k_spectral_norm_mb, dim3(sp.nb), dim3(1024), sp.lds, st,
+                               (const float *)mb.mip, h, w, sp.rpb, sp.steps,
+                               reinterpret_cast<unsigned long long *>(mb.T1), skip,
+                               mb.n2p + nblk);
             LAUNCH_CHECK("k_spectral_norm_mb");
         } else {
             const size_t lds = (size_t)(3 * std::min(h, w) + std::max(h, w)) * sizeof(double);
