@@ -180,6 +180,7 @@ __global__ __launch_bounds__(512) void k_contract_fwd_split(
     const unsigned *__restrict__ xmax, const int *__restrict__ gexp, float2 *__restrict__ Yp,
     int NN, int NNp, int KK, int KKs, int nkb, int nt, int nf, int kchunk,
     const int *__restrict__ skip, FreqMap fm, const float2 *__restrict__ Gx, int xcol)
+// (xmax: kRowmaxSlots slots of nf * nt maxima, see k_r2c_fft)
 {
     if (skip && *skip)
         return;
@@ -198,7 +199,8 @@ __global__ __launch_bounds__(512) void k_contract_fwd_split(
     const int ngroups = (nsteps + U - 1) / U;
     const int t = min(t0 + col, nt - 1);
     const float2 *xrow = X + ((size_t)k * nt + t) * KKs;
-    const int ex = f16_scale_exp(__uint_as_float(xmax[(size_t)k * nt + t]));
+    const size_t mstride = (size_t)nf * nt;
+    const int ex = f16_scale_exp(__uint_as_float(rowmax_of(xmax, mstride, (size_t)k * nt + t)));
     int cbk[CB];
 #pragma unroll
     for (int b = 0; b < CB; ++b)
@@ -342,7 +344,7 @@ __global__ __launch_bounds__(512) void k_contract_fwd_split(
         const int tt = t0 + 4 * kg + i;
         if (tt >= nt)
             continue;
-        const int sc = -(f16_scale_exp(__uint_as_float(xmax[(size_t)k * nt + tt])) + gx);
+        const int sc = -(f16_scale_exp(__uint_as_float(rowmax_of(xmax, mstride, (size_t)k * nt + tt))) + gx);
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
             const int c = 16 * (wave * CB + b) + col;
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(256) void k_contract_adj_split(
     const cplx16<typename P::S> *__restrict__ Hb, const float2 *__restrict__ Rs,
     const unsigned *__restrict__ rmax, const int *__restrict__ gexp, float2 *__restrict__ B,
     int NN, int NNp, int KK, int KKs, int nkb, int nt, const int *__restrict__ skip, FreqMap fm,
-    const float2 *__restrict__ Hx, int xc, int KKb)
+    const float2 *__restrict__ Hx, int xc, int KKb, size_t mstride)
 {
     if (skip && *skip)
         return;
@@ -396,7 +398,7 @@ __global__ __launch_bounds__(256) void k_contract_adj_split(
         int ex = 0;
         if (c < NN && c < 16 * ncc && tt < nt) {
             v = Rs[((size_t)k * nt + tt) * NN + c];
-            ex = f16_scale_exp(__uint_as_float(rmax[(size_t)k * nt + tt]));
+            ex = f16_scale_exp(__uint_as_float(rowmax_of(rmax, mstride, (size_t)k * nt + tt)));
         }
         S h, lo;
         S *dst = ra + ((size_t)(cc * 64 + l) * 4 + e) * 4;
@@ -501,7 +503,7 @@ __global__ __launch_bounds__(256) void k_contract_adj_split(
         const int tt = t0 + 4 * kg + i;
         if (tt >= nt)
             continue;
-        const int sc = -(f16_scale_exp(__uint_as_float(rmax[(size_t)k * nt + tt])) + gx);
+        const int sc = -(f16_scale_exp(__uint_as_float(rowmax_of(rmax, mstride, (size_t)k * nt + tt))) + gx);
         // the lone reduction index xc (if any), in float32: + R[t][xc] conj(H[xc][kk])
         const float2 r = xc >= 0 ? Rs[((size_t)k * nt + tt) * NN + xc] : make_float2(0.f, 0.f);
 #pragma unroll

@@ -459,6 +459,16 @@ __global__ void k_c2r(const TileBatch batch, const float2 *__restrict__ spec, si
 //   D (16 x 16): lane l holds D[4 * (l / 16) + i][l % 16] in element i.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// Fragment loads of the adjoint contraction, non-temporal: they are read once
+// per launch and far exceed the caches (measured faster; the same hint made
+// the forward contraction and the adjoint's stores slower)
+__device__ __forceinline__ float4 adj_load4(const float4 *p)
+{
+    const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+
 __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -880,7 +890,7 @@ __global__ __launch_bounds__(256) void k_contract_adj(const float4 *__restrict__
                 const int p = min(grp * U + u, npairs - 1);
 #pragma unroll
                 for (int b = 0; b < CB; ++b)
-                    gb[u][b] = fk[adj_frag(p, kbi[b], npairs, nkb, RB) * 64 + lane];
+                    gb[u][b] = adj_load4(&fk[adj_frag(p, kbi[b], npairs, nkb, RB) * 64 + lane]);
             }
         };
         auto compute_group = [&](int grp, const float4(&gb)[U][CB]) {
@@ -2180,16 +2190,17 @@ static bool fft_supported(int Q)
 }
 
 // LDS of the forward tile DFT: the PSF mode stages its input tile; the planes
-// mode needs only the half spectrum Z (plus twiddles and row maxima).
+// mode needs only the half spectrum Z and twiddles (the column magnitudes for
+// the row maxima reuse Z).
 static size_t lds_r2c_fft(const Geo &g)
 {
     const size_t a = (size_t)g.Q * g.Q * g.N * 4, b = (size_t)g.Q * g.QH * g.N * 8;
-    return std::max(a, b) + (size_t)g.Q * 8 + (size_t)g.Q * g.QH * 4;  // + row maxima
+    return std::max(a, b) + (size_t)g.Q * 8;
 }
 
 static size_t lds_r2c_fft_planes(const Geo &g)
 {
-    return (size_t)g.Q * g.QH * g.N * 8 + (size_t)g.Q * 8 + (size_t)g.Q * g.QH * 4;
+    return (size_t)g.Q * g.QH * g.N * 8 + (size_t)g.Q * 8;
 }
 
 static size_t lds_c2r_fft(const Geo &g)
@@ -2853,7 +2864,7 @@ static Sizes sizes_for(const Geo &g, int max_h, int max_w, int max_batch, int sp
         s.Hf = (size_t)g.nf * g.KKs * g.NNm * sizeof(cplx16<_Float16>);
         s.Hb = (size_t)g.nf * g.NNm * ((g.KK + 15) / 16 * 16) * sizeof(cplx16<_Float16>);
         s.gexp = (size_t)g.nf * sizeof(int);
-        s.rowmax = (size_t)g.nf * nt * sizeof(unsigned);
+        s.rowmax = (size_t)g.nf * nt * kRowmaxSlots * sizeof(unsigned);
     }
     return s;
 }
@@ -3508,7 +3519,8 @@ static int run_forward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipSt
         return set_error(LFRL_ERR_ARG, "batch of %d tiles exceeds the plan capacity %d", nt,
                          p->max_tiles);
     if (p->split) {
-        hipLaunchKernelGGL(k_zero_u32n, dim3(64), dim3(256), 0, st, p->xmax, (size_t)g.nf * nt);
+        hipLaunchKernelGGL(k_zero_u32n, dim3(64), dim3(256), 0, st, p->xmax,
+                           (size_t)g.nf * nt * kRowmaxSlots);
         LAUNCH_CHECK("k_zero_u32n");
     }
     if (p->use_fft)
@@ -3593,7 +3605,8 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
         return set_error(LFRL_ERR_ARG, "batch of %d tiles exceeds the plan capacity %d", nt,
                          p->max_tiles);
     if (p->split) {
-        hipLaunchKernelGGL(k_zero_u32n, dim3(64), dim3(256), 0, st, p->rmax, (size_t)g.nf * nt);
+        hipLaunchKernelGGL(k_zero_u32n, dim3(64), dim3(256), 0, st, p->rmax,
+                           (size_t)g.nf * nt * kRowmaxSlots);
         LAUNCH_CHECK("k_zero_u32n");
     }
     if (p->use_fft)
@@ -3635,7 +3648,7 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
                        (const cplx16<PT::S> *)p->Hb, (const float2 *)p->Rs,                      \
                        (const unsigned *)p->rmax, (const int *)p->gexp, p->X, g.NN, g.NNm,      \
                        g.KK, g.KKs, (g.KK + 15) / 16, nt, skip, freq_map(g.Q),                   \
-                       (const float2 *)p->Hx, g.xcol, g.KKb)
+                       (const float2 *)p->Hx, g.xcol, g.KKb, (size_t)g.nf * nt)
 #define LFRL_HADJ_CASE(CBV, UV)                                                                  \
     if (p->hadj_cb == CBV && p->hadj_u == UV) {                                                  \
         if (p->bf16)                                                                             \

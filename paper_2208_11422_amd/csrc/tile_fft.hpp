@@ -312,6 +312,18 @@ __device__ __forceinline__ float keep_if(float v, bool keep)
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
 // Remap the linear block id so that every XCD works through one contiguous
 // range of work items: items that share cache lines then share an L2.
+// Slots of the per-(frequency, tile) maxima of tile spectra (see k_r2c_fft)
+static constexpr int kRowmaxSlots = 8;
+__device__ __forceinline__ unsigned rowmax_of(const unsigned *__restrict__ m, size_t slot_stride,
+                                              size_t i)
+{
+    unsigned v = m[i];
+#pragma unroll
+    for (int s = 1; s < kRowmaxSlots; ++s)
+        v = max(v, m[(size_t)s * slot_stride + i]);
+    return v;
+}
+
 __device__ __forceinline__ int xcd_item(int bid, int n)
 {
     constexpr int kXcds = 8;
@@ -336,9 +348,12 @@ __device__ __forceinline__ int xcd_item(int bid, int n)
 //               circularly in the tile; blockIdx = (cr, a, j); `src` is the
 //               PSF; KKo is the row stride NNp of the spectra.
 //               obase = ((j*N*N + a) * NNp + cr*N), kstride = KK * NNp.
-//   rowmax (SRC_PLANES, may be null): rowmax[k * nt + tile] is raised (atomic
-//   max on the float bits) to the largest |re| or |im| the block writes at
-//   frequency k; the caller zeroes it first.
+//   rowmax (SRC_PLANES, may be null): rowmax[(s * Q*QH + k) * nt + tile] is
+//   raised (atomic max on the float bits) to the largest |re| or |im| the
+//   block writes at frequency k, in slot s = (j*N + ar) mod kRowmaxSlots (the
+//   blocks of one tile spread their atomics over the slots instead of queueing
+//   on one address); the caller zeroes all slots first and readers take the
+//   maximum over them (rowmax_of).
 template <int Q>
 __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const TileBatch batch,
                                                   const float *__restrict__ src, int N, int T,
@@ -352,27 +367,22 @@ __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const TileBatch batch
     float2 *tw = reinterpret_cast<float2 *>(smem);
     float *buf = smem + 2 * Q;
     float2 *Z = reinterpret_cast<float2 *>(buf);
-    // SRC_PLANES loads its rows straight from memory: buf holds only Z
-    const size_t zfloats = (size_t)2 * Q * QH * N;
-    const size_t buf_floats = (mode == SRC_PLANES || zfloats > (size_t)Q * Q * N)
-                                  ? zfloats : (size_t)Q * Q * N;
-    unsigned *kmax = reinterpret_cast<unsigned *>(buf + buf_floats);  // [Q * QH]
+    // SRC_PLANES loads its rows straight from memory: buf holds only Z (and,
+    // at the end, the column magnitudes for rowmax)
     const int tid = threadIdx.x;
     for (int i = tid; i < Q; i += blockDim.x)
         tw[i] = twg[i];
-    if (rowmax)
-        for (int i = tid; i < Q * QH; i += blockDim.x)
-            kmax[i] = 0u;
     const int rowlen = Q * N;
     size_t obase, kstride;
     const float *plane = nullptr;
-    int H = 0, W = 0, ly0 = 0, lx0 = 0, arow = 0;
+    int H = 0, W = 0, ly0 = 0, lx0 = 0, arow = 0, rslot = 0;
     if (mode == SRC_PLANES) {
         const int item = xcd_item(blockIdx.x, gridDim.x);
         const int njar = gridDim.x / nt;
         const int tile = item / njar, jar = item % njar;
         const int j = jar / N;
         arow = jar % N;
+        rslot = (j * N + arow) % kRowmaxSlots;
         const TileJob &fj = batch.job[batch_job(batch, tile)];
         if (fj.skip && *fj.skip)
             return;   // block-uniform, before any barrier
@@ -468,19 +478,26 @@ __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const TileBatch batch
         for (int ku = 0; ku < Q; ++ku)
             if (mode != SRC_PLANES || !freq_redundant<Q>(ku, kv))
                 out[obase + (size_t)(ku * QH + kv) * kstride + p] = v[ku];
-        if (rowmax) {
-#pragma unroll
-            for (int ku = 0; ku < Q; ++ku)
-                atomicMax(&kmax[ku * QH + kv],
-                          __float_as_uint(fmaxf(fabsf(v[ku].x), fabsf(v[ku].y))));
-        }
     }
     if (rowmax) {
+        // the column magnitudes through LDS (Z has been read by every
+        // thread), then the maximum over the N phases of each frequency
+        __syncthreads();
+        unsigned *mz = reinterpret_cast<unsigned *>(Z);  // [Q * QH][N]
+        if (tid < QH * N) {
+#pragma unroll
+            for (int ku = 0; ku < Q; ++ku)
+                mz[(size_t)ku * QH * N + tid] = __float_as_uint(fmaxf(fabsf(v[ku].x), fabsf(v[ku].y)));
+        }
         __syncthreads();
         const int tile = xcd_item(blockIdx.x, gridDim.x) / (gridDim.x / nt);
-        for (int i = tid; i < Q * QH; i += blockDim.x)
-            if (kmax[i])
-                atomicMax(&rowmax[(size_t)i * nt + tile], kmax[i]);
+        for (int i = tid; i < Q * QH; i += blockDim.x) {
+            unsigned m = 0u;
+            for (int q = 0; q < N; ++q)
+                m = max(m, mz[(size_t)i * N + q]);
+            if (m)
+                atomicMax(&rowmax[((size_t)rslot * Q * QH + i) * nt + tile], m);
+        }
     }
 }
 
