@@ -171,9 +171,16 @@ __device__ __forceinline__ void split_lohi(float v, typename P::S &hi, typename 
 // Forward contraction, split precision (see the FP32 k_contract_fwd for the
 // roles):
 //   Yp[s][k][t][c] = sum_{kk in chunk} X[k][t][kk] Gf[k][kk][c]
-// A = X rows (16 tiles x 32 kk, row stride KKs, scaled by 2^xexp and split),
-// B = Hf fragments (32 kk x 16 c), CB blocks of c per wave, U prefetched
-// steps, double-buffered (clamped loads).  kchunk is a multiple of 32.
+// A = X rows (16 tiles x 32 kk per step, row stride KKs, scaled by 2^xexp and
+// split hi/lo), B = Hf fragments (32 kk x 16 c), CB blocks of c per wave, U
+// steps per group.  Every wave needs the same A fragments, so the block
+// converts them once per group into a double-buffered LDS buffer (element
+// (L, e) of lane L's eight kk by thread tid + m * blockDim, the same element
+// in every group), one barrier per group; the B fragments are prefetched one
+// group ahead per wave (clamped loads; surplus steps meet zero A).  kchunk is
+// a multiple of 32.  The lone output column xcol (if any) is summed in FP32
+// by the converting threads from the values they load, then per tile in a
+// fixed order.
 template <class P, int CB, int U>
 __global__ __launch_bounds__(512) void k_contract_fwd_split(
     const cplx16<typename P::S> *__restrict__ Hf, const float2 *__restrict__ X,
@@ -186,68 +193,100 @@ __global__ __launch_bounds__(512) void k_contract_fwd_split(
         return;
     typedef typename P::S S;
     typedef typename P::v8 V8;
+    // A fragments: [buffer][step][lane][re hi, re lo, im hi, im lo], 8 values each
+    __shared__ uint4 la[2][U][64][4];
+    constexpr int kElems = 512 * U;  // (step, lane, element) per group
+    constexpr int KS = (kElems + 319) / 320;  // slots per thread (blocks of >= 320 threads)
+    __shared__ float2 colred[kElems];
     int k, s, tg;
     contraction_block(k, s, tg);
     k = unique_freq(k, fm);
     const int t0 = tg * 16;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int col = lane & 15, kg = lane >> 4;
     const int ncb = NNp / 16;
     const int kb0 = s * kchunk;
     const int kb1 = min(KK, kb0 + kchunk);
     const int nsteps = (kb1 - kb0 + 31) / 32;
     const int ngroups = (nsteps + U - 1) / U;
-    const int t = min(t0 + col, nt - 1);
-    const float2 *xrow = X + ((size_t)k * nt + t) * KKs;
     const size_t mstride = (size_t)nf * nt;
-    const int ex = f16_scale_exp(__uint_as_float(rowmax_of(xmax, mstride, (size_t)k * nt + t)));
     int cbk[CB];
 #pragma unroll
     for (int b = 0; b < CB; ++b)
         cbk[b] = min(wave * CB + b, ncb - 1);
     const size_t fbase = (size_t)k * nkb * ncb;
+    // waves past the column blocks (a block has at least 5 waves for the
+    // conversion slots) only convert
+    const bool cwave = wave * CB < ncb;
     f32x4v accr[CB], acci[CB];
 #pragma unroll
     for (int b = 0; b < CB; ++b) {
         accr[b] = f32x4v{0.f, 0.f, 0.f, 0.f};
         acci[b] = f32x4v{0.f, 0.f, 0.f, 0.f};
     }
-    float4 xa0[U][4], xa1[U][4];
-    uint4 gb0[U][CB][2], gb1[U][CB][2];
-    // the lone output column xcol (if any): X G in float32 on the vector ALU,
-    // from the X values the waves hold anyway; wave w takes the steps
-    // w, w + nw, ... and the partial sums meet in LDS at the end
-    const int nw = blockDim.x >> 6;
-    const float2 *gxk = Gx + (xcol >= 0 ? (size_t)k * KKs : 0);
-    float2 accx = make_float2(0.f, 0.f);
-    auto column_group = [&](int grp, const float4(&xa)[U][4]) {
+    // this thread's conversion slots: element idx = tid + m * nthr of a group
+    // (step u = idx / 512, lane L = idx / 8 % 64, element e = idx % 8: tile
+    // t0 + L % 16, kk = 32 step + 8 (L / 16) + e)
+    const float2 *xs[KS];
+    int xe[KS];
+    bool live[KS];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int step = grp * U + u;
-            const int kk = kb0 + 32 * step + 8 * kg;
-            if (xcol < 0 || step >= nsteps || step % nw != wave)
+    for (int m = 0; m < KS; ++m) {
+        const int idx = tid + m * nthr;
+        live[m] = idx < kElems;
+        const int L = (idx >> 3) & 63;
+        const int tt = min(t0 + (L & 15), nt - 1);
+        xs[m] = X + ((size_t)k * nt + tt) * KKs + kb0 + 8 * (L >> 4) + (idx & 7);
+        xe[m] = f16_scale_exp(__uint_as_float(rowmax_of(xmax, mstride, (size_t)k * nt + tt)));
+    }
+    const float2 *gxk = Gx + (xcol >= 0 ? (size_t)k * KKs + kb0 : 0);
+    float2 xv[KS], gv[KS], accx[KS];
+#pragma unroll
+    for (int m = 0; m < KS; ++m)
+        accx[m] = make_float2(0.f, 0.f);
+    auto a_load = [&](int grp) {
+#pragma unroll
+        for (int m = 0; m < KS; ++m) {
+            if (!live[m])
                 continue;
-            const float4 *gp = reinterpret_cast<const float4 *>(gxk + kk);
+            const int idx = tid + m * nthr;
+            const int step = min(grp * U + idx / 512, nsteps - 1);
+            xv[m] = xs[m][32 * step];
+            if (xcol >= 0)
+                gv[m] = gxk[32 * step + 8 * (((idx >> 3) & 63) >> 4) + (idx & 7)];
+        }
+    };
+    auto a_store = [&](int grp, int buf) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float4 g = gp[q], x = xa[u][q];
-                const bool ok0 = kk + 2 * q < kb1, ok1 = kk + 2 * q + 1 < kb1;
-                const float xr0 = ok0 ? x.x : 0.f, xi0 = ok0 ? x.y : 0.f;
-                const float xr1 = ok1 ? x.z : 0.f, xi1 = ok1 ? x.w : 0.f;
-                accx.x = fmaf(xr0, g.x, fmaf(-xi0, g.y, fmaf(xr1, g.z, fmaf(-xi1, g.w, accx.x))));
-                accx.y = fmaf(xr0, g.y, fmaf(xi0, g.x, fmaf(xr1, g.w, fmaf(xi1, g.z, accx.y))));
+        for (int m = 0; m < KS; ++m) {
+            if (!live[m])
+                continue;
+            const int idx = tid + m * nthr;
+            const int u = idx / 512, L = (idx >> 3) & 63, e = idx & 7;
+            const int step = grp * U + u;
+            const int kk = kb0 + 32 * step + 8 * (L >> 4) + e;
+            const bool ok = step < nsteps && kk < kb1;
+            const float re = ok ? xv[m].x : 0.f, im = ok ? xv[m].y : 0.f;
+            S h, l;
+            S *dst = reinterpret_cast<S *>(&la[buf][u][L][0]);
+            split_lohi<P>(ldexpf(re, xe[m]), h, l);
+            dst[e] = h;
+            dst[8 + e] = l;
+            split_lohi<P>(ldexpf(im, xe[m]), h, l);
+            dst[16 + e] = h;
+            dst[24 + e] = l;
+            if (xcol >= 0) {
+                accx[m].x = fmaf(re, gv[m].x, fmaf(-im, gv[m].y, accx[m].x));
+                accx[m].y = fmaf(re, gv[m].y, fmaf(im, gv[m].x, accx[m].y));
             }
         }
     };
-    auto load_group = [&](int grp, float4(&xa)[U][4], uint4(&gb)[U][CB][2]) {
+    uint4 gb0[U][CB][2], gb1[U][CB][2];
+    auto b_load = [&](int grp, uint4(&gb)[U][CB][2]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int step = min(grp * U + u, nsteps - 1);
-            const int kk = kb0 + 32 * step + 8 * kg;  // multiple of 8, < KKs
-            const float4 *xp = reinterpret_cast<const float4 *>(xrow + kk);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                xa[u][q] = xp[q];
             const size_t kbi = (size_t)(kb0 / 32 + step);
 #pragma unroll
             for (int b = 0; b < CB; ++b) {
@@ -258,26 +297,13 @@ __global__ __launch_bounds__(512) void k_contract_fwd_split(
             }
         }
     };
-    auto compute_group = [&](int grp, const float4(&xa)[U][4], const uint4(&gb)[U][CB][2]) {
+    auto compute_group = [&](int buf, const uint4(&gb)[U][CB][2]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int step = grp * U + u;
-            const int kk = kb0 + 32 * step + 8 * kg;
-            V8 arh, arl, aih, ail;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float4 q = xa[u][e / 2];
-                const bool ok = step < nsteps && kk + e < kb1;
-                const float re = ok ? ldexpf((e & 1) ? q.z : q.x, ex) : 0.f;
-                const float im = ok ? ldexpf((e & 1) ? q.w : q.y, ex) : 0.f;
-                S h, l;
-                split_lohi<P>(re, h, l);
-                arh[e] = h;
-                arl[e] = l;
-                split_lohi<P>(im, h, l);
-                aih[e] = h;
-                ail[e] = l;
-            }
+            const uint4 q0 = la[buf][u][lane][0], q1 = la[buf][u][lane][1];
+            const uint4 q2 = la[buf][u][lane][2], q3 = la[buf][u][lane][3];
+            const V8 arh = *reinterpret_cast<const V8 *>(&q0), arl = *reinterpret_cast<const V8 *>(&q1);
+            const V8 aih = *reinterpret_cast<const V8 *>(&q2), ail = *reinterpret_cast<const V8 *>(&q3);
             const V8 naih = neg16<V8, u16x8>(aih), nail = neg16<V8, u16x8>(ail);
 #pragma unroll
             for (int b = 0; b < CB; ++b) {
@@ -299,43 +325,46 @@ __global__ __launch_bounds__(512) void k_contract_fwd_split(
             }
         }
     };
-    // (measured: for this kernel, whose products wait on VALU conversions of
-    // the tile spectra, the plain double-buffered loop beats the straight-line
-    // form with scheduling barriers used by the other contractions)
-    if (ngroups > 0)
-        load_group(0, xa0, gb0);
+    a_load(0);
+    if (cwave)
+        b_load(0, gb0);
+    a_store(0, 0);
+    __syncthreads();
     for (int grp = 0; grp < ngroups; grp += 2) {
-        if (grp + 1 < ngroups)
-            load_group(grp + 1, xa1, gb1);
-        compute_group(grp, xa0, gb0);
-        column_group(grp, xa0);
-        if (grp + 1 < ngroups) {
-            if (grp + 2 < ngroups)
-                load_group(grp + 2, xa0, gb0);
-            compute_group(grp + 1, xa1, gb1);
-            column_group(grp + 1, xa1);
+        a_load(grp + 1);
+        if (cwave) {
+            b_load(grp + 1, gb1);
+            compute_group(0, gb0);
         }
+        a_store(grp + 1, 1);
+        __syncthreads();
+        a_load(grp + 2);
+        if (cwave) {
+            b_load(grp + 2, gb0);
+            compute_group(1, gb1);
+        }
+        a_store(grp + 2, 0);
+        __syncthreads();
     }
     // D[t][c] rows t0 + 4 kg + i carry the scale 2^(xexp[row] + gexp[k])
     float2 *yk = Yp + ((size_t)s * nf + k) * nt * NN;
-    // lone column: lane (t = col, kg) holds tile t's partial over its kk
-    // slice of this wave's steps; sum over kg, then over the waves in order
     if (xcol >= 0) {
-        __shared__ float2 colsum[8][16];
-        accx.x += __shfl_xor(accx.x, 16, 64);
-        accx.y += __shfl_xor(accx.y, 16, 64);
-        accx.x += __shfl_xor(accx.x, 32, 64);
-        accx.y += __shfl_xor(accx.y, 32, 64);
-        if (kg == 0)
-            colsum[wave][col] = accx;
+        // lone column: the slots' partial sums per tile, in element order
+#pragma unroll
+        for (int m = 0; m < KS; ++m)
+            if (live[m])
+                colred[tid + m * nthr] = accx[m];
         __syncthreads();
-        if (wave == 0 && kg == 0 && t0 + col < nt) {
-            float2 a = colsum[0][col];
-            for (int w = 1; w < nw; ++w) {
-                a.x += colsum[w][col].x;
-                a.y += colsum[w][col].y;
-            }
-            yk[(size_t)(t0 + col) * NN + xcol] = a;
+        if (tid < 16 && t0 + tid < nt) {
+            float2 a = make_float2(0.f, 0.f);
+            for (int u = 0; u < U; ++u)
+                for (int q = 0; q < 4; ++q)
+                    for (int e = 0; e < 8; ++e) {
+                        const float2 v = colred[u * 512 + (q * 16 + tid) * 8 + e];
+                        a.x += v.x;
+                        a.y += v.y;
+                    }
+            yk[(size_t)(t0 + tid) * NN + xcol] = a;
         }
     }
     const int gx = gexp[k];
@@ -367,13 +396,16 @@ __host__ __device__ __forceinline__ int split_adj_chunks(int ncc, int U)
 // per block into LDS, zero past NN), B = Hb fragments (16 c x 16 kk), CB
 // blocks of kk per wave, U prefetched steps in a straight-line
 // double-buffered loop (an odd last group has no partner; chunks past ncc
-// meet zeros in LDS).
+// meet zeros in LDS).  A block covers `ranges` kk ranges from one staging of
+// R; three blocks per CU are asked of the register allocator (the loop over
+// ranges otherwise costs one: measured 0.636 against 0.696 ms).
 template <class P, int CB, int U>
-__global__ __launch_bounds__(256) void k_contract_adj_split(
+__global__ __launch_bounds__(256, 3) void k_contract_adj_split(
     const cplx16<typename P::S> *__restrict__ Hb, const float2 *__restrict__ Rs,
     const unsigned *__restrict__ rmax, const int *__restrict__ gexp, float2 *__restrict__ B,
     int NN, int NNp, int KK, int KKs, int nkb, int nt, const int *__restrict__ skip, FreqMap fm,
-    const float2 *__restrict__ Hx, int xc, int KKb, size_t mstride)
+    const float2 *__restrict__ Hx, int xc, int KKb, size_t mstride, size_t osk, size_t ost,
+    int ranges)
 {
     if (skip && *skip)
         return;
@@ -410,113 +442,119 @@ __global__ __launch_bounds__(256) void k_contract_adj_split(
         dst[3] = lo;
     }
     __syncthreads();
-    int kbk[CB];
-    bool k_ok[CB];
-#pragma unroll
-    for (int b = 0; b < CB; ++b) {
-        const int kb = (by * nwaves + wave) * CB + b;
-        k_ok[b] = kb < nkb;
-        kbk[b] = min(kb, nkb - 1);
-    }
-    f32x4v accr[CB], acci[CB];
-#pragma unroll
-    for (int b = 0; b < CB; ++b) {
-        accr[b] = f32x4v{0.f, 0.f, 0.f, 0.f};
-        acci[b] = f32x4v{0.f, 0.f, 0.f, 0.f};
-    }
-    const size_t fbase = (size_t)k * ncc * nkb;
-    const int ngroups = ncl / U;
-    uint4 gb0[U][CB], gb1[U][CB];
-    auto load_group = [&](int grp, uint4(&gb)[U][CB]) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int cc = min(grp * U + u, ncc - 1);
-#pragma unroll
-            for (int b = 0; b < CB; ++b)
-                gb[u][b] = *reinterpret_cast<const uint4 *>(
-                    Hb + ((fbase + (size_t)cc * nkb + kbk[b]) * 64 + lane) * 4);
-        }
-    };
-    auto compute_group = [&](int grp, const uint4(&gb)[U][CB]) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int cc = grp * U + u;
-            const S *src = ra + (size_t)(cc * 64 + lane) * 16;
-            V4 rrh, rrl, rih, ril;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                rrh[e] = src[4 * e + 0];
-                rrl[e] = src[4 * e + 1];
-                rih[e] = src[4 * e + 2];
-                ril[e] = src[4 * e + 3];
-            }
-            const V4 nrrh = neg16<V4, u16x4>(rrh), nrrl = neg16<V4, u16x4>(rrl);
-            V4 gr[CB], gi[CB];
-#pragma unroll
-            for (int b = 0; b < CB; ++b) {
-                const cplx16<S> *hp = reinterpret_cast<const cplx16<S> *>(&gb[u][b]);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    gr[b][e] = hp[e].re;
-                    gi[b][e] = hp[e].im;
-                }
-            }
-            // conj(G) R = (Gr Rr + Gi Ri) + i (Gr Ri - Gi Rr), product-major
-#pragma unroll
-            for (int b = 0; b < CB; ++b) {
-                accr[b] = P::m16(rrh, gr[b], accr[b]);
-                acci[b] = P::m16(rih, gr[b], acci[b]);
-            }
-#pragma unroll
-            for (int b = 0; b < CB; ++b) {
-                accr[b] = P::m16(rrl, gr[b], accr[b]);
-                acci[b] = P::m16(ril, gr[b], acci[b]);
-            }
-#pragma unroll
-            for (int b = 0; b < CB; ++b) {
-                accr[b] = P::m16(rih, gi[b], accr[b]);
-                acci[b] = P::m16(nrrh, gi[b], acci[b]);
-            }
-#pragma unroll
-            for (int b = 0; b < CB; ++b) {
-                accr[b] = P::m16(ril, gi[b], accr[b]);
-                acci[b] = P::m16(nrrl, gi[b], acci[b]);
-            }
-        }
-    };
-    load_group(0, gb0);
-    for (int grp = 0; grp < ngroups; grp += 2) {
-        load_group(grp + 1, gb1);
-        __builtin_amdgcn_sched_barrier(0);
-        compute_group(grp, gb0);
-        __builtin_amdgcn_sched_barrier(0);
-        load_group(grp + 2, gb0);
-        __builtin_amdgcn_sched_barrier(0);
-        if (grp + 1 < ngroups)  // an odd last group has no partner
-            compute_group(grp + 1, gb1);
-        __builtin_amdgcn_sched_barrier(0);
-    }
-    float2 *bk = B + (size_t)k * nt * KKs;   // rows of KKs: 128-byte aligned
-    const int gx = gexp[k];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int tt = t0 + 4 * kg + i;
-        if (tt >= nt)
-            continue;
-        const int sc = -(f16_scale_exp(__uint_as_float(rowmax_of(rmax, mstride, (size_t)k * nt + tt))) + gx);
-        // the lone reduction index xc (if any), in float32: + R[t][xc] conj(H[xc][kk])
-        const float2 r = xc >= 0 ? Rs[((size_t)k * nt + tt) * NN + xc] : make_float2(0.f, 0.f);
+    // `ranges` kk ranges per block, all from the R staged once above
+    for (int rg = 0; rg < ranges; ++rg) {
+        const int kbw = ((by * ranges + rg) * nwaves + wave) * CB;
+        if (kbw >= nkb)
+            break;  // (wave-uniform; no barriers below)
+        int kbk[CB];
+        bool k_ok[CB];
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
-            const int kk = 16 * kbk[b] + col;
-            float2 o = make_float2(ldexpf(accr[b][i], sc), ldexpf(acci[b][i], sc));
-            if (xc >= 0) {
-                const float2 h = Hx[(size_t)k * KKb + 16 * kbk[b] + col];
-                o.x = fmaf(r.x, h.x, fmaf(r.y, h.y, o.x));
-                o.y = fmaf(r.y, h.x, fmaf(-r.x, h.y, o.y));
+            const int kb = kbw + b;
+            k_ok[b] = kb < nkb;
+            kbk[b] = min(kb, nkb - 1);
+        }
+        f32x4v accr[CB], acci[CB];
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            accr[b] = f32x4v{0.f, 0.f, 0.f, 0.f};
+            acci[b] = f32x4v{0.f, 0.f, 0.f, 0.f};
+        }
+        const size_t fbase = (size_t)k * ncc * nkb;
+        const int ngroups = ncl / U;
+        uint4 gb0[U][CB], gb1[U][CB];
+        auto load_group = [&](int grp, uint4(&gb)[U][CB]) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int cc = min(grp * U + u, ncc - 1);
+#pragma unroll
+                for (int b = 0; b < CB; ++b)
+                    gb[u][b] = *reinterpret_cast<const uint4 *>(
+                        Hb + ((fbase + (size_t)cc * nkb + kbk[b]) * 64 + lane) * 4);
             }
-            if (k_ok[b] && kk < KK)
-                bk[(size_t)tt * KKs + kk] = o;
+        };
+        auto compute_group = [&](int grp, const uint4(&gb)[U][CB]) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int cc = grp * U + u;
+                const S *src = ra + (size_t)(cc * 64 + lane) * 16;
+                V4 rrh, rrl, rih, ril;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    rrh[e] = src[4 * e + 0];
+                    rrl[e] = src[4 * e + 1];
+                    rih[e] = src[4 * e + 2];
+                    ril[e] = src[4 * e + 3];
+                }
+                const V4 nrrh = neg16<V4, u16x4>(rrh), nrrl = neg16<V4, u16x4>(rrl);
+                V4 gr[CB], gi[CB];
+#pragma unroll
+                for (int b = 0; b < CB; ++b) {
+                    const cplx16<S> *hp = reinterpret_cast<const cplx16<S> *>(&gb[u][b]);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        gr[b][e] = hp[e].re;
+                        gi[b][e] = hp[e].im;
+                    }
+                }
+                // conj(G) R = (Gr Rr + Gi Ri) + i (Gr Ri - Gi Rr), product-major
+#pragma unroll
+                for (int b = 0; b < CB; ++b) {
+                    accr[b] = P::m16(rrh, gr[b], accr[b]);
+                    acci[b] = P::m16(rih, gr[b], acci[b]);
+                }
+#pragma unroll
+                for (int b = 0; b < CB; ++b) {
+                    accr[b] = P::m16(rrl, gr[b], accr[b]);
+                    acci[b] = P::m16(ril, gr[b], acci[b]);
+                }
+#pragma unroll
+                for (int b = 0; b < CB; ++b) {
+                    accr[b] = P::m16(rih, gi[b], accr[b]);
+                    acci[b] = P::m16(nrrh, gi[b], acci[b]);
+                }
+#pragma unroll
+                for (int b = 0; b < CB; ++b) {
+                    accr[b] = P::m16(ril, gi[b], accr[b]);
+                    acci[b] = P::m16(nrrl, gi[b], acci[b]);
+                }
+            }
+        };
+        load_group(0, gb0);
+        for (int grp = 0; grp < ngroups; grp += 2) {
+            load_group(grp + 1, gb1);
+            __builtin_amdgcn_sched_barrier(0);
+            compute_group(grp, gb0);
+            __builtin_amdgcn_sched_barrier(0);
+            load_group(grp + 2, gb0);
+            __builtin_amdgcn_sched_barrier(0);
+            if (grp + 1 < ngroups)  // an odd last group has no partner
+                compute_group(grp + 1, gb1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        float2 *bk = B + (size_t)k * osk;   // rows of KKs: 128-byte aligned
+        const int gx = gexp[k];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int tt = t0 + 4 * kg + i;
+            if (tt >= nt)
+                continue;
+            const int sc = -(f16_scale_exp(__uint_as_float(rowmax_of(rmax, mstride, (size_t)k * nt + tt))) + gx);
+            // the lone reduction index xc (if any), in float32: + R[t][xc] conj(H[xc][kk])
+            const float2 r = xc >= 0 ? Rs[((size_t)k * nt + tt) * NN + xc] : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                const int kk = 16 * kbk[b] + col;
+                float2 o = make_float2(ldexpf(accr[b][i], sc), ldexpf(acci[b][i], sc));
+                if (xc >= 0) {
+                    const float2 h = Hx[(size_t)k * KKb + 16 * kbk[b] + col];
+                    o.x = fmaf(r.x, h.x, fmaf(r.y, h.y, o.x));
+                    o.y = fmaf(r.y, h.x, fmaf(-r.x, h.y, o.y));
+                }
+                if (k_ok[b] && kk < KK)
+                    bk[(size_t)tt * ost + kk] = o;
+            }
         }
     }
 }

@@ -811,7 +811,7 @@ __global__ __launch_bounds__(256) void k_contract_adj(const float4 *__restrict__
                                                       int KKs, int NCp, int nt, int ranges,
                                                       const int *__restrict__ skip, FreqMap fm,
                                                       const float2 *__restrict__ Hx, int xc,
-                                                      int KKb)
+                                                      int KKb, size_t osk, size_t ost)
 {
     if (skip && *skip)
         return;
@@ -857,7 +857,7 @@ __global__ __launch_bounds__(256) void k_contract_adj(const float4 *__restrict__
         rx[i] = xc >= 0 ? Rs[((size_t)k * nt + tt) * NN + xc] : make_float2(0.f, 0.f);
     }
     const float4 *fk = Fb + (size_t)k * npairs * nkb * 64;
-    float2 *bk = B + (size_t)k * nt * KKs;   // rows of KKs: 128-byte aligned
+    float2 *bk = B + (size_t)k * osk;   // rows of KKs: 128-byte aligned
     const int RB = nwaves * CB;  // column blocks per range (the packing's RB)
     for (int r = 0; r < ranges; ++r) {
         const int kb0 = ((by * ranges + r) * nwaves + wave) * CB;
@@ -990,7 +990,7 @@ __global__ __launch_bounds__(256) void k_contract_adj(const float4 *__restrict__
             for (int i = 0; i < 4; ++i) {
                 const int tt = t0 + 4 * kq + i;
                 if (tt < nt)
-                    bk[(size_t)tt * KKs + kk] = make_float2(accr[b][i], acci[b][i]);
+                    bk[(size_t)tt * ost + kk] = make_float2(accr[b][i], acci[b][i]);
             }
         }
     }
@@ -2705,6 +2705,10 @@ static int pick_q(const lfrl_plan_desc *d, size_t lds_max, int *q_out)
 static int pick_split(const Geo &g)
 {
     int s = (2048 + g.nf - 1) / g.nf;
+    // tuning override: LFRL_SPLIT_K (reduction chunks of the forward contraction)
+    if (const char *e = getenv("LFRL_SPLIT_K"))
+        if (atoi(e) > 0)
+            s = atoi(e);
     s = std::max(1, std::min(s, (g.KK + 255) / 256));
     return s;
 }
@@ -3372,6 +3376,16 @@ extern "C" int lfrl_plan(lfrl_plan_t *out, const lfrl_plan_desc *desc, const flo
         return rc;
     p->tune_ms = tune_ms;
     p->tune_candidates = tried;
+    // the graph-capture stream and the early-stop events, made here so that
+    // later calls create nothing
+    hipError_t e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+    for (hipEvent_t &ev : p->chunk_ev)
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        free_plan(p);
+        return set_error(LFRL_ERR_DEVICE, "plan stream/events: %s", hipGetErrorString(e));
+    }
     *out = p;
     return LFRL_OK;
 }
@@ -3456,7 +3470,7 @@ static int prof_event(lfrl_plan_s *p, int which, hipStream_t st)
         hipLaunchKernelGGL((k_contract_adj<CBV, UV>), grid, dim3(64 * kAdjWaves), lds, st,       \
                            (const float4 *)p->Fb, (const float2 *)p->Rs, p->X, g.NN, g.KK,      \
                            g.KKs, g.NCm, nt, ranges, skip, freq_map(g.Q), (const float2 *)p->Hx, \
-                           g.xc, g.KKb);                                                         \
+                           g.xc, g.KKb, osk, ost);                                               \
         launched = true;                                                                         \
     }
 #define LFRL_ADJ_CASES(CBV) LFRL_ADJ_CASE(CBV, 1) LFRL_ADJ_CASE(CBV, 2) LFRL_ADJ_CASE(CBV, 4)
@@ -3539,7 +3553,8 @@ static int run_forward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipSt
         kchunk = (kchunk + 31) / 32 * 32;
     const int split2 = (g.KK + kchunk - 1) / kchunk;
     const int fcb = p->split ? p->hfwd_cb : p->fwd_cb;
-    const int nwaves = (g.NNm / 16 + fcb - 1) / fcb;
+    // (the split kernel converts its A fragments with at least 5 waves)
+    const int nwaves = std::max((g.NNm / 16 + fcb - 1) / fcb, p->split ? 5 : 1);
     const dim3 grid(unique_freqs(g.Q), split2, (nt + 15) / 16);
     const dim3 block(64 * nwaves);
     if (p->prof) {
@@ -3618,16 +3633,16 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
                            g.Q, g.QH, g.T, g.hD, nt, g.NN, p->Rs, p->tw);
     LAUNCH_CHECK("k_vol_r2c(image)");
     const int *skip = n == 1 ? io[0].skip : nullptr;
+    // the back-projected tile spectra B, frequency-major [k][t][KKs] (measured
+    // no faster tile-major)
+    const size_t osk = (size_t)g.KKs * nt, ost = (size_t)g.KKs;
     const int acb = p->split ? p->hadj_cb : p->adj_cb;
     const int kk_per_range = 16 * acb * kAdjWaves;
     const int nrange = (g.KK + kk_per_range - 1) / kk_per_range;
-    // FP32: each block stages R once and covers `ranges` kk ranges, as many as
-    // keep about 2048 blocks in the launch
-    int ranges = 1;
-    if (!p->split) {
-        const long long blocks1 = (long long)unique_freqs(g.Q) * nrange * ((nt + 15) / 16);
-        ranges = (int)std::max(1LL, std::min(4LL, blocks1 / 2048));
-    }
+    // each block stages R once and covers `ranges` kk ranges, as many as keep
+    // about 2048 blocks in the launch (at most 4)
+    const long long blocks1 = (long long)unique_freqs(g.Q) * nrange * ((nt + 15) / 16);
+    const int ranges = (int)std::max(1LL, std::min(4LL, blocks1 / 2048));
     const dim3 grid(unique_freqs(g.Q), (nrange + ranges - 1) / ranges, (nt + 15) / 16);
     // FP32: rows of R staged in LDS, an even number of register groups of
     // 8 * adj_u reduction indices (as the kernel assumes), row stride kRsStride
@@ -3648,7 +3663,8 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
                        (const cplx16<PT::S> *)p->Hb, (const float2 *)p->Rs,                      \
                        (const unsigned *)p->rmax, (const int *)p->gexp, p->X, g.NN, g.NNm,      \
                        g.KK, g.KKs, (g.KK + 15) / 16, nt, skip, freq_map(g.Q),                   \
-                       (const float2 *)p->Hx, g.xcol, g.KKb, (size_t)g.nf * nt)
+                       (const float2 *)p->Hx, g.xcol, g.KKb, (size_t)g.nf * nt, osk, ost,      \
+                       ranges)
 #define LFRL_HADJ_CASE(CBV, UV)                                                                  \
     if (p->hadj_cb == CBV && p->hadj_u == UV) {                                                  \
         if (p->bf16)                                                                             \
@@ -3672,14 +3688,13 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
         if (rc)
             return rc;
     }
-    // B[k][t][kk], rows of KKs
-    const size_t sk = (size_t)g.KKs * nt;
+    // B, rows of KKs at k * osk + t * ost
     if (p->use_fft)
         launch_c2r_fft(g.Q, dim3(nt * g.Nz * g.N), p->thr_c2r, p->lds_c2r_bytes, st, batch, p->X,
-                       (size_t)0, 1, sk, g.KKs, 1, g.N, g.Nz, g.T, g.hD, p->tw);
+                       (size_t)0, 1, osk, ost, 1, g.N, g.Nz, g.T, g.hD, p->tw);
     else
         hipLaunchKernelGGL(k_c2r, dim3(nt, g.Nz * g.N), dim3(256), p->lds_c2r_bytes, st, batch,
-                           p->X, (size_t)0, 1, sk, (size_t)g.KKs, (size_t)1, g.N, g.Q, g.QH, g.T,
+                           p->X, (size_t)0, 1, osk, ost, (size_t)1, g.N, g.Q, g.QH, g.T,
                            g.hD, p->tw);
     LAUNCH_CHECK("k_c2r(backward)");
     return LFRL_OK;
