@@ -21,7 +21,53 @@ constexpr int radix_of()
                                                          : (L % 7 == 0) ? 7 : L;
 }
 
-// exp(SIGN * 2 pi i m / Q) from the table tw[m] = (cos, sin)(2 pi m / Q)
+// cos and sin of 2 pi m / Q as compile-time constants: Taylor series in double
+// of the angle reduced to (-pi, pi], rounded once to float.  Inside the
+// unrolled transforms m is a constant, so a twiddle is an immediate operand
+// rather than a table load.
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double taylor_cos(double x)
+{
+    double t = 1.0, s = 1.0;
+    for (int n = 1; n <= 30; ++n) {
+        t *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
+        s += t;
+    }
+    return s;
+}
+constexpr double taylor_sin(double x)
+{
+    double t = x, s = x;
+    for (int n = 1; n <= 30; ++n) {
+        t *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
+        s += t;
+    }
+    return s;
+}
+template <int Q>
+struct TwTable {
+    float c[Q], s[Q];
+    constexpr TwTable() : c(), s()
+    {
+        for (int m = 0; m < Q; ++m) {
+            const int mm = 2 * m > Q ? m - Q : m;
+            const double a = kTwoPi * mm / Q;
+            c[m] = (float)taylor_cos(a);
+            s[m] = (float)taylor_sin(a);
+        }
+    }
+};
+
+// exp(SIGN * 2 pi i m / Q), m a compile-time constant after unrolling
+template <int Q, int SIGN>
+__device__ __forceinline__ float2 twid_c(int m)
+{
+    constexpr TwTable<Q> t{};
+    return make_float2(t.c[m], SIGN > 0 ? t.s[m] : -t.s[m]);
+}
+
+// exp(SIGN * 2 pi i m / n) from a table tw[m] = (cos, sin)(2 pi m / n) (for
+// transforms whose length is known only at run time)
 template <int SIGN>
 __device__ __forceinline__ float2 twid(const float2 *__restrict__ tw, int m)
 {
@@ -139,7 +185,7 @@ __device__ __forceinline__ void dft_small(float2 (&v)[R], const float2 *__restri
             float2 acc = v[0];
 #pragma unroll
             for (int q = 1; q < R; ++q) {
-                const float2 w = twid<SIGN>(tw, ((p * q) % R) * (Q / R));
+                const float2 w = twid_c<Q, SIGN>(((p * q) % R) * (Q / R));
                 acc.x = fmaf(v[q].x, w.x, fmaf(-v[q].y, w.y, acc.x));
                 acc.y = fmaf(v[q].x, w.y, fmaf(v[q].y, w.x, acc.y));
             }
@@ -166,7 +212,7 @@ __device__ __forceinline__ void stage(const float2 (&in)[Q], float2 (&out)[Q],
         if (k != 0) {
 #pragma unroll
             for (int r = 1; r < R; ++r)
-                v[r] = cmulf(v[r], twid<SIGN>(tw, (k * r * (Q / (Ns * R))) % Q));
+                v[r] = cmulf(v[r], twid_c<Q, SIGN>((k * r * (Q / (Ns * R))) % Q));
         }
         dft_small<R, SIGN, Q>(v, tw);
         const int base = (j / Ns) * Ns * R + k;
