@@ -2214,6 +2214,21 @@ static int round64(int v)
     return (v + 63) / 64 * 64;
 }
 
+// LDS of the inverse transform's staged epilogue inputs (two arrays of the
+// tile's output pixels, rounded up to whole wave loads).
+static size_t c2r_stage_bytes(const Geo &g)
+{
+    return (size_t)2 * round64(g.T * g.T * g.N) * 4;
+}
+
+// Stage the epilogue inputs when the larger LDS still admits as many blocks
+// per CU (of 160 KiB, up to the four that the registers allow) as without.
+static bool c2r_stage_fits(const Geo &g, size_t lds_max)
+{
+    const size_t cu = 160 * 1024, base = lds_c2r_fft(g), st = base + c2r_stage_bytes(g);
+    return st <= lds_max && cu / st >= std::min<size_t>(4, cu / base);
+}
+
 // One thread per row pair / column of a tile; the kernels are built for at
 // most kFftMaxThreads threads per block (which leaves 256 VGPRs per thread).
 static constexpr int kFftMaxThreads = 512;
@@ -2273,13 +2288,13 @@ static void launch_r2c_fft(int Q, dim3 grid, int block, size_t lds, hipStream_t 
 static void launch_c2r_fft(int Q, dim3 grid, int block, size_t lds, hipStream_t st,
                            const TileBatch &batch, const float2 *spec, size_t split_stride,
                            int nsplit, size_t sk, size_t stile, size_t sc, int N, int planes,
-                           int T, int hD, const float2 *tw)
+                           int T, int hD, const float2 *tw, int stage)
 {
     switch (Q) {
 #define LFRL_CASE(q)                                                                        \
     case q:                                                                                 \
         hipLaunchKernelGGL(k_c2r_fft<q>, grid, dim3(block), lds, st, batch, spec,            \
-                           split_stride, nsplit, sk, stile, sc, N, planes, T, hD, tw);        \
+                           split_stride, nsplit, sk, stile, sc, N, planes, T, hD, tw, stage); \
         break;
         LFRL_FFT_Q_LIST(LFRL_CASE)
 #undef LFRL_CASE
@@ -2551,6 +2566,7 @@ struct lfrl_plan_s {
     int *gexp = nullptr;                // per-frequency exponents of the FP16 spectra
     unsigned *xmax = nullptr, *rmax = nullptr;  // per-(frequency, tile) maxima of tile spectra
     int thr_r2c = 256, thr_c2r = 256;
+    int c2r_stage = 0;        // inverse transform stages its epilogue inputs in LDS
     double tune_ms = 0.0;     // measured projection pair at the chosen tile (autotuned plans)
     // lfrl_deconvolve runs replayed from a captured graph (fixed-length stop modes)
     hipStream_t cap_stream = nullptr;
@@ -3186,7 +3202,10 @@ static int plan_build(lfrl_plan_s **out, const lfrl_plan_desc *desc, int q, cons
     if (p->use_fft) {
         p->lds_r2c_bytes = lds_r2c_fft(g);
         p->lds_r2c_vol_bytes = lds_r2c_fft_planes(g);
-        p->lds_c2r_bytes = lds_c2r_fft(g);
+        p->c2r_stage = c2r_stage_fits(g, lmax);
+        if (const char *e = getenv("LFRL_C2R_STAGE"))  // tuning override: 0 or 1
+            p->c2r_stage = atoi(e) != 0 && c2r_stage_bytes(g) + lds_c2r_fft(g) <= lmax;
+        p->lds_c2r_bytes = lds_c2r_fft(g) + (p->c2r_stage ? c2r_stage_bytes(g) : 0);
         p->thr_r2c = threads_r2c_fft(g);
         p->thr_c2r = threads_c2r_fft(g);
     } else {
@@ -3226,9 +3245,10 @@ static int plan_build(lfrl_plan_s **out, const lfrl_plan_desc *desc, int q, cons
         const double th = 2.0 * M_PI * (double)m / (double)g.Q;
         tw[m] = make_float2((float)std::cos(th), (float)std::sin(th));
     }
-    set_lds_attrs(std::max(p->lds_r2c_bytes, p->lds_c2r_bytes));
+    const size_t lds_fft = std::max({p->lds_r2c_bytes, p->lds_r2c_vol_bytes, p->lds_c2r_bytes});
+    set_lds_attrs(lds_fft);
     if (p->use_fft)
-        set_fft_lds_attrs(g.Q, std::max(p->lds_r2c_bytes, p->lds_c2r_bytes));
+        set_fft_lds_attrs(g.Q, lds_fft);
     hipError_t e = hipMemcpyAsync(p->tw, tw.data(), g.Q * sizeof(float2), hipMemcpyHostToDevice, st);
     if (timing) {
         // zero spectra: the projections' cost does not depend on the values
@@ -3599,7 +3619,8 @@ static int run_forward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipSt
     const size_t sk = (size_t)g.NN * nt, split_stride = (size_t)g.nf * sk;
     if (p->use_fft)
         launch_c2r_fft(g.Q, dim3(nt * g.N), p->thr_c2r, p->lds_c2r_bytes, st, batch, p->Yp,
-                       split_stride, split2, sk, g.NN, 1, g.N, 1, g.T, g.hD, p->tw);
+                       split_stride, split2, sk, g.NN, 1, g.N, 1, g.T, g.hD, p->tw,
+                       p->c2r_stage);
     else
         hipLaunchKernelGGL(k_c2r, dim3(nt, g.N), dim3(256), p->lds_c2r_bytes, st, batch, p->Yp,
                            split_stride, split2, sk, (size_t)g.NN, (size_t)1, g.N, g.Q, g.QH, g.T,
@@ -3691,7 +3712,7 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
     // B, rows of KKs at k * osk + t * ost
     if (p->use_fft)
         launch_c2r_fft(g.Q, dim3(nt * g.Nz * g.N), p->thr_c2r, p->lds_c2r_bytes, st, batch, p->X,
-                       (size_t)0, 1, osk, ost, 1, g.N, g.Nz, g.T, g.hD, p->tw);
+                       (size_t)0, 1, osk, ost, 1, g.N, g.Nz, g.T, g.hD, p->tw, p->c2r_stage);
     else
         hipLaunchKernelGGL(k_c2r, dim3(nt, g.Nz * g.N), dim3(256), p->lds_c2r_bytes, st, batch,
                            p->X, (size_t)0, 1, osk, ost, (size_t)1, g.N, g.Q, g.QH, g.T,

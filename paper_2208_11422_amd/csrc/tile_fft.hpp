@@ -462,14 +462,16 @@ __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const TileBatch batch
         kstride = (size_t)KK * KKo;
     }
     __syncthreads();
-    // row pass: two real rows per thread packed as one complex sequence
+    // row pass: two real rows per thread packed as one complex sequence, rows
+    // s and s + npairs (so that the lanes of a wave load consecutive rows s:
+    // runs of N adjacent pixels per tile row)
     const int nseq = Q * N;
     const int npairs = (nseq + 1) / 2;
     float2 v[Q];
     int s0 = -1, s1 = -1;
     if (tid < npairs) {
-        s0 = 2 * tid;
-        s1 = (2 * tid + 1 < nseq) ? 2 * tid + 1 : -1;
+        s0 = tid;
+        s1 = (tid + npairs < nseq) ? tid + npairs : -1;
         const int i0 = s0 / N, p0 = s0 % N;
         const int i1 = s1 >= 0 ? s1 / N : 0, p1 = s1 >= 0 ? s1 % N : 0;
         if (mode == SRC_PLANES) {
@@ -558,7 +560,8 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
                                                   const float2 *__restrict__ spec,
                                                   size_t split_stride, int nsplit, size_t sk,
                                                   size_t stile, size_t sc, int N, int planes,
-                                                  int T, int hD, const float2 *__restrict__ twg)
+                                                  int T, int hD, const float2 *__restrict__ twg,
+                                                  int stage)
 {
     constexpr int QH = Q / 2 + 1;
     extern __shared__ float smem[];
@@ -579,6 +582,29 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
     const float *__restrict__ aux1 = fj.aux1;
     const int mode = fj.mode;
     const float bg = fj.bg;
+    // epilogue geometry: whole pixel rows of the tile; the plane's base
+    // pointers are uniform and pixel offsets are 32-bit (a plane is < 2^30 pixels)
+    const int Ly = H / N, Lx = W / N;
+    const int rowpix = T * N;
+    const int ototal = T * rowpix;
+    const size_t plane_off = (mode == EPI_RATIO) ? 0 : (size_t)j * H * W;
+    const float *__restrict__ a0p = aux0 + plane_off;
+    const float *__restrict__ a1p = aux1 + plane_off;
+    float *__restrict__ dp = dst + plane_off;
+    // pixel offset of output idx (clamped into the image) and whether it is kept
+    auto epi_pixel = [&](int idx, bool &ok) -> unsigned {
+        const int ti = idx / rowpix, rem = idx % rowpix;
+        const int Lr = ty * T + ti, Lc = tx * T + rem / N;
+        ok = Lr < Ly && Lc < Lx;
+        const int pr = min(N * Lr + ar, H - 1), pc = min(N * tx * T + rem, W - 1);
+        return (unsigned)pr * (unsigned)W + (unsigned)pc;
+    };
+    // With `stage`, the epilogue inputs go straight from memory into LDS
+    // (a0s, a1s after obuf, 64 pixels per wave-wide load), issued right after
+    // the spectrum loads so that their latency overlaps both transforms; they
+    // are waited for before the barrier that precedes the epilogue.
+    const int ostage = (ototal + 63) / 64 * 64;
+    float *a0s = obuf + (size_t)T * T * N, *a1s = a0s + ostage;
     for (int i = tid; i < Q; i += blockDim.x)
         tw[i] = twg[i];
     __syncthreads();
@@ -587,8 +613,9 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
     // inverse along tile rows (ku -> i) for column (kv, p), keeping the T valid
     // rows: each thread loads its Q spectrum values straight from memory (Q
     // independent loads in flight, no staging buffer), summing split partials
-    if (tid < QH * N) {
-        const int kv = tid / N, p = tid % N;
+    const bool colthr = tid < QH * N;
+    const int kv = tid / N, p = tid % N;
+    if (colthr) {
         // a uniform base per row ku (scalar registers) plus one 32-bit byte
         // offset per thread (the launch keeps QH * sk * 8 below 2^32): the
         // loads need no 64-bit address per element
@@ -616,6 +643,21 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
                     }
             }
         }
+    }
+    // (every lane of a wave takes part in a direct-to-LDS load)
+    if (stage && mode != EPI_STORE) {
+        const int nw = blockDim.x >> 6, wave = tid >> 6, lane = tid & 63;
+        for (int c = wave; c < ostage / 64; c += nw) {
+            bool ok;
+            const unsigned o = epi_pixel(min(64 * c + lane, ototal - 1), ok);
+            __builtin_amdgcn_global_load_lds(
+                a0p + o, (__attribute__((address_space(3))) void *)(a0s + 64 * c), 4, 0, 0);
+            if (mode >= EPI_UPDATE)
+                __builtin_amdgcn_global_load_lds(
+                    a1p + o, (__attribute__((address_space(3))) void *)(a1s + 64 * c), 4, 0, 0);
+        }
+    }
+    if (colthr) {
         // the redundant rows of the columns kv = 0 and kv = Q/2 were never
         // written (see FreqMap): the conjugates of their partner rows, which
         // this thread holds, replace whatever was read there (a select, so
@@ -672,16 +714,31 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
             }
         }
     }
+    if (stage)  // this wave's direct-to-LDS loads have landed (vmcnt 0)
+        __builtin_amdgcn_s_waitcnt(0x0f70);
     __syncthreads();
-    // coalesced epilogue over whole pixel rows of the tile; the plane's base
-    // pointers are uniform and pixel offsets are 32-bit (a plane is < 2^30 pixels)
-    const int Ly = H / N, Lx = W / N;
-    const int rowpix = T * N;
-    const int ototal = T * rowpix;
-    const size_t plane_off = (mode == EPI_RATIO) ? 0 : (size_t)j * H * W;
-    const float *__restrict__ a0p = aux0 + plane_off;
-    const float *__restrict__ a1p = aux1 + plane_off;
-    float *__restrict__ dp = dst + plane_off;
+    if (stage) {
+        for (int idx = tid; idx < ototal; idx += blockDim.x) {
+            bool ok;
+            const unsigned o = epi_pixel(idx, ok);
+            if (!ok)
+                continue;
+            const float val = obuf[idx];
+            if (mode == EPI_STORE) {
+                dp[o] = val + bg;
+            } else if (mode == EPI_RATIO) {
+                const float m = val + bg;
+                dp[o] = m > 0.f ? a0s[idx] / m : 0.f;
+            } else if (mode == EPI_UPDATE) {
+                const float c = a1s[idx];
+                dp[o] = c > 0.f ? a0s[idx] * val / c : 0.f;
+            } else {
+                dp[o] = val > 0.f ? a0s[idx] * a1s[idx] / val : 0.f;
+            }
+        }
+        return;
+    }
+    // coalesced epilogue, inputs loaded in batches
     for (int base = tid; base < ototal; base += kEpiBatch * blockDim.x) {
         unsigned o[kEpiBatch];
         bool ok[kEpiBatch];
@@ -689,11 +746,8 @@ __global__ __launch_bounds__(512) void k_c2r_fft(const TileBatch batch,
 #pragma unroll
         for (int b = 0; b < kEpiBatch; ++b) {
             const int idx = min(base + b * (int)blockDim.x, ototal - 1);
-            const int ti = idx / rowpix, rem = idx % rowpix;
-            const int Lr = ty * T + ti, Lc = tx * T + rem / N;
-            ok[b] = base + b * (int)blockDim.x < ototal && Lr < Ly && Lc < Lx;
-            const int pr = min(N * Lr + ar, H - 1), pc = min(N * tx * T + rem, W - 1);
-            o[b] = (unsigned)pr * (unsigned)W + (unsigned)pc;
+            o[b] = epi_pixel(idx, ok[b]);
+            ok[b] = ok[b] && base + b * (int)blockDim.x < ototal;
             a0[b] = (mode != EPI_STORE) ? a0p[o[b]] : 0.f;
             a1[b] = (mode >= EPI_UPDATE) ? a1p[o[b]] : 0.f;
         }

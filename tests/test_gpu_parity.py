@@ -159,6 +159,38 @@ def test_rl_iterates_match_oracle(lf):
         plan.close()
 
 
+@pytest.mark.parametrize("n,ly,nz,k", [(5, 11, 5, 25), (15, 4, 2, 31)])
+def test_staged_epilogue_inputs_bitwise(lf, monkeypatch, n, ly, nz, k):
+    """The inverse tile DFT takes its epilogue inputs either staged in LDS by
+    direct loads (where the LDS admits it) or by batched register loads: the
+    same values bit for bit in every epilogue (store with a background, ratio,
+    RL update, ISRA), and both match the oracle's first RL iterate."""
+    import torch
+    psf = S.gaussian_psf(n, nz, k, seed=31 + n)
+    h = w = n * ly
+    rng = np.random.default_rng(8)
+    x = rng.uniform(0.0, 1.0, size=(nz, h, w)).astype(np.float32)
+    y = rng.uniform(0.5, 1.5, size=(h, w)).astype(np.float32)
+    outs = []
+    for stage in ("0", "1"):
+        monkeypatch.setenv("LFRL_C2R_STAGE", stage)
+        plan = lf.Plan(to_dev(psf), h, w)
+        try:
+            fx = plan.forward(to_dev(x))
+            v_rl, _ = plan.deconvolve(to_dev(y), 3, stop=lf.STOP_NONE, background=0.25)
+            v_isra, _ = plan.deconvolve(to_dev(y), 3, stop=lf.STOP_NONE, update=lf.UPDATE_ISRA)
+            v1, _ = plan.deconvolve(to_dev(y), 1, stop=lf.STOP_NONE)
+            torch.cuda.synchronize()
+            outs.append([t.cpu().numpy() for t in (fx, v_rl, v_isra, v1)])
+        finally:
+            plan.close()
+    monkeypatch.delenv("LFRL_C2R_STAGE")
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+    assert rel_l2(outs[1][0], oracle.forward(psf, x)) <= TOL
+    assert rel_l2(outs[1][3], oracle.rl(psf, y, 1)) <= TOL
+
+
 def test_rl_with_metric_matches_oracle(lf):
     """Metric trace, best iterate and stop decision over 30 iterations."""
     import torch
