@@ -174,7 +174,13 @@ typedef enum {
     LFRL_NORM_REGION = 1,  /* Frobenius norm of the coefficients in the region */
     LFRL_NORM_SPECTRAL = 2 /* largest singular value of the coefficient matrix
                               (equal to the image's: the DCT is orthonormal),
-                              by float64 Lanczos iteration; h + w <= 6144 */
+                              by float64 Lanczos iteration; h + w <= 6144.
+                              Images of 16384 pixels and more spread it over
+                              up to 32 workgroups that exchange partial sums
+                              through device memory and must be resident
+                              together; should they not be (a device crowded
+                              by other kernels), a bounded wait gives up and
+                              the metric is NaN instead of a hang */
 } lfrl_norm;
 
 typedef struct {
