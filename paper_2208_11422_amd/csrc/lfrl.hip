@@ -2250,15 +2250,41 @@ static bool fft_usable(const Geo &g, size_t lds_max)
            lds_c2r_fft(g) <= lds_max;
 }
 
+// The dynamic-LDS limit of a kernel holds for every later launch on the
+// device, while plans of one tile side (and different Nnum) need different
+// amounts: the limit is only ever raised (per kernel and device), so a plan
+// built later never lowers what an earlier one launches with.
+static void raise_lds_attr(const void *fn, size_t lds)
+{
+    struct Entry {
+        const void *fn;
+        int dev;
+        size_t lds;
+    };
+    static std::mutex mu;
+    static std::vector<Entry> set;
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(mu);
+    for (Entry &e : set)
+        if (e.fn == fn && e.dev == dev) {
+            if (lds > e.lds) {
+                (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                e.lds = lds;
+            }
+            return;
+        }
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    set.push_back({fn, dev, lds});
+}
+
 static void set_fft_lds_attrs(int Q, size_t lds)
 {
     switch (Q) {
 #define LFRL_CASE(q)                                                                        \
     case q:                                                                                 \
-        (void)hipFuncSetAttribute((const void *)k_r2c_fft<q>,                               \
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);    \
-        (void)hipFuncSetAttribute((const void *)k_c2r_fft<q>,                               \
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);    \
+        raise_lds_attr((const void *)k_r2c_fft<q>, lds);                                     \
+        raise_lds_attr((const void *)k_c2r_fft<q>, lds);                                     \
         break;
         LFRL_FFT_Q_LIST(LFRL_CASE)
 #undef LFRL_CASE
@@ -3134,9 +3160,9 @@ static int frame_alloc(Frame &f, const Geo &g, int h, int w, bool own_y)
 
 static void set_lds_attrs(size_t lds)
 {
-    (void)hipFuncSetAttribute((const void *)k_psf_r2c, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipFuncSetAttribute((const void *)k_vol_r2c, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipFuncSetAttribute((const void *)k_c2r, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    raise_lds_attr((const void *)k_psf_r2c, lds);
+    raise_lds_attr((const void *)k_vol_r2c, lds);
+    raise_lds_attr((const void *)k_c2r, lds);
 }
 
 // Allocate a plan for tile side q and build its spectra from `psf`.  With
@@ -3951,10 +3977,7 @@ static int run_metric(int nz, int h, int w, const float *vol, double xs, double 
     LAUNCH_CHECK("k_mip");
     if (norm == LFRL_NORM_SPECTRAL) {
         if (sp.nb > 0) {
-            static const hipError_t attr =
-                hipFuncSetAttribute((const void *)k_spectral_norm_mb,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSpecLds);
-            (void)attr;
+            raise_lds_attr((const void *)k_spectral_norm_mb, kSpecLds);
             hipLaunchKernelGGL(k_spectral_norm_mb, dim3(sp.nb), dim3(1024), sp.lds, st,
                                (const float *)mb.mip, h, w, sp.rpb, sp.steps,
                                reinterpret_cast<unsigned long long *>(mb.T1), skip,
@@ -3962,10 +3985,7 @@ static int run_metric(int nz, int h, int w, const float *vol, double xs, double 
             LAUNCH_CHECK("k_spectral_norm_mb");
         } else {
             const size_t lds = (size_t)(3 * std::min(h, w) + std::max(h, w)) * sizeof(double);
-            static const hipError_t attr = hipFuncSetAttribute(
-                (const void *)k_spectral_norm, hipFuncAttributeMaxDynamicSharedMemorySize,
-                (int)(2 * kSpectralMaxSides * sizeof(double)));
-            (void)attr;
+            raise_lds_attr((const void *)k_spectral_norm, 2 * kSpectralMaxSides * sizeof(double));
             hipLaunchKernelGGL(k_spectral_norm, dim3(1), dim3(1024), lds, st,
                                (const float *)mb.mip, h, w, kLanczosMaxSteps, skip, mb.n2p + nblk);
             LAUNCH_CHECK("k_spectral_norm");
@@ -5411,12 +5431,9 @@ extern "C" int lfrl_psf_compute(const lfrl_optics *o, const double *depths, floa
     const size_t lds_rows = ((size_t)n + w.G + (size_t)nl_rows * n) * sizeof(float2);
     const size_t lds_cols = ((size_t)n + (size_t)S * n) * sizeof(float2);
     const size_t lds_bin = ((size_t)n + (w.G + 1) / 2 + (size_t)nl_bin * n) * sizeof(float2);
-    (void)hipFuncSetAttribute((const void *)k_psf_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds_rows);
-    (void)hipFuncSetAttribute((const void *)k_psf_cols, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds_cols);
-    (void)hipFuncSetAttribute((const void *)k_psf_bin, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds_bin);
+    raise_lds_attr((const void *)k_psf_rows, lds_rows);
+    raise_lds_attr((const void *)k_psf_cols, lds_cols);
+    raise_lds_attr((const void *)k_psf_bin, lds_bin);
     for (int j = 0; j < nz; ++j) {
         const double2 *Uj = sc.U + (size_t)j * nrad;
         float *psf_j = psf + (size_t)j * nfield * K * K;

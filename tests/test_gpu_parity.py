@@ -363,6 +363,39 @@ def test_autotuned_plan(lf):
         tuned.close()
 
 
+def test_plans_of_one_tile_side_keep_their_lds(lf):
+    """Two plans with the same tile side and different Nnum need different
+    amounts of LDS in the same tile-DFT kernels; building the smaller one
+    after the larger must not lower what the larger launches with (here above
+    64 KiB)."""
+    import torch
+    q = 36
+    psf_a = random_psf(2, 15, 31, seed=41)          # 36 x 19 x 15 complex: 82 KB
+    ha = 15 * 4
+    rng = np.random.default_rng(43)
+    x = rng.uniform(0.0, 1.0, size=(2, ha, ha)).astype(np.float32)
+    y = rng.uniform(0.0, 1.0, size=(ha, ha)).astype(np.float32)
+    a = lf.Plan(to_dev(psf_a), ha, ha, tile_q=q)
+    try:
+        fa, ba = a.forward(to_dev(x)), a.backward(to_dev(y))
+        psf_b = random_psf(1, 3, 9, seed=42)
+        b = lf.Plan(to_dev(psf_b), 27, 27, tile_q=q)
+        try:
+            xb = rng.uniform(0.0, 1.0, size=(1, 27, 27)).astype(np.float32)
+            fb = b.forward(to_dev(xb))
+            torch.cuda.synchronize()
+            assert rel_l2(fb.cpu().numpy(), oracle.forward(psf_b, xb)) <= TOL
+        finally:
+            b.close()
+        fa2, ba2 = a.forward(to_dev(x)), a.backward(to_dev(y))
+        torch.cuda.synchronize()
+        assert torch.equal(fa, fa2) and torch.equal(ba, ba2)
+        assert rel_l2(fa.cpu().numpy(), oracle.forward(psf_a, x)) <= TOL
+        assert rel_l2(ba.cpu().numpy(), oracle.backward(psf_a, y)) <= TOL
+    finally:
+        a.close()
+
+
 def test_graph_replays_match_direct_launches(lf, monkeypatch):
     """Fixed-length runs replay a captured graph; every replay, with other
     work and synchronisations in between, equals the run with graphs off."""
