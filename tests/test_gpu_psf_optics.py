@@ -103,3 +103,36 @@ def test_psf_full_size_sampled(lf):
         assert np.linalg.norm(p - m) <= 1e-5 * np.linalg.norm(p)
         t = got[j, b, a].T
         assert np.linalg.norm(p - t) <= 1e-5 * np.linalg.norm(p)
+
+
+def test_computed_psf_drives_the_deconvolution(lf):
+    """The PSF set computed on the GPU is the plan's input as it stands (the
+    Fig. 1 path from optical parameters to a reconstruction): two RL
+    iterates with it match the oracle's RL on the same (downloaded) set."""
+    import torch
+
+    import lfrl_synth as S
+    import oracle
+    kw, depths = CASES[0]
+    o = O.Optics(**kw)
+    t = lf.psf_from_optics(wavelength=o.wavelength, na=o.na, n_medium=o.n_medium, mag=o.mag,
+                           d_ml=o.d_ml, f_ml=o.f_ml, nnum=o.nnum, ksize=o.ksize, depths=depths,
+                           osr=o.osr, nquad=o.nquad, unit_sum=True)
+    torch.cuda.synchronize()
+    psf = t.cpu().numpy()
+    n, nz = o.nnum, len(depths)
+    h = w = n * 9
+    x_true = S.bead_volume(nz, h, w, 12, seed=5)
+    y = S.measure(oracle.forward(psf, x_true), 500.0, 5.0, seed=6).astype(np.float32)
+    print(f"computed PSF {psf.shape} -> plan {h}x{w}", flush=True)
+    plan = lf.Plan(t, h, w)
+    try:
+        vol, rep = plan.deconvolve(torch.from_numpy(y).to(t.device), 2, stop=lf.STOP_NONE)
+        torch.cuda.synchronize()
+        got = vol.cpu().numpy().astype(np.float64)
+    finally:
+        plan.close()
+    want = oracle.rl(psf, y, 2)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print(f"x^2 rel L2 {err:.3e}", flush=True)
+    assert err <= TOL
