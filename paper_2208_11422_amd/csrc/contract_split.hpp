@@ -187,7 +187,7 @@ __global__ __launch_bounds__(512) void k_contract_fwd_split(
     const unsigned *__restrict__ xmax, const int *__restrict__ gexp, float2 *__restrict__ Yp,
     int NN, int NNp, int KK, int KKs, int nkb, int nt, int nf, int kchunk,
     const int *__restrict__ skip, FreqMap fm, const float2 *__restrict__ Gx, int xcol)
-// (xmax: kRowmaxSlots slots of nf * nt maxima, see k_r2c_fft)
+// (xmax: nf * nt maxima, see k_rowmax_reduce)
 {
     if (skip && *skip)
         return;
@@ -210,7 +210,6 @@ __global__ __launch_bounds__(512) void k_contract_fwd_split(
     const int kb1 = min(KK, kb0 + kchunk);
     const int nsteps = (kb1 - kb0 + 31) / 32;
     const int ngroups = (nsteps + U - 1) / U;
-    const size_t mstride = (size_t)nf * nt;
     int cbk[CB];
 #pragma unroll
     for (int b = 0; b < CB; ++b)
@@ -238,7 +237,7 @@ __global__ __launch_bounds__(512) void k_contract_fwd_split(
         const int L = (idx >> 3) & 63;
         const int tt = min(t0 + (L & 15), nt - 1);
         xs[m] = X + ((size_t)k * nt + tt) * KKs + kb0 + 8 * (L >> 4) + (idx & 7);
-        xe[m] = f16_scale_exp(__uint_as_float(rowmax_of(xmax, mstride, (size_t)k * nt + tt)));
+        xe[m] = f16_scale_exp(__uint_as_float(xmax[(size_t)k * nt + tt]));
     }
     const float2 *gxk = Gx + (xcol >= 0 ? (size_t)k * KKs + kb0 : 0);
     float2 xv[KS], gv[KS], accx[KS];
@@ -373,7 +372,7 @@ __global__ __launch_bounds__(512) void k_contract_fwd_split(
         const int tt = t0 + 4 * kg + i;
         if (tt >= nt)
             continue;
-        const int sc = -(f16_scale_exp(__uint_as_float(rowmax_of(xmax, mstride, (size_t)k * nt + tt))) + gx);
+        const int sc = -(f16_scale_exp(__uint_as_float(xmax[(size_t)k * nt + tt])) + gx);
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
             const int c = 16 * (wave * CB + b) + col;
@@ -404,8 +403,7 @@ __global__ __launch_bounds__(256, 3) void k_contract_adj_split(
     const cplx16<typename P::S> *__restrict__ Hb, const float2 *__restrict__ Rs,
     const unsigned *__restrict__ rmax, const int *__restrict__ gexp, float2 *__restrict__ B,
     int NN, int NNp, int KK, int KKs, int nkb, int nt, const int *__restrict__ skip, FreqMap fm,
-    const float2 *__restrict__ Hx, int xc, int KKb, size_t mstride, size_t osk, size_t ost,
-    int ranges)
+    const float2 *__restrict__ Hx, int xc, int KKb, size_t osk, size_t ost, int ranges)
 {
     if (skip && *skip)
         return;
@@ -430,7 +428,7 @@ __global__ __launch_bounds__(256, 3) void k_contract_adj_split(
         int ex = 0;
         if (c < NN && c < 16 * ncc && tt < nt) {
             v = Rs[((size_t)k * nt + tt) * NN + c];
-            ex = f16_scale_exp(__uint_as_float(rowmax_of(rmax, mstride, (size_t)k * nt + tt)));
+            ex = f16_scale_exp(__uint_as_float(rmax[(size_t)k * nt + tt]));
         }
         S h, lo;
         S *dst = ra + ((size_t)(cc * 64 + l) * 4 + e) * 4;
@@ -540,7 +538,7 @@ __global__ __launch_bounds__(256, 3) void k_contract_adj_split(
             const int tt = t0 + 4 * kg + i;
             if (tt >= nt)
                 continue;
-            const int sc = -(f16_scale_exp(__uint_as_float(rowmax_of(rmax, mstride, (size_t)k * nt + tt))) + gx);
+            const int sc = -(f16_scale_exp(__uint_as_float(rmax[(size_t)k * nt + tt])) + gx);
             // the lone reduction index xc (if any), in float32: + R[t][xc] conj(H[xc][kk])
             const float2 r = xc >= 0 ? Rs[((size_t)k * nt + tt) * NN + xc] : make_float2(0.f, 0.f);
 #pragma unroll

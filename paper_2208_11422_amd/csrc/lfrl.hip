@@ -2591,6 +2591,7 @@ struct lfrl_plan_s {
     cplx16<_Float16> *Hf = nullptr, *Hb = nullptr;  // 16-bit spectra in fragment order
     int *gexp = nullptr;                // per-frequency exponents of the FP16 spectra
     unsigned *xmax = nullptr, *rmax = nullptr;  // per-(frequency, tile) maxima of tile spectra
+    unsigned *rowpart = nullptr;                // their per-block parts (k_rowmax_reduce)
     int thr_r2c = 256, thr_c2r = 256;
     int c2r_stage = 0;        // inverse transform stages its epilogue inputs in LDS
     double tune_ms = 0.0;     // measured projection pair at the chosen tile (autotuned plans)
@@ -2882,10 +2883,10 @@ struct Sizes {
     size_t Ff = 0, Fb = 0;                      // FP32 fragment-ordered spectra
     size_t Hx = 0;                              // FP32: spectra row of the lone adjoint index
     size_t Gx = 0;                              // FP32: spectra column of the lone output column
-    size_t Hf = 0, Hb = 0, gexp = 0, rowmax = 0;  // split FP16 only
+    size_t Hf = 0, Hb = 0, gexp = 0, rowmax = 0, rowpart = 0;  // split FP16 only
     bool split = false;
     size_t resident() const { return (split ? Hf + Hb + gexp : Ff + Fb) + Hx + Gx + tw + psf; }
-    size_t workspace() const { return X + Yp + Rs + 2 * rowmax + frame; }
+    size_t workspace() const { return X + Yp + Rs + 2 * rowmax + rowpart + frame; }
 };
 
 static Sizes sizes_for(const Geo &g, int max_h, int max_w, int max_batch, int split, bool f16)
@@ -2910,7 +2911,9 @@ static Sizes sizes_for(const Geo &g, int max_h, int max_w, int max_batch, int sp
         s.Hf = (size_t)g.nf * g.KKs * g.NNm * sizeof(cplx16<_Float16>);
         s.Hb = (size_t)g.nf * g.NNm * ((g.KK + 15) / 16 * 16) * sizeof(cplx16<_Float16>);
         s.gexp = (size_t)g.nf * sizeof(int);
-        s.rowmax = (size_t)g.nf * nt * kRowmaxSlots * sizeof(unsigned);
+        s.rowmax = (size_t)g.nf * nt * sizeof(unsigned);
+        // per-block maxima of the volume transform (the image's fit in them)
+        s.rowpart = (size_t)g.Nz * g.N * nt * g.nf * sizeof(unsigned);
     }
     return s;
 }
@@ -2989,7 +2992,7 @@ static void free_plan(lfrl_plan_s *p)
     (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
     void *bufs[] = {p->Gf, p->Gb, p->Ff, p->Fb, p->Hx, p->Gx, p->tw, p->X, p->Yp, p->Rs, p->psf,
-                    p->Hf, p->Hb, p->gexp, p->xmax, p->rmax};
+                    p->Hf, p->Hb, p->gexp, p->xmax, p->rmax, p->rowpart};
     for (void *b : bufs)
         if (b)
             (void)hipFree(b);
@@ -3264,6 +3267,7 @@ static int plan_build(lfrl_plan_s **out, const lfrl_plan_desc *desc, int q, cons
         TRY(dalloc(&p->gexp, s.gexp));
         TRY(dalloc(&p->xmax, s.rowmax));
         TRY(dalloc(&p->rmax, s.rowmax));
+        TRY(dalloc(&p->rowpart, s.rowpart));
     }
     // twiddles exp(2 pi i m / Q), computed in double, rounded once
     std::vector<float2> tw(g.Q);
@@ -3578,21 +3582,21 @@ static int run_forward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipSt
     if (nt > p->max_tiles)
         return set_error(LFRL_ERR_ARG, "batch of %d tiles exceeds the plan capacity %d", nt,
                          p->max_tiles);
-    if (p->split) {
-        hipLaunchKernelGGL(k_zero_u32n, dim3(64), dim3(256), 0, st, p->xmax,
-                           (size_t)g.nf * nt * kRowmaxSlots);
-        LAUNCH_CHECK("k_zero_u32n");
-    }
+    // a launch of one frame stops with it; frames of a batch share the launch
+    const int *skip = n == 1 ? io[0].skip : nullptr;
     if (p->use_fft)
         launch_r2c_fft(g.Q, dim3(nt * g.Nz * g.N), p->thr_r2c, p->lds_r2c_vol_bytes, st, SRC_PLANES,
                        batch, nullptr, g.N, g.T, g.hD, nt, g.KKs, g.K, g.c0, g.KK, p->X, p->tw,
-                       p->split ? p->xmax : nullptr);
+                       p->split ? p->rowpart : nullptr);
     else
         hipLaunchKernelGGL(k_vol_r2c, dim3(nt, g.Nz * g.N), dim3(256), p->lds_r2c_bytes, st, batch,
                            g.N, g.Q, g.QH, g.T, g.hD, nt, g.KKs, p->X, p->tw);
     LAUNCH_CHECK("k_vol_r2c");
-    // a launch of one frame stops with it; frames of a batch share the launch
-    const int *skip = n == 1 ? io[0].skip : nullptr;
+    if (p->split) {
+        hipLaunchKernelGGL(k_rowmax_reduce, dim3((g.nf + 63) / 64, nt), dim3(1024), 0, st,
+                           (const unsigned *)p->rowpart, g.Nz * g.N, nt, g.nf, skip, p->xmax);
+        LAUNCH_CHECK("k_rowmax_reduce");
+    }
     int kchunk = 0;
     (void)contraction_split(p, &kchunk);
     if (p->split)
@@ -3666,20 +3670,20 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
     if (nt > p->max_tiles)
         return set_error(LFRL_ERR_ARG, "batch of %d tiles exceeds the plan capacity %d", nt,
                          p->max_tiles);
-    if (p->split) {
-        hipLaunchKernelGGL(k_zero_u32n, dim3(64), dim3(256), 0, st, p->rmax,
-                           (size_t)g.nf * nt * kRowmaxSlots);
-        LAUNCH_CHECK("k_zero_u32n");
-    }
+    const int *skip = n == 1 ? io[0].skip : nullptr;
     if (p->use_fft)
         launch_r2c_fft(g.Q, dim3(nt * g.N), p->thr_r2c, p->lds_r2c_vol_bytes, st, SRC_PLANES, batch,
                        nullptr, g.N, g.T, g.hD, nt, g.NN, g.K, g.c0, g.KK, p->Rs, p->tw,
-                       p->split ? p->rmax : nullptr);
+                       p->split ? p->rowpart : nullptr);
     else
         hipLaunchKernelGGL(k_vol_r2c, dim3(nt, g.N), dim3(256), p->lds_r2c_bytes, st, batch, g.N,
                            g.Q, g.QH, g.T, g.hD, nt, g.NN, p->Rs, p->tw);
     LAUNCH_CHECK("k_vol_r2c(image)");
-    const int *skip = n == 1 ? io[0].skip : nullptr;
+    if (p->split) {
+        hipLaunchKernelGGL(k_rowmax_reduce, dim3((g.nf + 63) / 64, nt), dim3(1024), 0, st,
+                           (const unsigned *)p->rowpart, g.N, nt, g.nf, skip, p->rmax);
+        LAUNCH_CHECK("k_rowmax_reduce");
+    }
     // the back-projected tile spectra B, frequency-major [k][t][KKs] (measured
     // no faster tile-major)
     const size_t osk = (size_t)g.KKs * nt, ost = (size_t)g.KKs;
@@ -3710,8 +3714,7 @@ static int run_backward(lfrl_plan_s *p, const FrameIO *io, int n, int mode, hipS
                        (const cplx16<PT::S> *)p->Hb, (const float2 *)p->Rs,                      \
                        (const unsigned *)p->rmax, (const int *)p->gexp, p->X, g.NN, g.NNm,      \
                        g.KK, g.KKs, (g.KK + 15) / 16, nt, skip, freq_map(g.Q),                   \
-                       (const float2 *)p->Hx, g.xcol, g.KKb, (size_t)g.nf * nt, osk, ost,      \
-                       ranges)
+                       (const float2 *)p->Hx, g.xcol, g.KKb, osk, ost, ranges)
 #define LFRL_HADJ_CASE(CBV, UV)                                                                  \
     if (p->hadj_cb == CBV && p->hadj_u == UV) {                                                  \
         if (p->bf16)                                                                             \

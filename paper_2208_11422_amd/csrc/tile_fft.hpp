@@ -358,16 +358,45 @@ __device__ __forceinline__ float keep_if(float v, bool keep)
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
 // Remap the linear block id so that every XCD works through one contiguous
 // range of work items: items that share cache lines then share an L2.
-// Slots of the per-(frequency, tile) maxima of tile spectra (see k_r2c_fft)
-static constexpr int kRowmaxSlots = 8;
-__device__ __forceinline__ unsigned rowmax_of(const unsigned *__restrict__ m, size_t slot_stride,
-                                              size_t i)
+// Per-(frequency, tile) maxima of tile spectra (split precision): every
+// forward tile-DFT block stores the maxima of its columns at each frequency,
+// rowpart[(grp * nt + tile) * Q*QH + k] (plain stores of the float bits,
+// grp = the block's column group), and k_rowmax_reduce folds the groups into
+// rowmax[k * nt + tile].  (Device-scope atomic maxima instead cost one 32-byte
+// memory write each: 3.1 M per volume transform at 600 x 600 x 31.)
+// Block (64 frequencies, tile) of 64 x 16 threads: thread (k, l) takes groups
+// l, l + 16, ... (8 loads in flight), the 16 partial maxima then meet in LDS.
+__global__ __launch_bounds__(1024) void k_rowmax_reduce(const unsigned *__restrict__ rowpart,
+                                                        int ngrp, int nt, int nk,
+                                                        const int *__restrict__ skip,
+                                                        unsigned *__restrict__ rowmax)
 {
-    unsigned v = m[i];
+    if (skip && *skip)
+        return;
+    __shared__ unsigned red[16][64];
+    const int kl = threadIdx.x & 63, l = threadIdx.x >> 6;
+    const int k = blockIdx.x * 64 + kl, tile = blockIdx.y;
+    const int kc = min(k, nk - 1);
+    unsigned m = 0u;
+    for (int g0 = l; g0 < ngrp; g0 += 8 * 16) {
+        unsigned v[8];
 #pragma unroll
-    for (int s = 1; s < kRowmaxSlots; ++s)
-        v = max(v, m[(size_t)s * slot_stride + i]);
-    return v;
+        for (int b = 0; b < 8; ++b) {
+            const int g = min(g0 + 16 * b, ngrp - 1);  // a repeated group leaves the max
+            v[b] = rowpart[((size_t)g * nt + tile) * nk + kc];
+        }
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+            m = max(m, v[b]);
+    }
+    red[l][kl] = m;
+    __syncthreads();
+    if (l == 0 && k < nk) {
+#pragma unroll
+        for (int q = 1; q < 16; ++q)
+            m = max(m, red[q][kl]);
+        rowmax[(size_t)k * nt + tile] = m;
+    }
 }
 
 __device__ __forceinline__ int xcd_item(int bid, int n)
@@ -394,19 +423,16 @@ __device__ __forceinline__ int xcd_item(int bid, int n)
 //               circularly in the tile; blockIdx = (cr, a, j); `src` is the
 //               PSF; KKo is the row stride NNp of the spectra.
 //               obase = ((j*N*N + a) * NNp + cr*N), kstride = KK * NNp.
-//   rowmax (SRC_PLANES, may be null): rowmax[(s * Q*QH + k) * nt + tile] is
-//   raised (atomic max on the float bits) to the largest |re| or |im| the
-//   block writes at frequency k, in slot s = (j*N + ar) mod kRowmaxSlots (the
-//   blocks of one tile spread their atomics over the slots instead of queueing
-//   on one address); the caller zeroes all slots first and readers take the
-//   maximum over them (rowmax_of).
+//   rowpart (SRC_PLANES, may be null): the largest |re| or |im| the block
+//   writes at frequency k (float bits) is stored at
+//   rowpart[(grp * nt + tile) * Q*QH + k], grp = j*N + ar (see k_rowmax_reduce).
 template <int Q>
 __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const TileBatch batch,
                                                   const float *__restrict__ src, int N, int T,
                                                   int hD, int nt, int KKo, int K, int c0, int KK,
                                                   float2 *__restrict__ out,
                                                   const float2 *__restrict__ twg,
-                                                  unsigned *__restrict__ rowmax)
+                                                  unsigned *__restrict__ rowpart)
 {
     constexpr int QH = Q / 2 + 1;
     extern __shared__ float smem[];
@@ -421,14 +447,14 @@ __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const TileBatch batch
     const int rowlen = Q * N;
     size_t obase, kstride;
     const float *plane = nullptr;
-    int H = 0, W = 0, ly0 = 0, lx0 = 0, arow = 0, rslot = 0;
+    int H = 0, W = 0, ly0 = 0, lx0 = 0, arow = 0, tile = 0, jar = 0;
     if (mode == SRC_PLANES) {
         const int item = xcd_item(blockIdx.x, gridDim.x);
         const int njar = gridDim.x / nt;
-        const int tile = item / njar, jar = item % njar;
+        tile = item / njar;
+        jar = item % njar;
         const int j = jar / N;
         arow = jar % N;
-        rslot = (j * N + arow) % kRowmaxSlots;
         const TileJob &fj = batch.job[batch_job(batch, tile)];
         if (fj.skip && *fj.skip)
             return;   // block-uniform, before any barrier
@@ -527,7 +553,7 @@ __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const TileBatch batch
             if (mode != SRC_PLANES || !freq_redundant<Q>(ku, kv))
                 out[obase + (size_t)(ku * QH + kv) * kstride + p] = v[ku];
     }
-    if (rowmax) {
+    if (rowpart) {
         // the column magnitudes through LDS (Z has been read by every
         // thread), then the maximum over the N phases of each frequency
         __syncthreads();
@@ -538,13 +564,12 @@ __global__ __launch_bounds__(512) void k_r2c_fft(int mode, const TileBatch batch
                 mz[(size_t)ku * QH * N + tid] = __float_as_uint(fmaxf(fabsf(v[ku].x), fabsf(v[ku].y)));
         }
         __syncthreads();
-        const int tile = xcd_item(blockIdx.x, gridDim.x) / (gridDim.x / nt);
+        unsigned *dst = rowpart + ((size_t)jar * nt + tile) * (Q * QH);
         for (int i = tid; i < Q * QH; i += blockDim.x) {
             unsigned m = 0u;
             for (int q = 0; q < N; ++q)
                 m = max(m, mz[(size_t)i * N + q]);
-            if (m)
-                atomicMax(&rowmax[((size_t)rslot * Q * QH + i) * nt + tile], m);
+            dst[i] = m;
         }
     }
 }
