@@ -2254,6 +2254,11 @@ static bool fft_usable(const Geo &g, size_t lds_max)
 // device, while plans of one tile side (and different Nnum) need different
 // amounts: the limit is only ever raised (per kernel and device), so a plan
 // built later never lowers what an earlier one launches with.
+static size_t lds_limit();
+
+// (A fixed table, so that no call allocates host memory either; should it
+// ever fill, the limit is set to the whole LDS of a workgroup, which is never
+// too low.)
 static void raise_lds_attr(const void *fn, size_t lds)
 {
     struct Entry {
@@ -2261,12 +2266,15 @@ static void raise_lds_attr(const void *fn, size_t lds)
         int dev;
         size_t lds;
     };
+    static constexpr int kEntries = 1024;
     static std::mutex mu;
-    static std::vector<Entry> set;
+    static Entry set[kEntries];
+    static int nset = 0;
     int dev = -1;
     (void)hipGetDevice(&dev);
     std::lock_guard<std::mutex> lk(mu);
-    for (Entry &e : set)
+    for (int i = 0; i < nset; ++i) {
+        Entry &e = set[i];
         if (e.fn == fn && e.dev == dev) {
             if (lds > e.lds) {
                 (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -2274,8 +2282,14 @@ static void raise_lds_attr(const void *fn, size_t lds)
             }
             return;
         }
+    }
+    if (nset == kEntries) {
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)std::max(lds, lds_limit()));
+        return;
+    }
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    set.push_back({fn, dev, lds});
+    set[nset++] = {fn, dev, lds};
 }
 
 static void set_fft_lds_attrs(int Q, size_t lds)
