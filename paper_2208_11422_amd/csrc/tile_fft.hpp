@@ -355,9 +355,6 @@ __device__ __forceinline__ float keep_if(float v, bool keep)
     return __uint_as_float(__float_as_uint(v) & (keep ? 0xffffffffu : 0u));
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
-// Remap the linear block id so that every XCD works through one contiguous
-// range of work items: items that share cache lines then share an L2.
 // Per-(frequency, tile) maxima of tile spectra (split precision): every
 // forward tile-DFT block stores the maxima of its columns at each frequency,
 // rowpart[(grp * nt + tile) * Q*QH + k] (plain stores of the float bits,
@@ -399,6 +396,9 @@ __global__ __launch_bounds__(1024) void k_rowmax_reduce(const unsigned *__restri
     }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Remap the linear block id so that every XCD works through one contiguous
+// range of work items: items that share cache lines then share an L2.
 __device__ __forceinline__ int xcd_item(int bid, int n)
 {
     constexpr int kXcds = 8;
