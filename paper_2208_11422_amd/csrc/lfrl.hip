@@ -683,12 +683,16 @@ __global__ __launch_bounds__(512) void k_contract_fwd(const float4 *__restrict__
 #if LFRL_KARA
         // three real products per complex product: accr = sum ar gr,
         // acci = sum ai gi, accs = sum (ar + ai)(gr + gi)
+        // (a wave's surplus column blocks, which repeat its last one and are
+        // not stored, skip their products: a wave-uniform branch)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const float4 a = la[buf][u][lane];
             const float s0 = a.x + a.y, s1 = a.z + a.w;
 #pragma unroll
             for (int b = 0; b < CB; ++b) {
+                if (b > 0 && wave * CB + b >= ncb)
+                    break;
                 const float4 g = gb[u][b];
                 accr[b] = mfma4(a.x, g.x, accr[b]);
                 acci[b] = mfma4(a.y, g.y, acci[b]);
@@ -696,6 +700,8 @@ __global__ __launch_bounds__(512) void k_contract_fwd(const float4 *__restrict__
             }
 #pragma unroll
             for (int b = 0; b < CB; ++b) {
+                if (b > 0 && wave * CB + b >= ncb)
+                    break;
                 const float4 g = gb[u][b];
                 accr[b] = mfma4(a.z, g.z, accr[b]);
                 acci[b] = mfma4(a.w, g.w, acci[b]);
